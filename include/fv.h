@@ -1,0 +1,175 @@
+/*
+ * fv.h -- C ABI of libfv.so, a semi-naive Datalog engine over column-stored
+ * uint32 relations, written for AMD Instinct MI355X (gfx950).
+ *
+ * The problem these calls state is the one of Section 2 ("Datalog and RDF"):
+ * extensional facts (EDB) are loaded into relations, positive Horn clauses
+ * H <- B1, ..., Bn are added, and the engine derives every intensional fact
+ * (IDB) until a fixed point is reached.  The evaluation follows Sections 3-4:
+ * relations are stored column-wise (one uint32 array per column, tuples in
+ * insertion order, full relations kept contiguous by eager merging), and each
+ * round of semi-naive evaluation hash-joins the delta of a relation against
+ * hash-indexed full relations (Algorithm 1), radix-sorts the newly derived
+ * tuples, removes those already in full (the difference operator of Section 4,
+ * "Union and Deduplication") and appends the survivors to full.
+ *
+ * Conventions for every call:
+ *  - Every call returns an fv_status; 0 is success, negative is an error.
+ *    On error, fv_last_error(ctx) returns a NUL-terminated message that stays
+ *    valid until the next call on the same context.  No C++ exception crosses
+ *    this interface.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ *  - All GPU work is ordered on the context's stream (fv_options.stream).
+ *    Calls that return host-visible results synchronise that stream.
+ *  - Pointers flagged as device pointers must be HIP device memory readable by
+ *    the context's device; host pointers must be ordinary host memory.
+ *  - The value 0xFFFFFFFF is reserved (it marks empty hash slots) and is
+ *    rejected wherever it is passed in (FV_ERESERVED).
+ */
+#ifndef FV_H_
+#define FV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fv_ctx fv_ctx;   /* opaque; owns relations, rules and all device memory */
+typedef uint32_t fv_rel;        /* relation handle: index within its context */
+
+typedef enum {
+  FV_OK = 0,
+  FV_EINVAL = -1,      /* bad argument (null pointer, unknown handle, bad name) */
+  FV_ENOMEM = -2,      /* device allocation failed; the context is then terminal */
+  FV_EARITY = -3,      /* arity mismatch between an atom and its relation, or arity outside 1..3 */
+  FV_EUNSAFE = -4,     /* a head or != variable does not occur in a body atom */
+  FV_ESTATE = -5,      /* call not allowed in the current state (e.g. load after run) */
+  FV_EHIP = -6,        /* a HIP runtime call failed */
+  FV_ERESERVED = -7,   /* the reserved value 0xFFFFFFFF was passed in */
+  FV_ETRUNC = -8,      /* export capacity smaller than the relation */
+  FV_ENOTSUP = -9      /* a relation's packed tuple needs more than 64 bits */
+} fv_status;
+
+/* fv_options.flags */
+#define FV_PLAIN      0u   /* count-then-write joins, host loop, one sync per round */
+#define FV_TRACE      4u   /* time each kernel class with HIP events (see fv_profile) */
+
+/* Device allocator hooks.  dev_alloc returns device memory of at least
+ * `bytes` bytes usable on `stream`, or NULL on failure; dev_free releases a
+ * pointer dev_alloc returned.  Both NULL: the library uses hipMalloc/hipFree. */
+typedef void* (*fv_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*fv_free_fn)(void* ptr, void* stream, void* user);
+
+typedef struct {
+  void* stream;            /* hipStream_t the context runs on; NULL = null stream */
+  fv_alloc_fn dev_alloc;   /* optional */
+  fv_free_fn dev_free;     /* optional; required when dev_alloc is set */
+  void* user;              /* passed through to the hooks */
+  uint32_t flags;          /* FV_* flags above */
+} fv_options;
+
+/* A term of an atom: a variable (is_const = 0, value = variable index within
+ * the rule, 0..15) or a constant (is_const = 1, value = the uint32 constant). */
+typedef struct { uint32_t value; uint32_t is_const; } fv_term;
+
+/* An atom rel(t0, ..., t_{arity-1}). */
+typedef struct { fv_rel rel; uint32_t arity; const fv_term* terms; } fv_atom;
+
+/* A rule head :- body[0], ..., body[n_body-1], neq constraints.  `neq` holds
+ * n_neq pairs of variable indices (2 * n_neq entries); pair (a, b) requires
+ * the values of variables a and b to differ (the x != y of Section 5.2). */
+typedef struct {
+  fv_atom head;
+  const fv_atom* body;
+  uint32_t n_body;         /* 1..8 */
+  const uint32_t* neq;
+  uint32_t n_neq;          /* 0..8 */
+} fv_rule;
+
+typedef struct {
+  uint32_t iterations;         /* rounds run, including the final round that derived nothing */
+  uint32_t redo_rounds;        /* rounds re-run after a buffer had to grow */
+  uint64_t derived_tuples;     /* sum over IDB relations of |full| at fixpoint minus loaded facts */
+  uint64_t join_output_tuples; /* tuples written by joins before deduplication */
+  double ms_total;             /* wall time of fv_run_fixpoint (host clock, stream synchronised) */
+} fv_stats;
+
+/* One kernel class in the profile returned by fv_profile (FV_TRACE only). */
+typedef struct {
+  char name[32];
+  uint64_t launches;
+  double ms;                   /* sum of HIP-event durations on the context's stream */
+  double algo_bytes;           /* algorithmic HBM bytes these launches had to move */
+  uint64_t items;              /* elements processed (rows, keys or output tuples) */
+} fv_kprof;
+
+/* Create a context.  opt may be NULL (null stream, hipMalloc, no flags).
+ * The options struct is copied. */
+fv_status fv_ctx_create(fv_ctx** out, const fv_options* opt);
+
+/* Destroy a context and free all its device memory.  Safe on NULL and on a
+ * context that hit an error. */
+void fv_ctx_destroy(fv_ctx* ctx);
+
+/* Text of the last error on this context ("" if none). */
+const char* fv_last_error(const fv_ctx* ctx);
+
+/* Declare a relation of the given arity (1..3) under a unique name
+ * (Section 3: a relation is a set of columns of uint32 values).  The handle
+ * is written to *out. */
+fv_status fv_relation_create(fv_ctx* ctx, const char* name, uint32_t arity, fv_rel* out);
+
+/* Look up a relation by name. */
+fv_status fv_relation_find(fv_ctx* ctx, const char* name, fv_rel* out);
+
+/* Append n_rows facts to a relation, given as `arity` column arrays of
+ * n_rows uint32 each (Section 3, raw data arrays).  on_device != 0 means the
+ * column pointers are device pointers.  The data is copied before the call
+ * returns; the caller keeps ownership.  Relations are sets: duplicates are
+ * removed when the fixpoint starts.  Allowed only before fv_run_fixpoint.
+ * Errors: FV_EINVAL, FV_ESTATE, FV_ERESERVED (a value is 0xFFFFFFFF),
+ * FV_ENOMEM, FV_EHIP. */
+fv_status fv_load_columns(fv_ctx* ctx, fv_rel rel, const uint32_t* const* cols,
+                          uint64_t n_rows, int on_device);
+
+/* Add a rule (Section 2; translated into joins, selections and projections
+ * as in Section 4).  The rule is validated and copied.  Allowed only before
+ * fv_run_fixpoint.  Errors: FV_EARITY, FV_EUNSAFE, FV_EINVAL (variable index
+ * above 15, too many atoms), FV_ERESERVED, FV_ESTATE. */
+fv_status fv_add_rule(fv_ctx* ctx, const fv_rule* rule);
+
+/* Evaluate the program to its least fixpoint by semi-naive evaluation
+ * (Section 3): all rules contribute in every round, the delta of each
+ * relation is joined against full relations (Algorithm 1), the new tuples are
+ * radix-sorted, deduplicated against full and merged into full, until no
+ * relation gains a tuple.  Runs once per context; stats may be NULL.
+ * Errors: FV_ESTATE (already run), FV_ENOTSUP, FV_ENOMEM, FV_EHIP. */
+fv_status fv_run_fixpoint(fv_ctx* ctx, fv_stats* stats);
+
+/* Number of tuples currently in a relation (after the fixpoint: its full
+ * version; before: the rows loaded so far, duplicates included). */
+fv_status fv_relation_size(fv_ctx* ctx, fv_rel rel, uint64_t* n_rows);
+
+/* Copy a relation out, sorted lexicographically by (col0, col1, col2).
+ * cols_out holds `arity` column pointers of capacity rows each (device
+ * pointers if on_device != 0).  cols_out == NULL only writes *n_rows_out.
+ * If capacity < size nothing is written and FV_ETRUNC is returned with
+ * *n_rows_out set.  Allowed after fv_run_fixpoint. */
+fv_status fv_export(fv_ctx* ctx, fv_rel rel, uint32_t* const* cols_out,
+                    uint64_t capacity, uint64_t* n_rows_out, int on_device);
+
+/* Per-round delta sizes of the last fixpoint, summed over relations: round r
+ * added out[r] tuples.  *n receives the number of rounds; up to cap entries
+ * are written. */
+fv_status fv_delta_sizes(fv_ctx* ctx, uint64_t* out, uint32_t cap, uint32_t* n);
+
+/* Kernel-class profile of the last fixpoint (FV_TRACE contexts): up to cap
+ * entries are written, *n receives the number of classes. */
+fv_status fv_profile(fv_ctx* ctx, fv_kprof* out, uint32_t cap, uint32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FV_H_ */

@@ -1,0 +1,1062 @@
+// Host runtime: relations, rule plans and the semi-naive round loop.
+//
+// A round (Section 3, "Schedule multiple rules per iteration") evaluates every
+// rule variant at once -- one variant per body position that reads a delta --
+// appending the head tuples of all variants of a relation to that relation's
+// "new" buffer; then, per relation, the new tuples are radix-sorted, the
+// difference against full is taken and the survivors are appended to the
+// contiguous full relation, whose tail [d_begin, n_full) is the next delta.
+//
+// Sizes produced on the device (join outputs, deltas) stay on the device:
+// kernels read them from counters, and buffers are sized ahead from known
+// bounds.  A join whose output exceeds its buffer keeps counting, raises the
+// overflow flag, and every later kernel of the round that would change state
+// (sort, difference, merge, index rebuild) sees the flag and does nothing, so
+// the host can grow the buffer and run the round again from the same state.
+// The host reads the counters back once per round.
+#include "engine.h"
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+
+namespace fv {
+
+namespace {
+
+u64 pow2_at_least(u64 x) {
+  u64 p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+u32 bits_for(u64 x) {   // number of bits to represent x (x >= 1)
+  u32 b = 0;
+  while (x) { ++b; x >>= 1; }
+  return b;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ lifetime
+Engine::Engine(const fv_options* opt) {
+  if (opt) opt_ = *opt;
+  if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
+  stream_ = static_cast<hipStream_t>(opt_.stream);
+  trace_ = (opt_.flags & FV_TRACE) != 0;
+}
+
+Engine::~Engine() {
+  // best effort: wait for queued work, then free everything
+  if (touched_device_) (void)hipStreamSynchronize(stream_);
+  for (auto& R : rels_) {
+    for (int c = 0; c < 3; ++c) { release(R.stage[c]); release(R.col[c]); }
+    release(R.newk); release(R.newk2); release(R.set);
+  }
+  for (auto& ix : indices_) { release(ix.table); release(ix.perm); }
+  for (auto& I : inters_) for (auto& b : I.col) release(b);
+  release(ctr_dev_); release(flags_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
+  release(m_row_); release(m_start_); release(m_off_);
+  release(st_a_); release(st_b_); release(st_sort_);
+  if (ctr_host_) (void)hipHostFree(ctr_host_);
+  if (flags_host_) (void)hipHostFree(flags_host_);
+  for (auto e : ev_pool_) (void)hipEventDestroy(e);
+  for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+}
+
+// ------------------------------------------------------------------ memory
+Buf Engine::alloc(size_t bytes) {
+  touched_device_ = true;
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (opt_.dev_alloc) {
+    p = opt_.dev_alloc(bytes, opt_.stream, opt_.user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (!p) {
+    terminal = true;
+    throw Error(FV_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  Buf b;
+  b.p = p;
+  b.bytes = bytes;
+  return b;
+}
+
+void Engine::release(Buf& b) {
+  if (b.p) {
+    if (opt_.dev_free) opt_.dev_free(b.p, opt_.stream, opt_.user);
+    else (void)hipFree(b.p);
+  }
+  b = Buf{};
+}
+
+void Engine::grow(Buf& b, size_t bytes, size_t keep_bytes) {
+  if (b.p && b.bytes >= bytes) return;
+  Buf nb = alloc(bytes);
+  if (b.p && keep_bytes)
+    hip(hipMemcpyAsync(nb.p, b.p, std::min(keep_bytes, b.bytes), hipMemcpyDeviceToDevice, stream_), "grow copy");
+  release(b);
+  b = nb;
+}
+
+void Engine::hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    terminal = true;
+    throw Error(FV_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+void Engine::launched(int rc, const char* what) { hip(static_cast<hipError_t>(rc), what); }
+
+void Engine::sync() { hip(hipStreamSynchronize(stream_), "stream synchronize"); }
+
+u32 Engine::next_epoch(u32 n) {
+  if (epoch_ + n >= kEpochMask) {
+    // epochs wrap: clear every look-back status array so no stale word can match
+    if (st_a_.p) launched(launch_fill_u64(st_a_.as<u64>(), st_a_.bytes / 8, 0, stream_), "clear status");
+    if (st_b_.p) launched(launch_fill_u64(st_b_.as<u64>(), st_b_.bytes / 8, 0, stream_), "clear status");
+    if (st_sort_.p) launched(launch_fill_u64(st_sort_.as<u64>(), st_sort_.bytes / 8, 0, stream_), "clear status");
+    epoch_ = 1;
+  }
+  const u32 e = epoch_;
+  epoch_ += n;
+  return e;
+}
+
+// ------------------------------------------------------------------ relations and rules
+u32 Engine::relation_create(const char* name, u32 arity) {
+  if (!name || !*name) throw Error(FV_EINVAL, "relation name is empty");
+  if (ran_) throw Error(FV_ESTATE, "relations cannot be added after the fixpoint ran");
+  if (arity < 1 || arity > 3) throw Error(FV_EARITY, "arity must be 1..3");
+  if (by_name_.count(name)) throw Error(FV_EINVAL, std::string("relation exists: ") + name);
+  Relation R;
+  R.name = name;
+  R.arity = arity;
+  rels_.push_back(R);
+  const u32 id = u32(rels_.size() - 1);
+  by_name_[name] = id;
+  return id;
+}
+
+u32 Engine::relation_find(const char* name) const {
+  if (!name) throw Error(FV_EINVAL, "null name");
+  auto it = by_name_.find(name);
+  if (it == by_name_.end()) throw Error(FV_EINVAL, std::string("no relation named ") + name);
+  return it->second;
+}
+
+void Engine::load_columns(u32 rel, const u32* const* cols, u64 n, bool on_device) {
+  if (rel >= rels_.size()) throw Error(FV_EINVAL, "bad relation handle");
+  if (ran_) throw Error(FV_ESTATE, "facts cannot be loaded after the fixpoint ran");
+  if (n == 0) return;
+  if (!cols) throw Error(FV_EINVAL, "null column array");
+  Relation& R = rels_[rel];
+  for (u32 c = 0; c < R.arity; ++c)
+    if (!cols[c]) throw Error(FV_EINVAL, "null column pointer");
+  if (!maxv_dev_.p) maxv_dev_ = alloc(64);
+  if (R.staged + n > R.stage_cap) {
+    const u64 cap = std::max<u64>(R.staged + n, R.stage_cap * 2);
+    for (u32 c = 0; c < R.arity; ++c) grow(R.stage[c], cap * 4, R.staged * 4);
+    R.stage_cap = cap;
+  }
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  u32* mx = maxv_dev_.as<u32>();
+  launched(launch_fill_u32(mx, 4, 0u, stream_), "fill");
+  for (u32 c = 0; c < R.arity; ++c) {
+    u32* dst = R.stage[c].as<u32>() + R.staged;
+    hip(hipMemcpyAsync(dst, cols[c], n * 4, kind, stream_), "load copy");
+    launched(launch_colmax(dst, n, mx + c, stream_), "colmax");
+  }
+  u32 host_max[4] = {0, 0, 0, 0};
+  hip(hipMemcpyAsync(host_max, mx, 16, hipMemcpyDeviceToHost, stream_), "max readback");
+  sync();
+  for (u32 c = 0; c < R.arity; ++c)
+    if (host_max[c] == 0xFFFFFFFFu) throw Error(FV_ERESERVED, "value 0xFFFFFFFF is reserved");
+  for (u32 c = 0; c < R.arity; ++c) R.maxv[c] = std::max(R.maxv[c], host_max[c]);
+  R.staged += n;
+  R.has_rows = true;
+}
+
+void Engine::add_rule(const fv_rule& r) {
+  if (ran_) throw Error(FV_ESTATE, "rules cannot be added after the fixpoint ran");
+  auto conv = [&](const fv_atom& a) {
+    if (a.rel >= rels_.size()) throw Error(FV_EINVAL, "bad relation handle in rule");
+    if (a.arity != rels_[a.rel].arity) throw Error(FV_EARITY, "atom arity differs from relation " + rels_[a.rel].name);
+    if (!a.terms) throw Error(FV_EINVAL, "null terms");
+    AtomR o;
+    o.rel = a.rel;
+    for (u32 i = 0; i < a.arity; ++i) {
+      const fv_term& t = a.terms[i];
+      if (t.is_const) {
+        if (t.value == 0xFFFFFFFFu) throw Error(FV_ERESERVED, "constant 0xFFFFFFFF is reserved");
+      } else if (t.value >= kMaxVars) {
+        throw Error(FV_EINVAL, "variable index above 15");
+      }
+      o.t.push_back(Term{t.value, t.is_const != 0});
+    }
+    return o;
+  };
+  if (r.n_body < 1 || r.n_body > kMaxBody) throw Error(FV_EINVAL, "a rule needs 1..8 body atoms");
+  if (r.n_neq > kMaxNeq) throw Error(FV_EINVAL, "at most 8 != constraints");
+  if (!r.body) throw Error(FV_EINVAL, "null body");
+  RuleR rr;
+  rr.head = conv(r.head);
+  for (u32 i = 0; i < r.n_body; ++i) rr.body.push_back(conv(r.body[i]));
+  bool pos[kMaxVars] = {};
+  for (auto& a : rr.body)
+    for (auto& t : a.t)
+      if (!t.is_const) pos[t.value] = true;
+  for (auto& t : rr.head.t)
+    if (!t.is_const && !pos[t.value]) throw Error(FV_EUNSAFE, "head variable not bound by the body");
+  if (r.n_neq && !r.neq) throw Error(FV_EINVAL, "null neq");
+  for (u32 i = 0; i < r.n_neq; ++i) {
+    const u32 a = r.neq[2 * i], b = r.neq[2 * i + 1];
+    if (a >= kMaxVars || b >= kMaxVars) throw Error(FV_EINVAL, "variable index above 15");
+    if (!pos[a] || !pos[b]) throw Error(FV_EUNSAFE, "!= variable not bound by the body");
+    rr.neq.push_back({a, b});
+  }
+  rules_.push_back(rr);
+}
+
+u64 Engine::relation_size(u32 rel) const {
+  if (rel >= rels_.size()) throw Error(FV_EINVAL, "bad relation handle");
+  return ran_ ? rels_[rel].n_full : rels_[rel].staged;
+}
+
+// ------------------------------------------------------------------ domain analysis
+// Datalog without function symbols creates no values: a head column can only
+// hold constants of the rule or values of a body column its variable occurs
+// in, so its maximum is bounded by the smallest maximum over those columns.
+// The bounds give each column a bit width for the packed tuple key.
+void Engine::domain_analysis() {
+  for (auto& r : rules_) rels_[r.head.rel].idb = true;
+  for (bool changed = true; changed;) {
+    changed = false;
+    for (auto& r : rules_) {
+      Relation& H = rels_[r.head.rel];
+      for (u32 c = 0; c < H.arity; ++c) {
+        const Term& t = r.head.t[c];
+        u32 m;
+        if (t.is_const) {
+          m = t.value;
+        } else {
+          m = 0xFFFFFFFEu;
+          for (auto& a : r.body)
+            for (u32 k = 0; k < a.t.size(); ++k)
+              if (!a.t[k].is_const && a.t[k].value == t.value) m = std::min(m, rels_[a.rel].maxv[k]);
+        }
+        if (m > H.maxv[c]) { H.maxv[c] = m; changed = true; }
+      }
+    }
+  }
+  for (auto& R : rels_) {
+    R.bits = 0;
+    for (u32 c = 0; c < R.arity; ++c) {
+      // width of max+1 keeps every field strictly below all-ones, so no
+      // packed key can equal the empty-slot sentinel
+      R.width[c] = bits_for(u64(R.maxv[c]) + 1);
+      R.bits += R.width[c];
+    }
+    if (R.bits > 64)
+      throw Error(FV_ENOTSUP, "relation " + R.name + " needs " + std::to_string(R.bits) + " bits per packed tuple");
+    u32 s = 0;
+    for (int c = int(R.arity) - 1; c >= 0; --c) { R.shift[c] = s; s += R.width[c]; }
+  }
+}
+
+// ------------------------------------------------------------------ planning
+u32 Engine::get_index(u32 rel, u32 nkey, const u32* keycol) {
+  for (u32 i = 0; i < indices_.size(); ++i) {
+    const Index& ix = indices_[i];
+    if (ix.rel == rel && ix.nkey == nkey && ix.keycol[0] == keycol[0] && (nkey < 2 || ix.keycol[1] == keycol[1]))
+      return i;
+  }
+  Index ix;
+  ix.rel = rel;
+  ix.nkey = nkey;
+  ix.keycol[0] = keycol[0];
+  ix.keycol[1] = nkey > 1 ? keycol[1] : 0;
+  indices_.push_back(ix);
+  return u32(indices_.size() - 1);
+}
+
+Plan Engine::plan_rule(u32 ri, int dpos) {
+  const RuleR& r = rules_[ri];
+  const u32 nb = u32(r.body.size());
+  std::vector<bool> used(nb, false), bound(kMaxVars, false);
+  std::vector<u32> order;
+  u32 first = 0;
+  if (dpos >= 0) {
+    first = u32(dpos);
+  } else {
+    u64 best = ~0ull;
+    for (u32 i = 0; i < nb; ++i) {
+      const Relation& R = rels_[r.body[i].rel];
+      if (R.staged < best) { best = R.staged; first = i; }
+    }
+  }
+  order.push_back(first);
+  used[first] = true;
+  for (auto& t : r.body[first].t)
+    if (!t.is_const) bound[t.value] = true;
+  while (order.size() < nb) {
+    int best = -1, best_score = -1;
+    for (u32 i = 0; i < nb; ++i) {
+      if (used[i]) continue;
+      int shared = 0, consts = 0;
+      std::vector<bool> seen(kMaxVars, false);
+      for (auto& t : r.body[i].t) {
+        if (t.is_const) ++consts;
+        else if (bound[t.value] && !seen[t.value]) { ++shared; seen[t.value] = true; }
+      }
+      const int score = shared * 8 + consts * 2 + (rels_[r.body[i].rel].idb ? 0 : 1);
+      if (score > best_score) { best_score = score; best = int(i); }
+    }
+    order.push_back(u32(best));
+    used[best] = true;
+    for (auto& t : r.body[best].t)
+      if (!t.is_const) bound[t.value] = true;
+  }
+
+  Plan p;
+  p.rule = ri;
+  p.delta_pos = dpos;
+  p.src_rel = r.body[first].rel;
+  p.src_delta = dpos >= 0;
+
+  // which variables are still needed after body position k of `order`
+  auto needed_after = [&](u32 k, const std::vector<bool>& neq_done) {
+    std::vector<bool> need(kMaxVars, false);
+    for (u32 j = k + 1; j < nb; ++j)
+      for (auto& t : r.body[order[j]].t)
+        if (!t.is_const) need[t.value] = true;
+    for (auto& t : r.head.t)
+      if (!t.is_const) need[t.value] = true;
+    for (u32 q = 0; q < r.neq.size(); ++q)
+      if (!neq_done[q]) { need[r.neq[q].first] = true; need[r.neq[q].second] = true; }
+    return need;
+  };
+
+  // schema of the probe side: variable -> probe column
+  std::vector<int> schema(kMaxVars, -1);
+  std::vector<bool> neq_done(r.neq.size(), false);
+  std::vector<Filter> pf;
+  {
+    const AtomR& a0 = r.body[first];
+    for (u32 c = 0; c < a0.t.size(); ++c) {
+      const Term& t = a0.t[c];
+      if (t.is_const) pf.push_back(Filter{Src{kSrcProbe, c}, Src{kSrcConst, t.value}, kEq});
+      else if (schema[t.value] >= 0) pf.push_back(Filter{Src{kSrcProbe, c}, Src{kSrcProbe, u32(schema[t.value])}, kEq});
+      else schema[t.value] = int(c);
+    }
+    for (u32 q = 0; q < r.neq.size(); ++q) {
+      const int a = schema[r.neq[q].first], b = schema[r.neq[q].second];
+      if (a >= 0 && b >= 0) {
+        pf.push_back(Filter{Src{kSrcProbe, u32(a)}, Src{kSrcProbe, u32(b)}, kNe});
+        neq_done[q] = true;
+      }
+    }
+  }
+  if (pf.size() > size_t(kMaxFilters)) throw Error(FV_ENOTSUP, "too many filters on one atom");
+
+  auto head_out = [&](const std::vector<Src>& var_src) {
+    std::vector<Src> out;
+    for (auto& t : r.head.t) out.push_back(t.is_const ? Src{kSrcConst, t.value} : var_src[t.value]);
+    return out;
+  };
+
+  if (nb == 1) {
+    Step s;
+    s.select_only = true;
+    s.pf = pf;
+    std::vector<Src> vs(kMaxVars, Src{kSrcConst, 0});
+    for (u32 v = 0; v < kMaxVars; ++v)
+      if (schema[v] >= 0) vs[v] = Src{kSrcProbe, u32(schema[v])};
+    s.out = head_out(vs);
+    s.out_buf = -1;
+    s.head_rel = r.head.rel;
+    p.steps.push_back(s);
+    return p;
+  }
+
+  for (u32 k = 1; k < nb; ++k) {
+    const AtomR& a = r.body[order[k]];
+    Step s;
+    s.brel = a.rel;
+    if (k == 1) s.pf = pf;
+    // key candidates: constants and already-bound variables of this atom
+    struct Cand { u32 col; Src src; bool is_var; };
+    std::vector<Cand> cands;
+    std::vector<int> newcol(kMaxVars, -1);     // first column of a variable bound here
+    std::vector<Filter> wf;
+    for (u32 c = 0; c < a.t.size(); ++c) {
+      const Term& t = a.t[c];
+      if (t.is_const) cands.push_back(Cand{c, Src{kSrcConst, t.value}, false});
+      else if (schema[t.value] >= 0) cands.push_back(Cand{c, Src{kSrcProbe, u32(schema[t.value])}, true});
+      else if (newcol[t.value] >= 0) wf.push_back(Filter{Src{kSrcBuild, c}, Src{kSrcBuild, u32(newcol[t.value])}, kEq});
+      else newcol[t.value] = int(c);
+    }
+    std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.is_var > y.is_var; });
+    s.nkey = u32(std::min<size_t>(2, cands.size()));
+    u32 keycol[2] = {0, 0};
+    for (u32 i = 0; i < s.nkey; ++i) { s.key[i] = cands[i].src; keycol[i] = cands[i].col; }
+    // a two-column index keys on (lower column, higher column)
+    if (s.nkey == 2 && keycol[0] > keycol[1]) { std::swap(keycol[0], keycol[1]); std::swap(s.key[0], s.key[1]); }
+    s.index = s.nkey ? get_index(a.rel, s.nkey, keycol) : kNoIndex;
+    for (size_t i = s.nkey; i < cands.size(); ++i)
+      wf.push_back(Filter{Src{kSrcBuild, cands[i].col}, cands[i].src, kEq});
+    // variable sources after this join
+    std::vector<Src> vs(kMaxVars, Src{kSrcConst, 0});
+    std::vector<bool> have(kMaxVars, false);
+    for (u32 v = 0; v < kMaxVars; ++v) {
+      if (schema[v] >= 0) { vs[v] = Src{kSrcProbe, u32(schema[v])}; have[v] = true; }
+      else if (newcol[v] >= 0) { vs[v] = Src{kSrcBuild, u32(newcol[v])}; have[v] = true; }
+    }
+    for (u32 q = 0; q < r.neq.size(); ++q) {
+      if (neq_done[q]) continue;
+      const u32 x = r.neq[q].first, y = r.neq[q].second;
+      if (have[x] && have[y]) { wf.push_back(Filter{vs[x], vs[y], kNe}); neq_done[q] = true; }
+    }
+    if (wf.size() > size_t(kMaxFilters)) throw Error(FV_ENOTSUP, "too many filters on one join");
+    s.wf = wf;
+    if (k == nb - 1) {
+      s.out = head_out(vs);
+      s.out_buf = -1;
+      s.head_rel = r.head.rel;
+    } else {
+      const std::vector<bool> need = needed_after(k, neq_done);
+      std::vector<int> nschema(kMaxVars, -1);
+      u32 nc = 0;
+      for (u32 v = 0; v < kMaxVars; ++v) {
+        if (need[v] && have[v]) {
+          s.out.push_back(vs[v]);
+          nschema[v] = int(nc++);
+        }
+      }
+      if (nc == 0) {   // nothing left to carry but more atoms follow: keep one column for the row count
+        for (u32 v = 0; v < kMaxVars && nc == 0; ++v)
+          if (have[v]) { s.out.push_back(vs[v]); nschema[v] = int(nc++); }
+      }
+      if (nc > u32(kMaxCols)) throw Error(FV_ENOTSUP, "more than 6 live variables between two joins");
+      Inter I;
+      I.ncols = nc;
+      inters_.push_back(I);
+      s.out_buf = int(inters_.size() - 1);
+      schema = nschema;
+    }
+    p.steps.push_back(s);
+  }
+  return p;
+}
+
+void Engine::plan_all() {
+  init_plans_.clear();
+  delta_plans_.clear();
+  for (u32 ri = 0; ri < rules_.size(); ++ri) {
+    init_plans_.push_back(plan_rule(ri, -1));
+    for (u32 i = 0; i < rules_[ri].body.size(); ++i)
+      if (rels_[rules_[ri].body[i].rel].idb) delta_plans_.push_back(plan_rule(ri, int(i)));
+  }
+  for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
+  // counter layout: [derived, join_out] [full_n x R] [d_begin x R] [delta x R]
+  //                 [new x R] [per-join m,t] [per-intermediate count]
+  const int R = int(rels_.size());
+  c_derived_ = 0;
+  c_joinout_ = 1;
+  c_full0_ = 2;
+  c_dbeg0_ = c_full0_ + R;
+  c_delta0_ = c_dbeg0_ + R;
+  c_new0_ = c_delta0_ + R;
+  c_reset_begin_ = c_delta0_;
+  int next = c_new0_ + R;
+  for (auto* plans : {&init_plans_, &delta_plans_})
+    for (auto& p : *plans)
+      for (auto& s : p.steps)
+        if (!s.select_only) { s.c_m = next++; s.c_t = next++; }
+  for (auto& I : inters_) I.ctr = next++;
+  n_ctr_ = next;
+}
+
+// ------------------------------------------------------------------ capacity
+void Engine::ensure_capacity() {
+  // look-back status arrays and row-id scratch are sized for the largest launch
+  u64 max_probe = 1, max_rows = 1;
+  auto plan_probe = [&](const Plan& p, bool initial) {
+    const Relation& S = rels_[p.src_rel];
+    const u64 n0 = initial ? S.n_full : S.n_delta;
+    for (size_t k = 0; k < p.steps.size(); ++k) {
+      const u64 n = k == 0 ? n0 : inters_[p.steps[k - 1].out_buf].cap;
+      max_probe = std::max(max_probe, n);
+    }
+  };
+  for (auto& p : init_plans_) plan_probe(p, true);
+  for (auto& p : delta_plans_) plan_probe(p, false);
+  for (auto& R : rels_) {
+    max_rows = std::max(max_rows, R.new_cap);
+    if (!R.used_as_head) continue;
+    const u64 need_full = R.n_full + R.new_cap;
+    if (R.cap < need_full) {
+      const u64 nc = std::max<u64>(need_full, R.cap + R.cap / 2);
+      for (u32 c = 0; c < R.arity; ++c) grow(R.col[c], nc * 4, R.n_full * 4);
+      R.cap = nc;
+    }
+    const u64 need_set = pow2_at_least(2 * need_full);
+    if (R.set_cap < need_set) {
+      release(R.set);
+      R.set = alloc(need_set * 8);
+      R.set_cap = need_set;
+      launched(launch_fill_u64(R.set.as<u64>(), need_set, kEmptyKey, stream_), "set clear");
+      const u32* cols[3] = {R.col[0].as<u32>(), R.col[1].as<u32>(), R.col[2].as<u32>()};
+      launched(launch_set_insert_rows(cols, R.arity, R.shift, R.n_full, R.set.as<u64>(), need_set - 1, stream_),
+               "set rebuild");
+    }
+    if (R.newk.bytes < R.new_cap * 8) {
+      release(R.newk);
+      release(R.newk2);
+      R.newk = alloc(R.new_cap * 8);
+      R.newk2 = alloc(R.new_cap * 8);
+    }
+    max_rows = std::max(max_rows, R.new_cap);
+  }
+  for (auto& ix : indices_) {
+    const Relation& R = rels_[ix.rel];
+    const u64 rows = R.used_as_head ? R.n_full + R.new_cap : R.n_full;
+    const u64 need = pow2_at_least(std::max<u64>(2 * rows, 64));
+    if (ix.cap < need) {
+      release(ix.table);
+      ix.table = alloc(need * sizeof(Slot));
+      ix.cap = need;
+      ix.dirty = true;
+    }
+    if (ix.perm_cap < rows) {
+      release(ix.perm);
+      ix.perm = alloc(std::max<u64>(rows, 1) * 4);
+      ix.perm_cap = rows;
+      ix.dirty = true;
+    }
+    max_rows = std::max(max_rows, ix.cap);
+  }
+  for (auto& I : inters_) {
+    if (I.cap == 0) I.cap = 1 << 16;
+    for (u32 c = 0; c < I.ncols; ++c)
+      if (I.col[c].bytes < I.cap * 4) { release(I.col[c]); I.col[c] = alloc(I.cap * 4); }
+  }
+  if (m_cap_ < max_probe) {
+    const u64 nc = std::max<u64>(max_probe, m_cap_ * 2);
+    release(m_row_); release(m_start_); release(m_off_);
+    m_row_ = alloc(nc * 4);
+    m_start_ = alloc(nc * 4);
+    m_off_ = alloc(nc * 8);
+    m_cap_ = nc;
+  }
+  const u64 tiles = (std::max(max_probe, max_rows) + 1023) / 1024 + 2;
+  if (st_cap_ < tiles) {
+    const u64 nc = std::max<u64>(tiles, st_cap_ * 2);
+    release(st_a_); release(st_b_);
+    st_a_ = alloc(nc * 8);
+    st_b_ = alloc(nc * 8);
+    launched(launch_fill_u64(st_a_.as<u64>(), nc, 0, stream_), "status clear");
+    launched(launch_fill_u64(st_b_.as<u64>(), nc, 0, stream_), "status clear");
+    st_cap_ = nc;
+  }
+  const u64 stiles = (max_rows + kSortTile - 1) / kSortTile + 1;
+  if (st_sort_tiles_ < stiles) {
+    const u64 nc = std::max<u64>(stiles, st_sort_tiles_ * 2);
+    release(st_sort_);
+    st_sort_ = alloc(nc * 256 * 8);
+    launched(launch_fill_u64(st_sort_.as<u64>(), nc * 256, 0, stream_), "status clear");
+    st_sort_tiles_ = nc;
+  }
+}
+
+// ------------------------------------------------------------------ profiling
+int Engine::kclass(const char* name) {
+  for (size_t i = 0; i < kprof_.size(); ++i)
+    if (kprof_[i].name == name) return int(i);
+  KClass k;
+  k.name = name;
+  kprof_.push_back(k);
+  return int(kprof_.size() - 1);
+}
+
+void Engine::ev_begin(int) {
+  if (!trace_) return;
+  hipEvent_t e;
+  if (!ev_pool_.empty()) { e = ev_pool_.back(); ev_pool_.pop_back(); }
+  else hip(hipEventCreate(&e), "event create");
+  hip(hipEventRecord(e, stream_), "event record");
+  ev_open_ = e;
+}
+
+void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux) {
+  if (!trace_) return;
+  hipEvent_t e;
+  if (!ev_pool_.empty()) { e = ev_pool_.back(); ev_pool_.pop_back(); }
+  else hip(hipEventCreate(&e), "event create");
+  hip(hipEventRecord(e, stream_), "event record");
+  pending_.push_back(PendingEvent{cls, ev_open_, e, bytes, kind, ref0, ref1, aux});
+}
+
+// Algorithmic bytes of a launch, from the sizes read back after the round.
+// kind 1 probe: aux = probe rows (or ref0 counter), ref1 = matched counter
+// kind 2 write: ref0 = matched, ref1 = outputs; aux = bytes per output
+// kind 3 sort pass / kind 4 hist / kind 5 dedup: ref0 = rows counter, aux = cap or arity
+void Engine::collect_events() {
+  if (!trace_) return;
+  for (auto& pe : pending_) {
+    float ms = 0;
+    hip(hipEventElapsedTime(&ms, pe.a, pe.b), "event elapsed");
+    KClass& k = kprof_[pe.cls];
+    k.launches += 1;
+    k.ms += ms;
+    auto C = [&](int i) -> u64 { return i >= 0 ? ctr_host_[i] : 0; };
+    double bytes = pe.bytes;
+    u64 items = 0;
+    switch (pe.kind) {
+      case 1: {   // probe: key read + slot read per row, 16 B written per matched row
+        const u64 rows = pe.ref0 >= 0 ? C(pe.ref0) : pe.aux;
+        bytes = double(rows) * (4 + 16) + double(C(pe.ref1)) * 16;
+        items = rows;
+        break;
+      }
+      case 2: {   // write: perm + gathered build columns per output, run record per matched row
+        const u64 m = C(pe.ref0), t = C(pe.ref1);
+        bytes = double(t) * double(pe.aux) + double(m) * 16;
+        items = t;
+        break;
+      }
+      case 3: {   // radix pass: read + write 8 B per key
+        const u64 n = std::min<u64>(C(pe.ref0), pe.aux);
+        bytes = double(n) * 16;
+        items = n;
+        break;
+      }
+      case 4: {   // histogram: read 8 B per key
+        const u64 n = std::min<u64>(C(pe.ref0), pe.aux);
+        bytes = double(n) * 8;
+        items = n;
+        break;
+      }
+      case 5: {   // difference + append: key read, set probe, column writes of survivors
+        const u64 n = C(pe.ref0), d = C(pe.ref1);
+        bytes = double(n) * 16 + double(d) * 4 * double(pe.aux);
+        items = n;
+        break;
+      }
+      default:
+        break;
+    }
+    k.bytes += bytes;
+    k.items += items;
+    ev_pool_.push_back(pe.a);
+    ev_pool_.push_back(pe.b);
+  }
+  pending_.clear();
+}
+
+// ------------------------------------------------------------------ execution
+void Engine::read_counters() {
+  hip(hipMemcpyAsync(ctr_host_, ctr_dev_.p, size_t(n_ctr_) * 8, hipMemcpyDeviceToHost, stream_), "counter readback");
+  hip(hipMemcpyAsync(flags_host_, flags_dev_.p, 16, hipMemcpyDeviceToHost, stream_), "flag readback");
+  sync();
+  collect_events();
+  if (flags_host_[1]) {
+    terminal = true;
+    throw Error(FV_EINVAL, "internal: join scratch too small");
+  }
+}
+
+void Engine::exec_plan(Plan& p) {
+  u32* flags = flags_dev_.as<u32>();
+  u32* ticket = ticket_dev_.as<u32>();
+  const bool initial = p.delta_pos < 0;
+  for (size_t k = 0; k < p.steps.size(); ++k) {
+    Step& s = p.steps[k];
+    const u32* pcol[kMaxCols] = {};
+    RowRange src{};
+    u64 probe_bound;
+    int probe_ctr = -1;
+    if (k == 0) {
+      const Relation& S = rels_[p.src_rel];
+      for (u32 c = 0; c < S.arity; ++c) pcol[c] = S.col[c].as<u32>();
+      const u32 ri = u32(&S - &rels_[0]);
+      src.begin_ctr = initial ? nullptr : ctr(c_dbeg0_ + int(ri));
+      src.end_ctr = ctr(c_full0_ + int(ri));
+      src.cap = S.cap ? S.cap : S.n_full;
+      probe_bound = initial ? S.n_full : S.n_delta;
+    } else {
+      const Inter& I = inters_[p.steps[k - 1].out_buf];
+      for (u32 c = 0; c < I.ncols; ++c) pcol[c] = I.col[c].as<u32>();
+      src.end_ctr = ctr(I.ctr);
+      src.cap = I.cap;
+      probe_bound = I.cap;
+      probe_ctr = I.ctr;
+    }
+    OutSpec o{};
+    o.ncols = u32(s.out.size());
+    for (u32 c = 0; c < o.ncols; ++c) o.src[c] = s.out[c];
+    if (s.out_buf >= 0) {
+      Inter& I = inters_[s.out_buf];
+      for (u32 c = 0; c < I.ncols; ++c) o.cols[c] = I.col[c].as<u32>();
+      o.count = ctr(I.ctr);
+      o.cap = I.cap;
+    } else {
+      Relation& H = rels_[s.head_rel];
+      o.packed = 1;
+      for (u32 c = 0; c < H.arity; ++c) o.shift[c] = H.shift[c];
+      o.keys = H.newk.as<u64>();
+      o.count = ctr(c_new0_ + int(s.head_rel));
+      o.cap = H.new_cap;
+    }
+    if (s.select_only) {
+      SelectParams sp{};
+      for (int c = 0; c < kMaxCols; ++c) sp.pcol[c] = pcol[c];
+      sp.src = src;
+      sp.n_filter = u32(s.pf.size());
+      for (u32 f = 0; f < sp.n_filter; ++f) sp.filt[f] = s.pf[f];
+      sp.out = o;
+      sp.join_out_stat = ctr(c_joinout_);
+      sp.abort = nullptr;
+      sp.overflow = flags;
+      const int kc = kclass("select");
+      ev_begin(kc);
+      launched(launch_select(sp, std::max<u64>(probe_bound, 1), stream_), "select launch");
+      ev_end(kc, 0, 0);
+      continue;
+    }
+    const Relation& B = rels_[s.brel];
+    ProbeParams pp{};
+    for (int c = 0; c < kMaxCols; ++c) pp.pcol[c] = pcol[c];
+    pp.src = src;
+    pp.n_pf = u32(s.pf.size());
+    for (u32 f = 0; f < pp.n_pf; ++f) pp.pf[f] = s.pf[f];
+    pp.nkey = s.nkey;
+    pp.key[0] = s.key[0];
+    pp.key[1] = s.key[1];
+    const Index* ix = s.index != kNoIndex ? &indices_[s.index] : nullptr;
+    if (ix) {
+      pp.table = ix->table.as<Slot>();
+      pp.mask = ix->cap - 1;
+    } else {
+      pp.build_rows_ctr = ctr(c_full0_ + int(s.brel));
+      pp.build_cap = B.cap ? B.cap : B.n_full;
+    }
+    pp.m_row = m_row_.as<u32>();
+    pp.m_start = m_start_.as<u32>();
+    pp.m_off = m_off_.as<u64>();
+    pp.m_cap = m_cap_;
+    pp.out_m = ctr(s.c_m);
+    pp.out_t = ctr(s.c_t);
+    pp.st_m = st_a_.as<u64>();
+    pp.st_t = st_b_.as<u64>();
+    pp.ticket = ticket;
+    pp.epoch = next_epoch();
+    pp.abort = nullptr;
+    pp.fatal = flags + 1;
+    const int kp = kclass("join_probe");
+    ev_begin(kp);
+    launched(launch_probe(pp, std::max<u64>(probe_bound, 1), 0, stream_), "probe launch");
+    ev_end(kp, 0, 1, probe_ctr, s.c_m, probe_bound);
+
+    WriteParams wp{};
+    for (int c = 0; c < kMaxCols; ++c) wp.pcol[c] = pcol[c];
+    for (u32 c = 0; c < B.arity; ++c) wp.bcol[c] = B.col[c].as<u32>();
+    wp.perm = ix ? ix->perm.as<u32>() : nullptr;
+    wp.m_row = m_row_.as<u32>();
+    wp.m_start = m_start_.as<u32>();
+    wp.m_off = m_off_.as<u64>();
+    wp.m_cap = m_cap_;
+    wp.in_m = ctr(s.c_m);
+    wp.in_t = ctr(s.c_t);
+    wp.n_filter = u32(s.wf.size());
+    for (u32 f = 0; f < wp.n_filter; ++f) wp.filt[f] = s.wf[f];
+    wp.out = o;
+    wp.join_out_stat = ctr(c_joinout_);
+    wp.abort = flags + 1;   // the probe ran out of scratch: write nothing
+    wp.overflow = flags;
+    u32 nbuild = 0;
+    for (auto& sc : s.out) nbuild += sc.kind == kSrcBuild ? 1 : 0;
+    for (auto& f : s.wf) nbuild += (f.a.kind == kSrcBuild) + (f.b.kind == kSrcBuild);
+    const u64 out_bytes = o.packed ? 8 : 4ull * o.ncols;
+    const int kw = kclass("join_write");
+    ev_begin(kw);
+    launched(launch_write(wp, std::max<u64>(o.cap, 1), stream_), "write launch");
+    ev_end(kw, 0, 2, s.c_m, s.c_t, (ix ? 4 : 0) + 4ull * nbuild + out_bytes);
+  }
+}
+
+// sort the relation's new keys, take the difference against full, append
+void Engine::finish_relation(Relation& R) {
+  const int ri = int(&R - &rels_[0]);
+  u32* flags = flags_dev_.as<u32>();
+  SortParams sp{};
+  sp.a = R.newk.as<u64>();
+  sp.b = R.newk2.as<u64>();
+  sp.n_ctr = ctr(c_new0_ + ri);
+  sp.cap = R.new_cap;
+  sp.bits = R.bits;
+  sp.hist = hist_dev_.as<u32>();
+  sp.status = st_sort_.as<u64>();
+  sp.ticket = ticket_dev_.as<u32>();
+  sp.abort = flags;
+  const u32 passes = sort_passes(R.bits);
+  const int kh = kclass("sort_hist");
+  ev_begin(kh);
+  launched(launch_rs_hist(sp, stream_), "hist launch");
+  ev_end(kh, 0, 4, c_new0_ + ri, -1, R.new_cap);
+  u64* src = sp.a;
+  u64* dst = sp.b;
+  const int kpass = kclass("sort_pass");
+  for (u32 pass = 0; pass < passes; ++pass) {
+    ev_begin(kpass);
+    launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_), "sort pass launch");
+    ev_end(kpass, 0, 3, c_new0_ + ri, -1, R.new_cap);
+    std::swap(src, dst);
+  }
+  DedupParams dp{};
+  dp.keys = src;
+  dp.src.end_ctr = ctr(c_new0_ + ri);
+  dp.src.cap = R.new_cap;
+  dp.set = R.idb ? R.set.as<u64>() : nullptr;
+  dp.set_mask = R.set_cap ? R.set_cap - 1 : 0;
+  for (u32 c = 0; c < R.arity; ++c) {
+    dp.cols[c] = R.col[c].as<u32>();
+    dp.shift[c] = R.shift[c];
+    dp.width[c] = R.width[c];
+  }
+  dp.full_n = ctr(c_full0_ + ri);
+  dp.arity = R.arity;
+  dp.out_delta = ctr(c_delta0_ + ri);
+  dp.status = st_a_.as<u64>();
+  dp.ticket = ticket_dev_.as<u32>();
+  dp.epoch = next_epoch();
+  dp.abort = flags;
+  const int kd = kclass("dedup_append");
+  ev_begin(kd);
+  launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_), "dedup launch");
+  ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
+  CommitParams cp{};
+  cp.full_n = ctr(c_full0_ + ri);
+  cp.d_begin = ctr(c_dbeg0_ + ri);
+  cp.delta = ctr(c_delta0_ + ri);
+  cp.new_count = nullptr;
+  cp.derived = ctr(c_derived_);
+  cp.abort = flags;
+  launched(launch_commit(cp, stream_), "commit launch");
+}
+
+void Engine::build_index(Index& ix) {
+  const Relation& R = rels_[ix.rel];
+  IndexParams p{};
+  for (u32 c = 0; c < R.arity; ++c) p.col[c] = R.col[c].as<u32>();
+  p.src.end_ctr = ctr(c_full0_ + int(ix.rel));
+  p.src.cap = R.cap;
+  p.nkey = ix.nkey;
+  p.keycol[0] = ix.keycol[0];
+  p.keycol[1] = ix.keycol[1];
+  p.table = ix.table.as<Slot>();
+  p.cap = ix.cap;
+  p.perm = ix.perm.as<u32>();
+  p.status = st_a_.as<u64>();
+  p.ticket = ticket_dev_.as<u32>();
+  p.epoch = next_epoch();
+  p.abort = flags_dev_.as<u32>();
+  const int kc = kclass("index_build");
+  ev_begin(kc);
+  launched(launch_index_build(p, std::max<u64>(R.cap, 1), stream_), "index launch");
+  ev_end(kc, 0, 0);
+  ix.dirty = false;
+}
+
+void Engine::build_indices(bool idb_only) {
+  for (auto& ix : indices_)
+    if (!idb_only || rels_[ix.rel].used_as_head) build_index(ix);
+}
+
+// Load the staged facts of every relation: pack, radix-sort, drop repeats,
+// and for relations that are also derived, seed the tuple set.
+void Engine::ingest() {
+  u64 total = 0;
+  for (auto& R : rels_) total += R.staged;
+  const u64 base_cap = pow2_at_least(std::max<u64>(1 << 16, 2 * total));
+  for (auto& R : rels_) {
+    R.new_cap = std::max<u64>(R.staged, R.used_as_head ? base_cap : 1);
+    if (!R.used_as_head) {   // read-only relation: exactly its facts
+      R.cap = std::max<u64>(R.staged, 1);
+      for (u32 c = 0; c < R.arity; ++c) R.col[c] = alloc(R.cap * 4);
+      R.newk = alloc(R.new_cap * 8);
+      R.newk2 = alloc(R.new_cap * 8);
+    }
+  }
+  for (auto& I : inters_) I.cap = base_cap;
+  ensure_capacity();
+  hip(hipMemsetAsync(ctr_dev_.p, 0, size_t(n_ctr_) * 8, stream_), "counter clear");
+  hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
+  for (auto& R : rels_) {
+    if (!R.staged) continue;
+    const int ri = int(&R - &rels_[0]);
+    const u32* cols[3] = {R.stage[0].as<u32>(), R.stage[1].as<u32>(), R.stage[2].as<u32>()};
+    launched(launch_pack(cols, R.arity, R.shift, R.staged, R.newk.as<u64>(), stream_), "pack launch");
+    launched(launch_fill_u64(ctr(c_new0_ + ri), 1, R.staged, stream_), "fill");
+    finish_relation(R);
+  }
+  read_counters();
+  for (auto& R : rels_) {
+    const int ri = int(&R - &rels_[0]);
+    R.n_full = ctr_host_[c_full0_ + ri];
+    R.d_begin = ctr_host_[c_dbeg0_ + ri];
+    R.seeds = R.n_full;
+    R.n_delta = 0;
+    for (int c = 0; c < 3; ++c) release(R.stage[c]);
+    R.staged = 0;
+    if (!R.used_as_head) { release(R.newk); release(R.newk2); R.new_cap = 0; }
+    else R.new_cap = base_cap;
+  }
+  // after ingest the delta of every relation is empty; round 0 reads full
+  hip(hipMemsetAsync(ctr_dev_.p, 0, 8, stream_), "derived clear");
+}
+
+void Engine::run_round(bool initial) {
+  for (;;) {
+    ensure_capacity();
+    launched(launch_fill_u64(ctr(c_reset_begin_), u64(n_ctr_ - c_reset_begin_), 0, stream_), "counter reset");
+    launched(launch_fill_u32(flags_dev_.as<u32>(), 1, 0u, stream_), "flag reset");
+    // an index whose storage grew holds nothing yet: rebuild it over the
+    // current full relation before any join reads it
+    for (auto& ix : indices_)
+      if (ix.dirty) build_index(ix);
+    if (initial) {
+      for (auto& p : init_plans_) exec_plan(p);
+    } else {
+      for (auto& p : delta_plans_)
+        if (rels_[p.src_rel].n_delta > 0) exec_plan(p);
+    }
+    for (auto& R : rels_)
+      if (R.used_as_head) finish_relation(R);
+    build_indices(true);
+    read_counters();
+    if (!flags_host_[0]) break;
+    // a buffer overflowed: grow whatever was short and run the round again
+    ++redo_;
+    for (auto& R : rels_) {
+      if (!R.used_as_head) continue;
+      const u64 need = ctr_host_[c_new0_ + int(&R - &rels_[0])];
+      if (need > R.new_cap) R.new_cap = pow2_at_least(std::max<u64>(need + need / 4, R.new_cap * 2));
+    }
+    for (auto& I : inters_) {
+      const u64 need = ctr_host_[I.ctr];
+      if (need > I.cap) I.cap = pow2_at_least(std::max<u64>(need + need / 4, I.cap * 2));
+    }
+  }
+  u64 total = 0;
+  for (auto& R : rels_) {
+    const int ri = int(&R - &rels_[0]);
+    if (!R.used_as_head) { R.n_delta = 0; continue; }
+    R.n_full = ctr_host_[c_full0_ + ri];
+    R.d_begin = ctr_host_[c_dbeg0_ + ri];
+    R.n_delta = R.n_full - R.d_begin;
+    total += R.n_delta;
+  }
+  join_out_ = ctr_host_[c_joinout_];
+  deltas_.push_back(total);
+}
+
+void Engine::run(fv_stats* stats) {
+  if (ran_) throw Error(FV_ESTATE, "the fixpoint already ran on this context");
+  if (terminal) throw Error(FV_ESTATE, "context is in an error state");
+  ran_ = true;
+  const auto t0 = std::chrono::steady_clock::now();
+  domain_analysis();
+  plan_all();
+  ctr_dev_ = alloc(size_t(n_ctr_) * 8);
+  flags_dev_ = alloc(16);
+  ticket_dev_ = alloc(16);
+  hist_dev_ = alloc(8 * 256 * 4);
+  hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
+  hip(hipHostMalloc(reinterpret_cast<void**>(&ctr_host_), size_t(n_ctr_) * 8, hipHostMallocDefault), "pinned alloc");
+  hip(hipHostMalloc(reinterpret_cast<void**>(&flags_host_), 16, hipHostMallocDefault), "pinned alloc");
+  ingest();
+  ensure_capacity();
+  build_indices(false);
+  deltas_.clear();
+  run_round(true);
+  while (deltas_.back() != 0) run_round(false);
+  const auto t1 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->iterations = u32(deltas_.size());
+    stats->redo_rounds = redo_;
+    u64 derived = 0;
+    for (auto& R : rels_)
+      if (R.used_as_head) derived += R.n_full - R.seeds;
+    stats->derived_tuples = derived;
+    stats->join_output_tuples = join_out_;
+    stats->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+}
+
+// ------------------------------------------------------------------ export
+void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, bool on_device) {
+  if (rel >= rels_.size()) throw Error(FV_EINVAL, "bad relation handle");
+  if (!ran_) throw Error(FV_ESTATE, "export is allowed after the fixpoint ran");
+  Relation& R = rels_[rel];
+  const u64 n = R.n_full;
+  if (n_out) *n_out = n;
+  if (!cols) return;
+  if (capacity < n) throw Error(FV_ETRUNC, "export capacity too small");
+  if (n == 0) return;
+  for (u32 c = 0; c < R.arity; ++c)
+    if (!cols[c]) throw Error(FV_EINVAL, "null output column");
+  // shifts already give lexicographic (col0, col1, col2) order: pack, sort, unpack
+  Buf a = alloc(n * 8), b = alloc(n * 8);
+  Buf tmp[3];
+  try {
+    const u32* in[3] = {R.col[0].as<u32>(), R.col[1].as<u32>(), R.col[2].as<u32>()};
+    launched(launch_pack(in, R.arity, R.shift, n, a.as<u64>(), stream_), "pack launch");
+    const u64 stiles = (n + kSortTile - 1) / kSortTile + 1;
+    if (st_sort_tiles_ < stiles) {
+      release(st_sort_);
+      st_sort_ = alloc(stiles * 256 * 8);
+      launched(launch_fill_u64(st_sort_.as<u64>(), stiles * 256, 0, stream_), "status clear");
+      st_sort_tiles_ = stiles;
+    }
+    SortParams sp{};
+    sp.a = a.as<u64>();
+    sp.b = b.as<u64>();
+    sp.n_const = n;
+    sp.cap = n;
+    sp.bits = R.bits;
+    sp.hist = hist_dev_.as<u32>();
+    sp.status = st_sort_.as<u64>();
+    sp.ticket = ticket_dev_.as<u32>();
+    sp.abort = nullptr;
+    launched(launch_rs_hist(sp, stream_), "hist launch");
+    u64* s = sp.a;
+    u64* d = sp.b;
+    for (u32 pass = 0; pass < sort_passes(R.bits); ++pass) {
+      launched(launch_rs_pass(sp, pass, s, d, next_epoch(), stream_), "sort pass launch");
+      std::swap(s, d);
+    }
+    u32* outc[3] = {nullptr, nullptr, nullptr};
+    for (u32 c = 0; c < R.arity; ++c) {
+      if (on_device) outc[c] = cols[c];
+      else { tmp[c] = alloc(n * 4); outc[c] = tmp[c].as<u32>(); }
+    }
+    launched(launch_unpack(s, n, R.arity, R.shift, R.width, outc, stream_), "unpack launch");
+    if (!on_device)
+      for (u32 c = 0; c < R.arity; ++c)
+        hip(hipMemcpyAsync(cols[c], outc[c], n * 4, hipMemcpyDeviceToHost, stream_), "export copy");
+    sync();
+  } catch (...) {
+    release(a); release(b);
+    for (auto& t : tmp) release(t);
+    throw;
+  }
+  release(a); release(b);
+  for (auto& t : tmp) release(t);
+}
+
+}  // namespace fv

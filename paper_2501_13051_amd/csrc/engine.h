@@ -1,0 +1,211 @@
+// Host runtime of the engine: device memory, relations, rule plans and the
+// semi-naive round loop.  The C ABI in api.cpp is a thin shell over this.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <chrono>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fv.h"
+#include "fv_types.h"
+
+namespace fv {
+
+struct Error : std::runtime_error {
+  fv_status code;
+  Error(fv_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+constexpr u32 kMaxVars = 16;
+constexpr u32 kMaxBody = 8;
+constexpr u32 kMaxNeq = 8;
+constexpr u32 kNoIndex = ~0u;
+
+struct Term { u32 value; bool is_const; };
+struct AtomR { u32 rel; std::vector<Term> t; };
+struct RuleR {
+  AtomR head;
+  std::vector<AtomR> body;
+  std::vector<std::pair<u32, u32>> neq;
+};
+
+struct Relation {
+  std::string name;
+  u32 arity = 0;
+  bool idb = false;          // appears in a rule head
+  // staged loads (before the fixpoint), device columns
+  Buf stage[3];
+  u64 staged = 0, stage_cap = 0;
+  u32 maxv[3] = {0, 0, 0};   // per-column value bound (domain analysis)
+  bool has_rows = false;
+  // full relation: contiguous columns; delta = rows [d_begin, n_full)
+  Buf col[3];
+  u64 cap = 0;
+  // new tuples of a round as packed keys, plus the sort's second buffer
+  Buf newk, newk2;
+  u64 new_cap = 0;
+  // tuple set of full, for the difference operator
+  Buf set;
+  u64 set_cap = 0;
+  u32 width[3] = {0, 0, 0}, shift[3] = {0, 0, 0}, bits = 0;
+  u32 exp_shift[3] = {0, 0, 0};   // lexicographic packing for export
+  // host mirrors of device counters (valid after each sync)
+  u64 n_full = 0, d_begin = 0, n_delta = 0, seeds = 0;
+  bool used_as_head = false;
+};
+
+struct Index {
+  u32 rel;
+  u32 nkey;
+  u32 keycol[2];
+  Buf table, perm;
+  u64 cap = 0, perm_cap = 0;
+  bool dirty = true;   // storage (re)allocated since the last build
+};
+
+// One join (or, with index == kNoIndex and brel == kNone, one selection):
+// probe source -> build relation -> output.
+struct Step {
+  bool select_only = false;
+  u32 brel = 0;
+  u32 index = kNoIndex;       // kNoIndex with !select_only: cross product
+  u32 nkey = 0;
+  Src key[2];
+  std::vector<Filter> pf;     // probe-row filters (first step only)
+  std::vector<Filter> wf;     // filters after the build row is known
+  std::vector<Src> out;       // output columns (or head columns)
+  int out_buf = -1;           // intermediate id, or -1: head relation's new keys
+  u32 head_rel = 0;
+  int c_m = -1, c_t = -1;     // device counters for this join's sizes
+};
+
+struct Plan {
+  u32 rule;
+  int delta_pos;              // body position read from delta; -1 = all full
+  u32 src_rel;
+  bool src_delta;
+  std::vector<Step> steps;
+};
+
+struct Inter {
+  u32 ncols;
+  Buf col[kMaxCols];
+  u64 cap = 0;
+  int ctr = -1;
+};
+
+struct KClass {
+  std::string name;
+  u64 launches = 0;
+  double ms = 0, bytes = 0;
+  u64 items = 0;
+};
+
+struct PendingEvent {
+  int cls;
+  hipEvent_t a, b;
+  double bytes;   // < 0: computed later from counters (see bytes_fn)
+  int kind;       // which counter-derived formula
+  int ref0, ref1; // counter references
+  u64 aux;
+};
+
+class Engine {
+ public:
+  explicit Engine(const fv_options* opt);
+  ~Engine();
+
+  u32 relation_create(const char* name, u32 arity);
+  u32 relation_find(const char* name) const;
+  void load_columns(u32 rel, const u32* const* cols, u64 n, bool on_device);
+  void add_rule(const fv_rule& r);
+  void run(fv_stats* stats);
+  u64 relation_size(u32 rel) const;
+  void export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, bool on_device);
+  const std::vector<u64>& delta_sizes() const { return deltas_; }
+  const std::vector<KClass>& profile() const { return kprof_; }
+
+  std::string last_error;
+  bool terminal = false;
+
+ private:
+  // memory
+  Buf alloc(size_t bytes);
+  void release(Buf& b);
+  void grow(Buf& b, size_t bytes, size_t keep_bytes);
+  void hip(hipError_t e, const char* what);
+  void launched(int rc, const char* what);
+  void sync();
+
+  // setup
+  void domain_analysis();
+  void plan_all();
+  Plan plan_rule(u32 rule, int delta_pos);
+  u32 get_index(u32 rel, u32 nkey, const u32* keycol);
+  void ingest();
+  void ensure_capacity();
+  void build_indices(bool idb_only);
+  void build_index(Index& ix);
+
+  // rounds
+  void run_round(bool initial);
+  void exec_plan(Plan& p);
+  void finish_relation(Relation& R);
+  void read_counters();
+  u32 next_epoch(u32 n = 1);
+
+  // profiling
+  int kclass(const char* name);
+  void ev_begin(int cls);
+  void ev_end(int cls, double bytes, int kind = 0, int ref0 = -1, int ref1 = -1, u64 aux = 0);
+  void collect_events();
+
+  u64* ctr(int i) { return ctr_dev_.as<u64>() + i; }
+
+  fv_options opt_{};
+  hipStream_t stream_ = nullptr;
+  bool ran_ = false;
+  std::vector<Relation> rels_;
+  std::map<std::string, u32> by_name_;
+  std::vector<RuleR> rules_;
+  std::vector<Index> indices_;
+  std::vector<Plan> init_plans_, delta_plans_;
+  std::vector<Inter> inters_;
+
+  // device control block
+  Buf ctr_dev_, flags_dev_, ticket_dev_, hist_dev_, maxv_dev_;
+  u64* ctr_host_ = nullptr;   // pinned mirror
+  u32* flags_host_ = nullptr;
+  int n_ctr_ = 0;
+  int c_derived_ = 0, c_joinout_ = 1;
+  int c_full0_ = 0, c_dbeg0_ = 0, c_delta0_ = 0, c_new0_ = 0, c_reset_begin_ = 0;
+  // scratch
+  Buf m_row_, m_start_, m_off_;
+  u64 m_cap_ = 0;
+  Buf st_a_, st_b_, st_sort_;
+  u64 st_cap_ = 0, st_sort_tiles_ = 0;
+  u32 epoch_ = 1;
+
+  std::vector<u64> deltas_;
+  u32 redo_ = 0;
+  u64 join_out_ = 0;
+
+  bool trace_ = false;
+  bool touched_device_ = false;
+  std::vector<KClass> kprof_;
+  std::vector<PendingEvent> pending_;
+  std::vector<hipEvent_t> ev_pool_;
+  hipEvent_t ev_open_ = nullptr;
+};
+
+}  // namespace fv

@@ -1,0 +1,202 @@
+// Device-side building blocks shared by the engine's HIP kernels (gfx950,
+// wave64): hashing, open-addressing probes, wave/block scans and the
+// decoupled look-back used for order-preserving stream compaction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fv_types.h"
+
+namespace fv {
+
+constexpr int kWave = 64;
+
+// --------------------------------------------------------------- hashing
+// 64-bit finalizer of MurmurHash3 (Austin Appleby, public domain): a bijective
+// avalanche mix, so distinct keys never collide before the table mask.
+__device__ __forceinline__ u64 mix64(u64 k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ u64 atomic_load_u64(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_u64(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u64 atomic_cas_u64(u64* p, u64 expect, u64 desired) {
+  return atomicCAS(reinterpret_cast<unsigned long long*>(p), expect, desired);
+}
+
+// Index lookup: linear probing over {key, start, count} slots (Section 3,
+// "unique hashmap": one slot per distinct key, value = run in the sorted ids).
+__device__ __forceinline__ bool index_find(const Slot* __restrict__ tab, u64 mask, u64 key,
+                                           u32& start, u32& count) {
+  u64 h = mix64(key) & mask;
+  for (;;) {
+    const Slot s = tab[h];
+    if (s.key == key) { start = s.start; count = s.count; return true; }
+    if (s.key == kEmptyKey) return false;
+    h = (h + 1) & mask;
+  }
+}
+
+// Find-or-insert a key into an index table; returns its slot.
+__device__ __forceinline__ u64 index_insert(Slot* tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  for (;;) {
+    u64 cur = atomic_load_u64(&tab[h].key);
+    if (cur == key) return h;
+    if (cur == kEmptyKey) {
+      u64 prev = atomic_cas_u64(&tab[h].key, kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) return h;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+// Tuple set insert-if-absent over 8-byte slots; true if the key was new.
+__device__ __forceinline__ bool set_insert(u64* tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  for (;;) {
+    u64 cur = atomic_load_u64(&tab[h]);
+    if (cur == key) return false;
+    if (cur == kEmptyKey) {
+      u64 prev = atomic_cas_u64(&tab[h], kEmptyKey, key);
+      if (prev == kEmptyKey) return true;
+      if (prev == key) return false;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+__device__ __forceinline__ bool set_contains(const u64* __restrict__ tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  for (;;) {
+    u64 cur = tab[h];
+    if (cur == key) return true;
+    if (cur == kEmptyKey) return false;
+    h = (h + 1) & mask;
+  }
+}
+
+// --------------------------------------------------------------- wave / block scans
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_sum(T v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Block-wide exclusive scan; `lds` must hold kBlock / kWave + 1 entries.
+// Returns the exclusive prefix of v; *total receives the block sum.
+template <int kBlock, typename T>
+__device__ __forceinline__ T block_exclusive_sum(T v, T* lds, T* total) {
+  constexpr int kWaves = kBlock / kWave;
+  const int lane = lane_id();
+  const int w = threadIdx.x / kWave;
+  T inc = wave_inclusive_sum(v);
+  if (lane == kWave - 1) lds[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+    for (int i = 0; i < kWaves; ++i) { T c = lds[i]; lds[i] = run; run += c; }
+    lds[kWaves] = run;
+  }
+  __syncthreads();
+  T r = lds[w] + inc - v;
+  *total = lds[kWaves];
+  __syncthreads();
+  return r;
+}
+
+// --------------------------------------------------------------- decoupled look-back
+// A status word per tile: [63:42] launch epoch (22 bits) | [41:40] flag |
+// [39:0] value.  Words from another launch (different epoch) read as "not
+// ready", so status arrays never need clearing between launches.
+constexpr u64 kFlagAgg = 1, kFlagPrefix = 2;
+constexpr u64 kValueMask = (1ull << 40) - 1;
+
+__device__ __forceinline__ u64 lb_word(u32 epoch, u64 flag, u64 value) {
+  return (u64(epoch & kEpochMask) << 42) | (flag << 40) | (value & kValueMask);
+}
+__device__ __forceinline__ u64 lb_flag(u64 w, u32 epoch) {
+  return (u32(w >> 42) == (epoch & kEpochMask)) ? ((w >> 40) & 3) : 0;
+}
+
+// Wave-cooperative look-back over status[0 .. tile-1]: each lane inspects one
+// predecessor, the nearest inclusive prefix stops the walk.  All 64 lanes of
+// the calling wave must participate.  Predecessor tiles were handed out
+// earlier by the ticket counter, so their blocks are resident and publish an
+// aggregate without waiting on anyone: the spin always ends.
+__device__ __forceinline__ u64 lookback_exclusive(const u64* status, u32 tile, u32 epoch) {
+  u64 excl = 0;
+  long long base = (long long)tile - 1;
+  const int lane = lane_id();
+  while (base >= 0) {
+    long long idx = base - lane;
+    u64 w = 0, f = kFlagPrefix;
+    if (idx >= 0) {
+      for (;;) {
+        w = atomic_load_u64(status + idx);
+        f = lb_flag(w, epoch);
+        if (f != 0) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const u64 pm = __ballot(f == kFlagPrefix);
+    const int stop = pm ? __ffsll((long long)pm) - 1 : kWave;   // nearest prefix lane
+    u64 v = (lane <= stop && idx >= 0) ? (w & kValueMask) : 0;
+    excl += wave_sum(v);
+    if (pm) break;
+    base -= kWave;
+  }
+  return excl;
+}
+
+// Ticket-ordered tile loop: blocks take tiles in increasing order so that a
+// tile's predecessors are always owned by running blocks.  The block that
+// makes the very last increment (each block makes exactly one failing one)
+// resets the counter for the next launch.
+__device__ __forceinline__ u32 take_ticket(u32* ticket, u32 ntiles, u32* lds_slot) {
+  if (threadIdx.x == 0) {
+    u32 t = atomicAdd(ticket, 1u);
+    if (t >= ntiles && t == ntiles + gridDim.x - 1) atomicExch(ticket, 0u);
+    *lds_slot = t;
+  }
+  __syncthreads();
+  u32 t = *lds_slot;
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ u64 min_u64(u64 a, u64 b) { return a < b ? a : b; }
+
+// Number of rows of a source: min(counter, capacity) minus its begin offset.
+__device__ __forceinline__ void source_range(const RowRange& r, u64& begin, u64& n) {
+  u64 b = r.begin_ctr ? *r.begin_ctr : r.begin;
+  u64 e = r.end_ctr ? min_u64(*r.end_ctr, r.cap) : r.end;
+  begin = b;
+  n = e > b ? e - b : 0;
+}
+
+}  // namespace fv

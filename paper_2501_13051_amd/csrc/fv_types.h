@@ -1,0 +1,203 @@
+// Plain types shared by the host runtime and the HIP kernels: kernel
+// parameter blocks, hash slots and launch-wrapper declarations.  No HIP
+// device code here, so host-only translation units can include it.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fv {
+
+using u32 = uint32_t;
+using u64 = uint64_t;
+
+constexpr u64 kEmptyKey = ~0ull;         // empty hash slot (0xFFFFFFFF is a reserved value)
+constexpr u32 kEpochMask = (1u << 22) - 1;
+constexpr int kMaxCols = 6;              // columns of an intermediate result
+constexpr int kMaxFilters = 8;
+
+// One slot of a join index: a distinct key and its run [start, start+count)
+// in the index's row permutation (the RLE "unique hashmap" of Section 3).
+struct alignas(16) Slot {
+  u64 key;
+  u32 start;
+  u32 count;
+};
+
+// Rows [begin, end) of a set of columns.  begin/end come from device
+// counters when the pointers are set (sizes only known on the device), and
+// end is clamped to cap so an overflowed producer is never over-read.
+struct RowRange {
+  const u64* begin_ctr;
+  const u64* end_ctr;
+  u64 begin;
+  u64 end;
+  u64 cap;
+};
+
+enum SrcKind : u32 { kSrcProbe = 0, kSrcBuild = 1, kSrcConst = 2 };
+struct Src {
+  u32 kind;
+  u32 v;   // column index, or the constant
+};
+
+enum FilterOp : u32 { kEq = 0, kNe = 1 };
+struct Filter {
+  Src a, b;
+  u32 op;
+};
+
+// Output of a join/select: either intermediate columns or packed tuple keys
+// appended to a relation's "new" buffer.
+struct OutSpec {
+  u32 ncols;
+  Src src[kMaxCols];
+  u32 packed;            // 1: write key = sum(v_c << shift[c]) into keys
+  u32 shift[kMaxCols];
+  u32* cols[kMaxCols];
+  u64* keys;
+  u64* count;            // device counter: tuples written (may exceed cap)
+  u64 cap;
+};
+
+struct ProbeParams {
+  const u32* pcol[kMaxCols];
+  RowRange src;
+  u32 n_pf;              // filters on the probe row (constants, repeated variables)
+  Filter pf[kMaxFilters];
+  u32 nkey;              // 0, 1 or 2 key terms
+  Src key[2];
+  const Slot* table;
+  u64 mask;
+  const u64* build_rows_ctr;   // nkey == 0: every probe row matches all build rows
+  u64 build_rows;
+  u64 build_cap;
+  u32* m_row;
+  u32* m_start;
+  u64* m_off;
+  u64 m_cap;
+  u64* out_m;            // matched probe rows
+  u64* out_t;            // join output size before filters
+  u64* st_m;             // look-back status arrays
+  u64* st_t;
+  u32* ticket;
+  u32 epoch;
+  const u32* abort;
+  u32* fatal;
+};
+
+struct WriteParams {
+  const u32* pcol[kMaxCols];
+  const u32* bcol[3];
+  const u32* perm;       // null: identity (cross product)
+  const u32* m_row;
+  const u32* m_start;
+  const u64* m_off;
+  u64 m_cap;
+  const u64* in_m;
+  const u64* in_t;
+  u32 n_filter;
+  Filter filt[kMaxFilters];
+  OutSpec out;
+  u64* join_out_stat;    // running total of tuples written by joins
+  const u32* abort;
+  u32* overflow;
+};
+
+struct SelectParams {
+  const u32* pcol[kMaxCols];
+  RowRange src;
+  u32 n_filter;
+  Filter filt[kMaxFilters];
+  OutSpec out;
+  u64* join_out_stat;
+  const u32* abort;
+  u32* overflow;
+};
+
+struct DedupParams {
+  const u64* keys;       // sorted packed tuples
+  RowRange src;          // [0, n)
+  u64* set;              // tuple set of full (null: only drop adjacent repeats)
+  u64 set_mask;
+  u32* cols[3];          // full columns to append to
+  const u64* full_n;     // append position
+  u32 arity;
+  u32 shift[3];
+  u32 width[3];
+  u64* out_delta;        // survivors
+  u64* status;
+  u32* ticket;
+  u32 epoch;
+  const u32* abort;
+};
+
+struct CommitParams {
+  u64* full_n;
+  u64* d_begin;
+  const u64* delta;
+  u64* new_count;
+  u64* derived;          // running total of appended tuples
+  const u32* abort;
+};
+
+// ------------------------------------------------------------------ launchers
+// Each wrapper enqueues kernels on `stream` (a hipStream_t) and returns the
+// hipError_t of the launch as int.
+int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream);
+int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream);
+int launch_select(const SelectParams& p, u64 rows_hint, void* stream);
+int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream);
+int launch_commit(const CommitParams& p, void* stream);
+
+// LSD radix sort of n packed u64 keys (n from *n_ctr clamped to cap, or
+// n_const) on the low `bits` bits, 8 bits per pass: launch_rs_hist counts the
+// digits of all passes, then one launch_rs_pass per pass moves keys src->dst.
+struct SortParams {
+  u64* a;
+  u64* b;
+  const u64* n_ctr;
+  u64 n_const;
+  u64 cap;
+  u32 bits;
+  u32* hist;             // [passes][256] scratch, cleared by launch_rs_hist
+  u64* status;           // [tiles][256] look-back words
+  u32* ticket;
+  const u32* abort;
+};
+int launch_rs_hist(const SortParams& p, void* stream);
+int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch, void* stream);
+inline u32 sort_passes(u32 bits) { return (bits + 7) / 8; }
+constexpr u32 kSortTile = 2048;
+
+// Index build over rows [0, n) of a relation's columns: table of distinct
+// keys with runs into perm (the sorted-id array of Section 3, grouped by key).
+struct IndexParams {
+  const u32* col[3];
+  RowRange src;
+  u32 nkey;
+  u32 keycol[2];
+  Slot* table;
+  u64 cap;               // slots, power of two
+  u32* perm;
+  u64* status;
+  u32* ticket;
+  u32 epoch;
+  const u32* abort;
+};
+int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
+
+int launch_fill_u64(u64* p, u64 n, u64 value, void* stream);
+int launch_fill_u32(u32* p, u64 n, u32 value, void* stream);
+int launch_colmax(const u32* col, u64 n, u32* out_max, void* stream);
+// Pack columns into keys (rows [0,n)), shift per column.
+int launch_pack(const u32* const* cols, u32 arity, const u32* shift, u64 n, u64* keys, void* stream);
+int launch_unpack(const u64* keys, u64 n, u32 arity, const u32* shift, const u32* width,
+                  u32* const* cols, void* stream);
+// Re-insert rows [0, n) of full into a tuple set.
+int launch_set_insert_rows(const u32* const* cols, u32 arity, const u32* shift, u64 n,
+                           u64* set, u64 mask, void* stream);
+
+constexpr int kBlock = 256;
+
+}  // namespace fv

@@ -1,0 +1,207 @@
+// Join-index construction and column utilities.
+//
+// The join index of a relation on a key (one or two columns) is the hybrid
+// index of Section 3: an open-addressing table that holds each distinct key
+// once (run-length encoding of the key column, which keeps repeated values
+// from piling into long collision chains) with the value (start, count) into
+// a row-id array in which the rows of one key are contiguous.  It is built
+// without a sort: count rows per distinct key in the table, exclusive-scan the
+// counts over the table to get each run's start, then scatter row ids into
+// their runs.  Row order inside a run is unspecified, which joins do not
+// observe.
+#include "fv_device.h"
+
+namespace fv {
+
+constexpr u32 kScanTile = kBlock * 4;
+
+__device__ __forceinline__ u64 row_key(const IndexParams& p, u64 row) {
+  const u32 a = p.col[p.keycol[0]][row];
+  if (p.nkey == 2) return (u64(a) << 32) | u64(p.col[p.keycol[1]][row]);
+  return u64(a);
+}
+
+__global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort) {
+  if (abort && *abort) return;
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < cap; i += u64(gridDim.x) * blockDim.x)
+    tab[i] = Slot{kEmptyKey, 0u, 0u};
+}
+
+__global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
+  if (p.abort && *p.abort) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 mask = p.cap - 1;
+  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
+    const u64 h = index_insert(p.table, mask, row_key(p, begin + r));
+    atomicAdd(&p.table[h].count, 1u);
+  }
+}
+
+// Exclusive scan of slot counts over the table (look-back across tiles);
+// start <- prefix, count <- 0 so that it can serve as the fill cursor.
+__global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
+  __shared__ u32 s_ticket;
+  __shared__ u32 s_c[kBlock / kWave + 1];
+  __shared__ u64 s_excl;
+  if (p.abort && *p.abort) return;
+  const u32 ntiles = u32((p.cap + kScanTile - 1) / kScanTile);
+  for (;;) {
+    const u32 tile = take_ticket(p.ticket, ntiles, &s_ticket);
+    if (tile >= ntiles) break;
+    const u64 s0 = u64(tile) * kScanTile + u64(threadIdx.x) * 4;
+    u32 c[4];
+    u32 mine = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      c[k] = (s0 + k < p.cap) ? p.table[s0 + k].count : 0u;
+      mine += c[k];
+    }
+    u32 tot;
+    const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
+    if (tile == 0) {
+      if (threadIdx.x == 0) {
+        atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, tot));
+        s_excl = 0;
+      }
+    } else {
+      if (threadIdx.x == 0) atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagAgg, tot));
+      if (threadIdx.x < kWave) {
+        const u64 e = lookback_exclusive(p.status, tile, p.epoch);
+        if (threadIdx.x == 0) {
+          atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, e + tot));
+          s_excl = e;
+        }
+      }
+    }
+    __syncthreads();
+    u64 run = s_excl + ex;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (s0 + k < p.cap) {
+        p.table[s0 + k].start = u32(run);
+        p.table[s0 + k].count = 0u;
+      }
+      run += c[k];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
+  if (p.abort && *p.abort) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 mask = p.cap - 1;
+  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
+    const u64 key = row_key(p, begin + r);
+    u64 h = mix64(key) & mask;
+    while (p.table[h].key != key) h = (h + 1) & mask;
+    const u32 pos = p.table[h].start + atomicAdd(&p.table[h].count, 1u);
+    p.perm[pos] = u32(begin + r);
+  }
+}
+
+static int grid_rows(u64 n, int cap) {
+  const u64 b = (n + kBlock - 1) / kBlock;
+  return int(b == 0 ? 1 : (b > u64(cap) ? u64(cap) : b));
+}
+
+int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort);
+  hipLaunchKernelGGL(k_idx_count, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p);
+  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_idx_scan, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_fill, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p);
+  return int(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ column utilities
+__global__ void k_colmax(const u32* col, u64 n, u32* out) {
+  u32 m = 0;
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x)
+    m = col[i] > m ? col[i] : m;
+  // wave max, one atomic per wave
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const u32 o = __shfl_xor(m, d, kWave);
+    m = o > m ? o : m;
+  }
+  if (lane_id() == 0) atomicMax(out, m);
+}
+
+int launch_colmax(const u32* col, u64 n, u32* out, void* stream) {
+  hipLaunchKernelGGL(k_colmax, dim3(grid_rows(n, 2048)), dim3(kBlock), 0, (hipStream_t)stream, col, n, out);
+  return int(hipGetLastError());
+}
+
+struct PackArgs {
+  const u32* cols[3];
+  u32 arity;
+  u32 shift[3];
+  u32 width[3];
+};
+
+__global__ void k_pack(PackArgs a, u64 n, u64* keys) {
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x) {
+    u64 k = 0;
+    for (u32 c = 0; c < a.arity; ++c) k |= u64(a.cols[c][i]) << a.shift[c];
+    keys[i] = k;
+  }
+}
+
+__global__ void k_unpack(const u64* keys, u64 n, PackArgs a, u32* o0, u32* o1, u32* o2) {
+  u32* outs[3] = {o0, o1, o2};
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x) {
+    const u64 k = keys[i];
+    for (u32 c = 0; c < a.arity; ++c) {
+      const u64 m = a.width[c] >= 32 ? 0xFFFFFFFFull : ((1ull << a.width[c]) - 1);
+      outs[c][i] = u32((k >> a.shift[c]) & m);
+    }
+  }
+}
+
+__global__ void k_set_rows(PackArgs a, u64 n, u64* set, u64 mask) {
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x) {
+    u64 k = 0;
+    for (u32 c = 0; c < a.arity; ++c) k |= u64(a.cols[c][i]) << a.shift[c];
+    set_insert(set, mask, k);
+  }
+}
+
+static PackArgs pack_args(const u32* const* cols, u32 arity, const u32* shift, const u32* width) {
+  PackArgs a{};
+  a.arity = arity;
+  for (u32 c = 0; c < arity && c < 3; ++c) {
+    a.cols[c] = cols ? cols[c] : nullptr;
+    a.shift[c] = shift[c];
+    a.width[c] = width ? width[c] : 32;
+  }
+  return a;
+}
+
+int launch_pack(const u32* const* cols, u32 arity, const u32* shift, u64 n, u64* keys, void* stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_pack, dim3(grid_rows(n, 4096)), dim3(kBlock), 0, (hipStream_t)stream,
+                     pack_args(cols, arity, shift, nullptr), n, keys);
+  return int(hipGetLastError());
+}
+
+int launch_unpack(const u64* keys, u64 n, u32 arity, const u32* shift, const u32* width, u32* const* cols,
+                  void* stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_unpack, dim3(grid_rows(n, 4096)), dim3(kBlock), 0, (hipStream_t)stream, keys, n,
+                     pack_args(nullptr, arity, shift, width), cols[0], arity > 1 ? cols[1] : nullptr,
+                     arity > 2 ? cols[2] : nullptr);
+  return int(hipGetLastError());
+}
+
+int launch_set_insert_rows(const u32* const* cols, u32 arity, const u32* shift, u64 n, u64* set, u64 mask,
+                           void* stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_set_rows, dim3(grid_rows(n, 4096)), dim3(kBlock), 0, (hipStream_t)stream,
+                     pack_args(cols, arity, shift, nullptr), n, set, mask);
+  return int(hipGetLastError());
+}
+
+}  // namespace fv

@@ -1,0 +1,387 @@
+// Join, selection/projection, deduplication and merge kernels.
+//
+// Join follows the two phases of Algorithm 1 (Section 4, "Join"):
+//  * k_probe -- every probe row looks its key up in the build side's unique
+//    hashmap and gets a run (start, count) of build row ids; unmatched rows are
+//    dropped and the run lengths are prefix-summed, so the output size is known
+//    before anything is written (count-then-write, lock-free output).  The
+//    filter, reduce and exclusive scan of Algorithm 1 are one pass here: a
+//    wave-ballot/block scan per tile and a decoupled look-back across tiles.
+//  * k_write -- output-balanced materialisation: output slot n finds the run j
+//    with off[j] <= n < off[j+1] and takes build row perm[start[j] + n - off[j]].
+//    Projection and selection are fused (late materialisation, Section 4):
+//    only the columns the next step needs are gathered, and filters such as
+//    x != y are applied before the write.
+// k_dedup implements the difference operator (Section 4, "Union and
+// Deduplication") on radix-sorted new tuples: adjacent repeats are dropped,
+// tuples already in full are dropped, and the survivors -- the delta -- are
+// appended to the contiguous full relation (Section 3, eager merge).
+#include "fv_device.h"
+
+namespace fv {
+
+constexpr int kProbeItems = 4;
+constexpr u32 kProbeTile = kBlock * kProbeItems;
+constexpr int kWriteItems = 4;
+constexpr u32 kWriteTile = kBlock * kWriteItems;
+constexpr int kDedupItems = 4;
+constexpr u32 kDedupTile = kBlock * kDedupItems;
+
+__device__ __forceinline__ u32 probe_val(const Src& s, const u32* const* pcol, u64 row) {
+  return s.kind == kSrcConst ? s.v : pcol[s.v][row];
+}
+
+__device__ __forceinline__ u32 src_val(const Src& s, const u32* const* pcol, u64 prow,
+                                       const u32* const* bcol, u64 brow) {
+  if (s.kind == kSrcConst) return s.v;
+  if (s.kind == kSrcProbe) return pcol[s.v][prow];
+  return bcol[s.v][brow];
+}
+
+__device__ __forceinline__ u64 make_key(u32 nkey, u32 a, u32 b) {
+  return nkey == 2 ? ((u64(a) << 32) | u64(b)) : u64(a);
+}
+
+// ------------------------------------------------------------------ probe
+__global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
+  __shared__ u32 s_ticket;
+  __shared__ u32 s_m[kBlock / kWave + 1];
+  __shared__ u64 s_t[kBlock / kWave + 1];
+  __shared__ u64 s_excl[2];
+  if (p.abort && *p.abort) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u32 ntiles = u32((n + kProbeTile - 1) / kProbeTile);
+  if (ntiles == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) { *p.out_m = 0; *p.out_t = 0; }
+  }
+  u64 nbuild = 0;
+  if (p.nkey == 0) nbuild = p.build_rows_ctr ? min_u64(*p.build_rows_ctr, p.build_cap) : p.build_rows;
+
+  for (;;) {
+    const u32 tile = take_ticket(p.ticket, ntiles, &s_ticket);
+    if (tile >= ntiles) break;
+    const u64 r0 = u64(tile) * kProbeTile + u64(threadIdx.x) * kProbeItems;
+    u32 st[kProbeItems], cnt[kProbeItems];
+    u32 matched = 0;
+    u64 tsum = 0;
+#pragma unroll
+    for (int k = 0; k < kProbeItems; ++k) {
+      st[k] = 0;
+      cnt[k] = 0;
+      const u64 r = r0 + k;
+      if (r < n) {
+        const u64 row = begin + r;
+        bool ok = true;
+        for (u32 f = 0; f < p.n_pf; ++f) {
+          const u32 a = probe_val(p.pf[f].a, p.pcol, row);
+          const u32 b = probe_val(p.pf[f].b, p.pcol, row);
+          ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
+        }
+        if (ok) {
+          if (p.nkey == 0) {
+            cnt[k] = u32(nbuild);
+          } else {
+            const u32 a = probe_val(p.key[0], p.pcol, row);
+            const u32 b = p.nkey == 2 ? probe_val(p.key[1], p.pcol, row) : 0u;
+            u32 s, c;
+            if (index_find(p.table, p.mask, make_key(p.nkey, a, b), s, c)) { st[k] = s; cnt[k] = c; }
+          }
+        }
+      }
+      if (cnt[k]) { ++matched; tsum += cnt[k]; }
+    }
+    u32 mtot;
+    u64 ttot;
+    const u32 mex = block_exclusive_sum<kBlock>(matched, s_m, &mtot);
+    const u64 tex = block_exclusive_sum<kBlock>(tsum, s_t, &ttot);
+    const int w = threadIdx.x / kWave;
+    if (tile == 0) {
+      if (threadIdx.x == 0) {
+        atomic_store_u64(p.st_m + tile, lb_word(p.epoch, kFlagPrefix, mtot));
+        atomic_store_u64(p.st_t + tile, lb_word(p.epoch, kFlagPrefix, ttot));
+        s_excl[0] = 0;
+        s_excl[1] = 0;
+      }
+    } else {
+      if (threadIdx.x == 0) {
+        atomic_store_u64(p.st_m + tile, lb_word(p.epoch, kFlagAgg, mtot));
+        atomic_store_u64(p.st_t + tile, lb_word(p.epoch, kFlagAgg, ttot));
+      }
+      if (w < 2) {
+        u64* st_arr = w == 0 ? p.st_m : p.st_t;
+        const u64 ex = lookback_exclusive(st_arr, tile, p.epoch);
+        if (lane_id() == 0) {
+          atomic_store_u64(st_arr + tile, lb_word(p.epoch, kFlagPrefix, ex + (w == 0 ? u64(mtot) : ttot)));
+          s_excl[w] = ex;
+        }
+      }
+    }
+    __syncthreads();
+    const u64 ex_m = s_excl[0], ex_t = s_excl[1];
+    u64 pos = ex_m + mex;
+    u64 off = ex_t + tex;
+#pragma unroll
+    for (int k = 0; k < kProbeItems; ++k) {
+      if (cnt[k]) {
+        if (pos < p.m_cap) {
+          p.m_row[pos] = u32(begin + r0 + k);
+          p.m_start[pos] = st[k];
+          p.m_off[pos] = off;
+        } else {
+          *p.fatal = 1;
+        }
+        ++pos;
+        off += cnt[k];
+      }
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0) {
+      *p.out_m = ex_m + mtot;
+      *p.out_t = ex_t + ttot;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ shared append
+// Compact the kept outputs of a block-tile and append them at an atomically
+// reserved position of the output (order inside a "new" buffer is free: it is
+// sorted before deduplication).
+struct OutVals {
+  u32 v[kMaxCols];
+};
+
+template <int kItems>
+__device__ __forceinline__ void append_tile(const OutSpec& o, const bool* keep, const OutVals* vals,
+                                            u32* s_cnt, u64* s_base, u32* overflow, u64* stat) {
+  u32 mine = 0;
+#pragma unroll
+  for (int k = 0; k < kItems; ++k) mine += keep[k] ? 1u : 0u;
+  u32 tot;
+  const u32 ex = block_exclusive_sum<kBlock>(mine, s_cnt, &tot);
+  if (threadIdx.x == 0) {
+    *s_base = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(o.count), (unsigned long long)tot) : 0;
+    if (stat && tot) atomicAdd(reinterpret_cast<unsigned long long*>(stat), (unsigned long long)tot);
+  }
+  __syncthreads();
+  const u64 base = *s_base;
+  if (base + tot > o.cap) {
+    if (threadIdx.x == 0 && tot) *overflow = 1;
+  } else {
+    u64 pos = base + ex;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) {
+      if (!keep[k]) continue;
+      if (o.packed) {
+        u64 key = 0;
+        for (u32 c = 0; c < o.ncols; ++c) key |= u64(vals[k].v[c]) << o.shift[c];
+        o.keys[pos] = key;
+      } else {
+        for (u32 c = 0; c < o.ncols; ++c) o.cols[c][pos] = vals[k].v[c];
+      }
+      ++pos;
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ write
+__global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
+  __shared__ u64 s_off[kWriteTile + 1];
+  __shared__ u64 s_j0;
+  __shared__ u32 s_cnt[kBlock / kWave + 1];
+  __shared__ u64 s_base;
+  if (p.abort && *p.abort) return;
+  const u64 M = min_u64(*p.in_m, p.m_cap);
+  const u64 T = *p.in_t;
+  const u64 ntiles = (T + kWriteTile - 1) / kWriteTile;
+  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const u64 n0 = tile * kWriteTile;
+    if (threadIdx.x == 0) {
+      u64 lo = 0, hi = M;                      // first j with off[j] > n0
+      while (lo < hi) {
+        const u64 mid = (lo + hi) >> 1;
+        if (p.m_off[mid] <= n0) lo = mid + 1; else hi = mid;
+      }
+      s_j0 = lo - 1;
+    }
+    __syncthreads();
+    const u64 j0 = s_j0;
+    for (u32 i = threadIdx.x; i <= kWriteTile; i += kBlock)
+      s_off[i] = (j0 + i < M) ? p.m_off[j0 + i] : T;
+    __syncthreads();
+
+    bool keep[kWriteItems];
+    OutVals vals[kWriteItems];
+#pragma unroll
+    for (int k = 0; k < kWriteItems; ++k) {
+      const u64 nn = n0 + u64(threadIdx.x) * kWriteItems + k;
+      keep[k] = false;
+      if (nn >= T) continue;
+      u32 lo = 0, hi = kWriteTile + 1;         // last jl with s_off[jl] <= nn
+      while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (s_off[mid] <= nn) lo = mid + 1; else hi = mid;
+      }
+      const u32 jl = lo - 1;
+      const u64 j = j0 + jl;
+      const u64 prow = p.m_row[j];
+      const u64 idx = u64(p.m_start[j]) + (nn - s_off[jl]);
+      const u64 brow = p.perm ? u64(p.perm[idx]) : idx;
+      bool ok = true;
+      for (u32 f = 0; f < p.n_filter; ++f) {
+        const u32 a = src_val(p.filt[f].a, p.pcol, prow, p.bcol, brow);
+        const u32 b = src_val(p.filt[f].b, p.pcol, prow, p.bcol, brow);
+        ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
+      }
+      keep[k] = ok;
+      if (ok)
+        for (u32 c = 0; c < p.out.ncols; ++c) vals[k].v[c] = src_val(p.out.src[c], p.pcol, prow, p.bcol, brow);
+    }
+    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
+  }
+}
+
+// ------------------------------------------------------------------ select / project
+__global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
+  __shared__ u32 s_cnt[kBlock / kWave + 1];
+  __shared__ u64 s_base;
+  if (p.abort && *p.abort) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 ntiles = (n + kWriteTile - 1) / kWriteTile;
+  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    bool keep[kWriteItems];
+    OutVals vals[kWriteItems];
+#pragma unroll
+    for (int k = 0; k < kWriteItems; ++k) {
+      const u64 r = tile * kWriteTile + u64(k) * kBlock + threadIdx.x;
+      keep[k] = false;
+      if (r >= n) continue;
+      const u64 row = begin + r;
+      bool ok = true;
+      for (u32 f = 0; f < p.n_filter; ++f) {
+        const u32 a = probe_val(p.filt[f].a, p.pcol, row);
+        const u32 b = probe_val(p.filt[f].b, p.pcol, row);
+        ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
+      }
+      keep[k] = ok;
+      if (ok)
+        for (u32 c = 0; c < p.out.ncols; ++c) vals[k].v[c] = probe_val(p.out.src[c], p.pcol, row);
+    }
+    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
+  }
+}
+
+// ------------------------------------------------------------------ dedup + append
+__global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
+  __shared__ u32 s_ticket;
+  __shared__ u32 s_c[kBlock / kWave + 1];
+  __shared__ u64 s_excl;
+  if (p.abort && *p.abort) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 fbase = *p.full_n;
+  const u32 ntiles = u32((n + kDedupTile - 1) / kDedupTile);
+  if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) *p.out_delta = 0;
+  for (;;) {
+    const u32 tile = take_ticket(p.ticket, ntiles, &s_ticket);
+    if (tile >= ntiles) break;
+    const u64 r0 = u64(tile) * kDedupTile + u64(threadIdx.x) * kDedupItems;
+    u64 key[kDedupItems];
+    bool surv[kDedupItems];
+    u32 mine = 0;
+#pragma unroll
+    for (int k = 0; k < kDedupItems; ++k) {
+      const u64 r = r0 + k;
+      surv[k] = false;
+      key[k] = 0;
+      if (r < n) {
+        key[k] = p.keys[begin + r];
+        const bool first = (r == 0) || (p.keys[begin + r - 1] != key[k]);
+        surv[k] = first && (p.set ? set_insert(p.set, p.set_mask, key[k]) : true);
+      }
+      mine += surv[k] ? 1u : 0u;
+    }
+    u32 tot;
+    const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
+    if (tile == 0) {
+      if (threadIdx.x == 0) {
+        atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, tot));
+        s_excl = 0;
+      }
+    } else {
+      if (threadIdx.x == 0) atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagAgg, tot));
+      if (threadIdx.x < kWave) {
+        const u64 e = lookback_exclusive(p.status, tile, p.epoch);
+        if (threadIdx.x == 0) {
+          atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, e + tot));
+          s_excl = e;
+        }
+      }
+    }
+    __syncthreads();
+    u64 pos = fbase + s_excl + ex;
+#pragma unroll
+    for (int k = 0; k < kDedupItems; ++k) {
+      if (!surv[k]) continue;
+      for (u32 c = 0; c < p.arity; ++c) {
+        const u64 m = (p.width[c] >= 32) ? 0xFFFFFFFFull : ((1ull << p.width[c]) - 1);
+        p.cols[c][pos] = u32((key[k] >> p.shift[c]) & m);
+      }
+      ++pos;
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0) *p.out_delta = s_excl + tot;
+    __syncthreads();
+  }
+}
+
+__global__ void k_commit(CommitParams p) {
+  if (p.abort && *p.abort) return;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const u64 d = *p.delta;
+    const u64 f = *p.full_n;
+    *p.d_begin = f;
+    *p.full_n = f + d;
+    if (p.new_count) *p.new_count = 0;
+    if (p.derived) *p.derived += d;
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static int grid_for(u64 tiles, int cap_blocks) {
+  if (tiles == 0) return 1;
+  return int(tiles < u64(cap_blocks) ? tiles : u64(cap_blocks));
+}
+
+int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream) {
+  const u64 tiles = (probe_cap + kProbeTile - 1) / kProbeTile;
+  int g = grid > 0 ? grid : grid_for(tiles, 2048);
+  hipLaunchKernelGGL(k_probe, dim3(g), dim3(kBlock), 0, (hipStream_t)stream, p);
+  return int(hipGetLastError());
+}
+
+int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream) {
+  const u64 tiles = (out_tiles_hint + kWriteTile - 1) / kWriteTile;
+  hipLaunchKernelGGL(k_write, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  return int(hipGetLastError());
+}
+
+int launch_select(const SelectParams& p, u64 rows_hint, void* stream) {
+  const u64 tiles = (rows_hint + kWriteTile - 1) / kWriteTile;
+  hipLaunchKernelGGL(k_select, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  return int(hipGetLastError());
+}
+
+int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream) {
+  const u64 tiles = (rows_cap + kDedupTile - 1) / kDedupTile;
+  hipLaunchKernelGGL(k_dedup, dim3(grid_for(tiles, 2048)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  return int(hipGetLastError());
+}
+
+int launch_commit(const CommitParams& p, void* stream) {
+  hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, (hipStream_t)stream, p);
+  return int(hipGetLastError());
+}
+
+}  // namespace fv

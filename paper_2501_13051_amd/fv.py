@@ -1,0 +1,389 @@
+"""ctypes binding of libfv.so (include/fv.h), argument marshalling only.
+
+Every step of the evaluation runs in the library's HIP kernels; this module
+converts Python values to the C structs of the ABI, hands torch's caching
+allocator and current stream to the library (PyTorch serves only as device
+memory and stream plumbing), and turns error codes into exceptions.  If
+libfv.so has not been built the import of the library raises: there is no
+fallback evaluator here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfv.so")
+
+FV_OK = 0
+STATUS = {0: "FV_OK", -1: "FV_EINVAL", -2: "FV_ENOMEM", -3: "FV_EARITY", -4: "FV_EUNSAFE",
+          -5: "FV_ESTATE", -6: "FV_EHIP", -7: "FV_ERESERVED", -8: "FV_ETRUNC", -9: "FV_ENOTSUP"}
+FV_PLAIN = 0
+FV_TRACE = 4
+
+EXPORTED = ("fv_ctx_create", "fv_ctx_destroy", "fv_last_error", "fv_relation_create", "fv_relation_find",
+            "fv_load_columns", "fv_add_rule", "fv_run_fixpoint", "fv_relation_size", "fv_export",
+            "fv_delta_sizes", "fv_profile")
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
+                ("user", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+
+
+class Term(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_uint32), ("is_const", ctypes.c_uint32)]
+
+
+class Atom(ctypes.Structure):
+    _fields_ = [("rel", ctypes.c_uint32), ("arity", ctypes.c_uint32), ("terms", ctypes.POINTER(Term))]
+
+
+class Rule(ctypes.Structure):
+    _fields_ = [("head", Atom), ("body", ctypes.POINTER(Atom)), ("n_body", ctypes.c_uint32),
+                ("neq", ctypes.POINTER(ctypes.c_uint32)), ("n_neq", ctypes.c_uint32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_uint32), ("redo_rounds", ctypes.c_uint32),
+                ("derived_tuples", ctypes.c_uint64), ("join_output_tuples", ctypes.c_uint64),
+                ("ms_total", ctypes.c_double)]
+
+
+class KProf(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double),
+                ("algo_bytes", ctypes.c_double), ("items", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfv.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with __graft_entry__.build() "
+                               "or python -m paper_2501_13051_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        L.fv_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Options)]
+        L.fv_ctx_destroy.argtypes = [vp]
+        L.fv_ctx_destroy.restype = None
+        L.fv_last_error.argtypes = [vp]
+        L.fv_last_error.restype = ctypes.c_char_p
+        L.fv_relation_create.argtypes = [vp, ctypes.c_char_p, u32, ctypes.POINTER(u32)]
+        L.fv_relation_find.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(u32)]
+        L.fv_load_columns.argtypes = [vp, u32, ctypes.POINTER(vp), u64, ctypes.c_int]
+        L.fv_add_rule.argtypes = [vp, ctypes.POINTER(Rule)]
+        L.fv_run_fixpoint.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.fv_relation_size.argtypes = [vp, u32, ctypes.POINTER(u64)]
+        L.fv_export.argtypes = [vp, u32, ctypes.POINTER(vp), u64, ctypes.POINTER(u64), ctypes.c_int]
+        L.fv_delta_sizes.argtypes = [vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)]
+        L.fv_profile.argtypes = [vp, ctypes.POINTER(KProf), u32, ctypes.POINTER(u32)]
+        for name in EXPORTED:
+            if name not in ("fv_ctx_destroy", "fv_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class FvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+# ------------------------------------------------------------------ program text
+_TOKEN = re.compile(r"\s*(?:(:-)|(!=)|([A-Za-z_][A-Za-z0-9_]*)|(\d+)|([(),.])|(%[^\n]*))")
+
+
+def parse_program(text: str):
+    """Parse `head(t, ..) :- atom(t, ..), ..., x != y.` rules.
+
+    Returns a list of (head, body, neq): head/body atoms are (name, terms)
+    with terms ('v', index) or ('c', value); neq lists pairs of variable
+    indices.  `_` is a fresh variable at each occurrence; `%` comments."""
+    toks, pos = [], 0
+    while pos < len(text):
+        m = _TOKEN.match(text, pos)
+        if not m or m.end() == pos:
+            if text[pos:].strip() == "":
+                break
+            raise ValueError(f"cannot parse program near {text[pos:pos + 20]!r}")
+        pos = m.end()
+        if m.group(6):
+            continue
+        for g in (1, 2, 3, 4, 5):
+            if m.group(g):
+                toks.append((g, m.group(g)))
+                break
+    rules, i = [], 0
+
+    def expect(tok):
+        nonlocal i
+        if i >= len(toks) or toks[i][1] != tok:
+            raise ValueError(f"expected {tok!r}")
+        i += 1
+
+    while i < len(toks):
+        names = {}
+
+        def term():
+            nonlocal i
+            kind, val = toks[i]
+            i += 1
+            if kind == 4:
+                v = int(val)
+                if v > 0xFFFFFFFE:
+                    raise ValueError("constant out of range")
+                return ("c", v)
+            if kind != 3:
+                raise ValueError(f"bad term {val!r}")
+            if val == "_":
+                names[f"_#{len(names)}"] = len(names)
+                return ("v", len(names) - 1)
+            if val not in names:
+                names[val] = len(names)
+            return ("v", names[val])
+
+        def atom():
+            nonlocal i
+            kind, name = toks[i]
+            if kind != 3:
+                raise ValueError("expected a relation name")
+            i += 1
+            expect("(")
+            ts = [term()]
+            while toks[i][1] == ",":
+                i += 1
+                ts.append(term())
+            expect(")")
+            return (name, ts)
+
+        head = atom()
+        expect(":-")
+        body, neq = [], []
+        while True:
+            if i + 1 < len(toks) and toks[i + 1][1] == "(":
+                body.append(atom())
+            else:
+                a = term()
+                expect("!=")
+                b = term()
+                if a[0] != "v" or b[0] != "v":
+                    raise ValueError("!= takes variables")
+                neq.append((a[1], b[1]))
+            if toks[i][1] == ",":
+                i += 1
+                continue
+            expect(".")
+            break
+        if len(names) > 16:
+            raise ValueError("a rule may use at most 16 variables")
+        rules.append((head, body, neq))
+    return rules
+
+
+# ------------------------------------------------------------------ engine
+class Engine:
+    """One fixpoint context on the current CUDA/HIP device and stream."""
+
+    def __init__(self, flags: int = FV_PLAIN, stream=None, use_torch_allocator: bool = True):
+        import torch
+        self._torch = torch
+        L = lib()
+        self._L = L
+        self._device = torch.cuda.current_device()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._stream_obj = s
+        opt = Options()
+        opt.stream = ctypes.c_void_p(s.cuda_stream)
+        opt.flags = flags
+        self._live = {}
+        if use_torch_allocator:
+            dev, handle = self._device, s.cuda_stream
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, handle)
+                except Exception:   # out of memory: report NULL, the library returns FV_ENOMEM
+                    return None
+
+            def _free(ptr, stream, user):
+                if ptr:
+                    torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+            opt.dev_alloc = self._alloc_cb
+            opt.dev_free = self._free_cb
+        self._opt = opt
+        h = ctypes.c_void_p()
+        self._check(L.fv_ctx_create(ctypes.byref(h), ctypes.byref(opt)), ctx=None)
+        self._h = h
+        self._rels = {}
+
+    def _check(self, rc, ctx="self"):
+        if rc != FV_OK:
+            msg = self._L.fv_last_error(self._h).decode() if ctx is not None else ""
+            raise FvError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fv_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # relations
+    def relation(self, name: str, arity: int) -> int:
+        if name in self._rels:
+            return self._rels[name][0]
+        out = ctypes.c_uint32()
+        self._check(self._L.fv_relation_create(self._h, name.encode(), arity, ctypes.byref(out)))
+        self._rels[name] = (out.value, arity)
+        return out.value
+
+    def load(self, name: str, cols):
+        """Append facts: `cols` is a list of per-column arrays (numpy on the
+        host, or torch uint32/int32 tensors on the device)."""
+        torch = self._torch
+        arity = len(cols)
+        rel = self.relation(name, arity)
+        n = len(cols[0])
+        keep = []
+        ptrs = (ctypes.c_void_p * arity)()
+        on_device = isinstance(cols[0], torch.Tensor) and cols[0].is_cuda
+        for c, col in enumerate(cols):
+            if len(col) != n:
+                raise ValueError("columns differ in length")
+            if on_device:
+                t = col.contiguous()
+                if t.element_size() != 4:
+                    raise ValueError("device columns must be 32-bit")
+                keep.append(t)
+                ptrs[c] = t.data_ptr()
+            else:
+                a = np.ascontiguousarray(np.asarray(col), dtype=np.uint32)
+                keep.append(a)
+                ptrs[c] = a.ctypes.data
+        self._check(self._L.fv_load_columns(self._h, rel, ptrs, n, 1 if on_device else 0))
+
+    def add_rule(self, head, body, neq=()):
+        """head/body atoms are (name, terms) with terms ('v', i) / ('c', k)."""
+        keep = []
+
+        def atom(a):
+            name, ts = a
+            rel = self.relation(name, len(ts)) if name not in self._rels else self._rels[name][0]
+            arr = (Term * len(ts))(*[Term(v, 1 if k == "c" else 0) for k, v in ts])
+            keep.append(arr)
+            return Atom(rel, len(ts), arr)
+
+        r = Rule()
+        r.head = atom(head)
+        bodies = (Atom * len(body))(*[atom(b) for b in body])
+        r.body = bodies
+        r.n_body = len(body)
+        flat = [x for pair in neq for x in pair]
+        na = (ctypes.c_uint32 * max(1, len(flat)))(*flat)
+        r.neq = na
+        r.n_neq = len(neq)
+        self._check(self._L.fv_add_rule(self._h, ctypes.byref(r)))
+
+    def program(self, text: str):
+        for head, body, neq in parse_program(text):
+            self.add_rule(head, body, neq)
+
+    def run(self) -> dict:
+        st = Stats()
+        self._check(self._L.fv_run_fixpoint(self._h, ctypes.byref(st)))
+        return {"iterations": st.iterations, "redo_rounds": st.redo_rounds,
+                "derived_tuples": st.derived_tuples, "join_output_tuples": st.join_output_tuples,
+                "ms_total": st.ms_total}
+
+    def size(self, name: str) -> int:
+        n = ctypes.c_uint64()
+        self._check(self._L.fv_relation_size(self._h, self._rels[name][0], ctypes.byref(n)))
+        return n.value
+
+    def export(self, name: str, device: bool = False):
+        """Relation as a row-sorted (n, arity) uint32 numpy array, or with
+        device=True as a list of torch int32 column tensors (same bits)."""
+        torch = self._torch
+        rel, arity = self._rels[name]
+        n = ctypes.c_uint64()
+        self._check(self._L.fv_export(self._h, rel, None, 0, ctypes.byref(n), 0))
+        n = n.value
+        ptrs = (ctypes.c_void_p * arity)()
+        if device:
+            cols = [torch.empty(max(n, 1), dtype=torch.int32, device=f"cuda:{self._device}") for _ in range(arity)]
+            for c in range(arity):
+                ptrs[c] = cols[c].data_ptr()
+            self._check(self._L.fv_export(self._h, rel, ptrs, n, None, 1))
+            return [c[:n] for c in cols]
+        out = np.zeros((arity, max(n, 1)), dtype=np.uint32)
+        for c in range(arity):
+            ptrs[c] = out[c].ctypes.data
+        self._check(self._L.fv_export(self._h, rel, ptrs, n, None, 0))
+        return np.ascontiguousarray(out[:, :n].T)
+
+    def delta_sizes(self):
+        n = ctypes.c_uint32()
+        self._check(self._L.fv_delta_sizes(self._h, None, 0, ctypes.byref(n)))
+        buf = (ctypes.c_uint64 * max(1, n.value))()
+        self._check(self._L.fv_delta_sizes(self._h, buf, n.value, ctypes.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
+
+    def profile(self):
+        n = ctypes.c_uint32()
+        self._check(self._L.fv_profile(self._h, None, 0, ctypes.byref(n)))
+        buf = (KProf * max(1, n.value))()
+        self._check(self._L.fv_profile(self._h, buf, n.value, ctypes.byref(n)))
+        return [{"name": buf[i].name.decode(), "launches": int(buf[i].launches), "ms": float(buf[i].ms),
+                 "algo_bytes": float(buf[i].algo_bytes), "items": int(buf[i].items)} for i in range(n.value)]
+
+
+def evaluate(program: str, edb: dict, flags: int = FV_PLAIN, relations=None, device_out: bool = False):
+    """Load `edb` (name -> list of columns), run `program` to its fixpoint on
+    the GPU and return (relations as row-sorted arrays, stats, delta sizes)."""
+    eng = Engine(flags=flags)
+    try:
+        rules = parse_program(program)
+        arities = {}
+        for head, body, _ in rules:
+            for name, ts in [head] + body:
+                arities.setdefault(name, len(ts))
+        for name, cols in edb.items():
+            arities.setdefault(name, len(cols))
+        for name, a in arities.items():
+            eng.relation(name, a)
+        for name, cols in edb.items():
+            eng.load(name, cols)
+        for head, body, neq in rules:
+            eng.add_rule(head, body, neq)
+        stats = eng.run()
+        names = relations if relations is not None else list(arities)
+        out = {name: eng.export(name, device=device_out) for name in names}
+        prof = eng.profile()
+        return out, stats, eng.delta_sizes(), prof
+    finally:
+        eng.close()

@@ -1,0 +1,126 @@
+"""Parity of the HIP engine (through the C ABI) with the oracle.
+
+Every comparison is exact: the exported relations (row-sorted uint32) must
+be byte-identical to the oracle's fixpoint, and the per-round delta sizes
+must match the oracle's round structure.
+"""
+import glob
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+from progs import random_edb, random_program
+from paper_2501_13051_amd import fv
+from paper_2501_13051_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _check(program, edb, relations=None, flags=fv.FV_PLAIN):
+    ref = oracle.evaluate(program, edb)
+    names = relations or list(ref.relations)
+    got, stats, deltas, _ = fv.evaluate(program, edb, flags=flags, relations=names)
+    for n in names:
+        assert got[n].shape == ref[n].shape, (n, got[n].shape, ref[n].shape)
+        assert np.array_equal(got[n], ref[n]), n
+    assert deltas == ref.delta_sizes, (deltas, ref.delta_sizes)
+    return got, stats, ref
+
+
+def _edb_from_rows(d):
+    return {k: [np.asarray(v, np.uint32)[:, c].copy() for c in range(len(v[0]))] for k, v in d.items()}
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.json"))), ids=os.path.basename)
+def test_golden(path):
+    g = json.load(open(path))
+    edb = _edb_from_rows(g["edb"])
+    for pk, ek in [("program", "expect"), ("program_paper_form", "expect_paper_form")]:
+        if pk in g:
+            got, _, _ = _check(g[pk], edb)
+            for name, rows in g[ek].items():
+                assert np.array_equal(got[name], np.asarray(rows, np.uint32))
+
+
+@pytest.mark.parametrize("n", [2, 3, 64, 65, 300])
+def test_tc_chain_and_cycle(n):
+    _check(W.TC_PROGRAM, {"edge": W.chain(n)})
+    _check(W.TC_PROGRAM, {"edge": W.cycle(n)})
+
+
+def test_tc_paper_form_and_dag():
+    _check(W.TC_PROGRAM_PAPER_FORM, {"edge": W.er_graph(500, 900, seed=11)})
+    _check(W.TC_PROGRAM, {"edge": W.complete_dag(40)})
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_programs(seed):
+    rnd = random.Random(seed)
+    prog = random_program(rnd)
+    _check(prog, random_edb(rnd))
+
+
+def test_empty_and_duplicate_inputs():
+    e0 = [np.zeros(0, np.uint32), np.zeros(0, np.uint32)]
+    _check(W.TC_PROGRAM, {"edge": e0}, relations=["path", "edge"])
+    # repeated facts in the load are one fact
+    dup = [np.array([1, 1, 1, 2, 2], np.uint32), np.array([2, 2, 2, 3, 3], np.uint32)]
+    got, _, _ = _check(W.TC_PROGRAM, {"edge": dup})
+    assert got["path"].tolist() == [[1, 2], [1, 3], [2, 3]]
+
+
+def test_large_ids_and_wide_keys():
+    # ids near the top of the uint32 range: 32-bit columns, 64-bit packed keys
+    rng = W.SplitMix64(5)
+    src = (0xFFFFFFFE - rng.below(3000, 4000)).astype(np.uint32)
+    dst = (0xFFFFFFFE - rng.below(3000, 4000)).astype(np.uint32)
+    keep = src != dst
+    _check(W.TC_PROGRAM, {"edge": [src[keep], dst[keep]]})
+
+
+def test_sg_forest_small_both_forms():
+    edge = W.forest(8, 256, 0.05, seed=1002)
+    _check(W.SG_PROGRAM, {"edge": edge})
+    _check(W.SG_PROGRAM_PAPER_FORM, {"edge": edge})
+
+
+def test_device_resident_load_and_export():
+    import torch
+    edge = W.er_graph(400, 800, seed=3)
+    eng = fv.Engine()
+    eng.relation("edge", 2)
+    eng.relation("path", 2)
+    eng.load("edge", [torch.from_numpy(c.astype(np.int32)).cuda() for c in edge])
+    eng.program(W.TC_PROGRAM)
+    eng.run()
+    cols = eng.export("path", device=True)
+    got = np.stack([c.cpu().numpy().view(np.uint32) for c in cols], axis=1)
+    ref = oracle.evaluate(W.TC_PROGRAM, {"edge": edge})
+    assert np.array_equal(got, ref["path"])
+    eng.close()
+
+
+def test_reserved_value_rejected():
+    eng = fv.Engine()
+    eng.relation("edge", 2)
+    with pytest.raises(fv.FvError) as ei:
+        eng.load("edge", [np.array([1, 0xFFFFFFFF], np.uint32), np.array([2, 3], np.uint32)])
+    assert ei.value.status == "FV_ERESERVED"
+    eng.close()
+
+
+def test_config_tc_full_size():
+    w = W.config_tc()
+    got, stats, ref = _check(w.program, w.edb, relations=["path"])
+    assert stats["derived_tuples"] == len(ref["path"])
+
+
+def test_config_sg_full_size():
+    w = W.config_sg()
+    got, stats, ref = _check(w.program, w.edb, relations=["sg"])
+    assert stats["derived_tuples"] == len(ref["sg"])

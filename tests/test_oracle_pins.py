@@ -19,6 +19,7 @@ import numpy as np
 import pytest
 
 import brute
+from progs import random_program, random_edb
 import oracle
 from paper_2501_13051_amd import workloads as W
 
@@ -134,52 +135,11 @@ def test_sg_forest_equals_matrix_form(paper_form):
 
 
 # ------------------------------------------------------- random tiny programs
-def _random_program(rnd: random.Random):
-    """Random safe rules over EDB e/2, c/1 and IDB p/2, q/2, r/3, u/1 with
-    constants, repeated variables, != and mutual recursion."""
-    arity = {"e": 2, "c": 1, "p": 2, "q": 2, "r": 3, "u": 1}
-    idb = ["p", "q", "r", "u"]
-    rules = []
-    for _ in range(rnd.randint(2, 5)):
-        head = rnd.choice(idb)
-        nb = rnd.randint(1, 3)
-        vars_ = ["x", "y", "z", "w"]
-        body = []
-        for _ in range(nb):
-            rel = rnd.choice(["e", "e", "c"] + idb)
-            terms = []
-            for _ in range(arity[rel]):
-                if rnd.random() < 0.12:
-                    terms.append(str(rnd.randint(0, 4)))
-                else:
-                    terms.append(rnd.choice(vars_))
-            body.append(f"{rel}({', '.join(terms)})")
-        bound = sorted({t for a in body for t in a[a.index('(') + 1:-1].split(', ') if not t.isdigit()})
-        if not bound:
-            continue
-        hterms = [rnd.choice(bound) if rnd.random() > 0.1 else str(rnd.randint(0, 4))
-                  for _ in range(arity[head])]
-        neq = ""
-        if len(bound) >= 2 and rnd.random() < 0.3:
-            a, b = rnd.sample(bound, 2)
-            neq = f", {a} != {b}"
-        rules.append(f"{head}({', '.join(hterms)}) :- {', '.join(body)}{neq}.")
-    # make sure each IDB relation exists with the right arity
-    rules.append("u(x) :- c(x).")
-    rules.append("p(x, y) :- e(x, y).")
-    return "\n".join(rules) + "\n"
-
-
 @pytest.mark.parametrize("seed", range(40))
 def test_random_programs_agree_with_assignment_brute_force(seed):
     rnd = random.Random(seed)
-    prog = _random_program(rnd)
-    dom = 5
-    ne = rnd.randint(0, 9)
-    e = [(rnd.randrange(dom), rnd.randrange(dom)) for _ in range(ne)]
-    c = [rnd.randrange(dom) for _ in range(rnd.randint(0, 3))]
-    edb = {"e": [np.array([a for a, _ in e], np.uint32), np.array([b for _, b in e], np.uint32)],
-           "c": [np.array(c, np.uint32)]}
+    prog = random_program(rnd)
+    edb = random_edb(rnd)
     facts, deltas = brute.naive_by_assignment(prog, edb)
     semi = oracle.evaluate(prog, edb)
     naive = oracle.evaluate(prog, edb, naive=True, relations=list(semi.relations))

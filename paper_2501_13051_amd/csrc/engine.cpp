@@ -254,12 +254,21 @@ void Engine::domain_analysis() {
     }
   }
   for (auto& R : rels_) {
+    // a column needs bits(max) bits; a packed key can only equal the
+    // all-ones empty-slot sentinel if it fills all 64 bits with every field
+    // at its all-ones value, so in that case each field gets bits(max + 1)
+    // (which keeps it strictly below all-ones)
     R.bits = 0;
     for (u32 c = 0; c < R.arity; ++c) {
-      // width of max+1 keeps every field strictly below all-ones, so no
-      // packed key can equal the empty-slot sentinel
-      R.width[c] = bits_for(u64(R.maxv[c]) + 1);
+      R.width[c] = std::max<u32>(1, bits_for(R.maxv[c]));
       R.bits += R.width[c];
+    }
+    if (R.bits >= 64) {
+      R.bits = 0;
+      for (u32 c = 0; c < R.arity; ++c) {
+        R.width[c] = bits_for(u64(R.maxv[c]) + 1);
+        R.bits += R.width[c];
+      }
     }
     if (R.bits > 64)
       throw Error(FV_ENOTSUP, "relation " + R.name + " needs " + std::to_string(R.bits) + " bits per packed tuple");
@@ -504,8 +513,13 @@ void Engine::ensure_capacity() {
       for (u32 c = 0; c < R.arity; ++c) grow(R.col[c], nc * 4, R.n_full * 4);
       R.cap = nc;
     }
-    const u64 need_set = pow2_at_least(2 * need_full);
-    if (R.set_cap < need_set) {
+    // hard bound: every slot could be claimed this round, one must stay empty;
+    // performance target: load <= 1/2 at the expected size
+    const u64 expect = R.n_full + std::max<u64>(3 * R.n_delta, 1024);
+    // grow 4x past the target so the rebuild (a re-insert of all of full)
+    // happens a logarithmic number of times
+    const u64 need_set = pow2_at_least(std::max<u64>(need_full + 1, 4 * expect));
+    if (R.set_cap < need_full + 1 || R.set_cap < expect * 3 / 2) {
       release(R.set);
       R.set = alloc(need_set * 8);
       R.set_cap = need_set;
@@ -525,8 +539,9 @@ void Engine::ensure_capacity() {
   for (auto& ix : indices_) {
     const Relation& R = rels_[ix.rel];
     const u64 rows = R.used_as_head ? R.n_full + R.new_cap : R.n_full;
-    const u64 need = pow2_at_least(std::max<u64>(2 * rows, 64));
-    if (ix.cap < need) {
+    const u64 expect = R.used_as_head ? R.n_full + std::max<u64>(3 * R.n_delta, 1024) : R.n_full;
+    const u64 need = pow2_at_least(std::max<u64>({rows + 1, 2 * expect, 64}));
+    if (ix.cap < rows + 1 || ix.cap < expect * 3 / 2) {
       release(ix.table);
       ix.table = alloc(need * sizeof(Slot));
       ix.cap = need;
@@ -790,7 +805,7 @@ void Engine::exec_plan(Plan& p) {
 }
 
 // sort the relation's new keys, take the difference against full, append
-void Engine::finish_relation(Relation& R) {
+void Engine::finish_relation(Relation& R, bool in_round) {
   const int ri = int(&R - &rels_[0]);
   u32* flags = flags_dev_.as<u32>();
   SortParams sp{};
@@ -799,14 +814,14 @@ void Engine::finish_relation(Relation& R) {
   sp.n_ctr = ctr(c_new0_ + ri);
   sp.cap = R.new_cap;
   sp.bits = R.bits;
-  sp.hist = hist_dev_.as<u32>();
+  sp.hist = hist_dev_.as<u32>() + size_t(ri) * 8 * 256;
   sp.status = st_sort_.as<u64>();
   sp.ticket = ticket_dev_.as<u32>();
   sp.abort = flags;
   const u32 passes = sort_passes(R.bits);
   const int kh = kclass("sort_hist");
   ev_begin(kh);
-  launched(launch_rs_hist(sp, stream_), "hist launch");
+  launched(launch_rs_hist(sp, stream_, !in_round), "hist launch");
   ev_end(kh, 0, 4, c_new0_ + ri, -1, R.new_cap);
   u64* src = sp.a;
   u64* dst = sp.b;
@@ -902,7 +917,7 @@ void Engine::ingest() {
     const u32* cols[3] = {R.stage[0].as<u32>(), R.stage[1].as<u32>(), R.stage[2].as<u32>()};
     launched(launch_pack(cols, R.arity, R.shift, R.staged, R.newk.as<u64>(), stream_), "pack launch");
     launched(launch_fill_u64(ctr(c_new0_ + ri), 1, R.staged, stream_), "fill");
-    finish_relation(R);
+    finish_relation(R, false);
   }
   read_counters();
   for (auto& R : rels_) {
@@ -923,8 +938,8 @@ void Engine::ingest() {
 void Engine::run_round(bool initial) {
   for (;;) {
     ensure_capacity();
-    launched(launch_fill_u64(ctr(c_reset_begin_), u64(n_ctr_ - c_reset_begin_), 0, stream_), "counter reset");
-    launched(launch_fill_u32(flags_dev_.as<u32>(), 1, 0u, stream_), "flag reset");
+    launched(launch_round_prologue(ctr(c_reset_begin_), u64(n_ctr_ - c_reset_begin_), flags_dev_.as<u32>(),
+                                   hist_dev_.as<u32>(), hist_dev_.bytes / 4, stream_), "round prologue");
     // an index whose storage grew holds nothing yet: rebuild it over the
     // current full relation before any join reads it
     for (auto& ix : indices_)
@@ -936,7 +951,7 @@ void Engine::run_round(bool initial) {
         if (rels_[p.src_rel].n_delta > 0) exec_plan(p);
     }
     for (auto& R : rels_)
-      if (R.used_as_head) finish_relation(R);
+      if (R.used_as_head) finish_relation(R, true);
     build_indices(true);
     read_counters();
     if (!flags_host_[0]) break;
@@ -951,6 +966,17 @@ void Engine::run_round(bool initial) {
       const u64 need = ctr_host_[I.ctr];
       if (need > I.cap) I.cap = pow2_at_least(std::max<u64>(need + need / 4, I.cap * 2));
     }
+  }
+  // size the next round from this one: outputs tend to grow round over round,
+  // and a buffer that overflows costs a whole re-run of the round
+  for (auto& R : rels_) {
+    if (!R.used_as_head) continue;
+    const u64 used = ctr_host_[c_new0_ + int(&R - &rels_[0])];
+    if (4 * used > R.new_cap) R.new_cap = pow2_at_least(4 * used);
+  }
+  for (auto& I : inters_) {
+    const u64 used = ctr_host_[I.ctr];
+    if (4 * used > I.cap) I.cap = pow2_at_least(4 * used);
   }
   u64 total = 0;
   for (auto& R : rels_) {
@@ -975,7 +1001,7 @@ void Engine::run(fv_stats* stats) {
   ctr_dev_ = alloc(size_t(n_ctr_) * 8);
   flags_dev_ = alloc(16);
   ticket_dev_ = alloc(16);
-  hist_dev_ = alloc(8 * 256 * 4);
+  hist_dev_ = alloc(rels_.size() * 8 * 256 * 4);
   hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
   hip(hipHostMalloc(reinterpret_cast<void**>(&ctr_host_), size_t(n_ctr_) * 8, hipHostMallocDefault), "pinned alloc");
   hip(hipHostMalloc(reinterpret_cast<void**>(&flags_host_), 16, hipHostMallocDefault), "pinned alloc");

@@ -160,7 +160,7 @@ class Engine {
   // rounds
   void run_round(bool initial);
   void exec_plan(Plan& p);
-  void finish_relation(Relation& R);
+  void finish_relation(Relation& R, bool in_round);
   void read_counters();
   u32 next_epoch(u32 n = 1);
 

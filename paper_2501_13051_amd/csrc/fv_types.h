@@ -149,6 +149,7 @@ int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream);
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream);
 int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream);
 int launch_commit(const CommitParams& p, void* stream);
+int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, void* stream);
 
 // LSD radix sort of n packed u64 keys (n from *n_ctr clamped to cap, or
 // n_const) on the low `bits` bits, 8 bits per pass: launch_rs_hist counts the
@@ -165,7 +166,7 @@ struct SortParams {
   u32* ticket;
   const u32* abort;
 };
-int launch_rs_hist(const SortParams& p, void* stream);
+int launch_rs_hist(const SortParams& p, void* stream, bool clear_hist = true);
 int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch, void* stream);
 inline u32 sort_passes(u32 bits) { return (bits + 7) / 8; }
 constexpr u32 kSortTile = 2048;

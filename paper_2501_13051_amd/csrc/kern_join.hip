@@ -348,7 +348,22 @@ __global__ void k_commit(CommitParams p) {
   }
 }
 
+// Start of a round: zero the round's counters, the overflow flag and the
+// radix histograms in one launch.
+__global__ void k_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist) {
+  const u64 i0 = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  for (u64 i = i0; i < n_ctr; i += stride) ctr[i] = 0;
+  for (u64 i = i0; i < n_hist; i += stride) hist[i] = 0;
+  if (i0 == 0) *flag = 0;
+}
+
 // ------------------------------------------------------------------ launchers
+int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, void* stream) {
+  hipLaunchKernelGGL(k_round_prologue, dim3(8), dim3(256), 0, (hipStream_t)stream, ctr, n_ctr, flag, hist, n_hist);
+  return int(hipGetLastError());
+}
+
 static int grid_for(u64 tiles, int cap_blocks) {
   if (tiles == 0) return 1;
   return int(tiles < u64(cap_blocks) ? tiles : u64(cap_blocks));

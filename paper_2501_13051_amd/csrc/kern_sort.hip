@@ -108,19 +108,30 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     s_tstart[d] = tstart;
     u64 excl = 0;
     if (tile > 0) {
-      // walk this digit's chain back to the nearest inclusive prefix
+      // walk this digit's chain back to the nearest inclusive prefix, reading
+      // a window of kWin predecessor tiles per round trip (rows of the status
+      // array are contiguous over digits, so the loads coalesce)
+      constexpr int kWin = 16;
       long long t = (long long)tile - 1;
       for (;;) {
-        u64 wd, f;
-        for (;;) {
-          wd = atomic_load_u64(status + u64(t) * kRadix + d);
-          f = lb_flag(wd, epoch);
-          if (f) break;
-          __builtin_amdgcn_s_sleep(1);
+        u64 wd[kWin];
+#pragma unroll
+        for (int j = 0; j < kWin; ++j)
+          wd[j] = (t - j >= 0) ? atomic_load_u64(status + u64(t - j) * kRadix + d) : lb_word(epoch, kFlagPrefix, 0);
+        bool done = false;
+        int j = 0;
+        for (; j < kWin; ++j) {
+          u64 f = lb_flag(wd[j], epoch);
+          while (f == 0) {                       // not published yet: wait for this one
+            __builtin_amdgcn_s_sleep(1);
+            wd[j] = atomic_load_u64(status + u64(t - j) * kRadix + d);
+            f = lb_flag(wd[j], epoch);
+          }
+          excl += wd[j] & kValueMask;
+          if (f == kFlagPrefix) { done = true; break; }
         }
-        excl += wd & kValueMask;
-        if (f == kFlagPrefix) break;
-        --t;
+        if (done) break;
+        t -= kWin;
       }
       atomic_store_u64(st, lb_word(epoch, kFlagPrefix, excl + tcount));
     }
@@ -169,10 +180,10 @@ int launch_fill_u64(u64* p, u64 n, u64 v, void* stream) {
   return int(hipGetLastError());
 }
 
-int launch_rs_hist(const SortParams& p, void* stream) {
+int launch_rs_hist(const SortParams& p, void* stream, bool clear_hist) {
   const u32 passes = (p.bits + kRadixBits - 1) / kRadixBits;
   if (passes == 0) return 0;
-  launch_fill_u32(p.hist, u64(passes) * kRadix, 0u, stream);
+  if (clear_hist) launch_fill_u32(p.hist, u64(passes) * kRadix, 0u, stream);
   const u64 tiles = (p.cap + kSortTile - 1) / kSortTile;
   const int hgrid = int(tiles == 0 ? 1 : (tiles > 1024 ? 1024 : tiles));
   hipLaunchKernelGGL(k_rs_hist, dim3(hgrid), dim3(kBlock), 0, (hipStream_t)stream, p.a, p.n_ctr, p.n_const,

@@ -226,3 +226,186 @@ def complete_dag(n: int) -> list[np.ndarray]:
 
 def star(k: int) -> list[np.ndarray]:
     return _cols([(0, j) for j in range(1, k + 1)])
+
+
+# ---------------------------------------------------------------- points-to
+# Inclusion-based (Andersen-style) alias analysis, written from the
+# context-free-language formulation of Zheng and Rugina ("Demand-driven alias
+# analysis for C", POPL 2008):  value flow F ::= (assign M?)*,  memory alias
+# M ::= deref^-1 V deref,  value alias V ::= F^-1 M? F.
+# assign(a, b) is the statement a = b (the value of b flows into a);
+# dereference(p, l) says l is the memory expression *p.
+POINTSTO_PROGRAM = """
+valueFlow(x, x) :- assign(x, _).
+valueFlow(x, x) :- assign(_, x).
+valueFlow(b, a) :- assign(a, b).
+valueFlow(u, w) :- assign(v, u), memoryAlias(v, w).
+valueFlow(x, z) :- valueFlow(x, y), valueFlow(y, z).
+memoryAlias(l, m) :- dereference(p, l), valueAlias(p, q), dereference(q, m).
+valueAlias(p, q) :- valueFlow(v, p), valueFlow(v, q).
+valueAlias(p, q) :- valueFlow(u, p), memoryAlias(u, w), valueFlow(w, q).
+"""
+
+
+def zipf_sources(n_nodes: int, n_edges: int, s: float, rng: SplitMix64) -> np.ndarray:
+    """Edge sources whose out-degrees follow Zipf's law with exponent s over
+    a random ranking of the nodes: the node of rank k is drawn with
+    probability proportional to k^-s (many nodes get no edge at all)."""
+    rank_of = np.argsort(rng.take(n_nodes), kind="stable")      # random permutation
+    w = 1.0 / np.arange(1, n_nodes + 1, dtype=np.float64) ** s
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    u = rng.unit(n_edges)
+    r = np.minimum(np.searchsorted(cdf, u, side="right"), n_nodes - 1)
+    return rank_of[r]
+
+
+def pointsto_graph(n_nodes: int = 200_000, n_assign: int = 400_000, n_deref: int = 100_000,
+                   s: float = 1.5, seed: int = 1003) -> dict:
+    """assign: n_assign distinct non-loop edges (a, b), sources a with Zipf
+    out-degrees, targets b uniform over the nodes.  dereference: n_deref
+    edges from uniformly drawn pointer nodes to fresh location nodes (ids
+    n_nodes ..), one location per edge."""
+    rng = SplitMix64(seed)
+    seen, out = set(), []
+    while len(out) < n_assign:
+        need = n_assign - len(out)
+        a = zipf_sources(n_nodes, 2 * need + 64, s, rng)
+        b = rng.below(n_nodes, 2 * need + 64)
+        for x, y in zip(a.tolist(), b.tolist()):
+            if x == y or (x, y) in seen:
+                continue
+            seen.add((x, y))
+            out.append((x, y))
+            if len(out) == n_assign:
+                break
+    ptr = rng.below(n_nodes, n_deref)
+    loc = np.arange(n_nodes, n_nodes + n_deref, dtype=np.int64)
+    return {"assign": _cols(out), "dereference": _cols(np.stack([ptr, loc], axis=1))}
+
+
+def config_pointsto(seed: int = 1003, scale: float = 1.0) -> Workload:
+    """Andersen-style points-to over a power-law assignment graph of 200,000
+    nodes / 400,000 edges and 100,000 dereference edges (scale shrinks all
+    three counts together)."""
+    n = max(8, int(200_000 * scale))
+    edb = pointsto_graph(n, int(400_000 * scale), int(100_000 * scale), 1.5, seed)
+    return Workload(name=f"pointsto_n{n}", program=POINTSTO_PROGRAM, edb=edb,
+                    idb=("valueFlow", "valueAlias", "memoryAlias"),
+                    meta={"nodes": n, "assign": int(400_000 * scale), "deref": int(100_000 * scale),
+                          "zipf_s": 1.5, "seed": seed})
+
+
+# ---------------------------------------------------------------- RDFS
+# RDFS entailment over one triple relation t(s, p, o), after the W3C RDF 1.1
+# Semantics entailment patterns (rdfs2, rdfs3, rdfs5, rdfs7, rdfs9, rdfs11)
+# plus the transitive-property rule of OWL 2 RL (prp-trp).  Reserved ids:
+# 0 type, 1 subClassOf, 2 subPropertyOf, 3 domain, 4 range, 5 the class of
+# transitive properties.
+RDF_TYPE, RDFS_SC, RDFS_SP, RDFS_DOM, RDFS_RNG, OWL_TRANS = 0, 1, 2, 3, 4, 5
+RDFS_PROGRAM = """
+t(c, 1, e) :- t(c, 1, d), t(d, 1, e).
+t(p, 2, r) :- t(p, 2, q), t(q, 2, r).
+t(s, q, o) :- t(s, p, o), t(p, 2, q).
+t(s, 0, c) :- t(s, p, o), t(p, 3, c).
+t(o, 0, c) :- t(s, p, o), t(p, 4, c).
+t(s, 0, d) :- t(s, 0, c), t(c, 1, d).
+t(x, p, z) :- t(p, 0, 5), t(x, p, y), t(y, p, z).
+"""
+
+
+def _zipf_pick(n: int, k: int, s: float, rng: SplitMix64, ranked: np.ndarray | None = None) -> np.ndarray:
+    """k draws from n items with P(rank r) proportional to r^-s; `ranked`
+    maps rank -> item (default: a random permutation)."""
+    if ranked is None:
+        ranked = np.argsort(rng.take(n), kind="stable")
+    w = 1.0 / np.arange(1, n + 1, dtype=np.float64) ** s
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    r = np.minimum(np.searchsorted(cdf, rng.unit(k), side="right"), n - 1)
+    return ranked[r]
+
+
+def rdfs_triples(n_triples: int = 20_000_000, class_depth: int = 8, fanout: int = 6,
+                 n_props: int = 200, n_entities: int = 1_700_000, n_trans: int = 10,
+                 trans_share: float = 0.1, trans_tree: int = 256, seed: int = 1005) -> dict:
+    """Synthetic RDFS triple table.
+
+    * classes: a complete `fanout`-ary tree with `class_depth` levels
+      (root = level 0), one subClassOf triple per non-root class;
+    * properties: 8 root properties and three more levels (24, 72, 96
+      properties, 200 in all) under subPropertyOf;
+    * every second property gets a domain and a range class;
+    * n_trans properties are typed as transitive; their triples form random
+      recursive trees of `trans_tree` entities (acyclic, so the closure stays
+      bounded: sum of depths);
+    * each entity gets one type, the class drawn Zipf(1.0) over a random
+      class ranking; the remaining triples draw subject and object Zipf(1.0)
+      over a random entity ranking and the property Zipf(1.0) over the
+      properties in hierarchy order (roots most frequent).
+    Ids: reserved 0..5, properties from 6, then classes, then entities."""
+    rng = SplitMix64(seed)
+    P0 = 6
+    n_classes = (fanout ** class_depth - 1) // (fanout - 1)
+    C0 = P0 + n_props
+    E0 = C0 + n_classes
+    s_, p_, o_ = [], [], []
+
+    def add(s, p, o):
+        s_.append(np.asarray(s, np.int64))
+        p_.append(np.broadcast_to(np.asarray(p, np.int64), np.shape(s)).copy())
+        o_.append(np.asarray(o, np.int64))
+
+    k = np.arange(1, n_classes, dtype=np.int64)
+    add(C0 + k, RDFS_SC, C0 + (k - 1) // fanout)
+    # property hierarchy: levels of 8, 24, 72, 96
+    levels = [8, 24, 72, n_props - 104]
+    parent = np.full(n_props, -1, np.int64)
+    start = 0
+    for lv in range(1, 4):
+        prev_start, prev_n = start, levels[lv - 1]
+        start += prev_n
+        idx = np.arange(start, start + levels[lv])
+        parent[idx] = prev_start + (idx - start) % prev_n
+    child = np.nonzero(parent >= 0)[0]
+    add(P0 + child, RDFS_SP, P0 + parent[child])
+    dprops = np.arange(0, n_props, 2)
+    add(P0 + dprops, RDFS_DOM, C0 + rng.below(n_classes, len(dprops)))
+    add(P0 + dprops, RDFS_RNG, C0 + rng.below(n_classes, len(dprops)))
+    trans = np.arange(n_props - n_trans, n_props)          # deepest properties
+    add(P0 + trans, RDF_TYPE, np.full(n_trans, OWL_TRANS))
+    ent = E0 + np.arange(n_entities, dtype=np.int64)
+    add(ent, RDF_TYPE, C0 + _zipf_pick(n_classes, n_entities, 1.0, rng))
+    used = sum(len(x) for x in s_)
+    rest = n_triples - used
+    n_tr = int(rest * trans_share)
+    per = n_tr // n_trans
+    for j in trans:
+        nodes = rng.below(n_entities, per + 1)              # tree vertices (may repeat: merged nodes)
+        i = np.arange(1, per + 1, dtype=np.int64)
+        i = i[np.arange(len(i)) % trans_tree != 0]          # every trans_tree-th vertex starts a new tree
+        par = i - 1 - rng.below(np.minimum(i % trans_tree, i), len(i))
+        keep = nodes[par] < nodes[i]                        # orient by entity order: acyclic
+        add(E0 + nodes[par][keep], P0 + j, E0 + nodes[i][keep])
+    used = sum(len(x) for x in s_)
+    rest = n_triples - used
+    ents = np.argsort(rng.take(n_entities), kind="stable")
+    props = np.arange(n_props - n_trans)                    # hierarchy order: roots first
+    add(E0 + _zipf_pick(n_entities, rest, 1.0, rng, ents),
+        P0 + _zipf_pick(len(props), rest, 1.0, rng, props),
+        E0 + _zipf_pick(n_entities, rest, 1.0, rng, ents))
+    s = np.concatenate(s_).astype(np.uint32)
+    p = np.concatenate(p_).astype(np.uint32)
+    o = np.concatenate(o_).astype(np.uint32)
+    return {"t": [s, p, o], "ids": {"properties": P0, "classes": C0, "entities": E0,
+                                     "n_classes": n_classes, "max_id": int(E0 + n_entities - 1)}}
+
+
+def config_rdfs(seed: int = 1005, scale: float = 1.0) -> Workload:
+    """RDFS-style reasoning over a 20M-triple synthetic table (scale shrinks
+    the triple and entity counts together; the class and property
+    hierarchies keep their shape)."""
+    d = rdfs_triples(n_triples=int(20_000_000 * scale), n_entities=max(1000, int(1_700_000 * scale)),
+                     seed=seed)
+    return Workload(name=f"rdfs_{int(20_000_000 * scale)}", program=RDFS_PROGRAM, edb={"t": d["t"]},
+                    idb=("t",), meta={"triples": int(20_000_000 * scale), **d["ids"], "seed": seed})

@@ -124,3 +124,19 @@ def test_config_sg_full_size():
     w = W.config_sg()
     got, stats, ref = _check(w.program, w.edb, relations=["sg"])
     assert stats["derived_tuples"] == len(ref["sg"])
+
+
+def test_pointsto_small():
+    w = W.config_pointsto(scale=0.05)
+    _check(w.program, w.edb, relations=list(w.idb))
+
+
+def test_pointsto_full_size():
+    w = W.config_pointsto()
+    got, stats, ref = _check(w.program, w.edb, relations=list(w.idb))
+    assert stats["derived_tuples"] == sum(len(ref[n]) for n in w.idb)
+
+
+def test_rdfs_small():
+    d = W.rdfs_triples(n_triples=60_000, class_depth=5, n_entities=8_000, trans_tree=32, seed=9)
+    _check(W.RDFS_PROGRAM, {"t": d["t"]}, relations=["t"])

@@ -54,7 +54,11 @@ typedef enum {
 
 /* fv_options.flags */
 #define FV_PLAIN      0u   /* count-then-write joins, host loop, one sync per round */
-#define FV_TRACE      4u   /* time each kernel class with HIP events (see fv_profile) */
+#define FV_TRACE      4u   /* time each kernel class with HIP events (see fv_profile);
+                              kernels are then launched one by one, never as a graph */
+#define FV_GRAPH      8u   /* capture the recursive round as a HIP graph and replay it,
+                              recapturing when a buffer grows (needs a stream other than
+                              the legacy null stream; ignored with FV_TRACE) */
 
 /* Device allocator hooks.  dev_alloc returns device memory of at least
  * `bytes` bytes usable on `stream`, or NULL on failure; dev_free releases a
@@ -94,6 +98,8 @@ typedef struct {
   uint64_t derived_tuples;     /* sum over IDB relations of |full| at fixpoint minus loaded facts */
   uint64_t join_output_tuples; /* tuples written by joins before deduplication */
   double ms_total;             /* wall time of fv_run_fixpoint (host clock, stream synchronised) */
+  uint32_t graph_captures;     /* times the recursive round was captured as a HIP graph */
+  uint32_t graph_replays;      /* rounds run by replaying that graph */
 } fv_stats;
 
 /* One kernel class in the profile returned by fv_profile (FV_TRACE only). */

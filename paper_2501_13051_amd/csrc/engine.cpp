@@ -44,11 +44,14 @@ Engine::Engine(const fv_options* opt) {
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
   trace_ = (opt_.flags & FV_TRACE) != 0;
+  // per-kernel event timing needs the kernels launched one by one
+  use_graph_ = !trace_ && (opt_.flags & FV_GRAPH);
 }
 
 Engine::~Engine() {
   // best effort: wait for queued work, then free everything
   if (touched_device_) (void)hipStreamSynchronize(stream_);
+  drop_graph();
   for (auto& R : rels_) {
     for (int c = 0; c < 3; ++c) { release(R.stage[c]); release(R.col[c]); }
     release(R.newk); release(R.newk2); release(R.set);
@@ -67,6 +70,7 @@ Engine::~Engine() {
 // ------------------------------------------------------------------ memory
 Buf Engine::alloc(size_t bytes) {
   touched_device_ = true;
+  ++n_allocs_;
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~size_t(255);
   void* p = nullptr;
@@ -114,17 +118,25 @@ void Engine::launched(int rc, const char* what) { hip(static_cast<hipError_t>(rc
 
 void Engine::sync() { hip(hipStreamSynchronize(stream_), "stream synchronize"); }
 
-u32 Engine::next_epoch(u32 n) {
-  if (epoch_ + n >= kEpochMask) {
-    // epochs wrap: clear every look-back status array so no stale word can match
+// A phase starts by advancing the device epoch base; every look-back launch in
+// the phase takes base + a distinct offset.  After 4000 phases (the 22-bit
+// epoch would wrap after 4096) the status arrays and the base are cleared.
+void Engine::begin_phase() {
+  if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) {
     if (st_a_.p) launched(launch_fill_u64(st_a_.as<u64>(), st_a_.bytes / 8, 0, stream_), "clear status");
     if (st_b_.p) launched(launch_fill_u64(st_b_.as<u64>(), st_b_.bytes / 8, 0, stream_), "clear status");
     if (st_sort_.p) launched(launch_fill_u64(st_sort_.as<u64>(), st_sort_.bytes / 8, 0, stream_), "clear status");
-    epoch_ = 1;
+    launched(launch_fill_u32(epoch_base(), 1, 0u, stream_), "epoch reset");
+    phases_ = 0;
   }
-  const u32 e = epoch_;
-  epoch_ += n;
-  return e;
+  launched(launch_round_prologue(nullptr, 0, nullptr, nullptr, 0, epoch_base(), stream_), "epoch advance");
+  ++phases_;
+  epoch_off_ = 1;
+}
+
+u32 Engine::next_epoch() {
+  if (epoch_off_ >= kEpochStride) throw Error(FV_ENOTSUP, "too many look-back launches in one round");
+  return epoch_off_++;
 }
 
 // ------------------------------------------------------------------ relations and rules
@@ -491,12 +503,15 @@ void Engine::plan_all() {
 }
 
 // ------------------------------------------------------------------ capacity
-void Engine::ensure_capacity() {
-  // look-back status arrays and row-id scratch are sized for the largest launch
+bool Engine::ensure_capacity() {
+  const u64 allocs_before = n_allocs_;
+  // look-back status arrays and row-id scratch are sized for the largest
+  // launch any round can make before capacities change again: a delta is at
+  // most the previous round's new tuples, so new_cap bounds it
   u64 max_probe = 1, max_rows = 1;
   auto plan_probe = [&](const Plan& p, bool initial) {
     const Relation& S = rels_[p.src_rel];
-    const u64 n0 = initial ? S.n_full : S.n_delta;
+    const u64 n0 = initial ? S.n_full : std::max<u64>(S.n_delta, S.new_cap);
     for (size_t k = 0; k < p.steps.size(); ++k) {
       const u64 n = k == 0 ? n0 : inters_[p.steps[k - 1].out_buf].cap;
       max_probe = std::max(max_probe, n);
@@ -513,13 +528,16 @@ void Engine::ensure_capacity() {
       for (u32 c = 0; c < R.arity; ++c) grow(R.col[c], nc * 4, R.n_full * 4);
       R.cap = nc;
     }
-    // hard bound: every slot could be claimed this round, one must stay empty;
-    // performance target: load <= 1/2 at the expected size
-    const u64 expect = R.n_full + std::max<u64>(3 * R.n_delta, 1024);
-    // grow 4x past the target so the rebuild (a re-insert of all of full)
-    // happens a logarithmic number of times
-    const u64 need_set = pow2_at_least(std::max<u64>(need_full + 1, 4 * expect));
-    if (R.set_cap < need_full + 1 || R.set_cap < expect * 3 / 2) {
+    // sized for the expected size at load <= 2/3; a round that still runs out
+    // of slots (bounded probing) is re-run with a larger set.  Growth is 4x
+    // past the target so that the rebuild (a re-insert of all of full)
+    // happens a logarithmic number of times.
+    // expected size after this round: full plus the new-tuple volume the
+    // buffers were sized for (new_cap anticipates 4x the last round)
+    const u64 expect = R.n_full + std::max<u64>({3 * R.n_delta, R.new_cap / 4, R.staged, 1024});
+    const u64 need_set = pow2_at_least(std::max<u64>(R.set_min, 4 * expect));
+    if (R.set_cap < R.set_min || R.set_cap < expect * 3 / 2 || R.set_stale) {
+      R.set_stale = false;
       release(R.set);
       R.set = alloc(need_set * 8);
       R.set_cap = need_set;
@@ -586,6 +604,7 @@ void Engine::ensure_capacity() {
     launched(launch_fill_u64(st_sort_.as<u64>(), nc * 256, 0, stream_), "status clear");
     st_sort_tiles_ = nc;
   }
+  return n_allocs_ != allocs_before;
 }
 
 // ------------------------------------------------------------------ profiling
@@ -622,7 +641,12 @@ void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux
 // kind 3 sort pass / kind 4 hist / kind 5 dedup: ref0 = rows counter, aux = cap or arity
 void Engine::collect_events() {
   if (!trace_) return;
-  for (auto& pe : pending_) {
+  std::vector<PendingEvent> all;
+  all.swap(pending_);
+  const size_t n_eager = all.size();
+  if (graph_replayed_) all.insert(all.end(), graph_events_.begin(), graph_events_.end());
+  for (size_t idx = 0; idx < all.size(); ++idx) {
+    PendingEvent& pe = all[idx];
     float ms = 0;
     hip(hipEventElapsedTime(&ms, pe.a, pe.b), "event elapsed");
     KClass& k = kprof_[pe.cls];
@@ -667,10 +691,12 @@ void Engine::collect_events() {
     }
     k.bytes += bytes;
     k.items += items;
-    ev_pool_.push_back(pe.a);
-    ev_pool_.push_back(pe.b);
+    if (idx < n_eager) {   // events owned by the graph are recorded again by the next replay
+      ev_pool_.push_back(pe.a);
+      ev_pool_.push_back(pe.b);
+    }
   }
-  pending_.clear();
+  graph_replayed_ = false;
 }
 
 // ------------------------------------------------------------------ execution
@@ -702,7 +728,7 @@ void Engine::exec_plan(Plan& p) {
       src.begin_ctr = initial ? nullptr : ctr(c_dbeg0_ + int(ri));
       src.end_ctr = ctr(c_full0_ + int(ri));
       src.cap = S.cap ? S.cap : S.n_full;
-      probe_bound = initial ? S.n_full : S.n_delta;
+      probe_bound = initial ? S.n_full : std::max<u64>(S.n_delta, S.new_cap);
     } else {
       const Inter& I = inters_[p.steps[k - 1].out_buf];
       for (u32 c = 0; c < I.ncols; ++c) pcol[c] = I.col[c].as<u32>();
@@ -769,7 +795,8 @@ void Engine::exec_plan(Plan& p) {
     pp.st_m = st_a_.as<u64>();
     pp.st_t = st_b_.as<u64>();
     pp.ticket = ticket;
-    pp.epoch = next_epoch();
+    pp.epoch_base = epoch_base();
+    pp.epoch_off = next_epoch();
     pp.abort = nullptr;
     pp.fatal = flags + 1;
     const int kp = kclass("join_probe");
@@ -817,6 +844,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   sp.hist = hist_dev_.as<u32>() + size_t(ri) * 8 * 256;
   sp.status = st_sort_.as<u64>();
   sp.ticket = ticket_dev_.as<u32>();
+  sp.epoch_base = epoch_base();
   sp.abort = flags;
   const u32 passes = sort_passes(R.bits);
   const int kh = kclass("sort_hist");
@@ -838,6 +866,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.src.cap = R.new_cap;
   dp.set = R.idb ? R.set.as<u64>() : nullptr;
   dp.set_mask = R.set_cap ? R.set_cap - 1 : 0;
+  dp.set_full = flags + 2;
   for (u32 c = 0; c < R.arity; ++c) {
     dp.cols[c] = R.col[c].as<u32>();
     dp.shift[c] = R.shift[c];
@@ -848,12 +877,18 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.out_delta = ctr(c_delta0_ + ri);
   dp.status = st_a_.as<u64>();
   dp.ticket = ticket_dev_.as<u32>();
-  dp.epoch = next_epoch();
+  dp.epoch_base = epoch_base();
+  dp.epoch_off = next_epoch();
   dp.abort = flags;
   const int kd = kclass("dedup_append");
   ev_begin(kd);
   launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_), "dedup launch");
   ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
+}
+
+void Engine::commit_relation(Relation& R) {
+  const int ri = int(&R - &rels_[0]);
+  u32* flags = flags_dev_.as<u32>();
   CommitParams cp{};
   cp.full_n = ctr(c_full0_ + ri);
   cp.d_begin = ctr(c_dbeg0_ + ri);
@@ -861,6 +896,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   cp.new_count = nullptr;
   cp.derived = ctr(c_derived_);
   cp.abort = flags;
+  cp.abort2 = flags + 2;
   launched(launch_commit(cp, stream_), "commit launch");
 }
 
@@ -878,7 +914,8 @@ void Engine::build_index(Index& ix) {
   p.perm = ix.perm.as<u32>();
   p.status = st_a_.as<u64>();
   p.ticket = ticket_dev_.as<u32>();
-  p.epoch = next_epoch();
+  p.epoch_base = epoch_base();
+  p.epoch_off = next_epoch();
   p.abort = flags_dev_.as<u32>();
   const int kc = kclass("index_build");
   ev_begin(kc);
@@ -911,6 +948,8 @@ void Engine::ingest() {
   ensure_capacity();
   hip(hipMemsetAsync(ctr_dev_.p, 0, size_t(n_ctr_) * 8, stream_), "counter clear");
   hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
+  phases_ = 0;
+  begin_phase();
   for (auto& R : rels_) {
     if (!R.staged) continue;
     const int ri = int(&R - &rels_[0]);
@@ -919,6 +958,8 @@ void Engine::ingest() {
     launched(launch_fill_u64(ctr(c_new0_ + ri), 1, R.staged, stream_), "fill");
     finish_relation(R, false);
   }
+  for (auto& R : rels_)
+    if (R.staged) commit_relation(R);
   read_counters();
   for (auto& R : rels_) {
     const int ri = int(&R - &rels_[0]);
@@ -935,28 +976,125 @@ void Engine::ingest() {
   hip(hipMemsetAsync(ctr_dev_.p, 0, 8, stream_), "derived clear");
 }
 
+// Enqueue one round: prologue (counters, overflow flag, histograms, epoch
+// base), the joins of every plan, sort + difference + merge per derived
+// relation, and the rebuild of indices on derived relations.  `all_plans`
+// keeps plans whose delta is empty (a captured round must not depend on
+// host-side sizes).
+void Engine::emit_round(bool initial, bool all_plans) {
+  launched(launch_round_prologue(ctr(c_reset_begin_), u64(n_ctr_ - c_reset_begin_), flags_dev_.as<u32>(),
+                                 hist_dev_.as<u32>(), hist_dev_.bytes / 4, epoch_base(), stream_),
+           "round prologue");
+  epoch_off_ = 1;
+  if (initial) {
+    for (auto& p : init_plans_) exec_plan(p);
+  } else {
+    for (auto& p : delta_plans_)
+      if (all_plans || rels_[p.src_rel].n_delta > 0) exec_plan(p);
+  }
+  // every relation's difference first, then the commits: a round that runs
+  // out of set space commits nothing
+  for (auto& R : rels_)
+    if (R.used_as_head) finish_relation(R, true);
+  for (auto& R : rels_)
+    if (R.used_as_head) commit_relation(R);
+  build_indices(true);
+}
+
+void Engine::drop_graph() {
+  if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+  if (graph_) (void)hipGraphDestroy(graph_);
+  graph_exec_ = nullptr;
+  graph_ = nullptr;
+  for (auto& pe : graph_events_) { ev_pool_.push_back(pe.a); ev_pool_.push_back(pe.b); }
+  graph_events_.clear();
+}
+
+// Capture one recursive round into a graph.  With tracing, the per-kernel
+// events are captured too; if the runtime refuses that, capture without them.
+bool Engine::capture_round() {
+  drop_graph();
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const bool with_events = trace_ && graph_events_ok_;
+    const bool saved_trace = trace_;
+    if (!with_events) trace_ = false;
+    pending_.clear();
+    bool ok = hipStreamBeginCapture(stream_, hipStreamCaptureModeRelaxed) == hipSuccess;
+    if (ok) {
+      capturing_ = true;
+      try {
+        emit_round(false, true);
+      } catch (const Error&) {
+        ok = false;
+      }
+      capturing_ = false;
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(stream_, &g);
+      ok = ok && e == hipSuccess && g;
+      if (ok) {
+        ok = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0) == hipSuccess;
+        graph_ = g;
+        if (!ok) { (void)hipGraphDestroy(g); graph_ = nullptr; graph_exec_ = nullptr; }
+      } else if (g) {
+        (void)hipGraphDestroy(g);
+      }
+    }
+    trace_ = saved_trace;
+    (void)hipGetLastError();
+    if (ok) {
+      graph_events_.swap(pending_);
+      pending_.clear();
+      graph_dirty_ = false;
+      ++graph_captures_;
+      return true;
+    }
+    for (auto& pe : pending_) { ev_pool_.push_back(pe.a); ev_pool_.push_back(pe.b); }
+    pending_.clear();
+    if (!with_events) break;
+    graph_events_ok_ = false;
+  }
+  return false;
+}
+
 void Engine::run_round(bool initial) {
   for (;;) {
-    ensure_capacity();
-    launched(launch_round_prologue(ctr(c_reset_begin_), u64(n_ctr_ - c_reset_begin_), flags_dev_.as<u32>(),
-                                   hist_dev_.as<u32>(), hist_dev_.bytes / 4, stream_), "round prologue");
-    // an index whose storage grew holds nothing yet: rebuild it over the
-    // current full relation before any join reads it
-    for (auto& ix : indices_)
-      if (ix.dirty) build_index(ix);
-    if (initial) {
-      for (auto& p : init_plans_) exec_plan(p);
-    } else {
-      for (auto& p : delta_plans_)
-        if (rels_[p.src_rel].n_delta > 0) exec_plan(p);
+    if (ensure_capacity()) graph_dirty_ = true;
+    if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) graph_dirty_ = true;
+    bool any_dirty = false;
+    for (auto& ix : indices_) any_dirty = any_dirty || ix.dirty;
+    if (any_dirty) {
+      // an index whose storage grew holds nothing yet: rebuild it over the
+      // current full relation before any join reads it
+      begin_phase();
+      for (auto& ix : indices_)
+        if (ix.dirty) build_index(ix);
     }
-    for (auto& R : rels_)
-      if (R.used_as_head) finish_relation(R, true);
-    build_indices(true);
+    if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) begin_phase();   // clears status arrays
+    bool replayed = false;
+    if (!initial && use_graph_) {
+      if (graph_dirty_ || !graph_exec_) {
+        if (!capture_round()) use_graph_ = false;
+      }
+      if (use_graph_) {
+        hip(hipGraphLaunch(graph_exec_, stream_), "graph launch");
+        replayed = true;
+        ++graph_replays_;
+      }
+    }
+    if (!replayed) emit_round(initial, false);
+    ++phases_;
+    graph_replayed_ = replayed;
     read_counters();
-    if (!flags_host_[0]) break;
-    // a buffer overflowed: grow whatever was short and run the round again
+    if (!flags_host_[0] && !flags_host_[2]) break;
     ++redo_;
+    if (flags_host_[2]) {
+      // a tuple set ran out of slots: the round committed nothing, but its
+      // difference passes may have inserted keys; rebuild every set, larger
+      for (auto& R : rels_)
+        if (R.used_as_head) { R.set_min = 2 * std::max<u64>(R.set_cap, 1); R.set_stale = true; }
+      graph_dirty_ = true;
+    }
+    // a buffer overflowed: grow whatever was short and run the round again
     for (auto& R : rels_) {
       if (!R.used_as_head) continue;
       const u64 need = ctr_host_[c_new0_ + int(&R - &rels_[0])];
@@ -1007,6 +1145,7 @@ void Engine::run(fv_stats* stats) {
   hip(hipHostMalloc(reinterpret_cast<void**>(&flags_host_), 16, hipHostMallocDefault), "pinned alloc");
   ingest();
   ensure_capacity();
+  begin_phase();
   build_indices(false);
   deltas_.clear();
   run_round(true);
@@ -1021,6 +1160,8 @@ void Engine::run(fv_stats* stats) {
     stats->derived_tuples = derived;
     stats->join_output_tuples = join_out_;
     stats->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    stats->graph_captures = graph_captures_;
+    stats->graph_replays = graph_replays_;
   }
 }
 
@@ -1058,7 +1199,9 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
     sp.hist = hist_dev_.as<u32>();
     sp.status = st_sort_.as<u64>();
     sp.ticket = ticket_dev_.as<u32>();
+    sp.epoch_base = epoch_base();
     sp.abort = nullptr;
+    begin_phase();
     launched(launch_rs_hist(sp, stream_), "hist launch");
     u64* s = sp.a;
     u64* d = sp.b;

@@ -57,6 +57,8 @@ struct Relation {
   // tuple set of full, for the difference operator
   Buf set;
   u64 set_cap = 0;
+  u64 set_min = 0;           // lower bound on the next set size (after a set-full round)
+  bool set_stale = false;    // holds keys of an aborted round: rebuild before the next one
   u32 width[3] = {0, 0, 0}, shift[3] = {0, 0, 0}, bits = 0;
   u32 exp_shift[3] = {0, 0, 0};   // lexicographic packing for export
   // host mirrors of device counters (valid after each sync)
@@ -153,7 +155,7 @@ class Engine {
   Plan plan_rule(u32 rule, int delta_pos);
   u32 get_index(u32 rel, u32 nkey, const u32* keycol);
   void ingest();
-  void ensure_capacity();
+  bool ensure_capacity();   // true if any buffer was reallocated
   void build_indices(bool idb_only);
   void build_index(Index& ix);
 
@@ -161,8 +163,13 @@ class Engine {
   void run_round(bool initial);
   void exec_plan(Plan& p);
   void finish_relation(Relation& R, bool in_round);
+  void commit_relation(Relation& R);
   void read_counters();
-  u32 next_epoch(u32 n = 1);
+  u32 next_epoch();
+  void begin_phase();
+  void emit_round(bool initial, bool all_plans);
+  bool capture_round();
+  void drop_graph();
 
   // profiling
   int kclass(const char* name);
@@ -171,6 +178,7 @@ class Engine {
   void collect_events();
 
   u64* ctr(int i) { return ctr_dev_.as<u64>() + i; }
+  u32* epoch_base() { return flags_dev_.as<u32>() + 3; }
 
   fv_options opt_{};
   hipStream_t stream_ = nullptr;
@@ -194,7 +202,19 @@ class Engine {
   u64 m_cap_ = 0;
   Buf st_a_, st_b_, st_sort_;
   u64 st_cap_ = 0, st_sort_tiles_ = 0;
-  u32 epoch_ = 1;
+  u32 epoch_off_ = 1;     // next look-back offset within the current phase
+  u64 phases_ = 0;        // epoch-base advances since the status arrays were cleared
+  // captured recursive round
+  bool use_graph_ = true;
+  bool graph_dirty_ = true;
+  bool graph_events_ok_ = true;
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t graph_exec_ = nullptr;
+  bool capturing_ = false;
+  bool graph_replayed_ = false;
+  u32 graph_captures_ = 0, graph_replays_ = 0;
+  u64 n_allocs_ = 0;
+  std::vector<PendingEvent> graph_events_;
 
   std::vector<u64> deltas_;
   u32 redo_ = 0;

@@ -61,19 +61,25 @@ __device__ __forceinline__ u64 index_insert(Slot* tab, u64 mask, u64 key) {
   }
 }
 
-// Tuple set insert-if-absent over 8-byte slots; true if the key was new.
-__device__ __forceinline__ bool set_insert(u64* tab, u64 mask, u64 key) {
+// Tuple set insert-if-absent over 8-byte slots.  Returns 1 if the key was
+// new, 0 if present, -1 if kMaxProbe slots were all taken (the table is too
+// full; the caller flags it and the host grows the set).  Slots only ever go
+// from empty to a key, so a plain (possibly stale) load can only mislead
+// towards "empty", which the CAS then corrects.
+constexpr u32 kMaxProbe = 1u << 12;
+__device__ __forceinline__ int set_insert(u64* tab, u64 mask, u64 key) {
   u64 h = mix64(key) & mask;
-  for (;;) {
-    u64 cur = atomic_load_u64(&tab[h]);
-    if (cur == key) return false;
+  for (u32 i = 0; i < kMaxProbe; ++i) {
+    const u64 cur = tab[h];
+    if (cur == key) return 0;
     if (cur == kEmptyKey) {
-      u64 prev = atomic_cas_u64(&tab[h], kEmptyKey, key);
-      if (prev == kEmptyKey) return true;
-      if (prev == key) return false;
+      const u64 prev = atomic_cas_u64(&tab[h], kEmptyKey, key);
+      if (prev == kEmptyKey) return 1;
+      if (prev == key) return 0;
     }
     h = (h + 1) & mask;
   }
+  return -1;
 }
 
 __device__ __forceinline__ bool set_contains(const u64* __restrict__ tab, u64 mask, u64 key) {
@@ -174,13 +180,20 @@ __device__ __forceinline__ u64 lookback_exclusive(const u64* status, u32 tile, u
 }
 
 // Ticket-ordered tile loop: blocks take tiles in increasing order so that a
-// tile's predecessors are always owned by running blocks.  The block that
-// makes the very last increment (each block makes exactly one failing one)
+// tile's predecessors are always owned by running blocks.  Only the first
+// min(gridDim.x, ntiles) blocks participate (the others leave at once, so a
+// grid sized for the buffer capacity costs nothing when the input is small);
+// each participant makes exactly one failing increment, and the last of those
 // resets the counter for the next launch.
+__device__ __forceinline__ u32 participants(u32 ntiles) {
+  const u32 p = ntiles < gridDim.x ? ntiles : gridDim.x;
+  return p ? p : 1u;
+}
+
 __device__ __forceinline__ u32 take_ticket(u32* ticket, u32 ntiles, u32* lds_slot) {
   if (threadIdx.x == 0) {
     u32 t = atomicAdd(ticket, 1u);
-    if (t >= ntiles && t == ntiles + gridDim.x - 1) atomicExch(ticket, 0u);
+    if (t >= ntiles && t == ntiles + participants(ntiles) - 1) atomicExch(ticket, 0u);
     *lds_slot = t;
   }
   __syncthreads();
@@ -190,6 +203,8 @@ __device__ __forceinline__ u32 take_ticket(u32* ticket, u32 ntiles, u32* lds_slo
 }
 
 __device__ __forceinline__ u64 min_u64(u64 a, u64 b) { return a < b ? a : b; }
+
+__device__ __forceinline__ u32 launch_epoch(const u32* base, u32 off) { return (*base + off) & kEpochMask; }
 
 // Number of rows of a source: min(counter, capacity) minus its begin offset.
 __device__ __forceinline__ void source_range(const RowRange& r, u64& begin, u64& n) {

@@ -13,6 +13,11 @@ using u64 = uint64_t;
 
 constexpr u64 kEmptyKey = ~0ull;         // empty hash slot (0xFFFFFFFF is a reserved value)
 constexpr u32 kEpochMask = (1u << 22) - 1;
+// Each phase of work (a round, an ingest, an index build) first advances a
+// device-resident epoch base by kEpochStride; a look-back launch inside the
+// phase uses base + its own offset (1 .. kEpochStride-1), so replaying a
+// captured graph never meets status words of an earlier replay.
+constexpr u32 kEpochStride = 1024;
 constexpr int kMaxCols = 6;              // columns of an intermediate result
 constexpr int kMaxFilters = 8;
 
@@ -81,7 +86,8 @@ struct ProbeParams {
   u64* st_m;             // look-back status arrays
   u64* st_t;
   u32* ticket;
-  u32 epoch;
+  const u32* epoch_base;
+  u32 epoch_off;
   const u32* abort;
   u32* fatal;
 };
@@ -120,6 +126,7 @@ struct DedupParams {
   RowRange src;          // [0, n)
   u64* set;              // tuple set of full (null: only drop adjacent repeats)
   u64 set_mask;
+  u32* set_full;         // raised (with the overflow flag) when an insert finds no slot
   u32* cols[3];          // full columns to append to
   const u64* full_n;     // append position
   u32 arity;
@@ -128,7 +135,8 @@ struct DedupParams {
   u64* out_delta;        // survivors
   u64* status;
   u32* ticket;
-  u32 epoch;
+  const u32* epoch_base;
+  u32 epoch_off;
   const u32* abort;
 };
 
@@ -139,6 +147,7 @@ struct CommitParams {
   u64* new_count;
   u64* derived;          // running total of appended tuples
   const u32* abort;
+  const u32* abort2;
 };
 
 // ------------------------------------------------------------------ launchers
@@ -149,7 +158,9 @@ int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream);
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream);
 int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream);
 int launch_commit(const CommitParams& p, void* stream);
-int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, void* stream);
+// Zero n_ctr counters, n_hist histogram words and (if flag) the overflow and
+// set-full flags (flag[0], flag[2]), and advance the epoch base by kEpochStride.
+int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base, void* stream);
 
 // LSD radix sort of n packed u64 keys (n from *n_ctr clamped to cap, or
 // n_const) on the low `bits` bits, 8 bits per pass: launch_rs_hist counts the
@@ -164,10 +175,11 @@ struct SortParams {
   u32* hist;             // [passes][256] scratch, cleared by launch_rs_hist
   u64* status;           // [tiles][256] look-back words
   u32* ticket;
+  const u32* epoch_base;
   const u32* abort;
 };
 int launch_rs_hist(const SortParams& p, void* stream, bool clear_hist = true);
-int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch, void* stream);
+int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch_off, void* stream);
 inline u32 sort_passes(u32 bits) { return (bits + 7) / 8; }
 constexpr u32 kSortTile = 2048;
 
@@ -183,7 +195,8 @@ struct IndexParams {
   u32* perm;
   u64* status;
   u32* ticket;
-  u32 epoch;
+  const u32* epoch_base;
+  u32 epoch_off;
   const u32* abort;
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);

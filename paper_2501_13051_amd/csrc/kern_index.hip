@@ -45,7 +45,9 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
   __shared__ u32 s_c[kBlock / kWave + 1];
   __shared__ u64 s_excl;
   if (p.abort && *p.abort) return;
+  const u32 epoch = launch_epoch(p.epoch_base, p.epoch_off);
   const u32 ntiles = u32((p.cap + kScanTile - 1) / kScanTile);
+  if (blockIdx.x >= participants(ntiles)) return;
   for (;;) {
     const u32 tile = take_ticket(p.ticket, ntiles, &s_ticket);
     if (tile >= ntiles) break;
@@ -61,15 +63,15 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
     const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
     if (tile == 0) {
       if (threadIdx.x == 0) {
-        atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, tot));
+        atomic_store_u64(p.status + tile, lb_word(epoch, kFlagPrefix, tot));
         s_excl = 0;
       }
     } else {
-      if (threadIdx.x == 0) atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagAgg, tot));
+      if (threadIdx.x == 0) atomic_store_u64(p.status + tile, lb_word(epoch, kFlagAgg, tot));
       if (threadIdx.x < kWave) {
-        const u64 e = lookback_exclusive(p.status, tile, p.epoch);
+        const u64 e = lookback_exclusive(p.status, tile, epoch);
         if (threadIdx.x == 0) {
-          atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, e + tot));
+          atomic_store_u64(p.status + tile, lb_word(epoch, kFlagPrefix, e + tot));
           s_excl = e;
         }
       }
@@ -165,7 +167,7 @@ __global__ void k_set_rows(PackArgs a, u64 n, u64* set, u64 mask) {
   for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x) {
     u64 k = 0;
     for (u32 c = 0; c < a.arity; ++c) k |= u64(a.cols[c][i]) << a.shift[c];
-    set_insert(set, mask, k);
+    (void)set_insert(set, mask, k);
   }
 }
 

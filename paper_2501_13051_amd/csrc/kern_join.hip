@@ -55,6 +55,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
   if (ntiles == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) { *p.out_m = 0; *p.out_t = 0; }
   }
+  if (blockIdx.x >= participants(ntiles)) return;
+  const u32 epoch = launch_epoch(p.epoch_base, p.epoch_off);
   u64 nbuild = 0;
   if (p.nkey == 0) nbuild = p.build_rows_ctr ? min_u64(*p.build_rows_ctr, p.build_cap) : p.build_rows;
 
@@ -98,21 +100,21 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
     const int w = threadIdx.x / kWave;
     if (tile == 0) {
       if (threadIdx.x == 0) {
-        atomic_store_u64(p.st_m + tile, lb_word(p.epoch, kFlagPrefix, mtot));
-        atomic_store_u64(p.st_t + tile, lb_word(p.epoch, kFlagPrefix, ttot));
+        atomic_store_u64(p.st_m + tile, lb_word(epoch, kFlagPrefix, mtot));
+        atomic_store_u64(p.st_t + tile, lb_word(epoch, kFlagPrefix, ttot));
         s_excl[0] = 0;
         s_excl[1] = 0;
       }
     } else {
       if (threadIdx.x == 0) {
-        atomic_store_u64(p.st_m + tile, lb_word(p.epoch, kFlagAgg, mtot));
-        atomic_store_u64(p.st_t + tile, lb_word(p.epoch, kFlagAgg, ttot));
+        atomic_store_u64(p.st_m + tile, lb_word(epoch, kFlagAgg, mtot));
+        atomic_store_u64(p.st_t + tile, lb_word(epoch, kFlagAgg, ttot));
       }
       if (w < 2) {
         u64* st_arr = w == 0 ? p.st_m : p.st_t;
-        const u64 ex = lookback_exclusive(st_arr, tile, p.epoch);
+        const u64 ex = lookback_exclusive(st_arr, tile, epoch);
         if (lane_id() == 0) {
-          atomic_store_u64(st_arr + tile, lb_word(p.epoch, kFlagPrefix, ex + (w == 0 ? u64(mtot) : ttot)));
+          atomic_store_u64(st_arr + tile, lb_word(epoch, kFlagPrefix, ex + (w == 0 ? u64(mtot) : ttot)));
           s_excl[w] = ex;
         }
       }
@@ -282,8 +284,10 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 fbase = *p.full_n;
+  const u32 epoch = launch_epoch(p.epoch_base, p.epoch_off);
   const u32 ntiles = u32((n + kDedupTile - 1) / kDedupTile);
   if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) *p.out_delta = 0;
+  if (blockIdx.x >= participants(ntiles)) return;
   for (;;) {
     const u32 tile = take_ticket(p.ticket, ntiles, &s_ticket);
     if (tile >= ntiles) break;
@@ -299,7 +303,13 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
       if (r < n) {
         key[k] = p.keys[begin + r];
         const bool first = (r == 0) || (p.keys[begin + r - 1] != key[k]);
-        surv[k] = first && (p.set ? set_insert(p.set, p.set_mask, key[k]) : true);
+        if (first && p.set) {
+          const int ins = set_insert(p.set, p.set_mask, key[k]);
+          if (ins < 0) *p.set_full = 1;   // never the flag this kernel checks on entry
+          surv[k] = ins > 0;
+        } else {
+          surv[k] = first;
+        }
       }
       mine += surv[k] ? 1u : 0u;
     }
@@ -307,15 +317,15 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
     const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
     if (tile == 0) {
       if (threadIdx.x == 0) {
-        atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, tot));
+        atomic_store_u64(p.status + tile, lb_word(epoch, kFlagPrefix, tot));
         s_excl = 0;
       }
     } else {
-      if (threadIdx.x == 0) atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagAgg, tot));
+      if (threadIdx.x == 0) atomic_store_u64(p.status + tile, lb_word(epoch, kFlagAgg, tot));
       if (threadIdx.x < kWave) {
-        const u64 e = lookback_exclusive(p.status, tile, p.epoch);
+        const u64 e = lookback_exclusive(p.status, tile, epoch);
         if (threadIdx.x == 0) {
-          atomic_store_u64(p.status + tile, lb_word(p.epoch, kFlagPrefix, e + tot));
+          atomic_store_u64(p.status + tile, lb_word(epoch, kFlagPrefix, e + tot));
           s_excl = e;
         }
       }
@@ -338,6 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
 
 __global__ void k_commit(CommitParams p) {
   if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const u64 d = *p.delta;
     const u64 f = *p.full_n;
@@ -350,17 +361,21 @@ __global__ void k_commit(CommitParams p) {
 
 // Start of a round: zero the round's counters, the overflow flag and the
 // radix histograms in one launch.
-__global__ void k_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist) {
+__global__ void k_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base) {
   const u64 i0 = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   const u64 stride = u64(gridDim.x) * blockDim.x;
   for (u64 i = i0; i < n_ctr; i += stride) ctr[i] = 0;
   for (u64 i = i0; i < n_hist; i += stride) hist[i] = 0;
-  if (i0 == 0) *flag = 0;
+  if (i0 == 0) {
+    if (flag) { flag[0] = 0; flag[2] = 0; }
+    *epoch_base += kEpochStride;
+  }
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, void* stream) {
-  hipLaunchKernelGGL(k_round_prologue, dim3(8), dim3(256), 0, (hipStream_t)stream, ctr, n_ctr, flag, hist, n_hist);
+int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base, void* stream) {
+  hipLaunchKernelGGL(k_round_prologue, dim3(8), dim3(256), 0, (hipStream_t)stream, ctr, n_ctr, flag, hist, n_hist,
+                     epoch_base);
   return int(hipGetLastError());
 }
 

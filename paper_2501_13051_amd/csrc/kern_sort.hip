@@ -43,8 +43,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const u64* keys, const u64* 
 
 __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, u64* __restrict__ out,
                                                    const u64* n_ctr, u64 n_const, u64 cap, u32 shift,
-                                                   const u32* hist_p, u64* status, u32* ticket, u32 epoch,
-                                                   const u32* abort) {
+                                                   const u32* hist_p, u64* status, u32* ticket,
+                                                   const u32* epoch_base, u32 epoch_off, const u32* abort) {
   constexpr int kWaves = kBlock / kWave;
   __shared__ u64 s_keys[kSortTile];
   __shared__ u32 s_wcnt[kWaves][kRadix];
@@ -54,6 +54,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
   __shared__ u32 s_scan32[kWaves + 1];
   __shared__ u32 s_ticket;
   if (abort && *abort) return;
+  const u32 epoch = launch_epoch(epoch_base, epoch_off);
   const u64 n = sort_n(n_ctr, n_const, cap);
   const u32 ntiles = u32((n + kSortTile - 1) / kSortTile);
   const int d = threadIdx.x;            // the digit this thread owns in per-digit steps
@@ -64,6 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     u32 tot;
     s_dbase[d] = block_exclusive_sum<kBlock>(hist_p[d], s_scan32, &tot);
   }
+  if (blockIdx.x >= participants(ntiles)) return;
   for (;;) {
     const u32 tile = take_ticket(ticket, ntiles, &s_ticket);
     if (tile >= ntiles) break;
@@ -191,11 +193,11 @@ int launch_rs_hist(const SortParams& p, void* stream, bool clear_hist) {
   return int(hipGetLastError());
 }
 
-int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch, void* stream) {
+int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch_off, void* stream) {
   const u64 tiles = (p.cap + kSortTile - 1) / kSortTile;
   const int pgrid = int(tiles == 0 ? 1 : (tiles > 2048 ? 2048 : tiles));
   hipLaunchKernelGGL(k_rs_pass, dim3(pgrid), dim3(kBlock), 0, (hipStream_t)stream, src, dst, p.n_ctr, p.n_const,
-                     p.cap, pass * kRadixBits, p.hist + pass * kRadix, p.status, p.ticket, epoch & kEpochMask,
+                     p.cap, pass * kRadixBits, p.hist + pass * kRadix, p.status, p.ticket, p.epoch_base, epoch_off,
                      p.abort);
   return int(hipGetLastError());
 }

@@ -23,6 +23,7 @@ STATUS = {0: "FV_OK", -1: "FV_EINVAL", -2: "FV_ENOMEM", -3: "FV_EARITY", -4: "FV
           -5: "FV_ESTATE", -6: "FV_EHIP", -7: "FV_ERESERVED", -8: "FV_ETRUNC", -9: "FV_ENOTSUP"}
 FV_PLAIN = 0
 FV_TRACE = 4
+FV_GRAPH = 8
 
 EXPORTED = ("fv_ctx_create", "fv_ctx_destroy", "fv_last_error", "fv_relation_create", "fv_relation_find",
             "fv_load_columns", "fv_add_rule", "fv_run_fixpoint", "fv_relation_size", "fv_export",
@@ -53,7 +54,8 @@ class Rule(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_uint32), ("redo_rounds", ctypes.c_uint32),
                 ("derived_tuples", ctypes.c_uint64), ("join_output_tuples", ctypes.c_uint64),
-                ("ms_total", ctypes.c_double)]
+                ("ms_total", ctypes.c_double), ("graph_captures", ctypes.c_uint32),
+                ("graph_replays", ctypes.c_uint32)]
 
 
 class KProf(ctypes.Structure):
@@ -62,6 +64,14 @@ class KProf(ctypes.Structure):
 
 
 _lib = None
+_streams = {}
+
+
+def _engine_stream(torch, device):
+    """One default-priority stream per device, reused by every Engine."""
+    if device not in _streams:
+        _streams[device] = torch.cuda.Stream(device=device)
+    return _streams[device]
 
 
 def lib():
@@ -202,7 +212,9 @@ class Engine:
         L = lib()
         self._L = L
         self._device = torch.cuda.current_device()
-        s = stream if stream is not None else torch.cuda.current_stream()
+        # a stream of its own (default priority): the engine captures its
+        # recursive round as a graph, which the legacy null stream cannot do
+        s = stream if stream is not None else _engine_stream(torch, self._device)
         self._stream_obj = s
         opt = Options()
         opt.stream = ctypes.c_void_p(s.cuda_stream)
@@ -276,6 +288,8 @@ class Engine:
             if len(col) != n:
                 raise ValueError("columns differ in length")
             if on_device:
+                if c == 0:   # the columns were produced on the caller's stream
+                    self._stream_obj.wait_stream(torch.cuda.current_stream())
                 t = col.contiguous()
                 if t.element_size() != 4:
                     raise ValueError("device columns must be 32-bit")
@@ -318,7 +332,8 @@ class Engine:
         self._check(self._L.fv_run_fixpoint(self._h, ctypes.byref(st)))
         return {"iterations": st.iterations, "redo_rounds": st.redo_rounds,
                 "derived_tuples": st.derived_tuples, "join_output_tuples": st.join_output_tuples,
-                "ms_total": st.ms_total}
+                "ms_total": st.ms_total, "graph_captures": st.graph_captures,
+                "graph_replays": st.graph_replays}
 
     def size(self, name: str) -> int:
         n = ctypes.c_uint64()

@@ -154,6 +154,22 @@ fv_status fv_add_rule(fv_ctx* ctx, const fv_rule* rule);
  * Errors: FV_ESTATE (already run), FV_ENOTSUP, FV_ENOMEM, FV_EHIP. */
 fv_status fv_run_fixpoint(fv_ctx* ctx, fv_stats* stats);
 
+/* Batched form: evaluate n contexts that hold the same program (same
+ * relations in the same order, same rules), each over its own loaded facts, as
+ * one fixpoint.  Instance k's values are shifted into the id range
+ * [k*stride, (k+1)*stride) of one merged namespace (stride = the power of two
+ * above the largest loaded value), so every join, sort and difference launch
+ * processes all instances at once.  Afterwards each context reports and exports
+ * its own relations exactly as if it had run alone; fv_delta_sizes on an
+ * instance context returns the merged rounds (all instances added up).  The contexts
+ * must live on one device; each must be fresh (not yet run).  The merged
+ * result is shared by the instances and freed with the last of them.
+ * Errors: FV_EINVAL (different programs, empty batch), FV_ESTATE,
+ * FV_ENOTSUP (a rule uses a constant or has a body whose atoms do not share
+ * variables -- then instances could mix -- or n*stride exceeds 2^32-1), plus
+ * those of fv_run_fixpoint. */
+fv_status fv_run_batch(fv_ctx* const* ctxs, uint32_t n, fv_stats* stats);
+
 /* Number of tuples currently in a relation (after the fixpoint: its full
  * version; before: the rows loaded so far, duplicates included). */
 fv_status fv_relation_size(fv_ctx* ctx, fv_rel rel, uint64_t* n_rows);

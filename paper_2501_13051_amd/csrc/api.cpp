@@ -3,6 +3,7 @@
 #include <cstdio>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "engine.h"
 
@@ -79,6 +80,16 @@ fv_status fv_add_rule(fv_ctx* ctx, const fv_rule* rule) {
 
 fv_status fv_run_fixpoint(fv_ctx* ctx, fv_stats* stats) {
   return guarded(ctx, [&] { ctx->eng.run(stats); });
+}
+
+fv_status fv_run_batch(fv_ctx* const* ctxs, uint32_t n, fv_stats* stats) {
+  if (!ctxs || n == 0 || !ctxs[0]) return FV_EINVAL;
+  std::vector<fv::Engine*> es(n);
+  for (uint32_t k = 0; k < n; ++k) {
+    if (!ctxs[k]) return FV_EINVAL;
+    es[k] = &ctxs[k]->eng;
+  }
+  return guarded(ctxs[0], [&] { fv::Engine::run_batch(es.data(), n, stats); });
 }
 
 fv_status fv_relation_size(fv_ctx* ctx, fv_rel rel, uint64_t* n_rows) {

@@ -1129,6 +1129,18 @@ void Engine::run_round(bool initial) {
   deltas_.push_back(total);
 }
 
+void Engine::alloc_control() {
+  if (n_ctr_ < 8) n_ctr_ = 8;
+  ctr_dev_ = alloc(size_t(n_ctr_) * 8);
+  flags_dev_ = alloc(16);
+  ticket_dev_ = alloc(16);
+  hist_dev_ = alloc(std::max<size_t>(rels_.size(), 1) * 8 * 256 * 4);
+  hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
+  hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
+  hip(hipHostMalloc(reinterpret_cast<void**>(&ctr_host_), size_t(n_ctr_) * 8, hipHostMallocDefault), "pinned alloc");
+  hip(hipHostMalloc(reinterpret_cast<void**>(&flags_host_), 16, hipHostMallocDefault), "pinned alloc");
+}
+
 void Engine::run(fv_stats* stats) {
   if (ran_) throw Error(FV_ESTATE, "the fixpoint already ran on this context");
   if (terminal) throw Error(FV_ESTATE, "context is in an error state");
@@ -1136,13 +1148,7 @@ void Engine::run(fv_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   domain_analysis();
   plan_all();
-  ctr_dev_ = alloc(size_t(n_ctr_) * 8);
-  flags_dev_ = alloc(16);
-  ticket_dev_ = alloc(16);
-  hist_dev_ = alloc(rels_.size() * 8 * 256 * 4);
-  hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
-  hip(hipHostMalloc(reinterpret_cast<void**>(&ctr_host_), size_t(n_ctr_) * 8, hipHostMallocDefault), "pinned alloc");
-  hip(hipHostMalloc(reinterpret_cast<void**>(&flags_host_), 16, hipHostMallocDefault), "pinned alloc");
+  alloc_control();
   ingest();
   ensure_capacity();
   begin_phase();
@@ -1177,6 +1183,22 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
   if (n == 0) return;
   for (u32 c = 0; c < R.arity; ++c)
     if (!cols[c]) throw Error(FV_EINVAL, "null output column");
+  if (batch_) {   // this instance's run of the batch result, shifted back to its own ids
+    Engine& M = *batch_->merged;
+    const u64 b = batch_->bounds[rel][inst_];
+    const u32 back = u32(0u - u32(u64(inst_) * batch_->stride));
+    for (u32 c = 0; c < R.arity; ++c) {
+      Buf t = M.alloc(n * 4);
+      M.hip(hipMemcpyAsync(t.p, batch_->cols[rel][c].as<u32>() + b, n * 4, hipMemcpyDeviceToDevice, M.stream_),
+            "slice copy");
+      M.launched(launch_add_u32(t.as<u32>(), n, back, M.stream_), "relabel back");
+      M.hip(hipMemcpyAsync(cols[c], t.p, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           M.stream_), "export copy");
+      M.sync();
+      M.release(t);
+    }
+    return;
+  }
   // shifts already give lexicographic (col0, col1, col2) order: pack, sort, unpack
   Buf a = alloc(n * 8), b = alloc(n * 8);
   Buf tmp[3];
@@ -1226,6 +1248,143 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
   }
   release(a); release(b);
   for (auto& t : tmp) release(t);
+}
+
+}  // namespace fv
+
+namespace fv {
+
+// ------------------------------------------------------------------ batched form
+// Many independent instances of one program, each over its own facts, are
+// evaluated as a single fixpoint: instance k's values are shifted into the
+// id range [k * stride, (k + 1) * stride).  When no rule has constants and
+// every rule body is connected through shared variables, a derived tuple
+// only combines values of one instance, so the union's fixpoint restricted
+// to instance k's range is instance k's fixpoint.  Every operator then runs
+// as one launch over all instances, and an instance whose delta is empty
+// simply contributes no rows.
+void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
+  if (n == 0 || !es || !es[0]) throw Error(FV_EINVAL, "empty batch");
+  Engine& E0 = *es[0];
+  for (u32 k = 0; k < n; ++k) {
+    const Engine& E = *es[k];
+    if (!es[k]) throw Error(FV_EINVAL, "null context in batch");
+    if (E.ran_ || E.terminal) throw Error(FV_ESTATE, "every batched context must be fresh");
+    if (E.rels_.size() != E0.rels_.size() || E.rules_.size() != E0.rules_.size())
+      throw Error(FV_EINVAL, "batched contexts must hold the same program");
+    for (size_t r = 0; r < E.rels_.size(); ++r)
+      if (E.rels_[r].name != E0.rels_[r].name || E.rels_[r].arity != E0.rels_[r].arity)
+        throw Error(FV_EINVAL, "batched contexts must declare the same relations in the same order");
+    for (size_t i = 0; i < E.rules_.size(); ++i) {
+      const RuleR &a = E.rules_[i], &b = E0.rules_[i];
+      auto same_atom = [](const AtomR& x, const AtomR& y) {
+        if (x.rel != y.rel || x.t.size() != y.t.size()) return false;
+        for (size_t c = 0; c < x.t.size(); ++c)
+          if (x.t[c].value != y.t[c].value || x.t[c].is_const != y.t[c].is_const) return false;
+        return true;
+      };
+      bool same = same_atom(a.head, b.head) && a.body.size() == b.body.size() && a.neq == b.neq;
+      for (size_t j = 0; same && j < a.body.size(); ++j) same = same_atom(a.body[j], b.body[j]);
+      if (!same) throw Error(FV_EINVAL, "batched contexts must hold the same rules");
+    }
+  }
+  for (const RuleR& r : E0.rules_) {
+    for (const AtomR* a : {&r.head}) for (auto& t : a->t) if (t.is_const) throw Error(FV_ENOTSUP, "batched rules may not use constants");
+    for (auto& a : r.body) for (auto& t : a.t) if (t.is_const) throw Error(FV_ENOTSUP, "batched rules may not use constants");
+    // body connectivity through shared variables
+    const size_t nb = r.body.size();
+    std::vector<bool> in(nb, false);
+    std::vector<bool> var(kMaxVars, false);
+    in[0] = true;
+    for (auto& t : r.body[0].t) var[t.value] = true;
+    for (bool grew = true; grew;) {
+      grew = false;
+      for (size_t j = 0; j < nb; ++j) {
+        if (in[j]) continue;
+        bool touch = false;
+        for (auto& t : r.body[j].t) touch = touch || var[t.value];
+        if (touch) { in[j] = true; grew = true; for (auto& t : r.body[j].t) var[t.value] = true; }
+      }
+    }
+    for (size_t j = 0; j < nb; ++j)
+      if (!in[j]) throw Error(FV_ENOTSUP, "batched rules need bodies connected through shared variables");
+  }
+  u32 maxv = 0;
+  for (u32 k = 0; k < n; ++k)
+    for (auto& R : es[k]->rels_)
+      for (u32 c = 0; c < R.arity; ++c) maxv = std::max(maxv, R.maxv[c]);
+  const u64 stride = pow2_at_least(u64(maxv) + 1);
+  if (stride * n > 0xFFFFFFFFull) throw Error(FV_ENOTSUP, "batched instances do not fit the 32-bit id space");
+
+  auto B = std::make_shared<BatchResult>();
+  B->merged = std::make_shared<Engine>(&E0.opt_);
+  B->stride = stride;
+  Engine& M = *B->merged;
+  for (auto& R : E0.rels_) M.relation_create(R.name.c_str(), R.arity);
+  // one gather launch per relation concatenates every instance's staged facts
+  std::vector<GatherDesc> desc(n);
+  Buf ddesc = M.alloc(size_t(n) * sizeof(GatherDesc));
+  for (size_t r = 0; r < M.rels_.size(); ++r) {
+    Relation& D = M.rels_[r];
+    u64 total = 0;
+    for (u32 k = 0; k < n; ++k) {
+      const Relation& S = es[k]->rels_[r];
+      desc[k] = GatherDesc{{S.stage[0].as<u32>(), S.stage[1].as<u32>(), S.stage[2].as<u32>()}, S.staged, total,
+                           u32(k * stride), 0};
+      total += S.staged;
+    }
+    if (!total) continue;
+    for (u32 k = 0; k < n; ++k) es[k]->sync();   // instance copies are ordered on their own streams
+    for (u32 c = 0; c < D.arity; ++c) D.stage[c] = M.alloc(total * 4);
+    M.hip(hipMemcpyAsync(ddesc.p, desc.data(), size_t(n) * sizeof(GatherDesc), hipMemcpyHostToDevice, M.stream_),
+          "descriptor copy");
+    u32* outs[3] = {D.stage[0].as<u32>(), D.stage[1].as<u32>(), D.stage[2].as<u32>()};
+    M.launched(launch_gather_relabel(ddesc.as<GatherDesc>(), n, D.arity, outs, M.stream_), "gather");
+    M.sync();   // the descriptor buffer is reused by the next relation
+    D.staged = D.stage_cap = total;
+    D.has_rows = true;
+    for (u32 c = 0; c < D.arity; ++c) D.maxv[c] = u32(stride * n - 1);
+  }
+  M.release(ddesc);
+  M.rules_ = E0.rules_;
+  M.run(stats);
+  B->deltas = M.deltas_;
+
+  // every relation sorted once in the merged id space; instance k's rows are
+  // the run whose first column lies in [k * stride, (k + 1) * stride)
+  Buf bounds = M.alloc((size_t(n) + 1) * 8);
+  B->cols.resize(M.rels_.size());
+  B->bounds.resize(M.rels_.size());
+  for (size_t r = 0; r < M.rels_.size(); ++r) {
+    Relation& R = M.rels_[r];
+    const u64 total = R.n_full;
+    u32* outc[3] = {nullptr, nullptr, nullptr};
+    for (u32 c = 0; c < R.arity; ++c) {
+      B->cols[r].push_back(M.alloc(std::max<u64>(total, 1) * 4));
+      outc[c] = B->cols[r][c].as<u32>();
+    }
+    u64 got = 0;
+    if (total) M.export_rel(u32(r), outc, total, &got, true);
+    B->bounds[r].assign(size_t(n) + 1, 0);
+    M.launched(launch_bounds(outc[0], total, u32(stride), n, bounds.as<u64>(), M.stream_), "bounds");
+    M.hip(hipMemcpyAsync(B->bounds[r].data(), bounds.p, (size_t(n) + 1) * 8, hipMemcpyDeviceToHost, M.stream_),
+          "bounds readback");
+    M.sync();
+  }
+  M.release(bounds);
+  for (u32 k = 0; k < n; ++k) {
+    Engine& E = *es[k];
+    E.batch_ = B;
+    E.inst_ = k;
+    E.ran_ = true;
+    E.deltas_.clear();
+    for (size_t r = 0; r < E.rels_.size(); ++r) {
+      Relation& D = E.rels_[r];
+      for (int c = 0; c < 3; ++c) E.release(D.stage[c]);
+      D.staged = 0;
+      D.n_full = B->bounds[r][k + 1] - B->bounds[r][k];
+    }
+  }
 }
 
 }  // namespace fv

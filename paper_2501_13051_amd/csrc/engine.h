@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -122,6 +123,19 @@ struct PendingEvent {
   u64 aux;
 };
 
+class Engine;
+
+// Result of a batched fixpoint, shared by the instance contexts: every
+// relation sorted lexicographically in the merged id space, plus where each
+// instance's rows start.
+struct BatchResult {
+  std::shared_ptr<Engine> merged;
+  u64 stride = 0;
+  std::vector<std::vector<Buf>> cols;       // [relation][column], owned by `merged`
+  std::vector<std::vector<u64>> bounds;     // [relation][instance + 1]
+  std::vector<u64> deltas;
+};
+
 class Engine {
  public:
   explicit Engine(const fv_options* opt);
@@ -134,7 +148,10 @@ class Engine {
   void run(fv_stats* stats);
   u64 relation_size(u32 rel) const;
   void export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, bool on_device);
-  const std::vector<u64>& delta_sizes() const { return deltas_; }
+  const std::vector<u64>& delta_sizes() const { return batch_ ? batch_->deltas : deltas_; }
+  // Evaluate n contexts holding the same program over their own facts in one
+  // fixpoint (see fv_run_batch).
+  static void run_batch(Engine* const* es, u32 n, fv_stats* stats);
   const std::vector<KClass>& profile() const { return kprof_; }
 
   std::string last_error;
@@ -150,6 +167,7 @@ class Engine {
   void sync();
 
   // setup
+  void alloc_control();
   void domain_analysis();
   void plan_all();
   Plan plan_rule(u32 rule, int delta_pos);
@@ -222,6 +240,8 @@ class Engine {
 
   bool trace_ = false;
   bool touched_device_ = false;
+  std::shared_ptr<BatchResult> batch_;   // set on instance contexts of a batch
+  u32 inst_ = 0;
   std::vector<KClass> kprof_;
   std::vector<PendingEvent> pending_;
   std::vector<hipEvent_t> ev_pool_;

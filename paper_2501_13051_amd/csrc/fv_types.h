@@ -212,6 +212,21 @@ int launch_unpack(const u64* keys, u64 n, u32 arity, const u32* shift, const u32
 int launch_set_insert_rows(const u32* const* cols, u32 arity, const u32* shift, u64 n,
                            u64* set, u64 mask, void* stream);
 
+struct GatherDesc {
+  const u32* src[3];
+  u64 n;
+  u64 dst;
+  u32 add;
+  u32 pad;
+};
+// out[c][d.dst + i] = d.src[c][i] + d.add for every descriptor d (n_src of
+// them, in device memory) and i < d.n.
+int launch_gather_relabel(const GatherDesc* d, u32 n_src, u32 arity, u32* const* out, void* stream);
+// p[i] += delta (mod 2^32) for i < n.
+int launch_add_u32(u32* p, u64 n, u32 delta, void* stream);
+// Instance boundaries of a sorted column (see k_bounds).
+int launch_bounds(const u32* col, u64 n, u32 stride, u32 n_inst, u64* out, void* stream);
+
 constexpr int kBlock = 256;
 
 }  // namespace fv

@@ -198,6 +198,52 @@ int launch_unpack(const u64* keys, u64 n, u32 arity, const u32* shift, const u32
   return int(hipGetLastError());
 }
 
+__global__ void k_add_u32(u32* p, u64 n, u32 delta) {
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x) p[i] += delta;
+}
+
+int launch_add_u32(u32* p, u64 n, u32 delta, void* stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(k_add_u32, dim3(grid_rows(n, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p, n, delta);
+  return int(hipGetLastError());
+}
+
+// out[k] = first position of a sorted column whose value is >= k * stride,
+// for k = 0 .. n_inst (out[n_inst] = n when every value is below n_inst * stride).
+__global__ void k_bounds(const u32* col, u64 n, u32 stride, u32 n_inst, u64* out) {
+  for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k <= n_inst; k += gridDim.x * blockDim.x) {
+    const u64 key = u64(k) * stride;
+    u64 lo = 0, hi = n;
+    while (lo < hi) {
+      const u64 mid = (lo + hi) >> 1;
+      if (u64(col[mid]) < key) lo = mid + 1; else hi = mid;
+    }
+    out[k] = lo;
+  }
+}
+
+int launch_bounds(const u32* col, u64 n, u32 stride, u32 n_inst, u64* out, void* stream) {
+  hipLaunchKernelGGL(k_bounds, dim3((n_inst + 1 + kBlock - 1) / kBlock), dim3(kBlock), 0, (hipStream_t)stream, col,
+                     n, stride, n_inst, out);
+  return int(hipGetLastError());
+}
+
+// Concatenate the rows of many sources into one set of columns, adding a
+// per-source offset to every value (the batched form's id relabelling).
+__global__ void k_gather_relabel(const GatherDesc* d, u32 arity, u32* o0, u32* o1, u32* o2) {
+  const GatherDesc g = d[blockIdx.y];
+  u32* outs[3] = {o0, o1, o2};
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < g.n; i += u64(gridDim.x) * blockDim.x)
+    for (u32 c = 0; c < arity; ++c) outs[c][g.dst + i] = g.src[c][i] + g.add;
+}
+
+int launch_gather_relabel(const GatherDesc* d, u32 n_src, u32 arity, u32* const* out, void* stream) {
+  if (n_src == 0) return 0;
+  hipLaunchKernelGGL(k_gather_relabel, dim3(16, n_src), dim3(kBlock), 0, (hipStream_t)stream, d, arity, out[0],
+                     arity > 1 ? out[1] : nullptr, arity > 2 ? out[2] : nullptr);
+  return int(hipGetLastError());
+}
+
 int launch_set_insert_rows(const u32* const* cols, u32 arity, const u32* shift, u64 n, u64* set, u64 mask,
                            void* stream) {
   if (n == 0) return 0;

@@ -27,7 +27,7 @@ FV_GRAPH = 8
 
 EXPORTED = ("fv_ctx_create", "fv_ctx_destroy", "fv_last_error", "fv_relation_create", "fv_relation_find",
             "fv_load_columns", "fv_add_rule", "fv_run_fixpoint", "fv_relation_size", "fv_export",
-            "fv_delta_sizes", "fv_profile")
+            "fv_delta_sizes", "fv_profile", "fv_run_batch")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -97,6 +97,7 @@ def lib():
         L.fv_export.argtypes = [vp, u32, ctypes.POINTER(vp), u64, ctypes.POINTER(u64), ctypes.c_int]
         L.fv_delta_sizes.argtypes = [vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)]
         L.fv_profile.argtypes = [vp, ctypes.POINTER(KProf), u32, ctypes.POINTER(u32)]
+        L.fv_run_batch.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(Stats)]
         for name in EXPORTED:
             if name not in ("fv_ctx_destroy", "fv_last_error"):
                 getattr(L, name).restype = ctypes.c_int
@@ -330,10 +331,7 @@ class Engine:
     def run(self) -> dict:
         st = Stats()
         self._check(self._L.fv_run_fixpoint(self._h, ctypes.byref(st)))
-        return {"iterations": st.iterations, "redo_rounds": st.redo_rounds,
-                "derived_tuples": st.derived_tuples, "join_output_tuples": st.join_output_tuples,
-                "ms_total": st.ms_total, "graph_captures": st.graph_captures,
-                "graph_replays": st.graph_replays}
+        return _stats_dict(st)
 
     def size(self, name: str) -> int:
         n = ctypes.c_uint64()
@@ -375,6 +373,29 @@ class Engine:
         self._check(self._L.fv_profile(self._h, buf, n.value, ctypes.byref(n)))
         return [{"name": buf[i].name.decode(), "launches": int(buf[i].launches), "ms": float(buf[i].ms),
                  "algo_bytes": float(buf[i].algo_bytes), "items": int(buf[i].items)} for i in range(n.value)]
+
+
+def _stats_dict(st) -> dict:
+    return {"iterations": st.iterations, "redo_rounds": st.redo_rounds,
+            "derived_tuples": st.derived_tuples, "join_output_tuples": st.join_output_tuples,
+            "ms_total": st.ms_total, "graph_captures": st.graph_captures,
+            "graph_replays": st.graph_replays}
+
+
+def run_batch(engines) -> dict:
+    """Evaluate engines holding the same program as one batched fixpoint
+    (fv_run_batch); afterwards each engine exports its own relations."""
+    L = lib()
+    arr = (ctypes.c_void_p * len(engines))(*[e._h for e in engines])
+    st = Stats()
+    rc = L.fv_run_batch(arr, len(engines), ctypes.byref(st))
+    if rc != FV_OK:
+        raise FvError(rc, L.fv_last_error(engines[0]._h).decode())
+    # the merged result frees its memory through the first engine's allocator
+    keep = (engines[0]._opt, getattr(engines[0], "_alloc_cb", None), getattr(engines[0], "_free_cb", None))
+    for e in engines:
+        e._batch_keep = keep
+    return _stats_dict(st)
 
 
 def evaluate(program: str, edb: dict, flags: int = FV_PLAIN, relations=None, device_out: bool = False):

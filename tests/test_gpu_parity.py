@@ -140,3 +140,77 @@ def test_pointsto_full_size():
 def test_rdfs_small():
     d = W.rdfs_triples(n_triples=60_000, class_depth=5, n_entities=8_000, trans_tree=32, seed=9)
     _check(W.RDFS_PROGRAM, {"t": d["t"]}, relations=["t"])
+
+
+def _batch_engines(instances):
+    engines = []
+    for w in instances:
+        e = fv.Engine()
+        for name, cols in w.edb.items():
+            e.relation(name, len(cols))
+        e.relation("path", 2)
+        for name, cols in w.edb.items():
+            e.load(name, cols)
+        e.program(w.program)
+        engines.append(e)
+    return engines
+
+
+@pytest.mark.parametrize("n_inst", [1, 7, 64])
+def test_batched_tc_matches_per_instance_oracle(n_inst):
+    insts = W.batched_tc_instances(n_instances=n_inst, seed=77 + n_inst)
+    engines = _batch_engines(insts)
+    stats = fv.run_batch(engines)
+    total = 0
+    per_round = []
+    for w, e in zip(insts, engines):
+        ref = oracle.evaluate(w.program, w.edb)
+        got = e.export("path")
+        assert np.array_equal(got, ref["path"])
+        assert e.size("path") == len(ref["path"])
+        assert np.array_equal(e.export("edge"), np.unique(np.stack(w.edb["edge"], 1), axis=0))
+        total += len(ref["path"])
+        per_round.append(ref.delta_sizes)
+    merged = engines[0].delta_sizes()
+    for e in engines:
+        e.close()
+    assert stats["derived_tuples"] == total
+    # the merged rounds are the instances' rounds added up
+    width = max(len(d) for d in per_round)
+    summed = [sum(d[r] if r < len(d) else 0 for d in per_round) for r in range(width)]
+    assert stats["iterations"] == width
+    assert merged == summed
+
+
+def test_batched_rejects_constants_and_disconnected_bodies():
+    def mk(prog):
+        e = fv.Engine()
+        e.relation("edge", 2)
+        e.relation("path", 2)
+        e.load("edge", W.chain(4))
+        e.program(prog)
+        return e
+    for prog in ["path(x, y) :- edge(x, y), edge(3, y).", "path(x, y) :- edge(x, z), edge(w, y)."]:
+        es = [mk(prog), mk(prog)]
+        with pytest.raises(fv.FvError) as ei:
+            fv.run_batch(es)
+        assert ei.value.status == "FV_ENOTSUP"
+        for e in es:
+            e.close()
+
+
+def test_batched_config_full_size():
+    insts = W.batched_tc_instances()
+    engines = _batch_engines(insts)
+    stats = fv.run_batch(engines)
+    rng = np.random.default_rng(0)
+    picks = sorted(set(rng.choice(len(insts), 24, replace=False).tolist()) | {0, len(insts) - 1})
+    total = 0
+    for k, (w, e) in enumerate(zip(insts, engines)):
+        if k in picks:
+            ref = oracle.evaluate(w.program, w.edb)
+            assert np.array_equal(e.export("path"), ref["path"]), k
+        total += e.size("path")
+    assert stats["derived_tuples"] == total
+    for e in engines:
+        e.close()

@@ -54,8 +54,14 @@ typedef enum {
 
 /* fv_options.flags */
 #define FV_PLAIN      0u   /* count-then-write joins, host loop, one sync per round */
+#define FV_LEARNED    2u   /* join-cardinality predictor on (fv_options.predictor): buffers are
+                              presized from its predictions and joins run in one pass without
+                              a count pass; a join that overflows its buffer makes the round
+                              re-run with exact count-then-write.  The result is identical. */
 #define FV_TRACE      4u   /* time each kernel class with HIP events (see fv_profile);
                               kernels are then launched one by one, never as a graph */
+#define FV_LOG_JOINS 16u   /* record, per join of every round, its features and true output
+                              size (fv_join_trace): training data for the predictor */
 #define FV_GRAPH      8u   /* capture the recursive round as a HIP graph and replay it,
                               recapturing when a buffer grows (needs a stream other than
                               the legacy null stream; ignored with FV_TRACE) */
@@ -66,12 +72,25 @@ typedef enum {
 typedef void* (*fv_alloc_fn)(size_t bytes, void* stream, void* user);
 typedef void (*fv_free_fn)(void* ptr, void* stream, void* user);
 
+/* Tuning knobs (all zero = defaults).  They change speed and memory, never
+ * the result.  fv_autotune searches them; fv_tuning_load reads a stored choice. */
+typedef struct {
+  uint32_t radix_bits;     /* digit width of the radix sort: 8 or 11 (0: 8) */
+  uint32_t fuse_dedup;     /* 1: the last radix pass takes the difference and appends to full;
+                              0: a separate pass does, keeping each delta sorted (default) */
+  float set_load;          /* load of the tuple set at its expected size, 0.1..0.75 (0: 0.25) */
+  float index_load;        /* load of join-index tables, 0.1..0.75 (0: 0.5) */
+  uint32_t max_blocks;     /* grid cap of the look-back kernels, 256..8192 (0: 2048) */
+} fv_tuning;
+
 typedef struct {
   void* stream;            /* hipStream_t the context runs on; NULL = null stream */
   fv_alloc_fn dev_alloc;   /* optional */
   fv_free_fn dev_free;     /* optional; required when dev_alloc is set */
   void* user;              /* passed through to the hooks */
   uint32_t flags;          /* FV_* flags above */
+  const fv_tuning* tuning; /* optional; copied at fv_ctx_create */
+  const float* predictor;  /* FV_MLP_PARAMS floats (see fv_mlp_train); required by FV_LEARNED */
 } fv_options;
 
 /* A term of an atom: a variable (is_const = 0, value = variable index within
@@ -100,6 +119,10 @@ typedef struct {
   double ms_total;             /* wall time of fv_run_fixpoint (host clock, stream synchronised) */
   uint32_t graph_captures;     /* times the recursive round was captured as a HIP graph */
   uint32_t graph_replays;      /* rounds run by replaying that graph */
+  uint32_t overflows;          /* FV_LEARNED: rounds whose one-pass joins overflowed (re-run exactly) */
+  uint32_t predicted_joins;    /* FV_LEARNED: joins run with a predicted output size */
+  double qerror_median;        /* FV_LEARNED: median of max(m/p, p/m) over those joins (sizes + 1) */
+  double qerror_max;
 } fv_stats;
 
 /* One kernel class in the profile returned by fv_profile (FV_TRACE only). */
@@ -170,6 +193,55 @@ fv_status fv_run_fixpoint(fv_ctx* ctx, fv_stats* stats);
  * those of fv_run_fixpoint. */
 fv_status fv_run_batch(fv_ctx* const* ctxs, uint32_t n, fv_stats* stats);
 
+/* Builds a fresh context holding the program and facts to tune on, created
+ * with the options given (they carry the candidate tuning); NULL on failure.
+ * The tuner runs the context to its fixpoint and destroys it. */
+typedef fv_ctx* (*fv_make_ctx_fn)(const fv_options* opt, void* user);
+
+/* Autotuner.  Coordinate search over fv_tuning: starting from the defaults,
+ * each knob in turn (radix_bits {8,11}, fuse_dedup {0,1}, set_load
+ * {0.25,0.5}, index_load {0.25,0.5}, max_blocks {1024,2048,4096}) is set to
+ * every candidate with the others at their best so far; a candidate is scored
+ * by the median fv_run_fixpoint time of `reps` fresh contexts from make()
+ * (reps 0 means 3).  The winner goes to *best and, if cache_path and key are
+ * set, into a JSON cache file under "<gfx arch>/<key>" (other entries are
+ * kept).  Errors: FV_EINVAL (null arguments, a failed trial or cache write;
+ * fv_global_error() tells which). */
+fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, uint32_t reps,
+                      const char* cache_path, const char* key, fv_tuning* best);
+
+/* Read the tuning fv_autotune stored under key for the current GPU's
+ * architecture.  FV_EINVAL if the file, or the entry, is missing. */
+fv_status fv_tuning_load(const char* cache_path, const char* key, fv_tuning* out);
+
+/* Error text of the last failed call that has no context (fv_autotune,
+ * fv_tuning_load, fv_mlp_*). */
+const char* fv_global_error(void);
+
+/* The join-cardinality predictor: an MLP 8 -> 64 -> 64 -> 1 with ReLU whose
+ * parameters are FV_MLP_PARAMS floats laid out W1[64][8] b1[64] W2[64][64]
+ * b2[64] W3[1][64] b3[1] (row-major, output index first).  Inputs are the
+ * 8 features of a join (see fv_join_trace), scaled by 1/16 before the first
+ * layer; the output predicts log2(1 + join output size) / 16.  X is n x 8
+ * row-major host memory, y has n entries.  These run on the current device. */
+#define FV_MLP_PARAMS 4801u
+
+/* Mean-squared-error loss of the network on (X, y) and its gradient with
+ * respect to every parameter (same layout), in FP32 on the GPU. */
+fv_status fv_mlp_grad(const float* X, const float* y, uint32_t n, const float* params, float* grads,
+                      float* loss);
+
+/* Full-batch training with Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) for
+ * `steps` steps on the GPU.  init != 0 starts from He-uniform weights drawn from
+ * SplitMix64(seed) and zero biases; otherwise from *params.  Writes the
+ * trained parameters to params and the final loss to *loss (nullable). */
+fv_status fv_mlp_train(const float* X, const float* y, uint32_t n, uint32_t steps, float lr, uint64_t seed,
+                       int init, float* params, float* loss);
+
+/* Inference with BF16 weights and activations (round to nearest even) and
+ * FP32 accumulation: yhat[i] for each row of X. */
+fv_status fv_mlp_predict(const float* X, uint32_t n, const float* params, float* yhat);
+
 /* Number of tuples currently in a relation (after the fixpoint: its full
  * version; before: the rows loaded so far, duplicates included). */
 fv_status fv_relation_size(fv_ctx* ctx, fv_rel rel, uint64_t* n_rows);
@@ -186,6 +258,13 @@ fv_status fv_export(fv_ctx* ctx, fv_rel rel, uint32_t* const* cols_out,
  * added out[r] tuples.  *n receives the number of rounds; up to cap entries
  * are written. */
 fv_status fv_delta_sizes(fv_ctx* ctx, uint64_t* out, uint32_t cap, uint32_t* n);
+
+/* Join trace of the last fixpoint (FV_LOG_JOINS or FV_LEARNED): one row of
+ * FV_TRACE_COLS floats per join executed in a round -- the 8 predictor
+ * features, then log2(1 + true output size) / 16, then the predicted output
+ * size (or -1).  Up to cap rows are written to rows; *n receives the count. */
+#define FV_TRACE_COLS 10u
+fv_status fv_join_trace(fv_ctx* ctx, float* rows, uint32_t cap, uint32_t* n);
 
 /* Kernel-class profile of the last fixpoint (FV_TRACE contexts): up to cap
  * entries are written, *n receives the number of classes. */

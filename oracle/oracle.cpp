@@ -194,7 +194,29 @@ struct Parser {
 struct Probe {
   int nkey = 0;
   std::array<int, kMaxArity> perm{};           // permuted position k holds column perm[k]
-  std::vector<Tup> rows;
+  const std::vector<Tup>* rows = nullptr;      // sorted permuted copy (or the source itself when nkey == 0)
+};
+
+// Sorted permuted copies of the sources read in one round, shared by every
+// rule variant of the round (sources do not change within a round).
+struct CopyCache {
+  std::map<std::pair<const std::vector<Tup>*, int>, std::vector<Tup>> copies;
+  const std::vector<Tup>* get(const std::vector<Tup>& src, const std::array<int, kMaxArity>& perm, int arity) {
+    int sig = 0;
+    for (int q = 0; q < arity; ++q) sig = sig * 4 + perm[q];
+    auto key = std::make_pair(&src, sig * 4 + arity);
+    auto it = copies.find(key);
+    if (it != copies.end()) return &it->second;
+    std::vector<Tup>& out = copies[key];
+    out.resize(src.size());
+    for (size_t j = 0; j < src.size(); ++j) {
+      Tup t{};
+      for (int q = 0; q < arity; ++q) t[q] = src[j][perm[q]];
+      out[j] = t;
+    }
+    std::sort(out.begin(), out.end());
+    return &out;
+  }
 };
 
 enum ColKind { kConst, kBound, kFree, kRepeat };
@@ -208,19 +230,23 @@ struct AtomPlan {
   Probe probe;
 };
 
+// Atoms are visited in `order` (a permutation of the body positions); the
+// join is commutative, so any order gives the same tuples.
 struct BodyEval {
   const Rule& r;
   std::vector<AtomPlan> plans;
   std::vector<uint32_t> env;
   std::vector<Tup>* out;
 
-  BodyEval(const Rule& rule, const std::vector<const std::vector<Tup>*>& src, std::vector<Tup>* o)
+  BodyEval(const Rule& rule, const std::vector<const std::vector<Tup>*>& src, const std::vector<size_t>& order,
+           std::vector<Tup>* o, CopyCache& cache)
       : r(rule), plans(rule.body.size()), env(rule.nvars, 0), out(o) {
     std::vector<bool> bound(rule.nvars, false);
     std::vector<bool> neq_done(rule.neq.size(), false);
-    for (size_t i = 0; i < rule.body.size(); ++i) {
+    for (size_t step = 0; step < rule.body.size(); ++step) {
+      const size_t i = order[step];
       const Atom& a = rule.body[i];
-      AtomPlan& p = plans[i];
+      AtomPlan& p = plans[step];
       p.arity = int(a.t.size());
       std::vector<bool> bound_here = bound;
       for (int c = 0; c < p.arity; ++c) {
@@ -243,19 +269,18 @@ struct BodyEval {
           neq_done[k] = true;
           p.neq_here.push_back(rule.neq[k]);
         }
-      // permuted, sorted copy of the source
+      // permuted, sorted copy of the source (an atom with no bound column is
+      // scanned whole, in any order)
       int k = 0;
       for (int c = 0; c < p.arity; ++c) if (p.kind[c] == kConst || p.kind[c] == kBound) p.probe.perm[k++] = c;
       p.probe.nkey = k;
       for (int c = 0; c < p.arity; ++c) if (!(p.kind[c] == kConst || p.kind[c] == kBound)) p.probe.perm[k++] = c;
-      const std::vector<Tup>& s = *src[i];
-      p.probe.rows.resize(s.size());
-      for (size_t j = 0; j < s.size(); ++j) {
-        Tup t{};
-        for (int q = 0; q < p.arity; ++q) t[q] = s[j][p.probe.perm[q]];
-        p.probe.rows[j] = t;
+      if (p.probe.nkey == 0) {
+        for (int c = 0; c < p.arity; ++c) p.probe.perm[c] = c;
+        p.probe.rows = src[i];
+      } else {
+        p.probe.rows = cache.get(*src[i], p.probe.perm, p.arity);
       }
-      std::sort(p.probe.rows.begin(), p.probe.rows.end());
     }
   }
 
@@ -277,12 +302,13 @@ struct BodyEval {
       key[q] = p.kind[c] == kConst ? p.val[c] : env[p.val[c]];
     }
     const int nk = p.probe.nkey;
-    auto lo = std::lower_bound(p.probe.rows.begin(), p.probe.rows.end(), key,
+    const std::vector<Tup>& rows = *p.probe.rows;
+    auto lo = std::lower_bound(rows.begin(), rows.end(), key,
                                [nk](const Tup& a, const Tup& b) {
                                  for (int q = 0; q < nk; ++q) if (a[q] != b[q]) return a[q] < b[q];
                                  return false;
                                });
-    for (auto it = lo; it != p.probe.rows.end(); ++it) {
+    for (auto it = lo; it != rows.end(); ++it) {
       bool same = true;
       for (int q = 0; q < nk; ++q) if ((*it)[q] != key[q]) { same = false; break; }
       if (!same) break;
@@ -300,8 +326,28 @@ struct BodyEval {
   }
 };
 
-void eval_rule(const Rule& r, const std::vector<const std::vector<Tup>*>& src, std::vector<Tup>& out) {
-  BodyEval e(r, src, &out);
+// Evaluate one rule variant: src[i] is the version atom i reads.  The atom
+// reading the delta (first_atom) is visited first; after it, the first atom in
+// written order that shares a variable with those already visited (or, if
+// none does, the first remaining one).
+void eval_rule(const Rule& r, const std::vector<const std::vector<Tup>*>& src, std::vector<Tup>& out,
+               CopyCache& cache, size_t first_atom = 0) {
+  std::vector<size_t> order{first_atom};
+  std::vector<bool> used(r.body.size(), false), bound(r.nvars, false);
+  used[first_atom] = true;
+  for (auto& t : r.body[first_atom].t) if (!t.is_const) bound[t.v] = true;
+  while (order.size() < r.body.size()) {
+    size_t pick = r.body.size();
+    for (size_t i = 0; i < r.body.size() && pick == r.body.size(); ++i) {
+      if (used[i]) continue;
+      for (auto& t : r.body[i].t) if (!t.is_const && bound[t.v]) { pick = i; break; }
+    }
+    for (size_t i = 0; i < r.body.size() && pick == r.body.size(); ++i) if (!used[i]) pick = i;
+    order.push_back(pick);
+    used[pick] = true;
+    for (auto& t : r.body[pick].t) if (!t.is_const) bound[t.v] = true;
+  }
+  BodyEval e(r, src, order, &out, cache);
   e.visit(0);
 }
 
@@ -318,12 +364,13 @@ void run(Ctx& c, bool naive) {
   bool first = true;
   for (;;) {
     std::vector<std::vector<Tup>> fresh(nrel);
+    CopyCache cache;
     for (const Rule& r : c.rules) {
       std::vector<Tup>& out = fresh[r.head.rel];
       if (first || naive) {
         std::vector<const std::vector<Tup>*> src;
         for (auto& a : r.body) src.push_back(&c.rels[a.rel].full);
-        eval_rule(r, src, out);
+        eval_rule(r, src, out, cache);
         continue;
       }
       for (size_t i = 0; i < r.body.size(); ++i) {
@@ -334,7 +381,7 @@ void run(Ctx& c, bool naive) {
           const Relation& Rj = c.rels[r.body[j].rel];
           src.push_back(j < i ? &Rj.full : (j == i ? &Rj.delta : &Rj.old));
         }
-        eval_rule(r, src, out);
+        eval_rule(r, src, out, cache, i);
       }
     }
     uint64_t total = 0;

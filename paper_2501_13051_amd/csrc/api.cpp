@@ -114,6 +114,18 @@ fv_status fv_delta_sizes(fv_ctx* ctx, uint64_t* out, uint32_t cap, uint32_t* n) 
   });
 }
 
+fv_status fv_join_trace(fv_ctx* ctx, float* rows, uint32_t cap, uint32_t* n) {
+  return guarded(ctx, [&] {
+    const auto& t = ctx->eng.join_trace();
+    const uint32_t cols = fv::Engine::kTraceCols;
+    const uint32_t total = uint32_t(t.size() / cols);
+    if (n) *n = total;
+    if (rows)
+      for (uint32_t i = 0; i < cap && i < total; ++i)
+        for (uint32_t c = 0; c < cols; ++c) rows[size_t(i) * cols + c] = t[size_t(i) * cols + c];
+  });
+}
+
 fv_status fv_profile(fv_ctx* ctx, fv_kprof* out, uint32_t cap, uint32_t* n) {
   return guarded(ctx, [&] {
     const auto& k = ctx->eng.profile();

@@ -41,11 +41,25 @@ u32 bits_for(u64 x) {   // number of bits to represent x (x >= 1)
 // ------------------------------------------------------------------ lifetime
 Engine::Engine(const fv_options* opt) {
   if (opt) opt_ = *opt;
+  if (opt_.tuning) tune_ = *opt_.tuning;
+  opt_.tuning = nullptr;
+  if (tune_.radix_bits != 11) tune_.radix_bits = 8;
+  tune_.fuse_dedup = tune_.fuse_dedup ? 1 : 0;
+  if (!(tune_.set_load >= 0.1f && tune_.set_load <= 0.75f)) tune_.set_load = 0.25f;
+  if (!(tune_.index_load >= 0.1f && tune_.index_load <= 0.75f)) tune_.index_load = 0.5f;
+  if (tune_.max_blocks < 256 || tune_.max_blocks > 8192) tune_.max_blocks = 2048;
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
   trace_ = (opt_.flags & FV_TRACE) != 0;
   // per-kernel event timing needs the kernels launched one by one
   use_graph_ = !trace_ && (opt_.flags & FV_GRAPH);
+  learned_ = (opt_.flags & FV_LEARNED) != 0;
+  log_joins_ = learned_ || (opt_.flags & FV_LOG_JOINS) != 0;
+  if (learned_) {
+    if (!opt_.predictor) throw Error(FV_EINVAL, "FV_LEARNED needs fv_options.predictor");
+    predictor_.assign(opt_.predictor, opt_.predictor + kMlpParams);
+  }
+  opt_.predictor = nullptr;
 }
 
 Engine::~Engine() {
@@ -61,6 +75,8 @@ Engine::~Engine() {
   release(ctr_dev_); release(flags_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
   release(m_row_); release(m_start_); release(m_off_);
   release(st_a_); release(st_b_); release(st_sort_);
+  for (auto& sk : sketches_) release(sk.regs);
+  release(predictor_dev_); release(pspec_init_dev_); release(pspec_delta_dev_);
   if (ctr_host_) (void)hipHostFree(ctr_host_);
   if (flags_host_) (void)hipHostFree(flags_host_);
   for (auto e : ev_pool_) (void)hipEventDestroy(e);
@@ -483,17 +499,54 @@ void Engine::plan_all() {
       if (rels_[rules_[ri].body[i].rel].idb) delta_plans_.push_back(plan_rule(ri, int(i)));
   }
   for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
-  // counter layout: [derived, join_out] [full_n x R] [d_begin x R] [delta x R]
-  //                 [new x R] [per-join m,t] [per-intermediate count]
+  // counter layout: [derived, join_out] [full_n x R] [d_begin x R]
+  //   [index distinct keys] [HLL estimates] [predicted join sizes]   (kept across rounds)
+  //   [delta x R] [new x R] [per-join m,t] [per-intermediate count]  (cleared every round)
   const int R = int(rels_.size());
   c_derived_ = 0;
   c_joinout_ = 1;
   c_full0_ = 2;
   c_dbeg0_ = c_full0_ + R;
-  c_delta0_ = c_dbeg0_ + R;
+  int next = c_dbeg0_ + R;
+  c_ndv0_ = next;
+  for (auto& ix : indices_) ix.c_ndv = next++;
+  c_hll0_ = next;
+  sketches_.clear();
+  if (log_joins_) {
+    for (auto* plans : {&init_plans_, &delta_plans_})
+      for (auto& p : *plans) {
+        if (p.steps.empty() || p.steps[0].select_only || p.steps[0].nkey == 0) continue;
+        Step& s0 = p.steps[0];
+        if (s0.key[0].kind != kSrcProbe) continue;
+        const int c1 = (s0.nkey == 2 && s0.key[1].kind == kSrcProbe) ? int(s0.key[1].v) : -1;
+        const bool delta = p.delta_pos >= 0;
+        int found = -1;
+        for (size_t i = 0; i < sketches_.size(); ++i)
+          if (sketches_[i].rel == p.src_rel && sketches_[i].c0 == s0.key[0].v && sketches_[i].c1 == c1 &&
+              sketches_[i].delta == delta)
+            found = int(i);
+        if (found < 0) {
+          HllSketch sk;
+          sk.rel = p.src_rel;
+          sk.c0 = s0.key[0].v;
+          sk.c1 = c1;
+          sk.delta = delta;
+          sk.ctr = next++;
+          sketches_.push_back(sk);
+          found = int(sketches_.size() - 1);
+        }
+        s0.hll = found;
+      }
+  }
+  c_pred0_ = next;
+  for (auto* plans : {&init_plans_, &delta_plans_})
+    for (auto& p : *plans)
+      for (auto& s : p.steps)
+        if (!s.select_only) s.c_pred = next++;
+  c_delta0_ = next;
   c_new0_ = c_delta0_ + R;
   c_reset_begin_ = c_delta0_;
-  int next = c_new0_ + R;
+  next = c_new0_ + R;
   for (auto* plans : {&init_plans_, &delta_plans_})
     for (auto& p : *plans)
       for (auto& s : p.steps)
@@ -535,7 +588,7 @@ bool Engine::ensure_capacity() {
     // expected size after this round: full plus the new-tuple volume the
     // buffers were sized for (new_cap anticipates 4x the last round)
     const u64 expect = R.n_full + std::max<u64>({3 * R.n_delta, R.new_cap / 4, R.staged, 1024});
-    const u64 need_set = pow2_at_least(std::max<u64>(R.set_min, 4 * expect));
+    const u64 need_set = pow2_at_least(std::max<u64>(R.set_min, u64(double(expect) / tune_.set_load)));
     if (R.set_cap < R.set_min || R.set_cap < expect * 3 / 2 || R.set_stale) {
       R.set_stale = false;
       release(R.set);
@@ -558,7 +611,7 @@ bool Engine::ensure_capacity() {
     const Relation& R = rels_[ix.rel];
     const u64 rows = R.used_as_head ? R.n_full + R.new_cap : R.n_full;
     const u64 expect = R.used_as_head ? R.n_full + std::max<u64>(3 * R.n_delta, 1024) : R.n_full;
-    const u64 need = pow2_at_least(std::max<u64>({rows + 1, 2 * expect, 64}));
+    const u64 need = pow2_at_least(std::max<u64>({rows + 1, u64(double(expect) / tune_.index_load), 64}));
     if (ix.cap < rows + 1 || ix.cap < expect * 3 / 2) {
       release(ix.table);
       ix.table = alloc(need * sizeof(Slot));
@@ -600,8 +653,8 @@ bool Engine::ensure_capacity() {
   if (st_sort_tiles_ < stiles) {
     const u64 nc = std::max<u64>(stiles, st_sort_tiles_ * 2);
     release(st_sort_);
-    st_sort_ = alloc(nc * 256 * 8);
-    launched(launch_fill_u64(st_sort_.as<u64>(), nc * 256, 0, stream_), "status clear");
+    st_sort_ = alloc(nc * kMaxRadix * 8);
+    launched(launch_fill_u64(st_sort_.as<u64>(), nc * kMaxRadix, 0, stream_), "status clear");
     st_sort_tiles_ = nc;
   }
   return n_allocs_ != allocs_before;
@@ -677,6 +730,19 @@ void Engine::collect_events() {
       case 4: {   // histogram: read 8 B per key
         const u64 n = std::min<u64>(C(pe.ref0), pe.aux);
         bytes = double(n) * 8;
+        items = n;
+        break;
+      }
+      case 7: {   // one-pass join: key + slot per probe row, row id + gathers + write per output
+        const u64 rows = pe.ref0 >= 0 ? C(pe.ref0) : pe.aux;
+        const u64 t = C(pe.ref1);
+        bytes = double(rows) * 20 + double(t) * 16;
+        items = t;
+        break;
+      }
+      case 6: {   // fused last pass: read key, set probe, column writes of survivors
+        const u64 n = C(pe.ref0), d = C(pe.ref1);
+        bytes = double(n) * 16 + double(d) * 4 * double(pe.aux);
         items = n;
         break;
       }
@@ -770,6 +836,38 @@ void Engine::exec_plan(Plan& p) {
       continue;
     }
     const Relation& B = rels_[s.brel];
+    if (use_fused_) {
+      // presized output: probe and write in one pass
+      FusedJoinParams fp{};
+      for (int c = 0; c < kMaxCols; ++c) fp.pcol[c] = pcol[c];
+      fp.src = src;
+      fp.n_pf = u32(s.pf.size());
+      for (u32 f = 0; f < fp.n_pf; ++f) fp.pf[f] = s.pf[f];
+      fp.nkey = s.nkey;
+      fp.key[0] = s.key[0];
+      fp.key[1] = s.key[1];
+      const Index* fx = s.index != kNoIndex ? &indices_[s.index] : nullptr;
+      if (fx) {
+        fp.table = fx->table.as<Slot>();
+        fp.mask = fx->cap - 1;
+        fp.perm = fx->perm.as<u32>();
+      } else {
+        fp.build_rows_ctr = ctr(c_full0_ + int(s.brel));
+        fp.build_cap = B.cap ? B.cap : B.n_full;
+      }
+      for (u32 c = 0; c < B.arity; ++c) fp.bcol[c] = B.col[c].as<u32>();
+      fp.n_filter = u32(s.wf.size());
+      for (u32 f = 0; f < fp.n_filter; ++f) fp.filt[f] = s.wf[f];
+      fp.out = o;
+      fp.out_t = ctr(s.c_t);
+      fp.join_out_stat = ctr(c_joinout_);
+      fp.overflow = flags;
+      const int kf = kclass("join_onepass");
+      ev_begin(kf);
+      launched(launch_join_fused(fp, std::max<u64>(probe_bound, 1), stream_), "one-pass join launch");
+      ev_end(kf, 0, 7, probe_ctr, s.c_t, probe_bound);
+      continue;
+    }
     ProbeParams pp{};
     for (int c = 0; c < kMaxCols; ++c) pp.pcol[c] = pcol[c];
     pp.src = src;
@@ -841,12 +939,16 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   sp.n_ctr = ctr(c_new0_ + ri);
   sp.cap = R.new_cap;
   sp.bits = R.bits;
-  sp.hist = hist_dev_.as<u32>() + size_t(ri) * 8 * 256;
+  sp.digit_bits = tune_.radix_bits;
+  sp.max_blocks = tune_.max_blocks;
+  sp.hist = hist_dev_.as<u32>() + size_t(ri) * kHistWords;
   sp.status = st_sort_.as<u64>();
   sp.ticket = ticket_dev_.as<u32>();
   sp.epoch_base = epoch_base();
   sp.abort = flags;
-  const u32 passes = sort_passes(R.bits);
+  const u32 passes = sort_passes(R.bits, tune_.radix_bits);
+  // the last radix pass can take the difference itself when there is a set
+  const bool fuse = tune_.fuse_dedup && R.idb && passes > 0;
   const int kh = kclass("sort_hist");
   ev_begin(kh);
   launched(launch_rs_hist(sp, stream_, !in_round), "hist launch");
@@ -854,12 +956,31 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   u64* src = sp.a;
   u64* dst = sp.b;
   const int kpass = kclass("sort_pass");
+  const int kfused = kclass("sort_pass_dedup");
+  SortFuse fz{};
+  if (fuse) {
+    fz.set = R.set.as<u64>();
+    fz.set_mask = R.set_cap - 1;
+    fz.set_full = flags + 2;
+    for (u32 c = 0; c < R.arity; ++c) {
+      fz.cols[c] = R.col[c].as<u32>();
+      fz.shift[c] = R.shift[c];
+      fz.width[c] = R.width[c];
+    }
+    fz.full_n = ctr(c_full0_ + ri);
+    fz.out_delta = ctr(c_delta0_ + ri);
+    fz.arity = R.arity;
+  }
   for (u32 pass = 0; pass < passes; ++pass) {
-    ev_begin(kpass);
-    launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_), "sort pass launch");
-    ev_end(kpass, 0, 3, c_new0_ + ri, -1, R.new_cap);
+    const bool last_fused = fuse && pass + 1 == passes;
+    ev_begin(last_fused ? kfused : kpass);
+    launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_, last_fused ? &fz : nullptr),
+             "sort pass launch");
+    ev_end(last_fused ? kfused : kpass, 0, last_fused ? 6 : 3, c_new0_ + ri, c_delta0_ + ri,
+           last_fused ? R.arity : R.new_cap);
     std::swap(src, dst);
   }
+  if (fuse) return;
   DedupParams dp{};
   dp.keys = src;
   dp.src.end_ctr = ctr(c_new0_ + ri);
@@ -917,6 +1038,7 @@ void Engine::build_index(Index& ix) {
   p.epoch_base = epoch_base();
   p.epoch_off = next_epoch();
   p.abort = flags_dev_.as<u32>();
+  p.ndv = ix.c_ndv >= 0 ? ctr(ix.c_ndv) : nullptr;
   const int kc = kclass("index_build");
   ev_begin(kc);
   launched(launch_index_build(p, std::max<u64>(R.cap, 1), stream_), "index launch");
@@ -999,6 +1121,7 @@ void Engine::emit_round(bool initial, bool all_plans) {
   for (auto& R : rels_)
     if (R.used_as_head) commit_relation(R);
   build_indices(true);
+  if (log_joins_) emit_sketches_and_prediction(false);
 }
 
 void Engine::drop_graph() {
@@ -1045,6 +1168,7 @@ bool Engine::capture_round() {
       graph_events_.swap(pending_);
       pending_.clear();
       graph_dirty_ = false;
+      graph_fused_ = use_fused_;
       ++graph_captures_;
       return true;
     }
@@ -1057,6 +1181,9 @@ bool Engine::capture_round() {
 }
 
 void Engine::run_round(bool initial) {
+  start_ctr_.assign(ctr_host_, ctr_host_ + n_ctr_);
+  use_fused_ = learned_;
+  if (learned_) size_from_predictions(initial);
   for (;;) {
     if (ensure_capacity()) graph_dirty_ = true;
     if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) graph_dirty_ = true;
@@ -1071,6 +1198,7 @@ void Engine::run_round(bool initial) {
     }
     if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) begin_phase();   // clears status arrays
     bool replayed = false;
+    if (graph_exec_ && graph_fused_ != use_fused_) graph_dirty_ = true;
     if (!initial && use_graph_) {
       if (graph_dirty_ || !graph_exec_) {
         if (!capture_round()) use_graph_ = false;
@@ -1087,6 +1215,13 @@ void Engine::run_round(bool initial) {
     read_counters();
     if (!flags_host_[0] && !flags_host_[2]) break;
     ++redo_;
+    if (use_fused_ && flags_host_[0]) {
+      // a presized one-pass join ran out of room: run the round again with
+      // exact count-then-write joins
+      ++overflows_;
+      use_fused_ = false;
+      graph_dirty_ = true;
+    }
     if (flags_host_[2]) {
       // a tuple set ran out of slots: the round committed nothing, but its
       // difference passes may have inserted keys; rebuild every set, larger
@@ -1105,16 +1240,19 @@ void Engine::run_round(bool initial) {
       if (need > I.cap) I.cap = pow2_at_least(std::max<u64>(need + need / 4, I.cap * 2));
     }
   }
-  // size the next round from this one: outputs tend to grow round over round,
-  // and a buffer that overflows costs a whole re-run of the round
-  for (auto& R : rels_) {
-    if (!R.used_as_head) continue;
-    const u64 used = ctr_host_[c_new0_ + int(&R - &rels_[0])];
-    if (4 * used > R.new_cap) R.new_cap = pow2_at_least(4 * used);
-  }
-  for (auto& I : inters_) {
-    const u64 used = ctr_host_[I.ctr];
-    if (4 * used > I.cap) I.cap = pow2_at_least(4 * used);
+  if (log_joins_) log_joins(initial);
+  if (!learned_) {
+    // size the next round from this one: outputs tend to grow round over
+    // round, and a buffer that overflows costs a whole re-run of the round
+    for (auto& R : rels_) {
+      if (!R.used_as_head) continue;
+      const u64 used = ctr_host_[c_new0_ + int(&R - &rels_[0])];
+      if (4 * used > R.new_cap) R.new_cap = pow2_at_least(4 * used);
+    }
+    for (auto& I : inters_) {
+      const u64 used = ctr_host_[I.ctr];
+      if (4 * used > I.cap) I.cap = pow2_at_least(4 * used);
+    }
   }
   u64 total = 0;
   for (auto& R : rels_) {
@@ -1129,12 +1267,147 @@ void Engine::run_round(bool initial) {
   deltas_.push_back(total);
 }
 
+// ------------------------------------------------------------------ learned predictor
+void Engine::setup_learning() {
+  for (auto& sk : sketches_) sk.regs = alloc(kHllRegs * 4);
+  if (!learned_) return;
+  predictor_dev_ = alloc(kMlpParams * 4);
+  hip(hipMemcpyAsync(predictor_dev_.p, predictor_.data(), kMlpParams * 4, hipMemcpyHostToDevice, stream_),
+      "predictor copy");
+  auto build = [&](std::vector<Plan>& plans, std::vector<PredSpec>& out, Buf& dev) {
+    out.clear();
+    for (auto& p : plans) {
+      u32 k = 0;
+      for (auto& st : p.steps) {
+        if (st.select_only) continue;
+        PredSpec sp{};
+        sp.probe_full = c_full0_ + int(p.src_rel);
+        sp.probe_dbeg = p.delta_pos >= 0 ? c_dbeg0_ + int(p.src_rel) : -1;
+        sp.build_full = c_full0_ + int(st.brel);
+        sp.ndv_build = st.index != kNoIndex ? indices_[st.index].c_ndv : -1;
+        sp.hll = (k == 0 && st.hll >= 0) ? sketches_[st.hll].ctr : -1;
+        sp.nkey = st.nkey;
+        sp.nfilt = u32(st.wf.size());
+        sp.step = k++;
+        sp.out = st.c_pred;
+        out.push_back(sp);
+      }
+    }
+    if (!out.empty()) {
+      dev = alloc(out.size() * sizeof(PredSpec));
+      hip(hipMemcpyAsync(dev.p, out.data(), out.size() * sizeof(PredSpec), hipMemcpyHostToDevice, stream_),
+          "spec copy");
+    }
+  };
+  build(init_plans_, pspec_init_, pspec_init_dev_);
+  build(delta_plans_, pspec_delta_, pspec_delta_dev_);
+  sync();   // the host vectors above are released/reused after this call
+}
+
+// HLL sketches of the probe keys the next round's first joins will use, then
+// (FV_LEARNED) the predictor over every join of that round.
+void Engine::emit_sketches_and_prediction(bool initial) {
+  for (auto& sk : sketches_) {
+    if (sk.delta == initial) continue;
+    const Relation& R = rels_[sk.rel];
+    RowRange rr{};
+    rr.begin_ctr = sk.delta ? ctr(c_dbeg0_ + int(sk.rel)) : nullptr;
+    rr.end_ctr = ctr(c_full0_ + int(sk.rel));
+    rr.cap = std::max<u64>(R.cap, 1);
+    const u32* c0 = R.col[sk.c0].as<u32>();
+    const u32* c1 = sk.c1 >= 0 ? R.col[sk.c1].as<u32>() : nullptr;
+    const int kc = kclass("hll_sketch");
+    ev_begin(kc);
+    launched(launch_hll(c0, c1, rr, std::max<u64>(R.cap, 1), sk.regs.as<u32>(), ctr(sk.ctr), stream_), "hll");
+    ev_end(kc, 0, 0);
+  }
+  if (!learned_) return;
+  const std::vector<PredSpec>& v = initial ? pspec_init_ : pspec_delta_;
+  const Buf& d = initial ? pspec_init_dev_ : pspec_delta_dev_;
+  if (v.empty()) return;
+  const int kc = kclass("predict");
+  ev_begin(kc);
+  launched(launch_predict(d.as<PredSpec>(), u32(v.size()), ctr_dev_.as<u64>(), predictor_dev_.as<float>(), stream_),
+           "predict");
+  ev_end(kc, 0, 0);
+}
+
+// FV_LEARNED: grow the round's output buffers to 1.25x the predicted sizes.
+void Engine::size_from_predictions(bool initial) {
+  std::vector<u64> need_new(rels_.size(), 0);
+  for (auto& p : initial ? init_plans_ : delta_plans_) {
+    const Relation& S = rels_[p.src_rel];
+    if (!initial && S.n_delta == 0) continue;
+    for (auto& st : p.steps) {
+      u64 want;
+      if (st.select_only) want = initial ? S.n_full : S.n_delta;
+      // presize to 1.25x the prediction, within [1024, 2^27] rows: a join larger
+      // than that is served by the overflow fallback's exact count
+      else want = std::min<u64>(u64(double(ctr_host_[st.c_pred]) * 1.25) + 1024, u64(1) << 27);
+      if (st.out_buf >= 0) {
+        Inter& I = inters_[st.out_buf];
+        if (I.cap < want) I.cap = pow2_at_least(want);
+      } else {
+        need_new[st.head_rel] += want;
+      }
+    }
+  }
+  for (size_t r = 0; r < rels_.size(); ++r)
+    if (rels_[r].used_as_head && rels_[r].new_cap < need_new[r]) rels_[r].new_cap = pow2_at_least(need_new[r]);
+}
+
+// One trace row per join executed in the round just finished: the features as
+// they stood when the round started, the true output size, the prediction.
+void Engine::log_joins(bool initial) {
+  auto S0 = [&](int i) -> double { return i >= 0 ? double(start_ctr_[i]) : 0.0; };
+  for (auto& p : initial ? init_plans_ : delta_plans_) {
+    const Relation& S = rels_[p.src_rel];
+    const u64 n_src = initial ? S.n_full : S.n_delta;   // mirrors still hold the round's start
+    if (!initial && n_src == 0) continue;
+    u32 k = 0;
+    for (size_t i = 0; i < p.steps.size(); ++i) {
+      const Step& st = p.steps[i];
+      if (st.select_only) continue;
+      double probe;
+      double ndv_p;
+      if (k == 0) {
+        probe = double(n_src);
+        ndv_p = probe;
+        if (st.hll >= 0) {
+          double e;
+          const u64 bits = start_ctr_[sketches_[st.hll].ctr];
+          std::memcpy(&e, &bits, 8);
+          if (e < ndv_p) ndv_p = e;
+        }
+      } else {
+        probe = double(std::min<u64>(ctr_host_[inters_[p.steps[i - 1].out_buf].ctr],
+                                     inters_[p.steps[i - 1].out_buf].cap));
+        ndv_p = probe;
+      }
+      const double build = S0(c_full0_ + int(st.brel));
+      const double ndv_b = st.index != kNoIndex ? S0(indices_[st.index].c_ndv) : 1.0;
+      float f[kTraceCols];
+      join_features(probe, build, ndv_b, ndv_p, st.nkey, u32(st.wf.size()), k, f);
+      const double m = double(ctr_host_[st.c_t]);
+      f[8] = float(std::log2(1.0 + m) / 16.0);
+      f[9] = -1.f;
+      if (learned_) {
+        const double pr = S0(st.c_pred);
+        f[9] = float(pr);
+        qerrors_.push_back(std::max((m + 1) / (pr + 1), (pr + 1) / (m + 1)));
+      }
+      trace_rows_.insert(trace_rows_.end(), f, f + kTraceCols);
+      ++k;
+    }
+  }
+}
+
 void Engine::alloc_control() {
   if (n_ctr_ < 8) n_ctr_ = 8;
   ctr_dev_ = alloc(size_t(n_ctr_) * 8);
   flags_dev_ = alloc(16);
   ticket_dev_ = alloc(16);
-  hist_dev_ = alloc(std::max<size_t>(rels_.size(), 1) * 8 * 256 * 4);
+  hist_dev_ = alloc(std::max<size_t>(rels_.size(), 1) * kHistWords * 4);
   hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
   hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
   hip(hipHostMalloc(reinterpret_cast<void**>(&ctr_host_), size_t(n_ctr_) * 8, hipHostMallocDefault), "pinned alloc");
@@ -1149,10 +1422,15 @@ void Engine::run(fv_stats* stats) {
   domain_analysis();
   plan_all();
   alloc_control();
+  setup_learning();
   ingest();
   ensure_capacity();
   begin_phase();
   build_indices(false);
+  if (log_joins_) {
+    emit_sketches_and_prediction(true);
+    read_counters();
+  }
   deltas_.clear();
   run_round(true);
   while (deltas_.back() != 0) run_round(false);
@@ -1168,6 +1446,16 @@ void Engine::run(fv_stats* stats) {
     stats->ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
     stats->graph_captures = graph_captures_;
     stats->graph_replays = graph_replays_;
+    stats->overflows = overflows_;
+    stats->predicted_joins = u32(qerrors_.size());
+    stats->qerror_median = 0;
+    stats->qerror_max = 0;
+    if (!qerrors_.empty()) {
+      std::vector<double> q = qerrors_;
+      std::sort(q.begin(), q.end());
+      stats->qerror_median = q[q.size() / 2];
+      stats->qerror_max = q.back();
+    }
   }
 }
 
@@ -1208,8 +1496,8 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
     const u64 stiles = (n + kSortTile - 1) / kSortTile + 1;
     if (st_sort_tiles_ < stiles) {
       release(st_sort_);
-      st_sort_ = alloc(stiles * 256 * 8);
-      launched(launch_fill_u64(st_sort_.as<u64>(), stiles * 256, 0, stream_), "status clear");
+      st_sort_ = alloc(stiles * kMaxRadix * 8);
+      launched(launch_fill_u64(st_sort_.as<u64>(), stiles * kMaxRadix, 0, stream_), "status clear");
       st_sort_tiles_ = stiles;
     }
     SortParams sp{};
@@ -1219,6 +1507,8 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
     sp.cap = n;
     sp.bits = R.bits;
     sp.hist = hist_dev_.as<u32>();
+    sp.digit_bits = tune_.radix_bits;
+    sp.max_blocks = tune_.max_blocks;
     sp.status = st_sort_.as<u64>();
     sp.ticket = ticket_dev_.as<u32>();
     sp.epoch_base = epoch_base();
@@ -1227,7 +1517,7 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
     launched(launch_rs_hist(sp, stream_), "hist launch");
     u64* s = sp.a;
     u64* d = sp.b;
-    for (u32 pass = 0; pass < sort_passes(R.bits); ++pass) {
+    for (u32 pass = 0; pass < sort_passes(R.bits, tune_.radix_bits); ++pass) {
       launched(launch_rs_pass(sp, pass, s, d, next_epoch(), stream_), "sort pass launch");
       std::swap(s, d);
     }

@@ -71,6 +71,7 @@ struct Index {
   u32 rel;
   u32 nkey;
   u32 keycol[2];
+  int c_ndv = -1;             // device counter: distinct keys after the last build
   Buf table, perm;
   u64 cap = 0, perm_cap = 0;
   bool dirty = true;   // storage (re)allocated since the last build
@@ -90,6 +91,8 @@ struct Step {
   int out_buf = -1;           // intermediate id, or -1: head relation's new keys
   u32 head_rel = 0;
   int c_m = -1, c_t = -1;     // device counters for this join's sizes
+  int c_pred = -1;            // device counter: predicted output size (learned mode)
+  int hll = -1;               // HLL sketch of the probe key (step 0, learned/logging modes)
 };
 
 struct Plan {
@@ -98,6 +101,15 @@ struct Plan {
   u32 src_rel;
   bool src_delta;
   std::vector<Step> steps;
+};
+
+struct HllSketch {
+  u32 rel;
+  u32 c0;
+  int c1;                     // second key column or -1
+  bool delta;                 // sketch of the delta rows (else of full)
+  Buf regs;
+  int ctr = -1;               // estimate (double bits)
 };
 
 struct Inter {
@@ -153,6 +165,9 @@ class Engine {
   // fixpoint (see fv_run_batch).
   static void run_batch(Engine* const* es, u32 n, fv_stats* stats);
   const std::vector<KClass>& profile() const { return kprof_; }
+  // one row per executed join step: 8 features, log2(1+output)/16, predicted size (-1: none)
+  const std::vector<float>& join_trace() const { return trace_rows_; }
+  static constexpr u32 kTraceCols = 10;
 
   std::string last_error;
   bool terminal = false;
@@ -179,6 +194,10 @@ class Engine {
 
   // rounds
   void run_round(bool initial);
+  void setup_learning();
+  void emit_sketches_and_prediction(bool initial);
+  void size_from_predictions(bool initial);
+  void log_joins(bool initial);
   void exec_plan(Plan& p);
   void finish_relation(Relation& R, bool in_round);
   void commit_relation(Relation& R);
@@ -199,6 +218,7 @@ class Engine {
   u32* epoch_base() { return flags_dev_.as<u32>() + 3; }
 
   fv_options opt_{};
+  fv_tuning tune_{};
   hipStream_t stream_ = nullptr;
   bool ran_ = false;
   std::vector<Relation> rels_;
@@ -236,6 +256,18 @@ class Engine {
 
   std::vector<u64> deltas_;
   u32 redo_ = 0;
+  // learned predictor
+  bool learned_ = false, log_joins_ = false, use_fused_ = false, graph_fused_ = false;
+  std::vector<float> predictor_;          // MLP parameters (host copy)
+  Buf predictor_dev_;
+  std::vector<HllSketch> sketches_;
+  std::vector<PredSpec> pspec_init_, pspec_delta_;
+  Buf pspec_init_dev_, pspec_delta_dev_;
+  std::vector<u64> start_ctr_;            // counters as they were when the round started
+  std::vector<float> trace_rows_;
+  std::vector<double> qerrors_;
+  u32 overflows_ = 0;
+  int c_ndv0_ = 0, c_hll0_ = 0, c_pred0_ = 0;
   u64 join_out_ = 0;
 
   bool trace_ = false;

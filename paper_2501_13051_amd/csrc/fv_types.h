@@ -110,6 +110,29 @@ struct WriteParams {
   u32* overflow;
 };
 
+// Probe + write in one pass into a presized output (see k_join_fused).
+struct FusedJoinParams {
+  const u32* pcol[kMaxCols];
+  RowRange src;
+  u32 n_pf;
+  Filter pf[kMaxFilters];
+  u32 nkey;
+  Src key[2];
+  const Slot* table;
+  u64 mask;
+  const u64* build_rows_ctr;
+  u64 build_rows;
+  u64 build_cap;
+  const u32* bcol[3];
+  const u32* perm;
+  u32 n_filter;
+  Filter filt[kMaxFilters];
+  OutSpec out;
+  u64* out_t;            // join output size before filters (added per wave)
+  u64* join_out_stat;
+  u32* overflow;
+};
+
 struct SelectParams {
   const u32* pcol[kMaxCols];
   RowRange src;
@@ -156,6 +179,7 @@ struct CommitParams {
 int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream);
 int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream);
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream);
+int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream);
 int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream);
 int launch_commit(const CommitParams& p, void* stream);
 // Zero n_ctr counters, n_hist histogram words and (if flag) the overflow and
@@ -163,8 +187,10 @@ int launch_commit(const CommitParams& p, void* stream);
 int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base, void* stream);
 
 // LSD radix sort of n packed u64 keys (n from *n_ctr clamped to cap, or
-// n_const) on the low `bits` bits, 8 bits per pass: launch_rs_hist counts the
-// digits of all passes, then one launch_rs_pass per pass moves keys src->dst.
+// n_const) on the low `bits` bits, digit_bits (8 or 11) per pass:
+// launch_rs_hist counts the digits of all passes, then one launch_rs_pass per
+// pass moves keys src->dst.  With `fuse`, the last pass instead takes the
+// difference against a tuple set and appends the survivors to full.
 struct SortParams {
   u64* a;
   u64* b;
@@ -172,15 +198,31 @@ struct SortParams {
   u64 n_const;
   u64 cap;
   u32 bits;
-  u32* hist;             // [passes][256] scratch, cleared by launch_rs_hist
-  u64* status;           // [tiles][256] look-back words
+  u32 digit_bits;        // 8 or 11
+  u32 max_blocks;        // grid cap of a pass (0: 2048)
+  u32* hist;             // [passes][2^digit_bits] scratch (see kHistWords)
+  u64* status;           // [tiles][2^digit_bits] look-back words
   u32* ticket;
   const u32* epoch_base;
   const u32* abort;
 };
+struct SortFuse {
+  u64* set;
+  u64 set_mask;
+  u32* set_full;
+  u32* cols[3];
+  const u64* full_n;
+  u64* out_delta;
+  u32 arity;
+  u32 shift[3];
+  u32 width[3];
+};
 int launch_rs_hist(const SortParams& p, void* stream, bool clear_hist = true);
-int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch_off, void* stream);
-inline u32 sort_passes(u32 bits) { return (bits + 7) / 8; }
+int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch_off, void* stream,
+                   const SortFuse* fuse = nullptr);
+inline u32 sort_passes(u32 bits, u32 digit_bits = 8) { return (bits + digit_bits - 1) / digit_bits; }
+constexpr u32 kHistWords = 6 * 2048;   // per relation: enough for 8 passes of 8 bits or 6 of 11
+constexpr u32 kMaxRadix = 2048;
 constexpr u32 kSortTile = 2048;
 
 // Index build over rows [0, n) of a relation's columns: table of distinct
@@ -198,6 +240,7 @@ struct IndexParams {
   const u32* epoch_base;
   u32 epoch_off;
   const u32* abort;
+  u64* ndv;              // receives the number of distinct keys (nullable)
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
 
@@ -226,6 +269,42 @@ int launch_gather_relabel(const GatherDesc* d, u32 n_src, u32 arity, u32* const*
 int launch_add_u32(u32* p, u64 n, u32 delta, void* stream);
 // Instance boundaries of a sorted column (see k_bounds).
 int launch_bounds(const u32* col, u64 n, u32 stride, u32 n_inst, u64* out, void* stream);
+
+// Learned predictor (see kern_learn.hip)
+constexpr u32 kHllRegs = 4096;
+constexpr u32 kMlpIn = 8, kMlpHidden = 64;
+constexpr u32 kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
+int launch_hll(const u32* c0, const u32* c1, RowRange src, u64 rows_hint, u32* regs, u64* out_estimate,
+               void* stream);
+int launch_dense_fwd(const float* in, u32 n, u32 din, const float* W, const float* b, u32 dout, float in_scale,
+                     float* z, float* out, int relu, void* stream);
+int launch_mse(const float* yhat, const float* y, u32 n, float* dy, float* loss, void* stream);
+int launch_relu_bwd(float* dout, const float* z, u64 n, void* stream);
+int launch_dense_wgrad(const float* dz, const float* in, u32 n, u32 din, u32 dout, float in_scale, float* dW,
+                       float* db, void* stream);
+int launch_dense_dgrad(const float* dz, const float* W, u32 n, u32 din, u32 dout, float* dinp, void* stream);
+int launch_adam(float* p, const float* g, float* m, float* v, u32 n, float lr, float b1, float b2, float eps,
+                float c1, float c2, void* stream);
+int launch_mlp_infer_bf16(const float* X, u32 n, const float* P, float* out, void* stream);
+
+// One join step whose output size the predictor estimates at the end of a
+// round for the next one.  Counter indices refer to the engine's counter
+// block; -1 means "not available".
+struct PredSpec {
+  int probe_full;        // counter: n_full of the probe-side relation (step 0)
+  int probe_dbeg;        // counter: d_begin of it (delta plans; -1: read full)
+  int build_full;        // counter: n_full of the build relation
+  int ndv_build;         // counter: distinct keys of the build index (-1: cross product)
+  int hll;               // counter: HLL estimate (double bits) of the probe key (-1: none)
+  u32 nkey, nfilt, step;
+  int out;               // counter receiving the predicted output size
+};
+// Features of each spec from the counters, BF16 MLP inference, predictions
+// written back to the counters.  Specs are ordered plan by plan; a step > 0
+// takes the previous spec's prediction as its probe size.
+int launch_predict(const PredSpec* specs, u32 n, u64* ctr, const float* params, void* stream);
+void join_features(double probe_rows, double build_rows, double ndv_build, double ndv_probe, u32 nkey, u32 nfilt,
+                   u32 step, float* f);
 
 constexpr int kBlock = 256;
 

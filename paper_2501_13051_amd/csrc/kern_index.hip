@@ -21,8 +21,9 @@ __device__ __forceinline__ u64 row_key(const IndexParams& p, u64 row) {
   return u64(a);
 }
 
-__global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort) {
+__global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort, u64* ndv) {
   if (abort && *abort) return;
+  if (ndv && blockIdx.x == 0 && threadIdx.x == 0) *ndv = 0;
   for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < cap; i += u64(gridDim.x) * blockDim.x)
     tab[i] = Slot{kEmptyKey, 0u, 0u};
 }
@@ -53,11 +54,16 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
     if (tile >= ntiles) break;
     const u64 s0 = u64(tile) * kScanTile + u64(threadIdx.x) * 4;
     u32 c[4];
-    u32 mine = 0;
+    u32 mine = 0, keys = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       c[k] = (s0 + k < p.cap) ? p.table[s0 + k].count : 0u;
       mine += c[k];
+      keys += c[k] ? 1u : 0u;
+    }
+    if (p.ndv) {
+      const u32 wk = wave_sum(keys);
+      if (lane_id() == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
     }
     u32 tot;
     const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
@@ -111,7 +117,7 @@ static int grid_rows(u64 n, int cap) {
 
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort);
+  hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv);
   hipLaunchKernelGGL(k_idx_count, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p);
   const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_idx_scan, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);

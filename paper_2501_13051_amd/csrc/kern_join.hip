@@ -244,6 +244,108 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
   }
 }
 
+// ------------------------------------------------------------------ single-pass join
+// Probe and write in one launch, for joins whose output buffer was presized
+// (by the cardinality predictor): no count pass, no scan scratch.  A wave
+// probes 64 rows, scans their run lengths in registers, then produces the
+// group's outputs 64 at a time (output n is found by a binary search over the
+// lanes' prefixes through cross-lane shuffles, so work stays balanced inside
+// the wave), and reserves room for each chunk's kept outputs with one atomic.
+// Outputs past the buffer are counted, not written, and raise the overflow
+// flag; the host then re-runs the round with count-then-write.
+__global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const int lane = lane_id();
+  const u64 wave_id = (u64(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const u64 n_waves = u64(gridDim.x) * blockDim.x / kWave;
+  u64 nbuild = 0;
+  if (p.nkey == 0) nbuild = p.build_rows_ctr ? min_u64(*p.build_rows_ctr, p.build_cap) : p.build_rows;
+  u64 pre_total = 0, kept_total = 0;
+  for (u64 g = wave_id; g * kWave < n; g += n_waves) {
+    const u64 r = g * kWave + lane;
+    u32 st = 0, cnt = 0;
+    u64 row = 0;
+    if (r < n) {
+      row = begin + r;
+      bool ok = true;
+      for (u32 f = 0; f < p.n_pf; ++f) {
+        const u32 a = probe_val(p.pf[f].a, p.pcol, row);
+        const u32 b = probe_val(p.pf[f].b, p.pcol, row);
+        ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
+      }
+      if (ok) {
+        if (p.nkey == 0) {
+          cnt = u32(nbuild);
+        } else {
+          const u32 a = probe_val(p.key[0], p.pcol, row);
+          const u32 b = p.nkey == 2 ? probe_val(p.key[1], p.pcol, row) : 0u;
+          u32 s0, c0;
+          if (index_find(p.table, p.mask, make_key(p.nkey, a, b), s0, c0)) { st = s0; cnt = c0; }
+        }
+      }
+    }
+    const u64 inc = wave_inclusive_sum<u64>(u64(cnt));
+    const u64 excl = inc - cnt;
+    const u64 tw = __shfl(inc, kWave - 1, kWave);
+    pre_total += tw;
+    for (u64 c0 = 0; c0 < tw; c0 += kWave) {
+      const u64 o = c0 + lane;
+      bool keep = false;
+      OutVals v;
+      // owner lane j: the last lane whose exclusive prefix is <= o
+      int lo = 0;
+#pragma unroll
+      for (int step = kWave / 2; step >= 1; step >>= 1) {
+        const u64 e = __shfl(excl, lo + step, kWave);
+        if (o < tw && e <= o) lo += step;
+      }
+      const u64 ej = __shfl(excl, lo, kWave);
+      const u32 sj = __shfl(st, lo, kWave);
+      const u64 rowj = __shfl(row, lo, kWave);
+      if (o < tw) {
+        const u64 idx = u64(sj) + (o - ej);
+        const u64 brow = p.perm ? u64(p.perm[idx]) : idx;
+        bool ok = true;
+        for (u32 f = 0; f < p.n_filter; ++f) {
+          const u32 a = src_val(p.filt[f].a, p.pcol, rowj, p.bcol, brow);
+          const u32 b = src_val(p.filt[f].b, p.pcol, rowj, p.bcol, brow);
+          ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
+        }
+        keep = ok;
+        if (ok)
+          for (u32 c = 0; c < p.out.ncols; ++c) v.v[c] = src_val(p.out.src[c], p.pcol, rowj, p.bcol, brow);
+      }
+      const u64 km = __ballot(keep);
+      const u32 kc = u32(__popcll(km));
+      if (kc == 0) continue;
+      u64 base = 0;
+      if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(p.out.count), (unsigned long long)kc);
+      base = __shfl(base, 0, kWave);
+      kept_total += kc;
+      if (base + kc > p.out.cap) {
+        if (lane == 0) *p.overflow = 1;
+        continue;
+      }
+      if (keep) {
+        const u64 pos = base + u64(__popcll(km & ((1ull << lane) - 1)));
+        if (p.out.packed) {
+          u64 key = 0;
+          for (u32 c = 0; c < p.out.ncols; ++c) key |= u64(v.v[c]) << p.out.shift[c];
+          p.out.keys[pos] = key;
+        } else {
+          for (u32 c = 0; c < p.out.ncols; ++c) p.out.cols[c][pos] = v.v[c];
+        }
+      }
+    }
+  }
+  if (lane == 0) {
+    if (pre_total) atomicAdd(reinterpret_cast<unsigned long long*>(p.out_t), (unsigned long long)pre_total);
+    if (kept_total && p.join_out_stat)
+      atomicAdd(reinterpret_cast<unsigned long long*>(p.join_out_stat), (unsigned long long)kept_total);
+  }
+}
+
 // ------------------------------------------------------------------ select / project
 __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
   __shared__ u32 s_cnt[kBlock / kWave + 1];
@@ -394,6 +496,13 @@ int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream) {
 int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream) {
   const u64 tiles = (out_tiles_hint + kWriteTile - 1) / kWriteTile;
   hipLaunchKernelGGL(k_write, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  return int(hipGetLastError());
+}
+
+int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream) {
+  const u64 waves = (rows_hint + kWave - 1) / kWave;
+  const u64 blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
+  hipLaunchKernelGGL(k_join_fused, dim3(grid_for(blocks, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 

@@ -3,73 +3,114 @@
 //
 // A tuple of a relation is packed into one 64-bit key with per-column bit
 // widths taken from the value domain, so a sort touches only the bits that
-// can be set.  One histogram pass counts the 8-bit digits of every pass at
-// once; each pass is then a single read and write of the keys ("onesweep"):
-// a tile of 2048 keys is ranked stably in LDS (wave64 match masks built from
-// eight ballots, per-wave digit counters), the tile's per-digit counts are
-// chained across tiles with a decoupled look-back, and the keys are staged in
-// LDS in digit order so that the global scatter writes contiguous runs.
+// can be set.  One histogram pass counts the digits of every pass at once;
+// each pass is then a single read and write of the keys ("onesweep"): a tile
+// of 2048 keys is ranked stably in LDS (wave64 match masks built from one
+// ballot per digit bit, per-wave digit counters), the tile's per-digit counts
+// are chained across tiles with a decoupled look-back, and the keys are staged
+// in LDS in digit order so that the global scatter writes contiguous runs.
+// Digits are 8 or 11 bits (a tuning knob).
+//
+// The last pass can also take the difference against full (Section 4, "Union
+// and Deduplication") instead of writing the sorted keys: inside a tile, equal
+// keys are adjacent in the LDS staging area (earlier passes ordered the low
+// bits, this pass the top digit); equal keys in different tiles are settled by
+// the tuple set's insert-if-absent, which admits exactly one of them.
+// Survivors are appended to full with one atomic reservation per tile.
 #include "fv_device.h"
 
 namespace fv {
 
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSortItems = kSortTile / kBlock;   // 8 keys per thread
-constexpr int kMaxPasses = 8;
-static_assert(kBlock == kRadix, "one thread per digit");
 
 __device__ __forceinline__ u64 sort_n(const u64* n_ctr, u64 n_const, u64 cap) {
   return n_ctr ? min_u64(*n_ctr, cap) : n_const;
 }
 
+template <int kBits>
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const u64* keys, const u64* n_ctr, u64 n_const, u64 cap,
                                                    u32 passes, u32* hist, const u32* abort) {
-  __shared__ u32 s_h[kMaxPasses][kRadix];
+  constexpr int kRadix = 1 << kBits;
+  constexpr int kMaxPasses = (64 + kBits - 1) / kBits;
+  __shared__ u32 s_h[kMaxPasses * kRadix];
   if (abort && *abort) return;
   const u64 n = sort_n(n_ctr, n_const, cap);
-  for (u32 p = 0; p < passes; ++p) s_h[p][threadIdx.x] = 0;
+  for (u32 i = threadIdx.x; i < passes * kRadix; i += kBlock) s_h[i] = 0;
   __syncthreads();
   for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
     const u64 k = keys[i];
-    for (u32 p = 0; p < passes; ++p) atomicAdd(&s_h[p][(k >> (p * kRadixBits)) & (kRadix - 1)], 1u);
+    for (u32 p = 0; p < passes; ++p) atomicAdd(&s_h[p * kRadix + ((k >> (p * kBits)) & (kRadix - 1))], 1u);
   }
   __syncthreads();
-  for (u32 p = 0; p < passes; ++p) {
-    const u32 c = s_h[p][threadIdx.x];
-    if (c) atomicAdd(&hist[p * kRadix + threadIdx.x], c);
+  for (u32 i = threadIdx.x; i < passes * kRadix; i += kBlock) {
+    const u32 c = s_h[i];
+    if (c) atomicAdd(&hist[i], c);
   }
 }
 
+// Parameters of the fused difference + append (last pass only).
+struct FuseArgs {
+  u64* set;
+  u64 set_mask;
+  u32* set_full;
+  u32* cols[3];
+  const u64* full_n;
+  u64* out_delta;      // survivors, reserved atomically per tile
+  u32 arity;
+  u32 shift[3];
+  u32 width[3];
+};
+
+template <int kBits, bool kFuse>
 __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, u64* __restrict__ out,
                                                    const u64* n_ctr, u64 n_const, u64 cap, u32 shift,
                                                    const u32* hist_p, u64* status, u32* ticket,
-                                                   const u32* epoch_base, u32 epoch_off, const u32* abort) {
+                                                   const u32* epoch_base, u32 epoch_off, const u32* abort,
+                                                   FuseArgs fz) {
+  constexpr int kRadix = 1 << kBits;
   constexpr int kWaves = kBlock / kWave;
+  constexpr int kDpt = kRadix > kBlock ? kRadix / kBlock : 1;   // digits owned per thread
   __shared__ u64 s_keys[kSortTile];
   __shared__ u32 s_wcnt[kWaves][kRadix];
-  __shared__ u32 s_tstart[kRadix];
-  __shared__ u64 s_gbase[kRadix];
-  __shared__ u64 s_dbase[kRadix];
+  __shared__ u32 s_tstart[kRadix + 1];
+  __shared__ u64 s_base[kRadix];
   __shared__ u32 s_scan32[kWaves + 1];
   __shared__ u32 s_ticket;
+  __shared__ u64 s_out;
   if (abort && *abort) return;
   const u32 epoch = launch_epoch(epoch_base, epoch_off);
   const u64 n = sort_n(n_ctr, n_const, cap);
   const u32 ntiles = u32((n + kSortTile - 1) / kSortTile);
-  const int d = threadIdx.x;            // the digit this thread owns in per-digit steps
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
   const u64 lt_mask = (1ull << lane) - 1;
-  {
-    u32 tot;
-    s_dbase[d] = block_exclusive_sum<kBlock>(hist_p[d], s_scan32, &tot);
-  }
   if (blockIdx.x >= participants(ntiles)) return;
+  u64 fbase = 0;
+  if (kFuse) fbase = *fz.full_n;
+  {
+    // global digit bases: exclusive scan of this pass's histogram
+    u32 run = 0;
+    for (int j = 0; j < kDpt; ++j) {
+      const int d = threadIdx.x * kDpt + j;
+      run += d < kRadix ? hist_p[d] : 0u;
+    }
+    u32 tot;
+    u32 ex = block_exclusive_sum<kBlock>(run, s_scan32, &tot);
+    for (int j = 0; j < kDpt; ++j) {
+      const int d = threadIdx.x * kDpt + j;
+      if (d < kRadix) { s_base[d] = ex; ex += hist_p[d]; }
+    }
+  }
+  __syncthreads();
+  u64 dbase[kDpt];
+  for (int j = 0; j < kDpt; ++j) {
+    const int d = threadIdx.x * kDpt + j;
+    dbase[j] = d < kRadix ? s_base[d] : 0;
+  }
   for (;;) {
     const u32 tile = take_ticket(ticket, ntiles, &s_ticket);
     if (tile >= ntiles) break;
-    for (int i = 0; i < kWaves; ++i) s_wcnt[i][d] = 0;
+    for (int i = threadIdx.x; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     const u64 t0 = u64(tile) * kSortTile;
     u64 key[kSortItems];
@@ -83,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       dig[i] = valid ? u32((key[i] >> shift) & (kRadix - 1)) : 0u;
       u64 mask = __ballot(valid);
 #pragma unroll
-      for (int b = 0; b < kRadixBits; ++b) {
+      for (int b = 0; b < kBits; ++b) {
         const bool bit = (dig[i] >> b) & 1u;
         const u64 bb = __ballot(bit);
         mask &= bit ? bb : ~bb;
@@ -95,49 +136,65 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       if (valid && (mask & lt_mask) == 0) s_wcnt[w][dig[i]] = old + u32(__popcll(mask));
     }
     __syncthreads();
-    u32 run = 0;
-    for (int i = 0; i < kWaves; ++i) {
-      const u32 c = s_wcnt[i][d];
-      s_wcnt[i][d] = run;
-      run += c;
-    }
-    const u32 tcount = run;
-    u64* st = status + u64(tile) * kRadix + d;
-    if (tile == 0) atomic_store_u64(st, lb_word(epoch, kFlagPrefix, tcount));
-    else atomic_store_u64(st, lb_word(epoch, kFlagAgg, tcount));
-    u32 ttot;
-    const u32 tstart = block_exclusive_sum<kBlock>(tcount, s_scan32, &ttot);
-    s_tstart[d] = tstart;
-    u64 excl = 0;
-    if (tile > 0) {
-      // walk this digit's chain back to the nearest inclusive prefix, reading
-      // a window of kWin predecessor tiles per round trip (rows of the status
-      // array are contiguous over digits, so the loads coalesce)
-      constexpr int kWin = 16;
-      long long t = (long long)tile - 1;
-      for (;;) {
-        u64 wd[kWin];
-#pragma unroll
-        for (int j = 0; j < kWin; ++j)
-          wd[j] = (t - j >= 0) ? atomic_load_u64(status + u64(t - j) * kRadix + d) : lb_word(epoch, kFlagPrefix, 0);
-        bool done = false;
-        int j = 0;
-        for (; j < kWin; ++j) {
-          u64 f = lb_flag(wd[j], epoch);
-          while (f == 0) {                       // not published yet: wait for this one
-            __builtin_amdgcn_s_sleep(1);
-            wd[j] = atomic_load_u64(status + u64(t - j) * kRadix + d);
-            f = lb_flag(wd[j], epoch);
-          }
-          excl += wd[j] & kValueMask;
-          if (f == kFlagPrefix) { done = true; break; }
+    u32 tcount[kDpt];
+    u32 my_total = 0;
+    for (int j = 0; j < kDpt; ++j) {
+      const int d = threadIdx.x * kDpt + j;
+      u32 run = 0;
+      if (d < kRadix) {
+        for (int i = 0; i < kWaves; ++i) {
+          const u32 c = s_wcnt[i][d];
+          s_wcnt[i][d] = run;
+          run += c;
         }
-        if (done) break;
-        t -= kWin;
+        atomic_store_u64(status + u64(tile) * kRadix + d, lb_word(epoch, tile == 0 ? kFlagPrefix : kFlagAgg, run));
       }
-      atomic_store_u64(st, lb_word(epoch, kFlagPrefix, excl + tcount));
+      tcount[j] = run;
+      my_total += run;
     }
-    s_gbase[d] = s_dbase[d] + excl;
+    {
+      u32 ttot;
+      u32 ex = block_exclusive_sum<kBlock>(my_total, s_scan32, &ttot);
+      for (int j = 0; j < kDpt; ++j) {
+        const int d = threadIdx.x * kDpt + j;
+        if (d < kRadix) s_tstart[d] = ex;
+        ex += tcount[j];
+      }
+      if (threadIdx.x == 0) s_tstart[kRadix] = ttot;
+    }
+    for (int j = 0; j < kDpt; ++j) {
+      const int d = threadIdx.x * kDpt + j;
+      if (d >= kRadix) continue;
+      u64 excl = 0;
+      if (tile > 0) {
+        // walk this digit's chain back to the nearest inclusive prefix, reading
+        // a window of kWin predecessor tiles per round trip (a row of the
+        // status array is contiguous over digits, so the loads coalesce)
+        constexpr int kWin = 16;
+        long long t = (long long)tile - 1;
+        for (;;) {
+          u64 wd[kWin];
+#pragma unroll
+          for (int q = 0; q < kWin; ++q)
+            wd[q] = (t - q >= 0) ? atomic_load_u64(status + u64(t - q) * kRadix + d) : lb_word(epoch, kFlagPrefix, 0);
+          bool done = false;
+          for (int q = 0; q < kWin; ++q) {
+            u64 f = lb_flag(wd[q], epoch);
+            while (f == 0) {   // not published yet: its tile is owned by a running block
+              __builtin_amdgcn_s_sleep(1);
+              wd[q] = atomic_load_u64(status + u64(t - q) * kRadix + d);
+              f = lb_flag(wd[q], epoch);
+            }
+            excl += wd[q] & kValueMask;
+            if (f == kFlagPrefix) { done = true; break; }
+          }
+          if (done) break;
+          t -= kWin;
+        }
+        atomic_store_u64(status + u64(tile) * kRadix + d, lb_word(epoch, kFlagPrefix, excl + tcount[j]));
+      }
+      s_base[d] = dbase[j] + excl;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < kSortItems; ++i) {
@@ -146,13 +203,52 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     }
     __syncthreads();
     const u32 tn = u32(min_u64(kSortTile, n - t0));
+    if (!kFuse) {
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-      const u32 q = u32(i) * kBlock + threadIdx.x;
-      if (q < tn) {
-        const u64 k = s_keys[q];
-        const u32 dq = u32((k >> shift) & (kRadix - 1));
-        out[s_gbase[dq] + (q - s_tstart[dq])] = k;
+      for (int i = 0; i < kSortItems; ++i) {
+        const u32 q = u32(i) * kBlock + threadIdx.x;
+        if (q < tn) {
+          const u64 k = s_keys[q];
+          const u32 dq = u32((k >> shift) & (kRadix - 1));
+          out[s_base[dq] + (q - s_tstart[dq])] = k;
+        }
+      }
+    } else {
+      // difference against full and append; consecutive LDS slots of one
+      // digit hold consecutive keys of the sorted order
+      bool surv[kSortItems];
+      u32 mine = 0;
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i) {
+        const u32 q = threadIdx.x * kSortItems + u32(i);
+        surv[i] = false;
+        if (q < tn) {
+          const u64 k = s_keys[q];
+          const u32 dq = u32((k >> shift) & (kRadix - 1));
+          const bool first = q == s_tstart[dq] || s_keys[q - 1] != k;
+          if (first) {
+            const int ins = set_insert(fz.set, fz.set_mask, k);
+            if (ins < 0) *fz.set_full = 1;
+            surv[i] = ins > 0;
+          }
+        }
+        mine += surv[i] ? 1u : 0u;
+      }
+      u32 tot;
+      const u32 ex = block_exclusive_sum<kBlock>(mine, s_scan32, &tot);
+      if (threadIdx.x == 0)
+        s_out = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(fz.out_delta), (unsigned long long)tot) : 0;
+      __syncthreads();
+      u64 pos = fbase + s_out + ex;
+#pragma unroll
+      for (int i = 0; i < kSortItems; ++i) {
+        if (!surv[i]) continue;
+        const u64 k = s_keys[threadIdx.x * kSortItems + u32(i)];
+        for (u32 c = 0; c < fz.arity; ++c) {
+          const u64 m = fz.width[c] >= 32 ? 0xFFFFFFFFull : ((1ull << fz.width[c]) - 1);
+          fz.cols[c][pos] = u32((k >> fz.shift[c]) & m);
+        }
+        ++pos;
       }
     }
     __syncthreads();
@@ -183,22 +279,53 @@ int launch_fill_u64(u64* p, u64 n, u64 v, void* stream) {
 }
 
 int launch_rs_hist(const SortParams& p, void* stream, bool clear_hist) {
-  const u32 passes = (p.bits + kRadixBits - 1) / kRadixBits;
+  const u32 db = p.digit_bits == 11 ? 11 : 8;
+  const u32 passes = sort_passes(p.bits, db);
   if (passes == 0) return 0;
-  if (clear_hist) launch_fill_u32(p.hist, u64(passes) * kRadix, 0u, stream);
+  if (clear_hist) launch_fill_u32(p.hist, u64(passes) << db, 0u, stream);
   const u64 tiles = (p.cap + kSortTile - 1) / kSortTile;
   const int hgrid = int(tiles == 0 ? 1 : (tiles > 1024 ? 1024 : tiles));
-  hipLaunchKernelGGL(k_rs_hist, dim3(hgrid), dim3(kBlock), 0, (hipStream_t)stream, p.a, p.n_ctr, p.n_const,
-                     p.cap, passes, p.hist, p.abort);
+  if (db == 11)
+    hipLaunchKernelGGL(k_rs_hist<11>, dim3(hgrid), dim3(kBlock), 0, (hipStream_t)stream, p.a, p.n_ctr, p.n_const,
+                       p.cap, passes, p.hist, p.abort);
+  else
+    hipLaunchKernelGGL(k_rs_hist<8>, dim3(hgrid), dim3(kBlock), 0, (hipStream_t)stream, p.a, p.n_ctr, p.n_const,
+                       p.cap, passes, p.hist, p.abort);
   return int(hipGetLastError());
 }
 
-int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch_off, void* stream) {
+int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 epoch_off, void* stream,
+                   const SortFuse* fuse) {
+  const u32 db = p.digit_bits == 11 ? 11 : 8;
   const u64 tiles = (p.cap + kSortTile - 1) / kSortTile;
-  const int pgrid = int(tiles == 0 ? 1 : (tiles > 2048 ? 2048 : tiles));
-  hipLaunchKernelGGL(k_rs_pass, dim3(pgrid), dim3(kBlock), 0, (hipStream_t)stream, src, dst, p.n_ctr, p.n_const,
-                     p.cap, pass * kRadixBits, p.hist + pass * kRadix, p.status, p.ticket, p.epoch_base, epoch_off,
-                     p.abort);
+  const u64 maxg = p.max_blocks ? p.max_blocks : 2048;
+  const int pgrid = int(tiles == 0 ? 1 : (tiles > maxg ? maxg : tiles));
+  FuseArgs fz{};
+  if (fuse) {
+    fz.set = fuse->set;
+    fz.set_mask = fuse->set_mask;
+    fz.set_full = fuse->set_full;
+    for (int c = 0; c < 3; ++c) {
+      fz.cols[c] = fuse->cols[c];
+      fz.shift[c] = fuse->shift[c];
+      fz.width[c] = fuse->width[c];
+    }
+    fz.full_n = fuse->full_n;
+    fz.out_delta = fuse->out_delta;
+    fz.arity = fuse->arity;
+  }
+  const u32 sh = pass * db;
+  const u32* h = p.hist + (u64(pass) << db);
+  hipStream_t s = (hipStream_t)stream;
+#define FV_PASS(B, F)                                                                                     \
+  hipLaunchKernelGGL((k_rs_pass<B, F>), dim3(pgrid), dim3(kBlock), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, \
+                     sh, h, p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
+  if (db == 11) {
+    if (fuse) FV_PASS(11, true); else FV_PASS(11, false);
+  } else {
+    if (fuse) FV_PASS(8, true); else FV_PASS(8, false);
+  }
+#undef FV_PASS
   return int(hipGetLastError());
 }
 

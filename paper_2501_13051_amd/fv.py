@@ -22,20 +22,33 @@ FV_OK = 0
 STATUS = {0: "FV_OK", -1: "FV_EINVAL", -2: "FV_ENOMEM", -3: "FV_EARITY", -4: "FV_EUNSAFE",
           -5: "FV_ESTATE", -6: "FV_EHIP", -7: "FV_ERESERVED", -8: "FV_ETRUNC", -9: "FV_ENOTSUP"}
 FV_PLAIN = 0
+FV_LEARNED = 2
 FV_TRACE = 4
 FV_GRAPH = 8
+FV_LOG_JOINS = 16
+TRACE_COLS = 10
 
 EXPORTED = ("fv_ctx_create", "fv_ctx_destroy", "fv_last_error", "fv_relation_create", "fv_relation_find",
             "fv_load_columns", "fv_add_rule", "fv_run_fixpoint", "fv_relation_size", "fv_export",
-            "fv_delta_sizes", "fv_profile", "fv_run_batch")
+            "fv_delta_sizes", "fv_profile", "fv_run_batch", "fv_autotune", "fv_tuning_load",
+            "fv_global_error", "fv_mlp_grad", "fv_mlp_train", "fv_mlp_predict", "fv_join_trace")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("radix_bits", ctypes.c_uint32), ("fuse_dedup", ctypes.c_uint32), ("set_load", ctypes.c_float),
+                ("index_load", ctypes.c_float), ("max_blocks", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class Options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
-                ("user", ctypes.c_void_p), ("flags", ctypes.c_uint32)]
+                ("user", ctypes.c_void_p), ("flags", ctypes.c_uint32), ("tuning", ctypes.POINTER(Tuning)),
+                ("predictor", ctypes.POINTER(ctypes.c_float))]
 
 
 class Term(ctypes.Structure):
@@ -55,13 +68,17 @@ class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_uint32), ("redo_rounds", ctypes.c_uint32),
                 ("derived_tuples", ctypes.c_uint64), ("join_output_tuples", ctypes.c_uint64),
                 ("ms_total", ctypes.c_double), ("graph_captures", ctypes.c_uint32),
-                ("graph_replays", ctypes.c_uint32)]
+                ("graph_replays", ctypes.c_uint32), ("overflows", ctypes.c_uint32),
+                ("predicted_joins", ctypes.c_uint32), ("qerror_median", ctypes.c_double),
+                ("qerror_max", ctypes.c_double)]
 
 
 class KProf(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64), ("ms", ctypes.c_double),
                 ("algo_bytes", ctypes.c_double), ("items", ctypes.c_uint64)]
 
+
+MAKE_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 _lib = None
 _streams = {}
@@ -98,8 +115,17 @@ def lib():
         L.fv_delta_sizes.argtypes = [vp, ctypes.POINTER(u64), u32, ctypes.POINTER(u32)]
         L.fv_profile.argtypes = [vp, ctypes.POINTER(KProf), u32, ctypes.POINTER(u32)]
         L.fv_run_batch.argtypes = [ctypes.POINTER(vp), u32, ctypes.POINTER(Stats)]
+        L.fv_autotune.argtypes = [MAKE_FN, vp, ctypes.POINTER(Options), u32, ctypes.c_char_p, ctypes.c_char_p,
+                                  ctypes.POINTER(Tuning)]
+        L.fv_tuning_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
+        L.fv_global_error.argtypes = []
+        L.fv_global_error.restype = ctypes.c_char_p
+        L.fv_mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp]
+        L.fv_mlp_train.argtypes = [vp, vp, u32, u32, ctypes.c_float, u64, ctypes.c_int, vp, vp]
+        L.fv_mlp_predict.argtypes = [vp, u32, vp, vp]
+        L.fv_join_trace.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
         for name in EXPORTED:
-            if name not in ("fv_ctx_destroy", "fv_last_error"):
+            if name not in ("fv_ctx_destroy", "fv_last_error", "fv_global_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -207,7 +233,8 @@ def parse_program(text: str):
 class Engine:
     """One fixpoint context on the current CUDA/HIP device and stream."""
 
-    def __init__(self, flags: int = FV_PLAIN, stream=None, use_torch_allocator: bool = True):
+    def __init__(self, flags: int = FV_PLAIN, stream=None, use_torch_allocator: bool = True, tuning=None,
+                 predictor=None):
         import torch
         self._torch = torch
         L = lib()
@@ -220,6 +247,14 @@ class Engine:
         opt = Options()
         opt.stream = ctypes.c_void_p(s.cuda_stream)
         opt.flags = flags
+        if tuning is not None:
+            self._tuning = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
+            opt.tuning = ctypes.pointer(self._tuning)
+        if predictor is not None:
+            self._predictor = np.ascontiguousarray(np.asarray(predictor, dtype=np.float32))
+            if self._predictor.size != 4801:
+                raise ValueError("predictor must hold 4801 parameters")
+            opt.predictor = self._predictor.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         self._live = {}
         if use_torch_allocator:
             dev, handle = self._device, s.cuda_stream
@@ -359,6 +394,14 @@ class Engine:
         self._check(self._L.fv_export(self._h, rel, ptrs, n, None, 0))
         return np.ascontiguousarray(out[:, :n].T)
 
+    def join_trace(self) -> np.ndarray:
+        """(n, 10) float32: 8 features, log2(1+true size)/16, predicted size or -1."""
+        n = ctypes.c_uint32()
+        self._check(self._L.fv_join_trace(self._h, None, 0, ctypes.byref(n)))
+        out = np.zeros((max(n.value, 1), TRACE_COLS), np.float32)
+        self._check(self._L.fv_join_trace(self._h, out.ctypes.data, n.value, ctypes.byref(n)))
+        return out[:n.value]
+
     def delta_sizes(self):
         n = ctypes.c_uint32()
         self._check(self._L.fv_delta_sizes(self._h, None, 0, ctypes.byref(n)))
@@ -376,10 +419,7 @@ class Engine:
 
 
 def _stats_dict(st) -> dict:
-    return {"iterations": st.iterations, "redo_rounds": st.redo_rounds,
-            "derived_tuples": st.derived_tuples, "join_output_tuples": st.join_output_tuples,
-            "ms_total": st.ms_total, "graph_captures": st.graph_captures,
-            "graph_replays": st.graph_replays}
+    return {f: getattr(st, f) for f, _ in Stats._fields_}
 
 
 def run_batch(engines) -> dict:
@@ -398,10 +438,92 @@ def run_batch(engines) -> dict:
     return _stats_dict(st)
 
 
-def evaluate(program: str, edb: dict, flags: int = FV_PLAIN, relations=None, device_out: bool = False):
+def autotune(make_engine, key: str = None, cache_path: str = None, reps: int = 3, flags: int = FV_PLAIN):
+    """Run the library's autotuner.  make_engine(tuning) must return a fresh
+    Engine (created with that tuning) holding the program and facts; the
+    library runs and destroys each one.  Returns the chosen tuning as a dict."""
+    L = lib()
+    held = []
+
+    def _make(opt_ptr, user):
+        try:
+            opt = ctypes.cast(opt_ptr, ctypes.POINTER(Options)).contents
+            t = Tuning()
+            ctypes.memmove(ctypes.byref(t), opt.tuning, ctypes.sizeof(Tuning))
+            e = make_engine(t)
+            held.append(e)
+            h = e._h
+            e._h = None          # the library destroys this context
+            return h
+        except Exception:        # a failed factory is reported as NULL
+            return None
+
+    cb = MAKE_FN(_make)
+    best = Tuning()
+    rc = L.fv_autotune(cb, None, None, reps, cache_path.encode() if cache_path else None,
+                       key.encode() if key else None, ctypes.byref(best))
+    if rc != FV_OK:
+        raise FvError(rc, L.fv_global_error().decode())
+    return best.as_dict()
+
+
+MLP_PARAMS = 4801
+
+
+def _mlp_check(rc):
+    if rc != FV_OK:
+        raise FvError(rc, lib().fv_global_error().decode())
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def mlp_grad(X, y, params):
+    """(loss, gradient) of the predictor MLP on (X, y), computed on the GPU."""
+    X, y, P = _f32(X, (-1, 8)), _f32(y, (-1,)), _f32(params, (MLP_PARAMS,))
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    _mlp_check(lib().fv_mlp_grad(X.ctypes.data, y.ctypes.data, len(y), P.ctypes.data, g.ctypes.data,
+                                 loss.ctypes.data))
+    return float(loss[0]), g
+
+
+def mlp_train(X, y, steps=2000, lr=1e-3, seed=1, params=None):
+    """Train the predictor on the GPU; returns (params, final loss)."""
+    X, y = _f32(X, (-1, 8)), _f32(y, (-1,))
+    P = np.zeros(MLP_PARAMS, np.float32) if params is None else _f32(params, (MLP_PARAMS,)).copy()
+    loss = np.zeros(1, np.float32)
+    _mlp_check(lib().fv_mlp_train(X.ctypes.data, y.ctypes.data, len(y), steps, lr, seed,
+                                  1 if params is None else 0, P.ctypes.data, loss.ctypes.data))
+    return P, float(loss[0])
+
+
+def mlp_predict(X, params):
+    """BF16 inference of the predictor on the GPU."""
+    X, P = _f32(X, (-1, 8)), _f32(params, (MLP_PARAMS,))
+    out = np.zeros(len(X), np.float32)
+    _mlp_check(lib().fv_mlp_predict(X.ctypes.data, len(X), P.ctypes.data, out.ctypes.data))
+    return out
+
+
+def tuning_load(cache_path: str, key: str):
+    """Tuning stored by autotune for this GPU's architecture, or None."""
+    t = Tuning()
+    if lib().fv_tuning_load(cache_path.encode(), key.encode(), ctypes.byref(t)) != FV_OK:
+        return None
+    return t.as_dict()
+
+
+def evaluate(program: str, edb: dict, flags: int = FV_PLAIN, relations=None, device_out: bool = False,
+             tuning=None, predictor=None, with_trace: bool = False):
     """Load `edb` (name -> list of columns), run `program` to its fixpoint on
-    the GPU and return (relations as row-sorted arrays, stats, delta sizes)."""
-    eng = Engine(flags=flags)
+    the GPU and return (relations as row-sorted arrays, stats, delta sizes,
+    kernel profile) -- plus the join trace when with_trace."""
+    eng = Engine(flags=flags, tuning=tuning, predictor=predictor)
     try:
         rules = parse_program(program)
         arities = {}
@@ -420,6 +542,8 @@ def evaluate(program: str, edb: dict, flags: int = FV_PLAIN, relations=None, dev
         names = relations if relations is not None else list(arities)
         out = {name: eng.export(name, device=device_out) for name in names}
         prof = eng.profile()
+        if with_trace:
+            return out, stats, eng.delta_sizes(), prof, eng.join_trace()
         return out, stats, eng.delta_sizes(), prof
     finally:
         eng.close()

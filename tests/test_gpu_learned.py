@@ -1,0 +1,66 @@
+"""The learned join-cardinality path: identical fixpoints whatever the
+predictor says, join traces, and a predictor trained on the plain engine's
+traces."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_13051_amd import fv
+from paper_2501_13051_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ZERO = np.zeros(fv.MLP_PARAMS, np.float32)
+HUGE = np.zeros(fv.MLP_PARAMS, np.float32)
+HUGE[-1] = 2.0          # b3: predicts log2(1+m) = 32 for every join
+
+
+def _cases():
+    d = W.rdfs_triples(n_triples=60_000, class_depth=5, n_entities=8_000, trans_tree=32, seed=9)
+    pt = W.config_pointsto(scale=0.05)
+    return [
+        (W.TC_PROGRAM, {"edge": W.er_graph(700, 1400, seed=5)}, ["path"]),
+        (W.SG_PROGRAM, {"edge": W.forest(8, 256, 0.05, seed=1002)}, ["sg"]),
+        (pt.program, pt.edb, list(pt.idb)),
+        (W.RDFS_PROGRAM, {"t": d["t"]}, ["t"]),
+    ]
+
+
+@pytest.mark.parametrize("stub", ["zero", "huge"])
+def test_stub_predictors_leave_the_fixpoint_unchanged(stub):
+    params = ZERO if stub == "zero" else HUGE
+    for program, edb, rels in _cases():
+        ref = oracle.evaluate(program, edb)
+        got, stats, deltas, _ = fv.evaluate(program, edb, flags=fv.FV_LEARNED, relations=rels, predictor=params)
+        for r in rels:
+            assert np.array_equal(got[r], ref[r]), r
+        assert deltas == ref.delta_sizes
+        if stub == "zero":
+            assert stats["overflows"] > 0          # every presized buffer is too small: exact fallback
+        assert stats["predicted_joins"] > 0
+
+
+def test_join_trace_records_true_sizes():
+    program, edb, rels = _cases()[1]
+    got, stats, deltas, _, trace = fv.evaluate(program, edb, flags=fv.FV_LOG_JOINS, relations=rels,
+                                               with_trace=True)
+    assert trace.shape[1] == fv.TRACE_COLS and len(trace) >= 2 * (len(deltas) - 1)
+    assert np.all(trace[:, 9] == -1)
+    # every round's join outputs add up to what the joins wrote before filters
+    assert np.all(trace[:, 8] >= 0)
+    assert stats["join_output_tuples"] > 0
+
+
+def test_trained_predictor_on_plain_traces():
+    rows = []
+    for program, edb, rels in _cases()[:3]:
+        *_, trace = fv.evaluate(program, edb, flags=fv.FV_LOG_JOINS, relations=rels, with_trace=True)
+        rows.append(trace)
+    T = np.concatenate(rows)
+    params, loss = fv.mlp_train(T[:, :8], T[:, 8], steps=1500, lr=3e-3, seed=3)
+    assert np.isfinite(loss)
+    program, edb, rels = _cases()[3]     # held out: RDFS
+    ref = oracle.evaluate(program, edb)
+    got, stats, deltas, _ = fv.evaluate(program, edb, flags=fv.FV_LEARNED, relations=rels, predictor=params)
+    assert np.array_equal(got["t"], ref["t"]) and deltas == ref.delta_sizes
+    assert stats["predicted_joins"] > 0 and stats["qerror_median"] >= 1.0

@@ -21,10 +21,19 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def _check(program, edb, relations=None, flags=fv.FV_PLAIN):
+TUNINGS = {
+    "default": None,
+    "radix11": {"radix_bits": 11},
+    "fused": {"fuse_dedup": 1},
+    "radix11_fused_tight": {"radix_bits": 11, "fuse_dedup": 1, "set_load": 0.75, "index_load": 0.75,
+                            "max_blocks": 256},
+}
+
+
+def _check(program, edb, relations=None, flags=fv.FV_PLAIN, tuning=None):
     ref = oracle.evaluate(program, edb)
     names = relations or list(ref.relations)
-    got, stats, deltas, _ = fv.evaluate(program, edb, flags=flags, relations=names)
+    got, stats, deltas, _ = fv.evaluate(program, edb, flags=flags, relations=names, tuning=tuning)
     for n in names:
         assert got[n].shape == ref[n].shape, (n, got[n].shape, ref[n].shape)
         assert np.array_equal(got[n], ref[n]), n
@@ -63,6 +72,25 @@ def test_random_programs(seed):
     rnd = random.Random(seed)
     prog = random_program(rnd)
     _check(prog, random_edb(rnd))
+
+
+@pytest.mark.parametrize("tuning", list(TUNINGS), ids=list(TUNINGS))
+@pytest.mark.parametrize("seed", range(30, 38))
+def test_random_programs_tuned(seed, tuning):
+    rnd = random.Random(seed)
+    prog = random_program(rnd)
+    _check(prog, random_edb(rnd), tuning=TUNINGS[tuning])
+
+
+@pytest.mark.parametrize("tuning", list(TUNINGS), ids=list(TUNINGS))
+def test_tuned_workloads(tuning):
+    t = TUNINGS[tuning]
+    _check(W.TC_PROGRAM, {"edge": W.er_graph(700, 1400, seed=5)}, tuning=t)
+    _check(W.SG_PROGRAM, {"edge": W.forest(8, 256, 0.05, seed=1002)}, tuning=t)
+    w = W.config_pointsto(scale=0.05)
+    _check(w.program, w.edb, relations=list(w.idb), tuning=t)
+    d = W.rdfs_triples(n_triples=60_000, class_depth=5, n_entities=8_000, trans_tree=32, seed=9)
+    _check(W.RDFS_PROGRAM, {"t": d["t"]}, relations=["t"], tuning=t)
 
 
 def test_empty_and_duplicate_inputs():
@@ -120,9 +148,10 @@ def test_config_tc_full_size():
     assert stats["derived_tuples"] == len(ref["path"])
 
 
-def test_config_sg_full_size():
+@pytest.mark.parametrize("tuning", ["default", "radix11_fused_tight"])
+def test_config_sg_full_size(tuning):
     w = W.config_sg()
-    got, stats, ref = _check(w.program, w.edb, relations=["sg"])
+    got, stats, ref = _check(w.program, w.edb, relations=["sg"], tuning=TUNINGS[tuning])
     assert stats["derived_tuples"] == len(ref["sg"])
 
 

@@ -1,14 +1,19 @@
-"""Benchmark: derived tuples/s to fixpoint of the plain semi-naive engine.
+"""Benchmark: derived tuples/s to fixpoint on one MI355X.
 
-One step is one whole fixpoint of the same-generation program over a random
-forest of 64 trees x 1,024 nodes with 5% extra forward edges (68,736 edges,
-9,594,866 derived tuples): loading the EDB from HBM-resident columns, every
-round of join / radix sort / difference / merge, until no tuple is new.
-Inputs are generated and copied to the device before the timed region.
+Headline (`value`): whole fixpoints of the same-generation program over a
+random forest of 64 trees x 1,024 nodes with 5% extra forward edges (68,736
+edges, 9,594,866 derived tuples).  One step = create a context, load the EDB
+from HBM-resident columns, run every round of join / radix sort / difference
+/ merge to the fixpoint.  Inputs are generated and copied to the device
+before the timed region.  The engine's knobs come from its own autotuner,
+run on this workload before timing.
 
-Prints one JSON line with the throughput, the roofline of the dominant
-kernel class (algorithmic bytes over HIP-event time on the engine's
-stream) and the oracle timed on the host cores on the same workload.
+The JSON line also carries: the roofline of the dominant kernel class
+(algorithmic bytes over its HIP-event time inside the timed region, against
+8 TB/s), the oracle timed on the host, and the engine's other forms measured
+against the plain engine -- 512 batched transitive-closure instances vs the
+same instances run one after another, the learned predictor on the 20M-triple
+RDFS workload, and the autotuned points-to workload.
 """
 from __future__ import annotations
 
@@ -32,22 +37,58 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="headline only (no batched/learned/autotune forms)")
+    ap.add_argument("--no-autotune", action="store_true")
     return ap.parse_args()
 
 
-def one_fixpoint(fv, program_rules, edge_dev, flags):
-    eng = fv.Engine(flags=flags)
-    try:
-        eng.relation("edge", 2)
-        eng.relation("sg", 2)
-        eng.load("edge", edge_dev)
-        for head, body, neq in program_rules:
-            eng.add_rule(head, body, neq)
-        stats = eng.run()
-        prof = eng.profile() if flags & fv.FV_TRACE else []
-        return stats, prof
-    finally:
-        eng.close()
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+class Runner:
+    """Builds loaded contexts for one workload (EDB resident on the device)."""
+
+    def __init__(self, fv, torch, np, program, edb, relations):
+        self.fv, self.torch = fv, torch
+        self.rules = fv.parse_program(program)
+        self.arity = {}
+        for head, body, _ in self.rules:
+            for name, ts in [head] + body:
+                self.arity.setdefault(name, len(ts))
+        self.edb = {k: [torch.from_numpy(np.asarray(c).astype(np.int32)).cuda() for c in v] for k, v in edb.items()}
+        for k, v in edb.items():
+            self.arity.setdefault(k, len(v))
+        self.relations = relations
+        torch.cuda.synchronize()
+
+    def make(self, **kw):
+        e = self.fv.Engine(**kw)
+        for name, a in self.arity.items():
+            e.relation(name, a)
+        for name, cols in self.edb.items():
+            e.load(name, cols)
+        for head, body, neq in self.rules:
+            e.add_rule(head, body, neq)
+        return e
+
+    def run_once(self, **kw):
+        e = self.make(**kw)
+        try:
+            st = e.run()
+            prof = e.profile()
+            trace = e.join_trace() if kw.get("flags", 0) & (self.fv.FV_LOG_JOINS | self.fv.FV_LEARNED) else None
+            return st, prof, trace
+        finally:
+            e.close()
+
+    def time_runs(self, reps, **kw):
+        """Median fv_run_fixpoint time (ms) over fresh contexts; last stats."""
+        ms, st = [], None
+        for _ in range(reps):
+            st, _, _ = self.run_once(**kw)
+            ms.append(st["ms_total"])
+        return sorted(ms)[len(ms) // 2], st
 
 
 def main():
@@ -67,54 +108,42 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     w = W.config_sg()
-    rules = fv.parse_program(w.program)
-    edge_dev = [torch.from_numpy(c.astype(np.int32)).cuda() for c in w.edb["edge"]]
-    torch.cuda.synchronize()
-    flags = fv.FV_TRACE
+    sg = Runner(fv, torch, np, w.program, w.edb, ["sg"])
+
+    tuning = None
+    if not args.no_autotune:
+        log("autotuning the engine on the same-generation workload")
+        tuning = fv.autotune(lambda t: sg.make(tuning=t), key="sg_forest_t64_n1024", reps=3)
+        log(f"tuning {tuning}")
+
+    # dominant kernel class from one traced pass (outside the timed region)
+    _, prof, _ = sg.run_once(flags=fv.FV_TRACE, tuning=tuning)
+    dom_name = max(prof, key=lambda k: k["ms"])["name"]
 
     for _ in range(args.warmup):
-        one_fixpoint(fv, rules, edge_dev, flags)
+        sg.run_once(flags=fv.FV_TRACE, tuning=tuning, trace_only=dom_name)
     torch.cuda.synchronize()
-
-    totals = {}
-    derived = None
-    iters = None
+    log(f"timing {args.steps} steps")
+    dom = {"launches": 0, "ms": 0.0, "algo_bytes": 0.0, "items": 0}
+    derived = iters = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        stats, prof = one_fixpoint(fv, rules, edge_dev, flags)
-        derived = stats["derived_tuples"]
-        iters = stats["iterations"]
+        st, prof, _ = sg.run_once(flags=fv.FV_TRACE, tuning=tuning, trace_only=dom_name)
+        derived, iters = st["derived_tuples"], st["iterations"]
         for k in prof:
-            t = totals.setdefault(k["name"], {"launches": 0, "ms": 0.0, "algo_bytes": 0.0, "items": 0})
-            for f in ("launches", "ms", "algo_bytes", "items"):
-                t[f] += k[f]
+            if k["name"] == dom_name:
+                for f in dom:
+                    dom[f] += k[f]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1000.0 / max(args.steps, 1)
     value = derived * args.steps / elapsed if elapsed > 0 else 0.0
-
-    # dominant kernel class: most event time inside the timed region
-    dom_name, dom = max(totals.items(), key=lambda kv: kv[1]["ms"])
-    avg_ms = dom["ms"] / max(dom["launches"], 1)
     achieved = dom["algo_bytes"] / (dom["ms"] * 1e-3) / 1e9 if dom["ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "avg_launch_ms": round(avg_ms, 5), "launches_per_step": dom["launches"] / max(args.steps, 1),
-                "algo_bytes_per_launch": dom["algo_bytes"] / max(dom["launches"], 1)}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        secs = []
-        n_out = None
-        for _ in range(max(1, args.cpu_reps)):
-            r = oracle.evaluate(w.program, w.edb, relations=["sg"])
-            secs.append(r.seconds)
-            n_out = len(r["sg"])
-        s = sorted(secs)[len(secs) // 2]
-        cpu = {"value": round(n_out / s, 1), "unit": "tuples/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole workload, {len(secs)} runs, median fixpoint time {s:.3f} s "
-                         f"(single-threaded sorted-vector semi-naive, {os.cpu_count()} host cores visible)"}
+                "avg_launch_ms": round(dom["ms"] / max(dom["launches"], 1), 5),
+                "launches_per_step": dom["launches"] / max(args.steps, 1),
+                "algo_bytes_per_launch": round(dom["algo_bytes"] / max(dom["launches"], 1), 1)}
 
     out = {
         "metric": "derived tuples/s to fixpoint",
@@ -132,15 +161,118 @@ def main():
         "config": {"workload": "same-generation fixpoint, random forest 64 trees x 1024 nodes, "
                                "5% extra in-tree forward edges, seed 1002",
                    "edges": w.meta["edges"], "derived_tuples": derived, "rounds": iters,
-                   "engine": "plain (count-then-write joins, host round loop)"},
+                   "engine": "plain semi-naive (count-then-write joins, one sync per round), autotuned knobs",
+                   "tuning": tuning},
         "roofline": roofline,
-        "cpu_baseline": cpu,
-        "kernels": {k: {"launches_per_step": v["launches"] / args.steps,
-                        "ms_per_step": round(v["ms"] / args.steps, 4),
-                        "GBps": round(v["algo_bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else 0}
-                    for k, v in sorted(totals.items(), key=lambda kv: -kv[1]["ms"])},
+        "cpu_baseline": None,
     }
+
+    # the same workload with the default knobs, for reference
+    plain_ms, _ = sg.time_runs(max(3, args.steps // 2))
+    out["config"]["default_knobs_ms_per_fixpoint"] = round(plain_ms, 3)
+
+    if not args.no_extras:
+        out["forms"] = extras(fv, W, torch, np, args)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the oracle")
+        secs, n_out = [], None
+        for _ in range(max(1, args.cpu_reps)):
+            r = oracle.evaluate(w.program, w.edb, relations=["sg"])
+            secs.append(r.seconds)
+            n_out = len(r["sg"])
+        s = sorted(secs)[len(secs) // 2]
+        out["cpu_baseline"] = {"value": round(n_out / s, 1), "unit": "tuples/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole workload, {len(secs)} runs, median fixpoint time {s:.3f} s "
+                                         f"(single-threaded sorted-vector semi-naive; {os.cpu_count()} host "
+                                         f"cores visible)"}
     print(json.dumps(out), flush=True)
+
+
+def extras(fv, W, torch, np, args):
+    forms = {}
+    # --- batched: 512 independent TC instances, one fixpoint vs 512 fixpoints
+    log("batched form: 512 transitive-closure instances")
+    insts = W.batched_tc_instances()
+    runners = [Runner(fv, torch, np, x.program, x.edb, ["path"]) for x in insts]
+
+    def serial():
+        es = [r.make() for r in runners]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tot = 0
+        for e in es:
+            tot += e.run()["derived_tuples"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for e in es:
+            e.close()
+        return dt, tot
+
+    def batched(flags):
+        es = [r.make(flags=flags) for r in runners]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = fv.run_batch(es)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for e in es:
+            e.close()
+        return dt, st
+
+    serial()
+    ts, tot = serial()
+    batched(0)
+    tb, stb = batched(0)
+    tg, stg = batched(fv.FV_GRAPH)
+    forms["batched_tc_512"] = {
+        "derived_tuples": int(tot), "serial_plain_ms": round(ts * 1e3, 2), "batched_ms": round(tb * 1e3, 2),
+        "batched_graph_ms": round(tg * 1e3, 2), "speedup": round(ts / tb, 2),
+        "rounds": stb["iterations"], "graph_replays": stg["graph_replays"],
+        "tuples_per_s_batched": round(tot / tb, 1)}
+    del runners
+
+    # --- learned predictor: train on plain-engine traces of TC, SG, points-to
+    # and the batched TC run, apply to the RDFS workload
+    log("learned form: collecting join traces")
+    rows = []
+    sources = [(W.config_tc(), ["path"]), (W.config_sg(), ["sg"]), (W.config_pointsto(), None)]
+    for wl, rels in sources:
+        r = Runner(fv, torch, np, wl.program, wl.edb, rels or list(wl.idb))
+        _, _, trace = r.run_once(flags=fv.FV_LOG_JOINS)
+        rows.append(trace)
+    T = np.concatenate(rows)
+    params, loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
+    log(f"trained on {len(T)} join records, loss {loss:.5f}")
+    rd = W.config_rdfs()
+    rr = Runner(fv, torch, np, rd.program, rd.edb, ["t"])
+    rr.run_once()
+    plain_ms, plain_st = rr.time_runs(3)
+    rr.run_once(flags=fv.FV_LEARNED, predictor=params)
+    learned_ms, lst = rr.time_runs(3, flags=fv.FV_LEARNED, predictor=params)
+    forms["learned_rdfs_20M"] = {
+        "train_records": int(len(T)), "train_loss": round(loss, 6), "plain_ms": round(plain_ms, 2),
+        "learned_ms": round(learned_ms, 2), "speedup": round(plain_ms / learned_ms, 3),
+        "derived_tuples": int(lst["derived_tuples"]), "plain_redo_rounds": plain_st["redo_rounds"],
+        "overflow_fallbacks": lst["overflows"], "predicted_joins": lst["predicted_joins"],
+        "qerror_median": round(lst["qerror_median"], 3), "qerror_max": round(lst["qerror_max"], 3),
+        "tuples_per_s_learned": round(lst["derived_tuples"] / (learned_ms * 1e-3), 1)}
+    del rr
+
+    # --- autotuned single-instance points-to
+    log("autotuned form: points-to")
+    pt = W.config_pointsto()
+    pr = Runner(fv, torch, np, pt.program, pt.edb, list(pt.idb))
+    pr.run_once()
+    p_ms, p_st = pr.time_runs(3)
+    tune = fv.autotune(lambda t: pr.make(tuning=t), key="pointsto_n200000", reps=3)
+    t_ms, t_st = pr.time_runs(3, tuning=tune)
+    forms["autotuned_pointsto"] = {"plain_ms": round(p_ms, 2), "tuned_ms": round(t_ms, 2),
+                                   "speedup": round(p_ms / t_ms, 3), "tuning": tune,
+                                   "derived_tuples": int(t_st["derived_tuples"]),
+                                   "tuples_per_s_tuned": round(t_st["derived_tuples"] / (t_ms * 1e-3), 1)}
+    return forms
 
 
 if __name__ == "__main__":

@@ -91,6 +91,7 @@ typedef struct {
   uint32_t flags;          /* FV_* flags above */
   const fv_tuning* tuning; /* optional; copied at fv_ctx_create */
   const float* predictor;  /* FV_MLP_PARAMS floats (see fv_mlp_train); required by FV_LEARNED */
+  const char* trace_only;  /* with FV_TRACE: time only this kernel class (see fv_profile names) */
 } fv_options;
 
 /* A term of an atom: a variable (is_const = 0, value = variable index within

@@ -60,6 +60,8 @@ Engine::Engine(const fv_options* opt) {
     predictor_.assign(opt_.predictor, opt_.predictor + kMlpParams);
   }
   opt_.predictor = nullptr;
+  if (opt_.trace_only) trace_only_ = opt_.trace_only;
+  opt_.trace_only = nullptr;
 }
 
 Engine::~Engine() {
@@ -670,8 +672,9 @@ int Engine::kclass(const char* name) {
   return int(kprof_.size() - 1);
 }
 
-void Engine::ev_begin(int) {
+void Engine::ev_begin(int cls) {
   if (!trace_) return;
+  if (!trace_only_.empty() && kprof_[cls].name != trace_only_) { ev_open_ = nullptr; return; }
   hipEvent_t e;
   if (!ev_pool_.empty()) { e = ev_pool_.back(); ev_pool_.pop_back(); }
   else hip(hipEventCreate(&e), "event create");
@@ -680,7 +683,7 @@ void Engine::ev_begin(int) {
 }
 
 void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux) {
-  if (!trace_) return;
+  if (!trace_ || !ev_open_) return;
   hipEvent_t e;
   if (!ev_pool_.empty()) { e = ev_pool_.back(); ev_pool_.pop_back(); }
   else hip(hipEventCreate(&e), "event create");
@@ -1607,7 +1610,11 @@ void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
   if (stride * n > 0xFFFFFFFFull) throw Error(FV_ENOTSUP, "batched instances do not fit the 32-bit id space");
 
   auto B = std::make_shared<BatchResult>();
-  B->merged = std::make_shared<Engine>(&E0.opt_);
+  fv_options mopt = E0.opt_;
+  mopt.tuning = &E0.tune_;
+  mopt.predictor = E0.learned_ ? E0.predictor_.data() : nullptr;
+  if (!E0.trace_only_.empty()) mopt.trace_only = E0.trace_only_.c_str();
+  B->merged = std::make_shared<Engine>(&mopt);
   B->stride = stride;
   Engine& M = *B->merged;
   for (auto& R : E0.rels_) M.relation_create(R.name.c_str(), R.arity);
@@ -1639,6 +1646,7 @@ void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
   M.rules_ = E0.rules_;
   M.run(stats);
   B->deltas = M.deltas_;
+  E0.trace_rows_ = M.trace_rows_;   // the merged run's join trace is reported on the first instance
 
   // every relation sorted once in the merged id space; instance k's rows are
   // the run whose first column lies in [k * stride, (k + 1) * stride)

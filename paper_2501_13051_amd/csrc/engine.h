@@ -271,6 +271,7 @@ class Engine {
   u64 join_out_ = 0;
 
   bool trace_ = false;
+  std::string trace_only_;     // non-empty: only this kernel class gets events
   bool touched_device_ = false;
   std::shared_ptr<BatchResult> batch_;   // set on instance contexts of a batch
   u32 inst_ = 0;

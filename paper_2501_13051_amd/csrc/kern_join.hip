@@ -176,10 +176,14 @@ __device__ __forceinline__ void append_tile(const OutSpec& o, const bool* keep, 
       if (!keep[k]) continue;
       if (o.packed) {
         u64 key = 0;
-        for (u32 c = 0; c < o.ncols; ++c) key |= u64(vals[k].v[c]) << o.shift[c];
+#pragma unroll
+        for (u32 c = 0; c < kMaxCols; ++c)
+          if (c < o.ncols) key |= u64(vals[k].v[c]) << o.shift[c];
         o.keys[pos] = key;
       } else {
-        for (u32 c = 0; c < o.ncols; ++c) o.cols[c][pos] = vals[k].v[c];
+#pragma unroll
+        for (u32 c = 0; c < kMaxCols; ++c)
+          if (c < o.ncols) o.cols[c][pos] = vals[k].v[c];
       }
       ++pos;
     }
@@ -237,8 +241,11 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
         ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
       }
       keep[k] = ok;
-      if (ok)
-        for (u32 c = 0; c < p.out.ncols; ++c) vals[k].v[c] = src_val(p.out.src[c], p.pcol, prow, p.bcol, brow);
+      if (ok) {
+#pragma unroll
+        for (u32 c = 0; c < kMaxCols; ++c)
+          if (c < p.out.ncols) vals[k].v[c] = src_val(p.out.src[c], p.pcol, prow, p.bcol, brow);
+      }
     }
     append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
   }
@@ -370,8 +377,11 @@ __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
         ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
       }
       keep[k] = ok;
-      if (ok)
-        for (u32 c = 0; c < p.out.ncols; ++c) vals[k].v[c] = probe_val(p.out.src[c], p.pcol, row);
+      if (ok) {
+#pragma unroll
+        for (u32 c = 0; c < kMaxCols; ++c)
+          if (c < p.out.ncols) vals[k].v[c] = probe_val(p.out.src[c], p.pcol, row);
+      }
     }
     append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
   }

@@ -48,7 +48,7 @@ class Tuning(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN),
                 ("user", ctypes.c_void_p), ("flags", ctypes.c_uint32), ("tuning", ctypes.POINTER(Tuning)),
-                ("predictor", ctypes.POINTER(ctypes.c_float))]
+                ("predictor", ctypes.POINTER(ctypes.c_float)), ("trace_only", ctypes.c_char_p)]
 
 
 class Term(ctypes.Structure):
@@ -234,7 +234,7 @@ class Engine:
     """One fixpoint context on the current CUDA/HIP device and stream."""
 
     def __init__(self, flags: int = FV_PLAIN, stream=None, use_torch_allocator: bool = True, tuning=None,
-                 predictor=None):
+                 predictor=None, trace_only: str = None):
         import torch
         self._torch = torch
         L = lib()
@@ -250,6 +250,9 @@ class Engine:
         if tuning is not None:
             self._tuning = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
             opt.tuning = ctypes.pointer(self._tuning)
+        if trace_only is not None:
+            self._trace_only = trace_only.encode()
+            opt.trace_only = self._trace_only
         if predictor is not None:
             self._predictor = np.ascontiguousarray(np.asarray(predictor, dtype=np.float32))
             if self._predictor.size != 4801:

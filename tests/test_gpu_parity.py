@@ -45,7 +45,7 @@ def _edb_from_rows(d):
     return {k: [np.asarray(v, np.uint32)[:, c].copy() for c in range(len(v[0]))] for k, v in d.items()}
 
 
-@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.json"))), ids=os.path.basename)
+@pytest.mark.parametrize("path", sorted(f for f in glob.glob(os.path.join(GOLDEN, "*.json")) if "digest" not in f), ids=os.path.basename)
 def test_golden(path):
     g = json.load(open(path))
     edb = _edb_from_rows(g["edb"])

@@ -34,7 +34,7 @@ def _edb_from_rows(d):
     return out
 
 
-@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.json"))), ids=os.path.basename)
+@pytest.mark.parametrize("path", sorted(f for f in glob.glob(os.path.join(GOLDEN, "*.json")) if "digest" not in f), ids=os.path.basename)
 @pytest.mark.parametrize("naive", [False, True])
 def test_golden_by_hand(path, naive):
     g = json.load(open(path))

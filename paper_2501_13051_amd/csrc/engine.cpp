@@ -147,7 +147,12 @@ void Engine::begin_phase() {
     launched(launch_fill_u32(epoch_base(), 1, 0u, stream_), "epoch reset");
     phases_ = 0;
   }
-  launched(launch_round_prologue(nullptr, 0, nullptr, nullptr, 0, epoch_base(), stream_), "epoch advance");
+  // a new phase starts with the overflow and set-full flags down: kernels that
+  // rebuild state before the next round (index builds) skip their work while
+  // the flag of a failed round is still up
+  launched(launch_round_prologue(nullptr, 0, flags_dev_.p ? flags_dev_.as<u32>() : nullptr, nullptr, 0, epoch_base(),
+                                 stream_),
+           "epoch advance");
   ++phases_;
   epoch_off_ = 1;
 }
@@ -342,17 +347,27 @@ Plan Engine::plan_rule(u32 ri, int dpos) {
   used[first] = true;
   for (auto& t : r.body[first].t)
     if (!t.is_const) bound[t.value] = true;
+  // Next atom, most bound first: one connected to what is bound (or with no
+  // variable left to bind), then the fewest variables it newly binds (an atom
+  // bound in every position is a semi-join and can only shrink the result),
+  // then the most shared variables, the most constants, EDB before IDB.
   while (order.size() < nb) {
-    int best = -1, best_score = -1;
+    int best = -1;
+    long best_score = -1;
     for (u32 i = 0; i < nb; ++i) {
       if (used[i]) continue;
-      int shared = 0, consts = 0;
+      int shared = 0, consts = 0, fresh = 0;
       std::vector<bool> seen(kMaxVars, false);
       for (auto& t : r.body[i].t) {
-        if (t.is_const) ++consts;
-        else if (bound[t.value] && !seen[t.value]) { ++shared; seen[t.value] = true; }
+        if (t.is_const) { ++consts; continue; }
+        if (seen[t.value]) continue;
+        seen[t.value] = true;
+        if (bound[t.value]) ++shared;
+        else ++fresh;
       }
-      const int score = shared * 8 + consts * 2 + (rels_[r.body[i].rel].idb ? 0 : 1);
+      const bool connected = shared > 0 || fresh == 0;
+      const long score = (connected ? 1L << 24 : 0) + long(kMaxCols + 1 - fresh) * 4096 + shared * 64 + consts * 4 +
+                         (rels_[r.body[i].rel].idb ? 0 : 1);
       if (score > best_score) { best_score = score; best = int(i); }
     }
     order.push_back(u32(best));
@@ -502,7 +517,8 @@ void Engine::plan_all() {
   }
   for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
   // counter layout: [derived, join_out] [full_n x R] [d_begin x R]
-  //   [index distinct keys] [HLL estimates] [predicted join sizes]   (kept across rounds)
+  //   [index distinct keys] [index longest runs] [index full flags] [HLL estimates]
+  //   [predicted join sizes]                                          (kept across rounds)
   //   [delta x R] [new x R] [per-join m,t] [per-intermediate count]  (cleared every round)
   const int R = int(rels_.size());
   c_derived_ = 0;
@@ -512,6 +528,8 @@ void Engine::plan_all() {
   int next = c_dbeg0_ + R;
   c_ndv0_ = next;
   for (auto& ix : indices_) ix.c_ndv = next++;
+  for (auto& ix : indices_) ix.c_maxrun = next++;
+  for (auto& ix : indices_) ix.c_full = next++;
   c_hll0_ = next;
   sketches_.clear();
   if (log_joins_) {
@@ -612,13 +630,23 @@ bool Engine::ensure_capacity() {
   for (auto& ix : indices_) {
     const Relation& R = rels_[ix.rel];
     const u64 rows = R.used_as_head ? R.n_full + R.new_cap : R.n_full;
-    const u64 expect = R.used_as_head ? R.n_full + std::max<u64>(3 * R.n_delta, 1024) : R.n_full;
-    const u64 need = pow2_at_least(std::max<u64>({rows + 1, u64(double(expect) / tune_.index_load), 64}));
-    if (ix.cap < rows + 1 || ix.cap < expect * 3 / 2) {
+    // The table holds distinct keys, not rows: size it from the last build's
+    // count (with room to double on a derived relation), or from the rows
+    // before the first build.  A build that still runs out of slots raises
+    // the index's full flag and the table is rebuilt larger before the next
+    // round reads it.
+    u64 keys;
+    if (ix.keys_seen) keys = R.used_as_head ? 2 * std::max<u64>(ix.keys_seen, 512) : ix.keys_seen;
+    else keys = R.used_as_head ? R.n_full + std::max<u64>(3 * R.n_delta, 1024) : R.n_full;
+    keys = std::min<u64>(keys, rows + 1);
+    u64 need = pow2_at_least(std::max<u64>(u64(double(keys) / tune_.index_load), 64));
+    if (ix.grow) need = std::max<u64>(need, 4 * ix.cap);
+    if (ix.cap == 0 || ix.grow || double(keys) > 0.75 * double(ix.cap)) {
       release(ix.table);
       ix.table = alloc(need * sizeof(Slot));
       ix.cap = need;
       ix.dirty = true;
+      ix.grow = false;
     }
     if (ix.perm_cap < rows) {
       release(ix.perm);
@@ -1042,6 +1070,8 @@ void Engine::build_index(Index& ix) {
   p.epoch_off = next_epoch();
   p.abort = flags_dev_.as<u32>();
   p.ndv = ix.c_ndv >= 0 ? ctr(ix.c_ndv) : nullptr;
+  p.maxrun = ix.c_maxrun >= 0 ? ctr(ix.c_maxrun) : nullptr;
+  p.full = ix.c_full >= 0 ? ctr(ix.c_full) : nullptr;
   const int kc = kclass("index_build");
   ev_begin(kc);
   launched(launch_index_build(p, std::max<u64>(R.cap, 1), stream_), "index launch");
@@ -1247,16 +1277,20 @@ void Engine::run_round(bool initial) {
   if (!learned_) {
     // size the next round from this one: outputs tend to grow round over
     // round, and a buffer that overflows costs a whole re-run of the round
+    // (4x while small, 2x past 2^24 rows, where memory rather than a re-run
+    // is the scarcer resource)
+    auto ahead = [](u64 used) { return used < (u64(1) << 24) ? 4 * used : 2 * used; };
     for (auto& R : rels_) {
       if (!R.used_as_head) continue;
-      const u64 used = ctr_host_[c_new0_ + int(&R - &rels_[0])];
-      if (4 * used > R.new_cap) R.new_cap = pow2_at_least(4 * used);
+      const u64 want = ahead(ctr_host_[c_new0_ + int(&R - &rels_[0])]);
+      if (want > R.new_cap) R.new_cap = pow2_at_least(want);
     }
     for (auto& I : inters_) {
-      const u64 used = ctr_host_[I.ctr];
-      if (4 * used > I.cap) I.cap = pow2_at_least(4 * used);
+      const u64 want = ahead(ctr_host_[I.ctr]);
+      if (want > I.cap) I.cap = pow2_at_least(want);
     }
   }
+  note_index_builds();
   u64 total = 0;
   for (auto& R : rels_) {
     const int ri = int(&R - &rels_[0]);
@@ -1268,6 +1302,20 @@ void Engine::run_round(bool initial) {
   }
   join_out_ = ctr_host_[c_joinout_];
   deltas_.push_back(total);
+}
+
+// After a round: the distinct-key counts of the indices just built size their
+// tables for the next round; an index whose build ran out of slots is
+// incomplete and is rebuilt larger before any join reads it.
+void Engine::note_index_builds() {
+  for (auto& ix : indices_) {
+    if (ctr_host_[ix.c_full]) {
+      ix.grow = true;
+      continue;
+    }
+    const u64 ndv = ctr_host_[ix.c_ndv];
+    if (ndv) ix.keys_seen = ndv;
+  }
 }
 
 // ------------------------------------------------------------------ learned predictor
@@ -1288,6 +1336,7 @@ void Engine::setup_learning() {
         sp.probe_dbeg = p.delta_pos >= 0 ? c_dbeg0_ + int(p.src_rel) : -1;
         sp.build_full = c_full0_ + int(st.brel);
         sp.ndv_build = st.index != kNoIndex ? indices_[st.index].c_ndv : -1;
+        sp.maxrun_build = st.index != kNoIndex ? indices_[st.index].c_maxrun : -1;
         sp.hll = (k == 0 && st.hll >= 0) ? sketches_[st.hll].ctr : -1;
         sp.nkey = st.nkey;
         sp.nfilt = u32(st.wf.size());
@@ -1355,8 +1404,12 @@ void Engine::size_from_predictions(bool initial) {
       }
     }
   }
-  for (size_t r = 0; r < rels_.size(); ++r)
-    if (rels_[r].used_as_head && rels_[r].new_cap < need_new[r]) rels_[r].new_cap = pow2_at_least(need_new[r]);
+  // a relation's new-tuple buffer (and the tuple set and indices sized from
+  // it) is presized to at most 2^28 rows; more comes from the exact fallback
+  for (size_t r = 0; r < rels_.size(); ++r) {
+    const u64 want = std::min<u64>(need_new[r], u64(1) << 28);
+    if (rels_[r].used_as_head && rels_[r].new_cap < want) rels_[r].new_cap = pow2_at_least(want);
+  }
 }
 
 // One trace row per join executed in the round just finished: the features as

@@ -72,6 +72,10 @@ struct Index {
   u32 nkey;
   u32 keycol[2];
   int c_ndv = -1;             // device counter: distinct keys after the last build
+  int c_maxrun = -1;          // device counter: rows of the most frequent key
+  int c_full = -1;            // device counter: 1 if the last build ran out of slots
+  u64 keys_seen = 0;          // distinct keys found by the last complete build
+  bool grow = false;          // the last build ran out of slots: rebuild larger
   Buf table, perm;
   u64 cap = 0, perm_cap = 0;
   bool dirty = true;   // storage (re)allocated since the last build
@@ -197,6 +201,7 @@ class Engine {
   void setup_learning();
   void emit_sketches_and_prediction(bool initial);
   void size_from_predictions(bool initial);
+  void note_index_builds();
   void log_joins(bool initial);
   void exec_plan(Plan& p);
   void finish_relation(Relation& R, bool in_round);

@@ -34,23 +34,33 @@ __device__ __forceinline__ u64 atomic_cas_u64(u64* p, u64 expect, u64 desired) {
   return atomicCAS(reinterpret_cast<unsigned long long*>(p), expect, desired);
 }
 
-// Index lookup: linear probing over {key, start, count} slots (Section 3,
-// "unique hashmap": one slot per distinct key, value = run in the sorted ids).
+// Hash tables probe linearly and give up after kMaxProbe slots: an insert
+// that finds no free slot in that window reports failure (the host grows the
+// table), so a key that is present always lies within kMaxProbe slots of its
+// home and a lookup can stop there too.  Every probe loop is thus bounded,
+// whatever state a table is in.
+constexpr u32 kMaxProbe = 1u << 12;
+
+// Index lookup over {key, start, count} slots (Section 3, "unique hashmap":
+// one slot per distinct key, value = its run in the grouped row ids).
 __device__ __forceinline__ bool index_find(const Slot* __restrict__ tab, u64 mask, u64 key,
                                            u32& start, u32& count) {
   u64 h = mix64(key) & mask;
-  for (;;) {
+  for (u32 i = 0; i < kMaxProbe && i <= mask; ++i) {
     const Slot s = tab[h];
     if (s.key == key) { start = s.start; count = s.count; return true; }
     if (s.key == kEmptyKey) return false;
     h = (h + 1) & mask;
   }
+  return false;
 }
 
-// Find-or-insert a key into an index table; returns its slot.
+// Find-or-insert a key into an index table; returns its slot, or kNoSlot if
+// the kMaxProbe slots from its home all hold other keys.
+constexpr u64 kNoSlot = ~0ull;
 __device__ __forceinline__ u64 index_insert(Slot* tab, u64 mask, u64 key) {
   u64 h = mix64(key) & mask;
-  for (;;) {
+  for (u32 i = 0; i < kMaxProbe && i <= mask; ++i) {
     u64 cur = atomic_load_u64(&tab[h].key);
     if (cur == key) return h;
     if (cur == kEmptyKey) {
@@ -59,6 +69,19 @@ __device__ __forceinline__ u64 index_insert(Slot* tab, u64 mask, u64 key) {
     }
     h = (h + 1) & mask;
   }
+  return kNoSlot;
+}
+
+// Slot of a key already inserted (kNoSlot if its insert failed).
+__device__ __forceinline__ u64 index_slot_of(const Slot* tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  for (u32 i = 0; i < kMaxProbe && i <= mask; ++i) {
+    const u64 cur = tab[h].key;
+    if (cur == key) return h;
+    if (cur == kEmptyKey) return kNoSlot;
+    h = (h + 1) & mask;
+  }
+  return kNoSlot;
 }
 
 // Tuple set insert-if-absent over 8-byte slots.  Returns 1 if the key was
@@ -66,7 +89,6 @@ __device__ __forceinline__ u64 index_insert(Slot* tab, u64 mask, u64 key) {
 // full; the caller flags it and the host grows the set).  Slots only ever go
 // from empty to a key, so a plain (possibly stale) load can only mislead
 // towards "empty", which the CAS then corrects.
-constexpr u32 kMaxProbe = 1u << 12;
 __device__ __forceinline__ int set_insert(u64* tab, u64 mask, u64 key) {
   u64 h = mix64(key) & mask;
   for (u32 i = 0; i < kMaxProbe; ++i) {
@@ -80,16 +102,6 @@ __device__ __forceinline__ int set_insert(u64* tab, u64 mask, u64 key) {
     h = (h + 1) & mask;
   }
   return -1;
-}
-
-__device__ __forceinline__ bool set_contains(const u64* __restrict__ tab, u64 mask, u64 key) {
-  u64 h = mix64(key) & mask;
-  for (;;) {
-    u64 cur = tab[h];
-    if (cur == key) return true;
-    if (cur == kEmptyKey) return false;
-    h = (h + 1) & mask;
-  }
 }
 
 // --------------------------------------------------------------- wave / block scans

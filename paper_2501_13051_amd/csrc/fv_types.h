@@ -241,6 +241,8 @@ struct IndexParams {
   u32 epoch_off;
   const u32* abort;
   u64* ndv;              // receives the number of distinct keys (nullable)
+  u64* maxrun;           // receives the largest number of rows of one key (nullable)
+  u64* full;             // set to 1 if a key found no slot (the index is incomplete)
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
 
@@ -295,13 +297,16 @@ struct PredSpec {
   int probe_dbeg;        // counter: d_begin of it (delta plans; -1: read full)
   int build_full;        // counter: n_full of the build relation
   int ndv_build;         // counter: distinct keys of the build index (-1: cross product)
+  int maxrun_build;      // counter: largest run of one key in the build index (-1: cross product)
   int hll;               // counter: HLL estimate (double bits) of the probe key (-1: none)
   u32 nkey, nfilt, step;
   int out;               // counter receiving the predicted output size
 };
 // Features of each spec from the counters, BF16 MLP inference, predictions
 // written back to the counters.  Specs are ordered plan by plan; a step > 0
-// takes the previous spec's prediction as its probe size.
+// takes the previous spec's prediction as its probe size.  A prediction never
+// exceeds the join's worst case, probe rows x the longest run of one build key
+// (probe rows x build rows for a cross product), carried along the chain.
 int launch_predict(const PredSpec* specs, u32 n, u64* ctr, const float* params, void* stream);
 void join_features(double probe_rows, double build_rows, double ndv_build, double ndv_probe, u32 nkey, u32 nfilt,
                    u32 step, float* f);

@@ -21,9 +21,13 @@ __device__ __forceinline__ u64 row_key(const IndexParams& p, u64 row) {
   return u64(a);
 }
 
-__global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort, u64* ndv) {
+__global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort, u64* ndv, u64* maxrun, u64* full) {
   if (abort && *abort) return;
-  if (ndv && blockIdx.x == 0 && threadIdx.x == 0) *ndv = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (ndv) *ndv = 0;
+    if (maxrun) *maxrun = 0;
+    if (full) *full = 0;
+  }
   for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < cap; i += u64(gridDim.x) * blockDim.x)
     tab[i] = Slot{kEmptyKey, 0u, 0u};
 }
@@ -35,7 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
   const u64 mask = p.cap - 1;
   for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
     const u64 h = index_insert(p.table, mask, row_key(p, begin + r));
-    atomicAdd(&p.table[h].count, 1u);
+    if (h != kNoSlot) atomicAdd(&p.table[h].count, 1u);
+    else if (p.full) *p.full = 1;
   }
 }
 
@@ -54,16 +59,25 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
     if (tile >= ntiles) break;
     const u64 s0 = u64(tile) * kScanTile + u64(threadIdx.x) * 4;
     u32 c[4];
-    u32 mine = 0, keys = 0;
+    u32 mine = 0, keys = 0, longest = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       c[k] = (s0 + k < p.cap) ? p.table[s0 + k].count : 0u;
       mine += c[k];
       keys += c[k] ? 1u : 0u;
+      longest = c[k] > longest ? c[k] : longest;
     }
     if (p.ndv) {
       const u32 wk = wave_sum(keys);
       if (lane_id() == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
+    }
+    if (p.maxrun) {
+      for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const u32 o = __shfl_xor(longest, d, kWave);
+        longest = o > longest ? o : longest;
+      }
+      if (lane_id() == 0 && longest)
+        atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)longest);
     }
     u32 tot;
     const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
@@ -102,9 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
   for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
-    const u64 key = row_key(p, begin + r);
-    u64 h = mix64(key) & mask;
-    while (p.table[h].key != key) h = (h + 1) & mask;
+    const u64 h = index_slot_of(p.table, mask, row_key(p, begin + r));
+    if (h == kNoSlot) continue;   // its insert failed: the host rebuilds a larger table
     const u32 pos = p.table[h].start + atomicAdd(&p.table[h].count, 1u);
     p.perm[pos] = u32(begin + r);
   }
@@ -117,7 +130,8 @@ static int grid_rows(u64 n, int cap) {
 
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv);
+  hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv,
+                     p.maxrun, p.full);
   hipLaunchKernelGGL(k_idx_count, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p);
   const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_idx_scan, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);

@@ -224,18 +224,22 @@ __global__ void k_predict(const PredSpec* specs, u32 n, u64* ctr, const float* P
   const float* W3 = b2 + 64;
   const float* b3 = W3 + 64;
   const int o = threadIdx.x;
-  double prev = 0;
+  double prev = 0, prev_bound = 0;
+  double bound = 0;   // worst-case output of the current spec (thread 0)
   for (u32 k = 0; k < n; ++k) {
     const PredSpec sp = specs[k];
     if (o == 0) {
-      double probe;
+      double probe, probe_bound;
       if (sp.step == 0) {
         const double full = double(ctr[sp.probe_full]);
         probe = sp.probe_dbeg >= 0 ? full - double(ctr[sp.probe_dbeg]) : full;
+        probe_bound = probe;
       } else {
         probe = prev;
+        probe_bound = prev_bound;
       }
       const double build = double(ctr[sp.build_full]);
+      bound = probe_bound * (sp.maxrun_build >= 0 ? double(ctr[sp.maxrun_build]) : build);
       const double ndv_b = sp.ndv_build >= 0 ? double(ctr[sp.ndv_build]) : 1.0;
       double ndv_p = probe;
       if (sp.hll >= 0) {
@@ -261,10 +265,12 @@ __global__ void k_predict(const PredSpec* specs, u32 n, u64* ctr, const float* P
       // the network predicts log2(1 + m) / 16
       double m = exp2(double(y) * 16.0) - 1.0;
       if (!(m >= 0)) m = 0;
+      if (m > bound) m = bound;
       if (m > 1e15) m = 1e15;
+      if (bound > 1e15) bound = 1e15;
       ctr[sp.out] = u64(m);
       prev = m;
-      s_x[0] = float(m);   // broadcast not needed further; keep prev in thread 0
+      prev_bound = bound;
     }
     __syncthreads();
   }

@@ -29,15 +29,22 @@ def _cases():
 @pytest.mark.parametrize("stub", ["zero", "huge"])
 def test_stub_predictors_leave_the_fixpoint_unchanged(stub):
     params = ZERO if stub == "zero" else HUGE
+    overflows = 0
     for program, edb, rels in _cases():
+        print(f"learned, {stub} predictor: {rels}", flush=True)
         ref = oracle.evaluate(program, edb)
         got, stats, deltas, _ = fv.evaluate(program, edb, flags=fv.FV_LEARNED, relations=rels, predictor=params)
         for r in rels:
             assert np.array_equal(got[r], ref[r]), r
         assert deltas == ref.delta_sizes
-        if stub == "zero":
-            assert stats["overflows"] > 0          # every presized buffer is too small: exact fallback
         assert stats["predicted_joins"] > 0
+        overflows += stats["overflows"]
+    if stub == "zero":
+        # buffers never shrink below max(2^16, 2 x facts) rows, so only joins
+        # larger than that overflow; the TC and RDFS cases have such joins
+        assert overflows > 0
+    else:
+        assert overflows == 0
 
 
 def test_join_trace_records_true_sizes():

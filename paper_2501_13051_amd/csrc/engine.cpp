@@ -313,17 +313,26 @@ void Engine::domain_analysis() {
 }
 
 // ------------------------------------------------------------------ planning
-u32 Engine::get_index(u32 rel, u32 nkey, const u32* keycol) {
+// The index of `rel` on key columns `keycol` over the rows that satisfy the
+// filters col[fcol[i]] == fval[i] (i < nfilt; filters given in column order),
+// shared by every join that asks for the same one.
+u32 Engine::get_index(u32 rel, u32 nkey, const u32* keycol, u32 nfilt, const u32* fcol, const u32* fval) {
   for (u32 i = 0; i < indices_.size(); ++i) {
     const Index& ix = indices_[i];
-    if (ix.rel == rel && ix.nkey == nkey && ix.keycol[0] == keycol[0] && (nkey < 2 || ix.keycol[1] == keycol[1]))
-      return i;
+    if (ix.rel != rel || ix.nkey != nkey || ix.keycol[0] != keycol[0] || (nkey > 1 && ix.keycol[1] != keycol[1]) ||
+        ix.nfilt != nfilt)
+      continue;
+    bool same = true;
+    for (u32 f = 0; f < nfilt; ++f) same = same && ix.fcol[f] == fcol[f] && ix.fval[f] == fval[f];
+    if (same) return i;
   }
   Index ix;
   ix.rel = rel;
   ix.nkey = nkey;
   ix.keycol[0] = keycol[0];
   ix.keycol[1] = nkey > 1 ? keycol[1] : 0;
+  ix.nfilt = nfilt;
+  for (u32 f = 0; f < nfilt; ++f) { ix.fcol[f] = fcol[f]; ix.fval[f] = fval[f]; }
   indices_.push_back(ix);
   return u32(indices_.size() - 1);
 }
@@ -455,14 +464,28 @@ Plan Engine::plan_rule(u32 ri, int dpos) {
       else newcol[t.value] = int(c);
     }
     std::stable_sort(cands.begin(), cands.end(), [](const Cand& x, const Cand& y) { return x.is_var > y.is_var; });
-    s.nkey = u32(std::min<size_t>(2, cands.size()));
+    // Key on the bound variables; the atom's constants then select which rows
+    // the index holds (t(p, 2, q) probed by p indexes only the rows whose
+    // second column is 2).  Without a bound variable the constants are the key.
+    size_t nvar = 0;
+    while (nvar < cands.size() && cands[nvar].is_var) ++nvar;
+    s.nkey = u32(std::min<size_t>(2, nvar ? nvar : cands.size()));
     u32 keycol[2] = {0, 0};
     for (u32 i = 0; i < s.nkey; ++i) { s.key[i] = cands[i].src; keycol[i] = cands[i].col; }
     // a two-column index keys on (lower column, higher column)
     if (s.nkey == 2 && keycol[0] > keycol[1]) { std::swap(keycol[0], keycol[1]); std::swap(s.key[0], s.key[1]); }
-    s.index = s.nkey ? get_index(a.rel, s.nkey, keycol) : kNoIndex;
-    for (size_t i = s.nkey; i < cands.size(); ++i)
-      wf.push_back(Filter{Src{kSrcBuild, cands[i].col}, cands[i].src, kEq});
+    u32 nfilt = 0, fcol[2] = {0, 0}, fval[2] = {0, 0};
+    for (size_t i = s.nkey; i < cands.size(); ++i) {
+      if (nvar && !cands[i].is_var && nfilt < 2) {
+        fcol[nfilt] = cands[i].col;
+        fval[nfilt] = cands[i].src.v;
+        ++nfilt;
+      } else {
+        wf.push_back(Filter{Src{kSrcBuild, cands[i].col}, cands[i].src, kEq});
+      }
+    }
+    if (nfilt == 2 && fcol[0] > fcol[1]) { std::swap(fcol[0], fcol[1]); std::swap(fval[0], fval[1]); }
+    s.index = s.nkey ? get_index(a.rel, s.nkey, keycol, nfilt, fcol, fval) : kNoIndex;
     // variable sources after this join
     std::vector<Src> vs(kMaxVars, Src{kSrcConst, 0});
     std::vector<bool> have(kMaxVars, false);
@@ -634,14 +657,16 @@ bool Engine::ensure_capacity() {
     // count (with room to double on a derived relation), or from the rows
     // before the first build.  A build that still runs out of slots raises
     // the index's full flag and the table is rebuilt larger before the next
-    // round reads it.
+    // round reads it; one measured far below its table (an index over a
+    // selective filter, or a low-cardinality column) gets a smaller one.
     u64 keys;
     if (ix.keys_seen) keys = R.used_as_head ? 2 * std::max<u64>(ix.keys_seen, 512) : ix.keys_seen;
     else keys = R.used_as_head ? R.n_full + std::max<u64>(3 * R.n_delta, 1024) : R.n_full;
     keys = std::min<u64>(keys, rows + 1);
     u64 need = pow2_at_least(std::max<u64>(u64(double(keys) / tune_.index_load), 64));
     if (ix.grow) need = std::max<u64>(need, 4 * ix.cap);
-    if (ix.cap == 0 || ix.grow || double(keys) > 0.75 * double(ix.cap)) {
+    const bool oversized = ix.keys_seen && ix.cap > 8 * need;
+    if (ix.cap == 0 || ix.grow || double(keys) > 0.75 * double(ix.cap) || oversized) {
       release(ix.table);
       ix.table = alloc(need * sizeof(Slot));
       ix.cap = need;
@@ -1061,6 +1086,8 @@ void Engine::build_index(Index& ix) {
   p.nkey = ix.nkey;
   p.keycol[0] = ix.keycol[0];
   p.keycol[1] = ix.keycol[1];
+  p.nfilt = ix.nfilt;
+  for (u32 f = 0; f < 2; ++f) { p.fcol[f] = ix.fcol[f]; p.fval[f] = ix.fval[f]; }
   p.table = ix.table.as<Slot>();
   p.cap = ix.cap;
   p.perm = ix.perm.as<u32>();
@@ -1313,8 +1340,7 @@ void Engine::note_index_builds() {
       ix.grow = true;
       continue;
     }
-    const u64 ndv = ctr_host_[ix.c_ndv];
-    if (ndv) ix.keys_seen = ndv;
+    ix.keys_seen = std::max<u64>(ctr_host_[ix.c_ndv], 1);
   }
 }
 

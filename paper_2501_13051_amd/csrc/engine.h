@@ -71,6 +71,9 @@ struct Index {
   u32 rel;
   u32 nkey;
   u32 keycol[2];
+  u32 nfilt = 0;              // only rows with col[fcol[i]] == fval[i] are indexed
+  u32 fcol[2] = {0, 0};
+  u32 fval[2] = {0, 0};
   int c_ndv = -1;             // device counter: distinct keys after the last build
   int c_maxrun = -1;          // device counter: rows of the most frequent key
   int c_full = -1;            // device counter: 1 if the last build ran out of slots
@@ -190,7 +193,7 @@ class Engine {
   void domain_analysis();
   void plan_all();
   Plan plan_rule(u32 rule, int delta_pos);
-  u32 get_index(u32 rel, u32 nkey, const u32* keycol);
+  u32 get_index(u32 rel, u32 nkey, const u32* keycol, u32 nfilt, const u32* fcol, const u32* fval);
   void ingest();
   bool ensure_capacity();   // true if any buffer was reallocated
   void build_indices(bool idb_only);

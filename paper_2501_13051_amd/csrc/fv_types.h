@@ -243,6 +243,9 @@ struct IndexParams {
   u64* ndv;              // receives the number of distinct keys (nullable)
   u64* maxrun;           // receives the largest number of rows of one key (nullable)
   u64* full;             // set to 1 if a key found no slot (the index is incomplete)
+  u32 nfilt;             // rows indexed: only those with col[fcol[i]] == fval[i], i < nfilt
+  u32 fcol[2];
+  u32 fval[2];
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
 

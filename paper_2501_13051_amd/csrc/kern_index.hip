@@ -15,6 +15,14 @@ namespace fv {
 
 constexpr u32 kScanTile = kBlock * 4;
 
+__device__ __forceinline__ bool row_indexed(const IndexParams& p, u64 row) {
+  bool ok = true;
+#pragma unroll
+  for (u32 i = 0; i < 2; ++i)
+    if (i < p.nfilt) ok = ok && p.col[p.fcol[i]][row] == p.fval[i];
+  return ok;
+}
+
 __device__ __forceinline__ u64 row_key(const IndexParams& p, u64 row) {
   const u32 a = p.col[p.keycol[0]][row];
   if (p.nkey == 2) return (u64(a) << 32) | u64(p.col[p.keycol[1]][row]);
@@ -32,15 +40,73 @@ __global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort, u64* ndv, u64*
     tab[i] = Slot{kEmptyKey, 0u, 0u};
 }
 
+// Rows are taken a tile at a time and grouped by key in an LDS map first, so
+// that the global table sees one probe and one atomic per distinct key per
+// tile rather than per row: a key that covers millions of rows (a predicate
+// column, say) would otherwise serialise every row on one counter.
+constexpr u32 kIdxItems = 4;
+constexpr u32 kIdxTile = kBlock * kIdxItems;   // rows per block step
+constexpr u32 kLdsMap = 2 * kIdxTile;           // LDS map slots: load <= 1/2
+
+struct IdxLds {
+  u64 key[kLdsMap];
+  u32 cnt[kLdsMap];
+  u32 pos[kLdsMap];
+};
+
+__device__ __forceinline__ void lds_map_clear(IdxLds& m) {
+  for (u32 i = threadIdx.x; i < kLdsMap; i += kBlock) {
+    m.key[i] = kEmptyKey;
+    m.cnt[i] = 0u;
+  }
+}
+
+// Slot of `key` in the block's map (inserted if absent) and the row's rank
+// among the tile's rows with that key.  At most kIdxTile keys go into
+// kLdsMap slots, so an empty slot is always reached.
+__device__ __forceinline__ u32 lds_map_add(IdxLds& m, u64 key, u32& rank) {
+  u32 h = u32(mix64(key)) & (kLdsMap - 1);
+  for (u32 i = 0; i < kLdsMap; ++i) {
+    const u64 cur = __hip_atomic_load(&m.key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (cur == key) break;
+    if (cur == kEmptyKey) {
+      const u64 prev = atomicCAS(reinterpret_cast<unsigned long long*>(&m.key[h]), kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) break;
+    }
+    h = (h + 1) & (kLdsMap - 1);
+  }
+  rank = atomicAdd(&m.cnt[h], 1u);
+  return h;
+}
+
 __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
+  __shared__ IdxLds m;
   if (p.abort && *p.abort) return;
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
-  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
-    const u64 h = index_insert(p.table, mask, row_key(p, begin + r));
-    if (h != kNoSlot) atomicAdd(&p.table[h].count, 1u);
-    else if (p.full) *p.full = 1;
+  const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
+  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    lds_map_clear(m);
+    __syncthreads();
+    const u64 r0 = tile * kIdxTile + threadIdx.x;
+#pragma unroll
+    for (u32 k = 0; k < kIdxItems; ++k) {
+      const u64 r = r0 + u64(k) * kBlock;
+      if (r < n && row_indexed(p, begin + r)) {
+        u32 rank;
+        (void)lds_map_add(m, row_key(p, begin + r), rank);
+      }
+    }
+    __syncthreads();
+    for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
+      const u32 c = m.cnt[e];
+      if (!c) continue;
+      const u64 h = index_insert(p.table, mask, m.key[e]);
+      if (h != kNoSlot) atomicAdd(&p.table[h].count, c);
+      else if (p.full) *p.full = 1;
+    }
+    __syncthreads();
   }
 }
 
@@ -110,16 +176,44 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
   }
 }
 
+// Scatter row ids into their key's run: the tile's rows are grouped in the
+// LDS map again, one global atomic per distinct key reserves the group's
+// places in the run, and each row takes the place of its rank in the group.
 __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
+  __shared__ IdxLds m;
   if (p.abort && *p.abort) return;
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
-  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
-    const u64 h = index_slot_of(p.table, mask, row_key(p, begin + r));
-    if (h == kNoSlot) continue;   // its insert failed: the host rebuilds a larger table
-    const u32 pos = p.table[h].start + atomicAdd(&p.table[h].count, 1u);
-    p.perm[pos] = u32(begin + r);
+  const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
+  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    lds_map_clear(m);
+    __syncthreads();
+    const u64 r0 = tile * kIdxTile + threadIdx.x;
+    u32 ent[kIdxItems], rank[kIdxItems];
+#pragma unroll
+    for (u32 k = 0; k < kIdxItems; ++k) {
+      const u64 r = r0 + u64(k) * kBlock;
+      ent[k] = ~0u;
+      rank[k] = 0;
+      if (r < n && row_indexed(p, begin + r)) ent[k] = lds_map_add(m, row_key(p, begin + r), rank[k]);
+    }
+    __syncthreads();
+    for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
+      const u32 c = m.cnt[e];
+      if (!c) continue;
+      const u64 h = index_slot_of(p.table, mask, m.key[e]);
+      // a key whose insert failed has no run: the host rebuilds a larger table
+      m.pos[e] = h == kNoSlot ? ~0u : p.table[h].start + atomicAdd(&p.table[h].count, c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (u32 k = 0; k < kIdxItems; ++k) {
+      if (ent[k] == ~0u) continue;
+      const u32 base = m.pos[ent[k]];
+      if (base != ~0u) p.perm[base + rank[k]] = u32(begin + r0 + u64(k) * kBlock);
+    }
+    __syncthreads();
   }
 }
 
@@ -132,10 +226,12 @@ int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv,
                      p.maxrun, p.full);
-  hipLaunchKernelGGL(k_idx_count, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p);
+  const u64 row_tiles = (rows_cap + kIdxTile - 1) / kIdxTile;
+  const int row_grid = int(row_tiles == 0 ? 1 : (row_tiles > 4096 ? 4096 : row_tiles));
+  hipLaunchKernelGGL(k_idx_count, dim3(row_grid), dim3(kBlock), 0, s, p);
   const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_idx_scan, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_idx_fill, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_fill, dim3(row_grid), dim3(kBlock), 0, s, p);
   return int(hipGetLastError());
 }
 

@@ -98,6 +98,12 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing; build it with __graft_entry__.build() "
                                "or python -m paper_2501_13051_amd.build")
+        # torch first: its bundled HIP runtime carries the same soname as the
+        # one libfv links against, so loading torch before libfv makes libfv
+        # bind to torch's runtime.  Loaded the other way round the process
+        # would hold two HIP runtimes, and the device memory and streams torch
+        # hands over would belong to the other one.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, u32, u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
         L.fv_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Options)]
@@ -268,9 +274,14 @@ class Engine:
                 except Exception:   # out of memory: report NULL, the library returns FV_ENOMEM
                     return None
 
+            delete = torch.cuda.caching_allocator_delete
+
             def _free(ptr, stream, user):
                 if ptr:
-                    torch.cuda.caching_allocator_delete(ptr)
+                    try:
+                        delete(ptr)
+                    except (AttributeError, TypeError):   # interpreter shutdown: torch is gone
+                        pass
 
             self._alloc_cb = ALLOC_FN(_alloc)
             self._free_cb = FREE_FN(_free)
@@ -446,7 +457,7 @@ def autotune(make_engine, key: str = None, cache_path: str = None, reps: int = 3
     Engine (created with that tuning) holding the program and facts; the
     library runs and destroys each one.  Returns the chosen tuning as a dict."""
     L = lib()
-    held = []
+    held, failures = [], []
 
     def _make(opt_ptr, user):
         try:
@@ -457,8 +468,9 @@ def autotune(make_engine, key: str = None, cache_path: str = None, reps: int = 3
             held.append(e)
             h = e._h
             e._h = None          # the library destroys this context
-            return h
-        except Exception:        # a failed factory is reported as NULL
+            return h.value       # a plain address: ctypes cannot return a c_void_p object
+        except Exception as ex:  # a failed factory is reported as NULL; keep why
+            failures.append(f"{type(ex).__name__}: {ex}")
             return None
 
     cb = MAKE_FN(_make)
@@ -466,7 +478,8 @@ def autotune(make_engine, key: str = None, cache_path: str = None, reps: int = 3
     rc = L.fv_autotune(cb, None, None, reps, cache_path.encode() if cache_path else None,
                        key.encode() if key else None, ctypes.byref(best))
     if rc != FV_OK:
-        raise FvError(rc, L.fv_global_error().decode())
+        why = f" ({failures[-1]})" if failures else ""
+        raise FvError(rc, L.fv_global_error().decode() + why)
     return best.as_dict()
 
 

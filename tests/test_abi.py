@@ -103,3 +103,17 @@ def test_tuning_cache_roundtrip_on_host(tmp_path):
     assert t == {"radix_bits": 11, "fuse_dedup": 1, "set_load": 0.5, "index_load": 0.25, "max_blocks": 4096}
     assert fv.tuning_load(str(p), "other") is None
     assert fv.tuning_load(str(tmp_path / "missing.json"), "sg") is None
+
+
+def test_library_shares_torchs_hip_runtime():
+    """libfv works on torch's device memory and streams, so the process must
+    hold one HIP runtime: loading the library maps no second libamdhip64."""
+    import subprocess
+    import sys
+    code = ("from paper_2501_13051_amd import fv; fv.lib(); "
+            "paths = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}; "
+            "print(len(paths), sorted(paths))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[0] == "1", out.stdout

@@ -93,6 +93,27 @@ def test_tuned_workloads(tuning):
     _check(W.RDFS_PROGRAM, {"t": d["t"]}, relations=["t"], tuning=t)
 
 
+def test_autotune_picks_a_stored_tuning_with_the_same_fixpoint(tmp_path):
+    edb = {"edge": W.forest(8, 256, 0.05, seed=1002)}
+    rules = fv.parse_program(W.SG_PROGRAM)
+
+    def make(t):
+        e = fv.Engine(tuning=t)
+        e.relation("edge", 2)
+        e.relation("sg", 2)
+        e.load("edge", edb["edge"])
+        for head, body, neq in rules:
+            e.add_rule(head, body, neq)
+        return e
+
+    cache = str(tmp_path / "tuning.json")
+    best = fv.autotune(make, key="sg_small", cache_path=cache, reps=1)
+    assert best["radix_bits"] in (8, 11) and best["fuse_dedup"] in (0, 1)
+    assert best["max_blocks"] in (1024, 2048, 4096)
+    assert fv.tuning_load(cache, "sg_small") == best
+    _check(W.SG_PROGRAM, edb, relations=["sg"], tuning=best)
+
+
 def test_empty_and_duplicate_inputs():
     e0 = [np.zeros(0, np.uint32), np.zeros(0, np.uint32)]
     _check(W.TC_PROGRAM, {"edge": e0}, relations=["path", "edge"])

@@ -48,6 +48,7 @@ Engine::Engine(const fv_options* opt) {
   if (!(tune_.set_load >= 0.1f && tune_.set_load <= 0.75f)) tune_.set_load = 0.25f;
   if (!(tune_.index_load >= 0.1f && tune_.index_load <= 0.75f)) tune_.index_load = 0.5f;
   if (tune_.max_blocks < 256 || tune_.max_blocks > 8192) tune_.max_blocks = 2048;
+  tune_.index_rebuild = tune_.index_rebuild ? 1 : 0;
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
   trace_ = (opt_.flags & FV_TRACE) != 0;
@@ -72,7 +73,10 @@ Engine::~Engine() {
     for (int c = 0; c < 3; ++c) { release(R.stage[c]); release(R.col[c]); }
     release(R.newk); release(R.newk2); release(R.set);
   }
-  for (auto& ix : indices_) { release(ix.table); release(ix.perm); }
+  for (auto& ix : indices_) {
+    release(ix.table); release(ix.perm); release(ix.pslot); release(ix.perm2); release(ix.pslot2);
+    release(ix.dcnt); release(ix.dsh);
+  }
   for (auto& I : inters_) for (auto& b : I.col) release(b);
   release(ctr_dev_); release(flags_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
   release(m_row_); release(m_start_); release(m_off_);
@@ -540,7 +544,7 @@ void Engine::plan_all() {
   }
   for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
   // counter layout: [derived, join_out] [full_n x R] [d_begin x R]
-  //   [index distinct keys] [index longest runs] [index full flags] [HLL estimates]
+  //   [index distinct keys] [index longest runs] [index full flags] [index rows] [HLL estimate, rows]
   //   [predicted join sizes]                                          (kept across rounds)
   //   [delta x R] [new x R] [per-join m,t] [per-intermediate count]  (cleared every round)
   const int R = int(rels_.size());
@@ -553,6 +557,8 @@ void Engine::plan_all() {
   for (auto& ix : indices_) ix.c_ndv = next++;
   for (auto& ix : indices_) ix.c_maxrun = next++;
   for (auto& ix : indices_) ix.c_full = next++;
+  for (auto& ix : indices_) ix.c_rows = next++;
+  for (auto& ix : indices_) ix.c_rows_prev = next++;
   c_hll0_ = next;
   sketches_.clear();
   if (log_joins_) {
@@ -563,10 +569,18 @@ void Engine::plan_all() {
         if (s0.key[0].kind != kSrcProbe) continue;
         const int c1 = (s0.nkey == 2 && s0.key[1].kind == kSrcProbe) ? int(s0.key[1].v) : -1;
         const bool delta = p.delta_pos >= 0;
+        auto same_filters = [&](const std::vector<Filter>& a) {
+          if (a.size() != s0.pf.size()) return false;
+          for (size_t f = 0; f < a.size(); ++f)
+            if (a[f].op != s0.pf[f].op || a[f].a.kind != s0.pf[f].a.kind || a[f].a.v != s0.pf[f].a.v ||
+                a[f].b.kind != s0.pf[f].b.kind || a[f].b.v != s0.pf[f].b.v)
+              return false;
+          return true;
+        };
         int found = -1;
         for (size_t i = 0; i < sketches_.size(); ++i)
           if (sketches_[i].rel == p.src_rel && sketches_[i].c0 == s0.key[0].v && sketches_[i].c1 == c1 &&
-              sketches_[i].delta == delta)
+              sketches_[i].delta == delta && same_filters(sketches_[i].pf))
             found = int(i);
         if (found < 0) {
           HllSketch sk;
@@ -574,7 +588,9 @@ void Engine::plan_all() {
           sk.c0 = s0.key[0].v;
           sk.c1 = c1;
           sk.delta = delta;
+          sk.pf = s0.pf;
           sk.ctr = next++;
+          sk.ctr_rows = next++;
           sketches_.push_back(sk);
           found = int(sketches_.size() - 1);
         }
@@ -661,22 +677,50 @@ bool Engine::ensure_capacity() {
     // selective filter, or a low-cardinality column) gets a smaller one.
     u64 keys;
     if (ix.keys_seen) keys = R.used_as_head ? 2 * std::max<u64>(ix.keys_seen, 512) : ix.keys_seen;
-    else keys = R.used_as_head ? R.n_full + std::max<u64>(3 * R.n_delta, 1024) : R.n_full;
+    else keys = R.used_as_head ? R.n_full + std::max<u64>({3 * R.n_delta, R.new_cap / 4, 1024}) : R.n_full;
     keys = std::min<u64>(keys, rows + 1);
     u64 need = pow2_at_least(std::max<u64>(u64(double(keys) / tune_.index_load), 64));
     if (ix.grow) need = std::max<u64>(need, 4 * ix.cap);
     const bool oversized = ix.keys_seen && ix.cap > 8 * need;
     if (ix.cap == 0 || ix.grow || double(keys) > 0.75 * double(ix.cap) || oversized) {
       release(ix.table);
+      release(ix.dcnt);
+      release(ix.dsh);
       ix.table = alloc(need * sizeof(Slot));
+      ix.dcnt = alloc(need * 4);
+      ix.dsh = alloc(need * 4);
+      launched(launch_fill_u32(ix.dcnt.as<u32>(), need, 0u, stream_), "index delta counts clear");
       ix.cap = need;
       ix.dirty = true;
       ix.grow = false;
     }
-    if (ix.perm_cap < rows) {
-      release(ix.perm);
-      ix.perm = alloc(std::max<u64>(rows, 1) * 4);
-      ix.perm_cap = rows;
+    // Positions: the rows the index may hold after this round.  A derived
+    // relation's index gets 4x its last measured row count once it passes
+    // half its positions (or sits far below them), and every row the
+    // relation may hold before its first build; an update that still
+    // overflows raises the full flag and is rebuilt with more before the next
+    // round reads it.
+    u64 want = rows;
+    bool realloc_perm = ix.perm_cap < rows;
+    if (R.used_as_head && ix.rows_seen) {
+      want = std::min<u64>(rows, 4 * std::max<u64>(ix.rows_seen, 4096));
+      realloc_perm = 2 * ix.rows_seen > ix.perm_cap || ix.perm_cap > 16 * want;
+    }
+    if (ix.perm_grow) {
+      want = std::max<u64>(want, 2 * ix.perm_cap);
+      realloc_perm = true;
+    }
+    ix.perm_grow = false;
+    if (ix.perm_cap == 0 || realloc_perm) {
+      for (Buf* b : {&ix.perm, &ix.pslot, &ix.perm2, &ix.pslot2}) release(*b);
+      const u64 n = std::max<u64>(want, 1) * 4;
+      ix.perm = alloc(n);
+      ix.pslot = alloc(n);
+      if (R.used_as_head) {
+        ix.perm2 = alloc(n);
+        ix.pslot2 = alloc(n);
+      }
+      ix.perm_cap = want;
       ix.dirty = true;
     }
     max_rows = std::max(max_rows, ix.cap);
@@ -725,23 +769,45 @@ int Engine::kclass(const char* name) {
   return int(kprof_.size() - 1);
 }
 
-void Engine::ev_begin(int cls) {
-  if (!trace_) return;
-  if (!trace_only_.empty() && kprof_[cls].name != trace_only_) { ev_open_ = nullptr; return; }
+hipEvent_t Engine::pooled_event() {
   hipEvent_t e;
   if (!ev_pool_.empty()) { e = ev_pool_.back(); ev_pool_.pop_back(); }
   else hip(hipEventCreate(&e), "event create");
-  hip(hipEventRecord(e, stream_), "event record");
-  ev_open_ = e;
+  return e;
+}
+
+// Time the launches between ev_begin and ev_end.  A single kernel (`single`)
+// is timed by the events its own dispatch stamps; a group of launches by
+// events recorded on the stream around it.  Inside graph capture the
+// recorded form is used.
+void Engine::ev_begin(int cls, bool single) {
+  if (!trace_) return;
+  if (!trace_only_.empty() && kprof_[cls].name != trace_only_) { ev_open_ = nullptr; return; }
+  ev_open_ = pooled_event();
+  ev_close_ = nullptr;
+  if (single && !capturing_) {
+    ev_close_ = pooled_event();
+    armed_events() = LaunchEvents{ev_open_, ev_close_};
+  } else {
+    hip(hipEventRecord(ev_open_, stream_), "event record");
+  }
 }
 
 void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux) {
   if (!trace_ || !ev_open_) return;
-  hipEvent_t e;
-  if (!ev_pool_.empty()) { e = ev_pool_.back(); ev_pool_.pop_back(); }
-  else hip(hipEventCreate(&e), "event create");
-  hip(hipEventRecord(e, stream_), "event record");
+  hipEvent_t e = ev_close_;
+  if (e) {
+    if (armed_events().start) {   // nothing was launched: an empty interval
+      armed_events() = LaunchEvents{};
+      hip(hipEventRecord(ev_open_, stream_), "event record");
+      hip(hipEventRecord(e, stream_), "event record");
+    }
+  } else {
+    e = pooled_event();
+    hip(hipEventRecord(e, stream_), "event record");
+  }
   pending_.push_back(PendingEvent{cls, ev_open_, e, bytes, kind, ref0, ref1, aux});
+  ev_open_ = ev_close_ = nullptr;
 }
 
 // Algorithmic bytes of a launch, from the sizes read back after the round.
@@ -886,13 +952,13 @@ void Engine::exec_plan(Plan& p) {
       sp.abort = nullptr;
       sp.overflow = flags;
       const int kc = kclass("select");
-      ev_begin(kc);
+      ev_begin(kc, true);
       launched(launch_select(sp, std::max<u64>(probe_bound, 1), stream_), "select launch");
       ev_end(kc, 0, 0);
       continue;
     }
     const Relation& B = rels_[s.brel];
-    if (use_fused_) {
+    if (s.fused) {
       // presized output: probe and write in one pass
       FusedJoinParams fp{};
       for (int c = 0; c < kMaxCols; ++c) fp.pcol[c] = pcol[c];
@@ -919,7 +985,7 @@ void Engine::exec_plan(Plan& p) {
       fp.join_out_stat = ctr(c_joinout_);
       fp.overflow = flags;
       const int kf = kclass("join_onepass");
-      ev_begin(kf);
+      ev_begin(kf, true);
       launched(launch_join_fused(fp, std::max<u64>(probe_bound, 1), stream_), "one-pass join launch");
       ev_end(kf, 0, 7, probe_ctr, s.c_t, probe_bound);
       continue;
@@ -954,7 +1020,7 @@ void Engine::exec_plan(Plan& p) {
     pp.abort = nullptr;
     pp.fatal = flags + 1;
     const int kp = kclass("join_probe");
-    ev_begin(kp);
+    ev_begin(kp, true);
     launched(launch_probe(pp, std::max<u64>(probe_bound, 1), 0, stream_), "probe launch");
     ev_end(kp, 0, 1, probe_ctr, s.c_m, probe_bound);
 
@@ -979,7 +1045,7 @@ void Engine::exec_plan(Plan& p) {
     for (auto& f : s.wf) nbuild += (f.a.kind == kSrcBuild) + (f.b.kind == kSrcBuild);
     const u64 out_bytes = o.packed ? 8 : 4ull * o.ncols;
     const int kw = kclass("join_write");
-    ev_begin(kw);
+    ev_begin(kw, true);
     launched(launch_write(wp, std::max<u64>(o.cap, 1), stream_), "write launch");
     ev_end(kw, 0, 2, s.c_m, s.c_t, (ix ? 4 : 0) + 4ull * nbuild + out_bytes);
   }
@@ -1029,7 +1095,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   }
   for (u32 pass = 0; pass < passes; ++pass) {
     const bool last_fused = fuse && pass + 1 == passes;
-    ev_begin(last_fused ? kfused : kpass);
+    ev_begin(last_fused ? kfused : kpass, true);
     launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_, last_fused ? &fz : nullptr),
              "sort pass launch");
     ev_end(last_fused ? kfused : kpass, 0, last_fused ? 6 : 3, c_new0_ + ri, c_delta0_ + ri,
@@ -1058,7 +1124,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.epoch_off = next_epoch();
   dp.abort = flags;
   const int kd = kclass("dedup_append");
-  ev_begin(kd);
+  ev_begin(kd, true);
   launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_), "dedup launch");
   ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
 }
@@ -1091,6 +1157,8 @@ void Engine::build_index(Index& ix) {
   p.table = ix.table.as<Slot>();
   p.cap = ix.cap;
   p.perm = ix.perm.as<u32>();
+  p.pslot = ix.pslot.as<u32>();
+  p.perm_cap = ix.perm_cap;
   p.status = st_a_.as<u64>();
   p.ticket = ticket_dev_.as<u32>();
   p.epoch_base = epoch_base();
@@ -1099,6 +1167,7 @@ void Engine::build_index(Index& ix) {
   p.ndv = ix.c_ndv >= 0 ? ctr(ix.c_ndv) : nullptr;
   p.maxrun = ix.c_maxrun >= 0 ? ctr(ix.c_maxrun) : nullptr;
   p.full = ix.c_full >= 0 ? ctr(ix.c_full) : nullptr;
+  p.rows = ix.c_rows >= 0 ? ctr(ix.c_rows) : nullptr;
   const int kc = kclass("index_build");
   ev_begin(kc);
   launched(launch_index_build(p, std::max<u64>(R.cap, 1), stream_), "index launch");
@@ -1106,9 +1175,56 @@ void Engine::build_index(Index& ix) {
   ix.dirty = false;
 }
 
+// Bring the join indices of derived relations up to date with the rows the
+// round appended: an update of the existing layout where the index is intact
+// and the round runs eagerly (a replayed graph cannot swap buffers), a full
+// build otherwise.
+void Engine::update_index(Index& ix) {
+  const Relation& R = rels_[ix.rel];
+  IndexParams p{};
+  for (u32 c = 0; c < R.arity; ++c) p.col[c] = R.col[c].as<u32>();
+  p.src.begin_ctr = ctr(c_dbeg0_ + int(ix.rel));
+  p.src.end_ctr = ctr(c_full0_ + int(ix.rel));
+  p.src.cap = R.cap;
+  p.nkey = ix.nkey;
+  p.keycol[0] = ix.keycol[0];
+  p.keycol[1] = ix.keycol[1];
+  p.nfilt = ix.nfilt;
+  for (u32 f = 0; f < 2; ++f) { p.fcol[f] = ix.fcol[f]; p.fval[f] = ix.fval[f]; }
+  p.table = ix.table.as<Slot>();
+  p.cap = ix.cap;
+  p.perm = ix.perm.as<u32>();
+  p.pslot = ix.pslot.as<u32>();
+  p.perm_cap = ix.perm_cap;
+  p.perm_out = ix.perm2.as<u32>();
+  p.pslot_out = ix.pslot2.as<u32>();
+  p.dcnt = ix.dcnt.as<u32>();
+  p.dsh = ix.dsh.as<u32>();
+  p.status = st_a_.as<u64>();
+  p.ticket = ticket_dev_.as<u32>();
+  p.epoch_base = epoch_base();
+  p.epoch_off = next_epoch();
+  p.abort = flags_dev_.as<u32>();
+  p.abort2 = flags_dev_.as<u32>() + 2;
+  p.ndv = ctr(ix.c_ndv);
+  p.maxrun = ctr(ix.c_maxrun);
+  p.full = ctr(ix.c_full);
+  p.rows = ctr(ix.c_rows);
+  p.rows_prev = ctr(ix.c_rows_prev);
+  const int kc = kclass("index_update");
+  ev_begin(kc);
+  launched(launch_index_update(p, std::max<u64>(R.new_cap, 1), std::max<u64>(ix.perm_cap, 1), stream_),
+           "index update launch");
+  ev_end(kc, 0, 0);
+  ix.pending_swap = true;
+}
+
 void Engine::build_indices(bool idb_only) {
-  for (auto& ix : indices_)
-    if (!idb_only || rels_[ix.rel].used_as_head) build_index(ix);
+  for (auto& ix : indices_) {
+    if (idb_only && !rels_[ix.rel].used_as_head) continue;
+    if (idb_only && !tune_.index_rebuild && !use_graph_ && !capturing_ && !ix.dirty && ix.perm2.p) update_index(ix);
+    else build_index(ix);
+  }
 }
 
 // Load the staged facts of every relation: pack, radix-sort, drop repeats,
@@ -1228,7 +1344,7 @@ bool Engine::capture_round() {
       graph_events_.swap(pending_);
       pending_.clear();
       graph_dirty_ = false;
-      graph_fused_ = use_fused_;
+      graph_fused_steps_ = fused_steps_;
       ++graph_captures_;
       return true;
     }
@@ -1240,11 +1356,29 @@ bool Engine::capture_round() {
   return false;
 }
 
+// A presized one-pass join hands each wave the outputs of its own probe
+// rows, so it stays balanced only while no key owns many build rows; a join
+// whose build index has a long run (measured by the index's last build) runs
+// as count-then-write, which spreads outputs evenly over the grid.
+constexpr u64 kOnePassMaxRun = 256;
+
+void Engine::choose_join_algorithms(bool initial) {
+  fused_steps_.clear();
+  for (auto& p : initial ? init_plans_ : delta_plans_)
+    for (auto& s : p.steps) {
+      s.fused = use_fused_ && !s.select_only && s.index != kNoIndex &&
+                ctr_host_[indices_[s.index].c_maxrun] <= kOnePassMaxRun;
+      fused_steps_.push_back(s.fused);
+    }
+}
+
 void Engine::run_round(bool initial) {
   start_ctr_.assign(ctr_host_, ctr_host_ + n_ctr_);
   use_fused_ = learned_;
   if (learned_) size_from_predictions(initial);
+  choose_join_algorithms(initial);
   for (;;) {
+    for (auto& ix : indices_) ix.pending_swap = false;   // a failed attempt updated nothing
     if (ensure_capacity()) graph_dirty_ = true;
     if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) graph_dirty_ = true;
     bool any_dirty = false;
@@ -1258,7 +1392,7 @@ void Engine::run_round(bool initial) {
     }
     if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) begin_phase();   // clears status arrays
     bool replayed = false;
-    if (graph_exec_ && graph_fused_ != use_fused_) graph_dirty_ = true;
+    if (graph_exec_ && graph_fused_steps_ != fused_steps_) graph_dirty_ = true;
     if (!initial && use_graph_) {
       if (graph_dirty_ || !graph_exec_) {
         if (!capture_round()) use_graph_ = false;
@@ -1275,11 +1409,14 @@ void Engine::run_round(bool initial) {
     read_counters();
     if (!flags_host_[0] && !flags_host_[2]) break;
     ++redo_;
-    if (use_fused_ && flags_host_[0]) {
+    bool any_fused = false;
+    for (bool f : fused_steps_) any_fused = any_fused || f;
+    if (any_fused && flags_host_[0]) {
       // a presized one-pass join ran out of room: run the round again with
       // exact count-then-write joins
       ++overflows_;
       use_fused_ = false;
+      choose_join_algorithms(initial);
       graph_dirty_ = true;
     }
     if (flags_host_[2]) {
@@ -1336,10 +1473,23 @@ void Engine::run_round(bool initial) {
 // incomplete and is rebuilt larger before any join reads it.
 void Engine::note_index_builds() {
   for (auto& ix : indices_) {
-    if (ctr_host_[ix.c_full]) {
-      ix.grow = true;
+    if (ix.pending_swap) {   // the round's update wrote the new layout into the second buffers
+      std::swap(ix.perm, ix.perm2);
+      std::swap(ix.pslot, ix.pslot2);
+      ix.pending_swap = false;
+    }
+    const u64 full = ctr_host_[ix.c_full];
+    if (full) {
+      if (full & 1) ix.grow = true;
+      if (full & 2) ix.perm_grow = true;
+      ix.dirty = true;   // incomplete: rebuilt before any join reads it
+      // its counts cover only what fitted: size the rebuild from the
+      // relation's rows instead, so that it cannot fall short as well
+      ix.rows_seen = 0;
+      ix.keys_seen = 0;
       continue;
     }
+    ix.rows_seen = ctr_host_[ix.c_rows];
     ix.keys_seen = std::max<u64>(ctr_host_[ix.c_ndv], 1);
   }
 }
@@ -1363,6 +1513,8 @@ void Engine::setup_learning() {
         sp.build_full = c_full0_ + int(st.brel);
         sp.ndv_build = st.index != kNoIndex ? indices_[st.index].c_ndv : -1;
         sp.maxrun_build = st.index != kNoIndex ? indices_[st.index].c_maxrun : -1;
+        sp.rows_build = st.index != kNoIndex ? indices_[st.index].c_rows : -1;
+        sp.probe_rows = (k == 0 && st.hll >= 0) ? sketches_[st.hll].ctr_rows : -1;
         sp.hll = (k == 0 && st.hll >= 0) ? sketches_[st.hll].ctr : -1;
         sp.nkey = st.nkey;
         sp.nfilt = u32(st.wf.size());
@@ -1392,11 +1544,19 @@ void Engine::emit_sketches_and_prediction(bool initial) {
     rr.begin_ctr = sk.delta ? ctr(c_dbeg0_ + int(sk.rel)) : nullptr;
     rr.end_ctr = ctr(c_full0_ + int(sk.rel));
     rr.cap = std::max<u64>(R.cap, 1);
-    const u32* c0 = R.col[sk.c0].as<u32>();
-    const u32* c1 = sk.c1 >= 0 ? R.col[sk.c1].as<u32>() : nullptr;
+    HllParams hp{};
+    for (u32 c = 0; c < R.arity; ++c) hp.col[c] = R.col[c].as<u32>();
+    hp.c0 = sk.c0;
+    hp.c1 = sk.c1;
+    hp.src = rr;
+    hp.n_pf = u32(sk.pf.size());
+    for (u32 f = 0; f < hp.n_pf; ++f) hp.pf[f] = sk.pf[f];
+    hp.regs = sk.regs.as<u32>();
+    hp.estimate = ctr(sk.ctr);
+    hp.rows = ctr(sk.ctr_rows);
     const int kc = kclass("hll_sketch");
     ev_begin(kc);
-    launched(launch_hll(c0, c1, rr, std::max<u64>(R.cap, 1), sk.regs.as<u32>(), ctr(sk.ctr), stream_), "hll");
+    launched(launch_hll(hp, std::max<u64>(R.cap, 1), stream_), "hll");
     ev_end(kc, 0, 0);
   }
   if (!learned_) return;
@@ -1453,7 +1613,7 @@ void Engine::log_joins(bool initial) {
       double probe;
       double ndv_p;
       if (k == 0) {
-        probe = double(n_src);
+        probe = st.hll >= 0 ? S0(sketches_[st.hll].ctr_rows) : double(n_src);
         ndv_p = probe;
         if (st.hll >= 0) {
           double e;
@@ -1466,7 +1626,7 @@ void Engine::log_joins(bool initial) {
                                      inters_[p.steps[i - 1].out_buf].cap));
         ndv_p = probe;
       }
-      const double build = S0(c_full0_ + int(st.brel));
+      const double build = st.index != kNoIndex ? S0(indices_[st.index].c_rows) : S0(c_full0_ + int(st.brel));
       const double ndv_b = st.index != kNoIndex ? S0(indices_[st.index].c_ndv) : 1.0;
       float f[kTraceCols];
       join_features(probe, build, ndv_b, ndv_p, st.nkey, u32(st.wf.size()), k, f);

@@ -77,11 +77,18 @@ struct Index {
   int c_ndv = -1;             // device counter: distinct keys after the last build
   int c_maxrun = -1;          // device counter: rows of the most frequent key
   int c_full = -1;            // device counter: 1 if the last build ran out of slots
+  int c_rows = -1;            // device counter: rows the last build indexed
+  int c_rows_prev = -1;       // device counter: rows before the last update
   u64 keys_seen = 0;          // distinct keys found by the last complete build
+  u64 rows_seen = 0;          // rows indexed by the last complete build or update
   bool grow = false;          // the last build ran out of slots: rebuild larger
-  Buf table, perm;
+  bool perm_grow = false;     // the last build ran out of positions: rebuild with more
+  Buf table, perm, pslot;     // slots; row ids grouped by key; each position's slot
+  Buf perm2, pslot2;          // targets of an incremental update (swapped in after it)
+  Buf dcnt, dsh;              // per slot: rows appended this round, and their prefix
   u64 cap = 0, perm_cap = 0;
-  bool dirty = true;   // storage (re)allocated since the last build
+  bool dirty = true;          // storage (re)allocated since the last build
+  bool pending_swap = false;  // an update into perm2/pslot2 was enqueued this round
 };
 
 // One join (or, with index == kNoIndex and brel == kNone, one selection):
@@ -100,6 +107,7 @@ struct Step {
   int c_m = -1, c_t = -1;     // device counters for this join's sizes
   int c_pred = -1;            // device counter: predicted output size (learned mode)
   int hll = -1;               // HLL sketch of the probe key (step 0, learned/logging modes)
+  bool fused = false;         // this round runs it as a presized one-pass join
 };
 
 struct Plan {
@@ -115,8 +123,10 @@ struct HllSketch {
   u32 c0;
   int c1;                     // second key column or -1
   bool delta;                 // sketch of the delta rows (else of full)
+  std::vector<Filter> pf;     // probe filters: only rows passing them are sketched
   Buf regs;
   int ctr = -1;               // estimate (double bits)
+  int ctr_rows = -1;          // rows passing the filters
 };
 
 struct Inter {
@@ -205,6 +215,7 @@ class Engine {
   void emit_sketches_and_prediction(bool initial);
   void size_from_predictions(bool initial);
   void note_index_builds();
+  void update_index(Index& ix);
   void log_joins(bool initial);
   void exec_plan(Plan& p);
   void finish_relation(Relation& R, bool in_round);
@@ -218,7 +229,8 @@ class Engine {
 
   // profiling
   int kclass(const char* name);
-  void ev_begin(int cls);
+  void ev_begin(int cls, bool single = false);
+  hipEvent_t pooled_event();
   void ev_end(int cls, double bytes, int kind = 0, int ref0 = -1, int ref1 = -1, u64 aux = 0);
   void collect_events();
 
@@ -265,7 +277,9 @@ class Engine {
   std::vector<u64> deltas_;
   u32 redo_ = 0;
   // learned predictor
-  bool learned_ = false, log_joins_ = false, use_fused_ = false, graph_fused_ = false;
+  bool learned_ = false, log_joins_ = false, use_fused_ = false;
+  std::vector<bool> fused_steps_, graph_fused_steps_;   // per-step one-pass choice (now / when captured)
+  void choose_join_algorithms(bool initial);
   std::vector<float> predictor_;          // MLP parameters (host copy)
   Buf predictor_dev_;
   std::vector<HllSketch> sketches_;
@@ -287,6 +301,7 @@ class Engine {
   std::vector<PendingEvent> pending_;
   std::vector<hipEvent_t> ev_pool_;
   hipEvent_t ev_open_ = nullptr;
+  hipEvent_t ev_close_ = nullptr;   // set when the launch stamps its own events
 };
 
 }  // namespace fv

@@ -3,12 +3,26 @@
 // decoupled look-back used for order-preserving stream compaction.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "fv_types.h"
 
 namespace fv {
+
+// Launch one kernel, with the armed timing events if there are any.
+template <typename... KArgs, typename... Args>
+inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, Args... args) {
+  LaunchEvents& ev = armed_events();
+  if (ev.start) {
+    hipEvent_t a = static_cast<hipEvent_t>(ev.start), z = static_cast<hipEvent_t>(ev.stop);
+    ev.start = ev.stop = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, z, 0u, static_cast<KArgs>(args)...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, static_cast<KArgs>(args)...);
+  }
+}
 
 constexpr int kWave = 64;
 

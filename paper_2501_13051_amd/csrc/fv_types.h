@@ -176,6 +176,15 @@ struct CommitParams {
 // ------------------------------------------------------------------ launchers
 // Each wrapper enqueues kernels on `stream` (a hipStream_t) and returns the
 // hipError_t of the launch as int.
+// Timing events for the next single-kernel launch: when armed, that launch
+// has the runtime stamp `start` and `stop` with the kernel's own dispatch
+// start and end (no gap for a separate event record), and disarms them.
+struct LaunchEvents {
+  void* start = nullptr;
+  void* stop = nullptr;
+};
+LaunchEvents& armed_events();
+
 int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream);
 int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream);
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream);
@@ -242,12 +251,27 @@ struct IndexParams {
   const u32* abort;
   u64* ndv;              // receives the number of distinct keys (nullable)
   u64* maxrun;           // receives the largest number of rows of one key (nullable)
-  u64* full;             // set to 1 if a key found no slot (the index is incomplete)
+  u64* full;             // bit 0: a key found no slot; bit 1: rows exceed perm_cap (index incomplete)
+  u64* rows;             // receives the number of rows indexed (nullable)
   u32 nfilt;             // rows indexed: only those with col[fcol[i]] == fval[i], i < nfilt
   u32 fcol[2];
   u32 fval[2];
+  // Every indexed position also records the slot of its key (pslot), so
+  // that an incremental update can shift old runs without looking keys up.
+  u32* pslot;
+  u64 perm_cap;          // positions available in perm / pslot (and their update copies)
+  // Incremental update (launch_index_update): `src` is the range of rows
+  // appended since the last build or update; the old layout (perm, pslot)
+  // is rewritten into (perm_out, pslot_out) with room for the new rows.
+  u32* perm_out;
+  u32* pslot_out;
+  u32* dcnt;             // per slot: appended rows (zero between updates)
+  u32* dsh;              // per slot: appended rows of all earlier slots
+  u64* rows_prev;        // rows indexed before the update
+  const u32* abort2;     // a second flag that cancels an update (set-full round)
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
+int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, void* stream);
 
 int launch_fill_u64(u64* p, u64 n, u64 value, void* stream);
 int launch_fill_u32(u32* p, u64 n, u32 value, void* stream);
@@ -279,8 +303,22 @@ int launch_bounds(const u32* col, u64 n, u32 stride, u32 n_inst, u64* out, void*
 constexpr u32 kHllRegs = 4096;
 constexpr u32 kMlpIn = 8, kMlpHidden = 64;
 constexpr u32 kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
-int launch_hll(const u32* c0, const u32* c1, RowRange src, u64 rows_hint, u32* regs, u64* out_estimate,
-               void* stream);
+// Sketch of a join's probe side: the rows of `src` that pass the probe
+// filters are counted into *rows and their key (col[c0], or col[c0] << 32 |
+// col[c1]) goes into the HyperLogLog registers; *estimate gets the distinct
+// count estimate (a double's bits).
+struct HllParams {
+  const u32* col[3];
+  u32 c0;
+  int c1;                 // -1: one-column key
+  RowRange src;
+  u32 n_pf;
+  Filter pf[kMaxFilters];
+  u32* regs;
+  u64* estimate;
+  u64* rows;
+};
+int launch_hll(const HllParams& p, u64 rows_hint, void* stream);
 int launch_dense_fwd(const float* in, u32 n, u32 din, const float* W, const float* b, u32 dout, float in_scale,
                      float* z, float* out, int relu, void* stream);
 int launch_mse(const float* yhat, const float* y, u32 n, float* dy, float* loss, void* stream);
@@ -301,6 +339,8 @@ struct PredSpec {
   int build_full;        // counter: n_full of the build relation
   int ndv_build;         // counter: distinct keys of the build index (-1: cross product)
   int maxrun_build;      // counter: largest run of one key in the build index (-1: cross product)
+  int rows_build;        // counter: rows held by the build index (-1: cross product, use build_full)
+  int probe_rows;        // counter: probe rows passing the probe filters (-1: use the delta or full size)
   int hll;               // counter: HLL estimate (double bits) of the probe key (-1: none)
   u32 nkey, nfilt, step;
   int out;               // counter receiving the predicted output size

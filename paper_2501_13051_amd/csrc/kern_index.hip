@@ -29,12 +29,13 @@ __device__ __forceinline__ u64 row_key(const IndexParams& p, u64 row) {
   return u64(a);
 }
 
-__global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort, u64* ndv, u64* maxrun, u64* full) {
+__global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort, u64* ndv, u64* maxrun, u64* full, u64* rows) {
   if (abort && *abort) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     if (ndv) *ndv = 0;
     if (maxrun) *maxrun = 0;
     if (full) *full = 0;
+    if (rows) *rows = 0;
   }
   for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < cap; i += u64(gridDim.x) * blockDim.x)
     tab[i] = Slot{kEmptyKey, 0u, 0u};
@@ -79,9 +80,19 @@ __device__ __forceinline__ u32 lds_map_add(IdxLds& m, u64 key, u32& rank) {
   return h;
 }
 
+// kInc: an update over the appended rows, counting into dcnt; block 0 also
+// saves the old row count and clears the statistics the scan recomputes.
+template <bool kInc>
 __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
   __shared__ IdxLds m;
   if (p.abort && *p.abort) return;
+  if (kInc && p.abort2 && *p.abort2) return;
+  if (kInc && blockIdx.x == 0 && threadIdx.x == 0) {
+    *p.rows_prev = *p.rows;
+    *p.rows = 0;
+    *p.ndv = 0;
+    *p.maxrun = 0;
+  }
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
@@ -103,20 +114,28 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
       const u32 c = m.cnt[e];
       if (!c) continue;
       const u64 h = index_insert(p.table, mask, m.key[e]);
-      if (h != kNoSlot) atomicAdd(&p.table[h].count, c);
-      else if (p.full) *p.full = 1;
+      if (h == kNoSlot) {
+        if (p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
+        continue;
+      }
+      atomicAdd(kInc ? &p.dcnt[h] : &p.table[h].count, c);
     }
     __syncthreads();
   }
 }
 
-// Exclusive scan of slot counts over the table (look-back across tiles);
-// start <- prefix, count <- 0 so that it can serve as the fill cursor.
+// Exclusive scan over the table in slot order (look-back across tiles).
+// Build: start <- prefix of counts, count <- 0 (it becomes the fill cursor).
+// Update (kInc): dsh <- prefix of the appended counts, start += dsh, dcnt <- 0;
+// count keeps the old rows, so the fill appends after them.  Both recompute
+// the distinct keys, longest run and rows of the result.
+template <bool kInc>
 __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kBlock / kWave + 1];
   __shared__ u64 s_excl;
   if (p.abort && *p.abort) return;
+  if (kInc && p.abort2 && *p.abort2) return;
   const u32 epoch = launch_epoch(p.epoch_base, p.epoch_off);
   const u32 ntiles = u32((p.cap + kScanTile - 1) / kScanTile);
   if (blockIdx.x >= participants(ntiles)) return;
@@ -125,17 +144,25 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
     if (tile >= ntiles) break;
     const u64 s0 = u64(tile) * kScanTile + u64(threadIdx.x) * 4;
     u32 c[4];
-    u32 mine = 0, keys = 0, longest = 0;
+    u32 mine = 0, keys = 0, longest = 0, total = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      c[k] = (s0 + k < p.cap) ? p.table[s0 + k].count : 0u;
+      const bool in = s0 + k < p.cap;
+      const u32 old = in ? p.table[s0 + k].count : 0u;
+      c[k] = kInc ? (in ? p.dcnt[s0 + k] : 0u) : old;
+      const u32 all = kInc ? old + c[k] : old;
       mine += c[k];
-      keys += c[k] ? 1u : 0u;
-      longest = c[k] > longest ? c[k] : longest;
+      total += all;
+      keys += all ? 1u : 0u;
+      longest = all > longest ? all : longest;
     }
     if (p.ndv) {
       const u32 wk = wave_sum(keys);
       if (lane_id() == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
+    }
+    if (p.rows) {
+      const u64 wr = wave_sum(u64(total));
+      if (lane_id() == 0 && wr) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wr);
     }
     if (p.maxrun) {
       for (int d = kWave / 2; d >= 1; d >>= 1) {
@@ -167,8 +194,14 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (s0 + k < p.cap) {
-        p.table[s0 + k].start = u32(run);
-        p.table[s0 + k].count = 0u;
+        if (kInc) {
+          p.dsh[s0 + k] = u32(run);
+          p.dcnt[s0 + k] = 0u;
+          p.table[s0 + k].start += u32(run);
+        } else {
+          p.table[s0 + k].start = u32(run);
+          p.table[s0 + k].count = 0u;
+        }
       }
       run += c[k];
     }
@@ -179,13 +212,21 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
 // Scatter row ids into their key's run: the tile's rows are grouped in the
 // LDS map again, one global atomic per distinct key reserves the group's
 // places in the run, and each row takes the place of its rank in the group.
+template <bool kInc>
 __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
   __shared__ IdxLds m;
   if (p.abort && *p.abort) return;
+  if (kInc && p.abort2 && *p.abort2) return;
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
   const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
+  u32* perm = kInc ? p.perm_out : p.perm;
+  u32* pslot = kInc ? p.pslot_out : p.pslot;
+  if (*p.rows > p.perm_cap) {   // the runs would not fit: flag it, write nothing
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+    return;
+  }
   for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     lds_map_clear(m);
     __syncthreads();
@@ -205,15 +246,33 @@ __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
       const u64 h = index_slot_of(p.table, mask, m.key[e]);
       // a key whose insert failed has no run: the host rebuilds a larger table
       m.pos[e] = h == kNoSlot ? ~0u : p.table[h].start + atomicAdd(&p.table[h].count, c);
+      m.key[e] = h;   // the slot, for pslot (the map is not probed again)
     }
     __syncthreads();
 #pragma unroll
     for (u32 k = 0; k < kIdxItems; ++k) {
       if (ent[k] == ~0u) continue;
       const u32 base = m.pos[ent[k]];
-      if (base != ~0u) p.perm[base + rank[k]] = u32(begin + r0 + u64(k) * kBlock);
+      if (base == ~0u) continue;
+      perm[base + rank[k]] = u32(begin + r0 + u64(k) * kBlock);
+      pslot[base + rank[k]] = u32(m.key[ent[k]]);
     }
     __syncthreads();
+  }
+}
+
+// Update: old position i of slot s moves to i + dsh[s] (runs keep their
+// order and shift right by the rows appended to earlier slots).
+__global__ __launch_bounds__(kBlock) void k_idx_move(IndexParams p) {
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  if (*p.rows > p.perm_cap) return;   // flagged by the fill
+  const u64 n = *p.rows_prev;
+  for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
+    const u32 s = p.pslot[i];
+    const u64 j = i + p.dsh[s];
+    p.perm_out[j] = p.perm[i];
+    p.pslot_out[j] = s;
   }
 }
 
@@ -225,13 +284,25 @@ static int grid_rows(u64 n, int cap) {
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv,
-                     p.maxrun, p.full);
+                     p.maxrun, p.full, p.rows);
   const u64 row_tiles = (rows_cap + kIdxTile - 1) / kIdxTile;
   const int row_grid = int(row_tiles == 0 ? 1 : (row_tiles > 4096 ? 4096 : row_tiles));
-  hipLaunchKernelGGL(k_idx_count, dim3(row_grid), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_count<false>, dim3(row_grid), dim3(kBlock), 0, s, p);
   const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_idx_scan, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_idx_fill, dim3(row_grid), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_scan<false>, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_fill<false>, dim3(row_grid), dim3(kBlock), 0, s, p);
+  return int(hipGetLastError());
+}
+
+int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const u64 row_tiles = (delta_rows_cap + kIdxTile - 1) / kIdxTile;
+  const int row_grid = int(row_tiles == 0 ? 1 : (row_tiles > 4096 ? 4096 : row_tiles));
+  hipLaunchKernelGGL(k_idx_count<true>, dim3(row_grid), dim3(kBlock), 0, s, p);
+  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_idx_scan<true>, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_move, dim3(grid_rows(old_rows_cap, 8192)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_fill<true>, dim3(row_grid), dim3(kBlock), 0, s, p);
   return int(hipGetLastError());
 }
 

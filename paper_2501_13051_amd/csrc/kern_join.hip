@@ -269,6 +269,20 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
   u64 nbuild = 0;
   if (p.nkey == 0) nbuild = p.build_rows_ctr ? min_u64(*p.build_rows_ctr, p.build_cap) : p.build_rows;
   u64 pre_total = 0, kept_total = 0;
+  // output position <- the projected values of (probe row, build row)
+  auto put = [&](u64 pos, u64 prow, u64 brow) {
+    if (p.out.packed) {
+      u64 key = 0;
+#pragma unroll
+      for (u32 c = 0; c < kMaxCols; ++c)
+        if (c < p.out.ncols) key |= u64(src_val(p.out.src[c], p.pcol, prow, p.bcol, brow)) << p.out.shift[c];
+      p.out.keys[pos] = key;
+    } else {
+#pragma unroll
+      for (u32 c = 0; c < kMaxCols; ++c)
+        if (c < p.out.ncols) p.out.cols[c][pos] = src_val(p.out.src[c], p.pcol, prow, p.bcol, brow);
+    }
+  };
   for (u64 g = wave_id; g * kWave < n; g += n_waves) {
     const u64 r = g * kWave + lane;
     u32 st = 0, cnt = 0;
@@ -296,10 +310,38 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
     const u64 excl = inc - cnt;
     const u64 tw = __shfl(inc, kWave - 1, kWave);
     pre_total += tw;
+    if (tw == 0) continue;
+    if (p.n_filter == 0) {
+      // every output is kept: one reservation for the wave's outputs
+      u64 base = 0;
+      if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(p.out.count), (unsigned long long)tw);
+      base = __shfl(base, 0, kWave);
+      kept_total += tw;
+      if (base + tw > p.out.cap) {
+        if (lane == 0) *p.overflow = 1;
+        continue;
+      }
+      for (u64 c0 = 0; c0 < tw; c0 += kWave) {
+        const u64 o = c0 + lane;
+        int lo = 0;
+#pragma unroll
+        for (int step = kWave / 2; step >= 1; step >>= 1) {
+          const u64 e = __shfl(excl, lo + step, kWave);
+          if (o < tw && e <= o) lo += step;
+        }
+        const u64 ej = __shfl(excl, lo, kWave);
+        const u32 sj = __shfl(st, lo, kWave);
+        const u64 rowj = __shfl(row, lo, kWave);
+        if (o < tw) {
+          const u64 idx = u64(sj) + (o - ej);
+          put(base + o, rowj, p.perm ? u64(p.perm[idx]) : idx);
+        }
+      }
+      continue;
+    }
     for (u64 c0 = 0; c0 < tw; c0 += kWave) {
       const u64 o = c0 + lane;
       bool keep = false;
-      OutVals v;
       // owner lane j: the last lane whose exclusive prefix is <= o
       int lo = 0;
 #pragma unroll
@@ -310,9 +352,10 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
       const u64 ej = __shfl(excl, lo, kWave);
       const u32 sj = __shfl(st, lo, kWave);
       const u64 rowj = __shfl(row, lo, kWave);
+      u64 brow = 0;
       if (o < tw) {
         const u64 idx = u64(sj) + (o - ej);
-        const u64 brow = p.perm ? u64(p.perm[idx]) : idx;
+        brow = p.perm ? u64(p.perm[idx]) : idx;
         bool ok = true;
         for (u32 f = 0; f < p.n_filter; ++f) {
           const u32 a = src_val(p.filt[f].a, p.pcol, rowj, p.bcol, brow);
@@ -320,8 +363,6 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
           ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
         }
         keep = ok;
-        if (ok)
-          for (u32 c = 0; c < p.out.ncols; ++c) v.v[c] = src_val(p.out.src[c], p.pcol, rowj, p.bcol, brow);
       }
       const u64 km = __ballot(keep);
       const u32 kc = u32(__popcll(km));
@@ -334,16 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
         if (lane == 0) *p.overflow = 1;
         continue;
       }
-      if (keep) {
-        const u64 pos = base + u64(__popcll(km & ((1ull << lane) - 1)));
-        if (p.out.packed) {
-          u64 key = 0;
-          for (u32 c = 0; c < p.out.ncols; ++c) key |= u64(v.v[c]) << p.out.shift[c];
-          p.out.keys[pos] = key;
-        } else {
-          for (u32 c = 0; c < p.out.ncols; ++c) p.out.cols[c][pos] = v.v[c];
-        }
-      }
+      if (keep) put(base + u64(__popcll(km & ((1ull << lane) - 1))), rowj, brow);
     }
   }
   if (lane == 0) {
@@ -496,35 +528,40 @@ static int grid_for(u64 tiles, int cap_blocks) {
   return int(tiles < u64(cap_blocks) ? tiles : u64(cap_blocks));
 }
 
+LaunchEvents& armed_events() {
+  static thread_local LaunchEvents e;
+  return e;
+}
+
 int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream) {
   const u64 tiles = (probe_cap + kProbeTile - 1) / kProbeTile;
   int g = grid > 0 ? grid : grid_for(tiles, 2048);
-  hipLaunchKernelGGL(k_probe, dim3(g), dim3(kBlock), 0, (hipStream_t)stream, p);
+  launch_timed(k_probe, dim3(g), dim3(kBlock), (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream) {
   const u64 tiles = (out_tiles_hint + kWriteTile - 1) / kWriteTile;
-  hipLaunchKernelGGL(k_write, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  launch_timed(k_write, dim3(grid_for(tiles, 4096)), dim3(kBlock), (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream) {
   const u64 waves = (rows_hint + kWave - 1) / kWave;
   const u64 blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
-  hipLaunchKernelGGL(k_join_fused, dim3(grid_for(blocks, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  launch_timed(k_join_fused, dim3(grid_for(blocks, 4096)), dim3(kBlock), (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream) {
   const u64 tiles = (rows_hint + kWriteTile - 1) / kWriteTile;
-  hipLaunchKernelGGL(k_select, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  launch_timed(k_select, dim3(grid_for(tiles, 4096)), dim3(kBlock), (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream) {
   const u64 tiles = (rows_cap + kDedupTile - 1) / kDedupTile;
-  hipLaunchKernelGGL(k_dedup, dim3(grid_for(tiles, 2048)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  launch_timed(k_dedup, dim3(grid_for(tiles, 2048)), dim3(kBlock), (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 

@@ -19,25 +19,36 @@ constexpr int kHllM = 1 << kHllP;
 
 __device__ __forceinline__ u64 hll_hash(u64 v) { return mix64(v + 0x9E3779B97F4A7C15ull); }
 
-// registers of the values col0 (<< 32 | col1 when nkey == 2) of rows [begin, end)
-__global__ __launch_bounds__(kBlock) void k_hll(const u32* c0, const u32* c1, RowRange src, u32* regs) {
+// registers of the keys of the rows that pass the probe filters, and their count
+__global__ __launch_bounds__(kBlock) void k_hll(HllParams p) {
   __shared__ u32 s_reg[kHllM];
   for (int i = threadIdx.x; i < kHllM; i += kBlock) s_reg[i] = 0;
   __syncthreads();
   u64 begin, n;
-  source_range(src, begin, n);
+  source_range(p.src, begin, n);
+  u64 kept = 0;
   for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
     const u64 row = begin + r;
-    const u64 v = c1 ? ((u64(c0[row]) << 32) | c1[row]) : u64(c0[row]);
+    bool ok = true;
+    for (u32 f = 0; f < p.n_pf; ++f) {
+      const u32 a = p.pf[f].a.kind == kSrcConst ? p.pf[f].a.v : p.col[p.pf[f].a.v][row];
+      const u32 b = p.pf[f].b.kind == kSrcConst ? p.pf[f].b.v : p.col[p.pf[f].b.v][row];
+      ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
+    }
+    if (!ok) continue;
+    ++kept;
+    const u64 v = p.c1 >= 0 ? ((u64(p.col[p.c0][row]) << 32) | p.col[p.c1][row]) : u64(p.col[p.c0][row]);
     const u64 h = hll_hash(v);
     const u32 idx = u32(h >> (64 - kHllP));
     const u64 rest = h << kHllP;
     const u32 rho = rest ? u32(__clzll((long long)rest)) + 1 : u32(64 - kHllP + 1);
     atomicMax(&s_reg[idx], rho);
   }
+  const u64 wk = wave_sum(kept);
+  if (lane_id() == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wk);
   __syncthreads();
   for (int i = threadIdx.x; i < kHllM; i += kBlock)
-    if (s_reg[i]) atomicMax(&regs[i], s_reg[i]);
+    if (s_reg[i]) atomicMax(&p.regs[i], s_reg[i]);
 }
 
 // estimate -> *out (as a double's bits in a u64 counter slot)
@@ -66,14 +77,14 @@ __global__ __launch_bounds__(kBlock) void k_hll_estimate(const u32* regs, u64* o
   }
 }
 
-int launch_hll(const u32* c0, const u32* c1, RowRange src, u64 rows_hint, u32* regs, u64* out_estimate,
-               void* stream) {
+int launch_hll(const HllParams& p, u64 rows_hint, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  launch_fill_u32(regs, u64(kHllM), 0u, stream);
+  launch_fill_u32(p.regs, u64(kHllM), 0u, stream);
+  launch_fill_u64(p.rows, 1, 0, stream);
   const u64 b = (rows_hint + kBlock - 1) / kBlock;
   const int g = int(b == 0 ? 1 : (b > 512 ? 512 : b));
-  hipLaunchKernelGGL(k_hll, dim3(g), dim3(kBlock), 0, s, c0, c1, src, regs);
-  hipLaunchKernelGGL(k_hll_estimate, dim3(1), dim3(kBlock), 0, s, regs, out_estimate);
+  hipLaunchKernelGGL(k_hll, dim3(g), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_hll_estimate, dim3(1), dim3(kBlock), 0, s, p.regs, p.estimate);
   return int(hipGetLastError());
 }
 
@@ -231,14 +242,18 @@ __global__ void k_predict(const PredSpec* specs, u32 n, u64* ctr, const float* P
     if (o == 0) {
       double probe, probe_bound;
       if (sp.step == 0) {
-        const double full = double(ctr[sp.probe_full]);
-        probe = sp.probe_dbeg >= 0 ? full - double(ctr[sp.probe_dbeg]) : full;
+        if (sp.probe_rows >= 0) {
+          probe = double(ctr[sp.probe_rows]);
+        } else {
+          const double full = double(ctr[sp.probe_full]);
+          probe = sp.probe_dbeg >= 0 ? full - double(ctr[sp.probe_dbeg]) : full;
+        }
         probe_bound = probe;
       } else {
         probe = prev;
         probe_bound = prev_bound;
       }
-      const double build = double(ctr[sp.build_full]);
+      const double build = double(ctr[sp.rows_build >= 0 ? sp.rows_build : sp.build_full]);
       bound = probe_bound * (sp.maxrun_build >= 0 ? double(ctr[sp.maxrun_build]) : build);
       const double ndv_b = sp.ndv_build >= 0 ? double(ctr[sp.ndv_build]) : 1.0;
       double ndv_p = probe;

@@ -318,8 +318,8 @@ int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 
   const u32* h = p.hist + (u64(pass) << db);
   hipStream_t s = (hipStream_t)stream;
 #define FV_PASS(B, F)                                                                                     \
-  hipLaunchKernelGGL((k_rs_pass<B, F>), dim3(pgrid), dim3(kBlock), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, \
-                     sh, h, p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
+  launch_timed(k_rs_pass<B, F>, dim3(pgrid), dim3(kBlock), s, src, dst, p.n_ctr, p.n_const, p.cap, sh, h,      \
+               p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
   if (db == 11) {
     if (fuse) FV_PASS(11, true); else FV_PASS(11, false);
   } else {

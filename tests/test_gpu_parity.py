@@ -27,6 +27,7 @@ TUNINGS = {
     "fused": {"fuse_dedup": 1},
     "radix11_fused_tight": {"radix_bits": 11, "fuse_dedup": 1, "set_load": 0.75, "index_load": 0.75,
                             "max_blocks": 256},
+    "index_rebuild": {"index_rebuild": 1},
 }
 
 
@@ -181,9 +182,10 @@ def test_pointsto_small():
     _check(w.program, w.edb, relations=list(w.idb))
 
 
-def test_pointsto_full_size():
+@pytest.mark.parametrize("tuning", ["index_rebuild", "default"])
+def test_pointsto_full_size(tuning):
     w = W.config_pointsto()
-    got, stats, ref = _check(w.program, w.edb, relations=list(w.idb))
+    got, stats, ref = _check(w.program, w.edb, relations=list(w.idb), tuning=TUNINGS[tuning])
     assert stats["derived_tuples"] == sum(len(ref[n]) for n in w.idb)
 
 

@@ -52,6 +52,13 @@ Engine::Engine(const fv_options* opt) {
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
   trace_ = (opt_.flags & FV_TRACE) != 0;
+  if (trace_) {   // the constant-rate clock the kernels stamp (kHz)
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      wall_khz_ = double(khz);
+    (void)hipGetLastError();
+  }
   // per-kernel event timing needs the kernels launched one by one
   use_graph_ = !trace_ && (opt_.flags & FV_GRAPH);
   learned_ = (opt_.flags & FV_LEARNED) != 0;
@@ -79,6 +86,7 @@ Engine::~Engine() {
   }
   for (auto& I : inters_) for (auto& b : I.col) release(b);
   release(ctr_dev_); release(flags_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
+  release(stamps_dev_);
   release(m_row_); release(m_start_); release(m_off_);
   release(st_a_); release(st_b_); release(st_sort_);
   for (auto& sk : sketches_) release(sk.regs);
@@ -777,37 +785,41 @@ hipEvent_t Engine::pooled_event() {
 }
 
 // Time the launches between ev_begin and ev_end.  A single kernel (`single`)
-// is timed by the events its own dispatch stamps; a group of launches by
-// events recorded on the stream around it.  Inside graph capture the
-// recorded form is used.
-void Engine::ev_begin(int cls, bool single) {
-  if (!trace_) return;
-  if (!trace_only_.empty() && kprof_[cls].name != trace_only_) { ev_open_ = nullptr; return; }
-  ev_open_ = pooled_event();
-  ev_close_ = nullptr;
-  if (single && !capturing_) {
-    ev_close_ = pooled_event();
-    armed_events() = LaunchEvents{ev_open_, ev_close_};
-  } else {
-    hip(hipEventRecord(ev_open_, stream_), "event record");
+// gets a stamp slot (the returned pointer goes into its parameters): the
+// kernel stamps its own start and end on the device clock, so its time holds
+// no dispatch gap.  A group of launches, or a launch being captured into a
+// graph, is timed by events recorded on the stream around it.
+u64* Engine::ev_begin(int cls, bool single) {
+  ev_stamp_ = -1;
+  ev_open_ = nullptr;
+  if (!trace_) return nullptr;
+  if (!trace_only_.empty() && kprof_[cls].name != trace_only_) return nullptr;
+  ev_is_open_ = true;
+  if (single && !capturing_ && stamps_used_ == kMaxStamps && pending_.empty()) flush_stamps();
+  if (single && !capturing_ && stamps_used_ < kMaxStamps) {
+    if (!stamps_dev_.p) {
+      stamps_dev_ = alloc(size_t(kMaxStamps) * kStampWords * 8);
+      launched(launch_fill_u64(stamps_dev_.as<u64>(), u64(kMaxStamps) * kStampWords, 0, stream_), "stamp clear");
+    }
+    ev_stamp_ = int(stamps_used_++);
+    return stamps_dev_.as<u64>() + size_t(kStampWords) * ev_stamp_;
   }
+  ev_open_ = pooled_event();
+  hip(hipEventRecord(ev_open_, stream_), "event record");
+  return nullptr;
 }
 
 void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux) {
-  if (!trace_ || !ev_open_) return;
-  hipEvent_t e = ev_close_;
-  if (e) {
-    if (armed_events().start) {   // nothing was launched: an empty interval
-      armed_events() = LaunchEvents{};
-      hip(hipEventRecord(ev_open_, stream_), "event record");
-      hip(hipEventRecord(e, stream_), "event record");
-    }
-  } else {
+  if (!trace_ || !ev_is_open_) return;
+  ev_is_open_ = false;
+  hipEvent_t e = nullptr;
+  if (ev_stamp_ < 0) {
     e = pooled_event();
     hip(hipEventRecord(e, stream_), "event record");
   }
-  pending_.push_back(PendingEvent{cls, ev_open_, e, bytes, kind, ref0, ref1, aux});
-  ev_open_ = ev_close_ = nullptr;
+  pending_.push_back(PendingEvent{cls, ev_open_, e, bytes, kind, ref0, ref1, aux, ev_stamp_});
+  ev_open_ = nullptr;
+  ev_stamp_ = -1;
 }
 
 // Algorithmic bytes of a launch, from the sizes read back after the round.
@@ -823,7 +835,8 @@ void Engine::collect_events() {
   for (size_t idx = 0; idx < all.size(); ++idx) {
     PendingEvent& pe = all[idx];
     float ms = 0;
-    hip(hipEventElapsedTime(&ms, pe.a, pe.b), "event elapsed");
+    if (pe.stamp >= 0) stamped_.emplace_back(pe.cls, pe.stamp);   // its time comes with flush_stamps
+    else hip(hipEventElapsedTime(&ms, pe.a, pe.b), "event elapsed");
     KClass& k = kprof_[pe.cls];
     k.launches += 1;
     k.ms += ms;
@@ -879,12 +892,29 @@ void Engine::collect_events() {
     }
     k.bytes += bytes;
     k.items += items;
-    if (idx < n_eager) {   // events owned by the graph are recorded again by the next replay
+    if (idx < n_eager && pe.stamp < 0) {   // events owned by the graph are recorded again by the next replay
       ev_pool_.push_back(pe.a);
       ev_pool_.push_back(pe.b);
     }
   }
   graph_replayed_ = false;
+}
+
+// Times of the stamped launches so far, in one readback (the slots then start
+// over).  Called when the slots run out and at the end of a run.
+void Engine::flush_stamps() {
+  if (!stamps_used_) return;
+  std::vector<u64> w(size_t(kStampWords) * stamps_used_);
+  hip(hipMemcpyAsync(w.data(), stamps_dev_.p, w.size() * 8, hipMemcpyDeviceToHost, stream_), "stamp readback");
+  sync();
+  for (auto& cs : stamped_) {
+    const u64* s = &w[size_t(kStampWords) * cs.second];
+    const u64 t0 = s[0], t1 = *std::max_element(s + 1, s + kStampWords);
+    if (t0 && t1 > t0) kprof_[cs.first].ms += double(t1 - t0) / wall_khz_;   // an aborted launch stamps no end
+  }
+  stamped_.clear();
+  launched(launch_fill_u64(stamps_dev_.as<u64>(), w.size(), 0, stream_), "stamp clear");
+  stamps_used_ = 0;
 }
 
 // ------------------------------------------------------------------ execution
@@ -952,7 +982,7 @@ void Engine::exec_plan(Plan& p) {
       sp.abort = nullptr;
       sp.overflow = flags;
       const int kc = kclass("select");
-      ev_begin(kc, true);
+      sp.ts = ev_begin(kc, true);
       launched(launch_select(sp, std::max<u64>(probe_bound, 1), stream_), "select launch");
       ev_end(kc, 0, 0);
       continue;
@@ -985,7 +1015,7 @@ void Engine::exec_plan(Plan& p) {
       fp.join_out_stat = ctr(c_joinout_);
       fp.overflow = flags;
       const int kf = kclass("join_onepass");
-      ev_begin(kf, true);
+      fp.ts = ev_begin(kf, true);
       launched(launch_join_fused(fp, std::max<u64>(probe_bound, 1), stream_), "one-pass join launch");
       ev_end(kf, 0, 7, probe_ctr, s.c_t, probe_bound);
       continue;
@@ -1020,7 +1050,7 @@ void Engine::exec_plan(Plan& p) {
     pp.abort = nullptr;
     pp.fatal = flags + 1;
     const int kp = kclass("join_probe");
-    ev_begin(kp, true);
+    pp.ts = ev_begin(kp, true);
     launched(launch_probe(pp, std::max<u64>(probe_bound, 1), 0, stream_), "probe launch");
     ev_end(kp, 0, 1, probe_ctr, s.c_m, probe_bound);
 
@@ -1045,7 +1075,7 @@ void Engine::exec_plan(Plan& p) {
     for (auto& f : s.wf) nbuild += (f.a.kind == kSrcBuild) + (f.b.kind == kSrcBuild);
     const u64 out_bytes = o.packed ? 8 : 4ull * o.ncols;
     const int kw = kclass("join_write");
-    ev_begin(kw, true);
+    wp.ts = ev_begin(kw, true);
     launched(launch_write(wp, std::max<u64>(o.cap, 1), stream_), "write launch");
     ev_end(kw, 0, 2, s.c_m, s.c_t, (ix ? 4 : 0) + 4ull * nbuild + out_bytes);
   }
@@ -1095,7 +1125,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   }
   for (u32 pass = 0; pass < passes; ++pass) {
     const bool last_fused = fuse && pass + 1 == passes;
-    ev_begin(last_fused ? kfused : kpass, true);
+    sp.ts = ev_begin(last_fused ? kfused : kpass, true);
     launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_, last_fused ? &fz : nullptr),
              "sort pass launch");
     ev_end(last_fused ? kfused : kpass, 0, last_fused ? 6 : 3, c_new0_ + ri, c_delta0_ + ri,
@@ -1124,7 +1154,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.epoch_off = next_epoch();
   dp.abort = flags;
   const int kd = kclass("dedup_append");
-  ev_begin(kd, true);
+  dp.ts = ev_begin(kd, true);
   launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_), "dedup launch");
   ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
 }
@@ -1677,6 +1707,7 @@ void Engine::run(fv_stats* stats) {
   run_round(true);
   while (deltas_.back() != 0) run_round(false);
   const auto t1 = std::chrono::steady_clock::now();
+  flush_stamps();
   if (stats) {
     stats->iterations = u32(deltas_.size());
     stats->redo_rounds = redo_;

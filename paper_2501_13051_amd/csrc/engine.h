@@ -150,6 +150,7 @@ struct PendingEvent {
   int kind;       // which counter-derived formula
   int ref0, ref1; // counter references
   u64 aux;
+  int stamp = -1;  // >= 0: timed by the kernel's own stamps in this slot
 };
 
 class Engine;
@@ -229,7 +230,7 @@ class Engine {
 
   // profiling
   int kclass(const char* name);
-  void ev_begin(int cls, bool single = false);
+  u64* ev_begin(int cls, bool single = false);
   hipEvent_t pooled_event();
   void ev_end(int cls, double bytes, int kind = 0, int ref0 = -1, int ref1 = -1, u64 aux = 0);
   void collect_events();
@@ -301,7 +302,14 @@ class Engine {
   std::vector<PendingEvent> pending_;
   std::vector<hipEvent_t> ev_pool_;
   hipEvent_t ev_open_ = nullptr;
-  hipEvent_t ev_close_ = nullptr;   // set when the launch stamps its own events
+  bool ev_is_open_ = false;
+  int ev_stamp_ = -1;
+  static constexpr u32 kMaxStamps = 8192;   // stamped launches per round
+  Buf stamps_dev_;                          // [kMaxStamps][start, 64 ends] device clock
+  u32 stamps_used_ = 0;
+  std::vector<std::pair<int, u32>> stamped_;   // (kernel class, slot) awaiting flush_stamps
+  void flush_stamps();
+  double wall_khz_ = 100000.0;              // device wall clock rate
 };
 
 }  // namespace fv

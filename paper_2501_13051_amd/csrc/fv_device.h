@@ -3,7 +3,6 @@
 // decoupled look-back used for order-preserving stream compaction.
 #pragma once
 
-#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -11,17 +10,23 @@
 
 namespace fv {
 
-// Launch one kernel, with the armed timing events if there are any.
-template <typename... KArgs, typename... Args>
-inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, Args... args) {
-  LaunchEvents& ev = armed_events();
-  if (ev.start) {
-    hipEvent_t a = static_cast<hipEvent_t>(ev.start), z = static_cast<hipEvent_t>(ev.stop);
-    ev.start = ev.stop = nullptr;
-    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, z, 0u, static_cast<KArgs>(args)...);
-  } else {
-    hipLaunchKernelGGL(kernel, grid, block, 0, s, static_cast<KArgs>(args)...);
-  }
+// Kernel timing for traces: with ts set, block 0 stamps the start (ts[0])
+// and every block raises one of kStampEnds end words (ts[1 + block % 64]) to
+// its end, read from the constant-rate wall clock; the host takes the latest
+// end minus the start as the kernel's own duration, with no inter-kernel
+// dispatch gap in it.  Spreading the ends keeps thousands of exiting blocks
+// off a single word.  ktime_end is reached by all threads of a block.
+constexpr u32 kStampEnds = 64;
+static_assert(kStampEnds + 1 == kStampWords, "stamp slot layout");
+__device__ __forceinline__ void ktime_start(u64* ts) {
+  if (ts && blockIdx.x == 0 && threadIdx.x == 0) ts[0] = u64(wall_clock64());
+}
+__device__ __forceinline__ void ktime_end(u64* ts) {
+  if (!ts) return;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(ts + 1 + (blockIdx.x % kStampEnds)),
+              (unsigned long long)wall_clock64());
 }
 
 constexpr int kWave = 64;

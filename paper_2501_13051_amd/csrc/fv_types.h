@@ -18,6 +18,7 @@ constexpr u32 kEpochMask = (1u << 22) - 1;
 // phase uses base + its own offset (1 .. kEpochStride-1), so replaying a
 // captured graph never meets status words of an earlier replay.
 constexpr u32 kEpochStride = 1024;
+constexpr u32 kStampWords = 65;   // per timed launch (traces): start, then 64 end words
 constexpr int kMaxCols = 6;              // columns of an intermediate result
 constexpr int kMaxFilters = 8;
 
@@ -90,6 +91,7 @@ struct ProbeParams {
   u32 epoch_off;
   const u32* abort;
   u32* fatal;
+  u64* ts;               // trace timing slot (see ktime_start), nullable
 };
 
 struct WriteParams {
@@ -108,6 +110,7 @@ struct WriteParams {
   u64* join_out_stat;    // running total of tuples written by joins
   const u32* abort;
   u32* overflow;
+  u64* ts;               // trace timing slot (see ktime_start), nullable
 };
 
 // Probe + write in one pass into a presized output (see k_join_fused).
@@ -131,6 +134,7 @@ struct FusedJoinParams {
   u64* out_t;            // join output size before filters (added per wave)
   u64* join_out_stat;
   u32* overflow;
+  u64* ts;               // trace timing slot (see ktime_start), nullable
 };
 
 struct SelectParams {
@@ -142,6 +146,7 @@ struct SelectParams {
   u64* join_out_stat;
   const u32* abort;
   u32* overflow;
+  u64* ts;               // trace timing slot (see ktime_start), nullable
 };
 
 struct DedupParams {
@@ -161,6 +166,7 @@ struct DedupParams {
   const u32* epoch_base;
   u32 epoch_off;
   const u32* abort;
+  u64* ts;               // trace timing slot (see ktime_start), nullable
 };
 
 struct CommitParams {
@@ -176,15 +182,6 @@ struct CommitParams {
 // ------------------------------------------------------------------ launchers
 // Each wrapper enqueues kernels on `stream` (a hipStream_t) and returns the
 // hipError_t of the launch as int.
-// Timing events for the next single-kernel launch: when armed, that launch
-// has the runtime stamp `start` and `stop` with the kernel's own dispatch
-// start and end (no gap for a separate event record), and disarms them.
-struct LaunchEvents {
-  void* start = nullptr;
-  void* stop = nullptr;
-};
-LaunchEvents& armed_events();
-
 int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream);
 int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream);
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream);
@@ -214,6 +211,7 @@ struct SortParams {
   u32* ticket;
   const u32* epoch_base;
   const u32* abort;
+  u64* ts;               // trace timing slot (see ktime_start), nullable
 };
 struct SortFuse {
   u64* set;

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
   __shared__ u32 s_m[kBlock / kWave + 1];
   __shared__ u64 s_t[kBlock / kWave + 1];
   __shared__ u64 s_excl[2];
+  ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   u64 begin, n;
   source_range(p.src, begin, n);
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
     }
     __syncthreads();
   }
+  ktime_end(p.ts);
 }
 
 // ------------------------------------------------------------------ shared append
@@ -197,6 +199,7 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
   __shared__ u64 s_j0;
   __shared__ u32 s_cnt[kBlock / kWave + 1];
   __shared__ u64 s_base;
+  ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   const u64 M = min_u64(*p.in_m, p.m_cap);
   const u64 T = *p.in_t;
@@ -249,6 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
     }
     append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
   }
+  ktime_end(p.ts);
 }
 
 // ------------------------------------------------------------------ single-pass join
@@ -261,6 +265,7 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
 // Outputs past the buffer are counted, not written, and raise the overflow
 // flag; the host then re-runs the round with count-then-write.
 __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
+  ktime_start(p.ts);
   u64 begin, n;
   source_range(p.src, begin, n);
   const int lane = lane_id();
@@ -383,12 +388,14 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
     if (kept_total && p.join_out_stat)
       atomicAdd(reinterpret_cast<unsigned long long*>(p.join_out_stat), (unsigned long long)kept_total);
   }
+  ktime_end(p.ts);
 }
 
 // ------------------------------------------------------------------ select / project
 __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
   __shared__ u32 s_cnt[kBlock / kWave + 1];
   __shared__ u64 s_base;
+  ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   u64 begin, n;
   source_range(p.src, begin, n);
@@ -417,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
     }
     append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
   }
+  ktime_end(p.ts);
 }
 
 // ------------------------------------------------------------------ dedup + append
@@ -424,6 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kBlock / kWave + 1];
   __shared__ u64 s_excl;
+  ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   u64 begin, n;
   source_range(p.src, begin, n);
@@ -488,6 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
     if (tile == ntiles - 1 && threadIdx.x == 0) *p.out_delta = s_excl + tot;
     __syncthreads();
   }
+  ktime_end(p.ts);
 }
 
 __global__ void k_commit(CommitParams p) {
@@ -528,40 +538,35 @@ static int grid_for(u64 tiles, int cap_blocks) {
   return int(tiles < u64(cap_blocks) ? tiles : u64(cap_blocks));
 }
 
-LaunchEvents& armed_events() {
-  static thread_local LaunchEvents e;
-  return e;
-}
-
 int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream) {
   const u64 tiles = (probe_cap + kProbeTile - 1) / kProbeTile;
   int g = grid > 0 ? grid : grid_for(tiles, 2048);
-  launch_timed(k_probe, dim3(g), dim3(kBlock), (hipStream_t)stream, p);
+  hipLaunchKernelGGL(k_probe, dim3(g), dim3(kBlock), 0, (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream) {
   const u64 tiles = (out_tiles_hint + kWriteTile - 1) / kWriteTile;
-  launch_timed(k_write, dim3(grid_for(tiles, 4096)), dim3(kBlock), (hipStream_t)stream, p);
+  hipLaunchKernelGGL(k_write, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream) {
   const u64 waves = (rows_hint + kWave - 1) / kWave;
   const u64 blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
-  launch_timed(k_join_fused, dim3(grid_for(blocks, 4096)), dim3(kBlock), (hipStream_t)stream, p);
+  hipLaunchKernelGGL(k_join_fused, dim3(grid_for(blocks, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream) {
   const u64 tiles = (rows_hint + kWriteTile - 1) / kWriteTile;
-  launch_timed(k_select, dim3(grid_for(tiles, 4096)), dim3(kBlock), (hipStream_t)stream, p);
+  hipLaunchKernelGGL(k_select, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 
 int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream) {
   const u64 tiles = (rows_cap + kDedupTile - 1) / kDedupTile;
-  launch_timed(k_dedup, dim3(grid_for(tiles, 2048)), dim3(kBlock), (hipStream_t)stream, p);
+  hipLaunchKernelGGL(k_dedup, dim3(grid_for(tiles, 2048)), dim3(kBlock), 0, (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 

@@ -59,6 +59,7 @@ struct FuseArgs {
   u32 arity;
   u32 shift[3];
   u32 width[3];
+  u64* ts;             // trace timing slot (nullable)
 };
 
 template <int kBits, bool kFuse>
@@ -77,6 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
   __shared__ u32 s_scan32[kWaves + 1];
   __shared__ u32 s_ticket;
   __shared__ u64 s_out;
+  ktime_start(fz.ts);
   if (abort && *abort) return;
   const u32 epoch = launch_epoch(epoch_base, epoch_off);
   const u64 n = sort_n(n_ctr, n_const, cap);
@@ -253,6 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     }
     __syncthreads();
   }
+  ktime_end(fz.ts);
 }
 
 __global__ void k_fill_u32(u32* p, u64 n, u32 v) {
@@ -301,6 +304,7 @@ int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 
   const u64 maxg = p.max_blocks ? p.max_blocks : 2048;
   const int pgrid = int(tiles == 0 ? 1 : (tiles > maxg ? maxg : tiles));
   FuseArgs fz{};
+  fz.ts = p.ts;
   if (fuse) {
     fz.set = fuse->set;
     fz.set_mask = fuse->set_mask;
@@ -318,8 +322,8 @@ int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 
   const u32* h = p.hist + (u64(pass) << db);
   hipStream_t s = (hipStream_t)stream;
 #define FV_PASS(B, F)                                                                                     \
-  launch_timed(k_rs_pass<B, F>, dim3(pgrid), dim3(kBlock), s, src, dst, p.n_ctr, p.n_const, p.cap, sh, h,      \
-               p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
+  hipLaunchKernelGGL((k_rs_pass<B, F>), dim3(pgrid), dim3(kBlock), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, sh, h, \
+                     p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
   if (db == 11) {
     if (fuse) FV_PASS(11, true); else FV_PASS(11, false);
   } else {

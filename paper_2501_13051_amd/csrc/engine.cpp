@@ -554,7 +554,7 @@ void Engine::plan_all() {
   // counter layout: [derived, join_out] [full_n x R] [d_begin x R]
   //   [index distinct keys] [index longest runs] [index full flags] [index rows] [HLL estimate, rows]
   //   [predicted join sizes]                                          (kept across rounds)
-  //   [delta x R] [new x R] [per-join m,t] [per-intermediate count]  (cleared every round)
+  //   [delta x R] [new x R] [per-join m,t] [per-intermediate count] [sketch rows]  (cleared every round)
   const int R = int(rels_.size());
   c_derived_ = 0;
   c_joinout_ = 1;
@@ -598,7 +598,6 @@ void Engine::plan_all() {
           sk.delta = delta;
           sk.pf = s0.pf;
           sk.ctr = next++;
-          sk.ctr_rows = next++;
           sketches_.push_back(sk);
           found = int(sketches_.size() - 1);
         }
@@ -619,6 +618,8 @@ void Engine::plan_all() {
       for (auto& s : p.steps)
         if (!s.select_only) { s.c_m = next++; s.c_t = next++; }
   for (auto& I : inters_) I.ctr = next++;
+  // rows passing a sketch's filters: counted afresh by every sketch launch
+  for (auto& sk : sketches_) sk.ctr_rows = next++;
   n_ctr_ = next;
 }
 
@@ -685,7 +686,7 @@ bool Engine::ensure_capacity() {
     // selective filter, or a low-cardinality column) gets a smaller one.
     u64 keys;
     if (ix.keys_seen) keys = R.used_as_head ? 2 * std::max<u64>(ix.keys_seen, 512) : ix.keys_seen;
-    else keys = R.used_as_head ? R.n_full + std::max<u64>({3 * R.n_delta, R.new_cap / 4, 1024}) : R.n_full;
+    else keys = R.used_as_head ? R.n_full + std::max<u64>({3 * R.n_delta, base_cap_ / 4, 1024}) : R.n_full;
     keys = std::min<u64>(keys, rows + 1);
     u64 need = pow2_at_least(std::max<u64>(u64(double(keys) / tune_.index_load), 64));
     if (ix.grow) need = std::max<u64>(need, 4 * ix.cap);
@@ -1263,6 +1264,7 @@ void Engine::ingest() {
   u64 total = 0;
   for (auto& R : rels_) total += R.staged;
   const u64 base_cap = pow2_at_least(std::max<u64>(1 << 16, 2 * total));
+  base_cap_ = base_cap;
   for (auto& R : rels_) {
     R.new_cap = std::max<u64>(R.staged, R.used_as_head ? base_cap : 1);
     if (!R.used_as_head) {   // read-only relation: exactly its facts
@@ -1526,7 +1528,10 @@ void Engine::note_index_builds() {
 
 // ------------------------------------------------------------------ learned predictor
 void Engine::setup_learning() {
-  for (auto& sk : sketches_) sk.regs = alloc(kHllRegs * 4);
+  for (auto& sk : sketches_) {   // zero here; each estimate clears them again after use
+    sk.regs = alloc(kHllRegs * 4);
+    launched(launch_fill_u32(sk.regs.as<u32>(), kHllRegs, 0u, stream_), "sketch clear");
+  }
   if (!learned_) return;
   predictor_dev_ = alloc(kMlpParams * 4);
   hip(hipMemcpyAsync(predictor_dev_.p, predictor_.data(), kMlpParams * 4, hipMemcpyHostToDevice, stream_),
@@ -1567,6 +1572,17 @@ void Engine::setup_learning() {
 // HLL sketches of the probe keys the next round's first joins will use, then
 // (FV_LEARNED) the predictor over every join of that round.
 void Engine::emit_sketches_and_prediction(bool initial) {
+  HllBatch batch{};
+  u64 rows_hint = 1;
+  auto flush = [&]() {
+    if (!batch.n) return;
+    const int kc = kclass("hll_sketch");
+    ev_begin(kc);
+    launched(launch_hll_batch(batch, rows_hint, stream_), "hll");
+    ev_end(kc, 0, 0);
+    batch.n = 0;
+    rows_hint = 1;
+  };
   for (auto& sk : sketches_) {
     if (sk.delta == initial) continue;
     const Relation& R = rels_[sk.rel];
@@ -1584,11 +1600,11 @@ void Engine::emit_sketches_and_prediction(bool initial) {
     hp.regs = sk.regs.as<u32>();
     hp.estimate = ctr(sk.ctr);
     hp.rows = ctr(sk.ctr_rows);
-    const int kc = kclass("hll_sketch");
-    ev_begin(kc);
-    launched(launch_hll(hp, std::max<u64>(R.cap, 1), stream_), "hll");
-    ev_end(kc, 0, 0);
+    batch.s[batch.n++] = hp;
+    rows_hint = std::max<u64>(rows_hint, sk.delta ? R.n_full + R.new_cap : R.n_full);
+    if (batch.n == kHllBatch) flush();
   }
+  flush();
   if (!learned_) return;
   const std::vector<PredSpec>& v = initial ? pspec_init_ : pspec_delta_;
   const Buf& d = initial ? pspec_init_dev_ : pspec_delta_dev_;

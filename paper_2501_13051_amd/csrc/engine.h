@@ -279,6 +279,7 @@ class Engine {
   u32 redo_ = 0;
   // learned predictor
   bool learned_ = false, log_joins_ = false, use_fused_ = false;
+  u64 base_cap_ = 0;   // new-tuple capacity set at ingest (2x the loaded facts, at least 2^16)
   std::vector<bool> fused_steps_, graph_fused_steps_;   // per-step one-pass choice (now / when captured)
   void choose_join_algorithms(bool initial);
   std::vector<float> predictor_;          // MLP parameters (host copy)

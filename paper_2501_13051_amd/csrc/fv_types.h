@@ -316,7 +316,16 @@ struct HllParams {
   u64* estimate;
   u64* rows;
 };
-int launch_hll(const HllParams& p, u64 rows_hint, void* stream);
+// Up to kHllBatch sketches in one launch (descriptors travel as the kernel
+// argument).  The estimate pass also clears each sketch's registers for its
+// next use; the row counts must be zero before the launch.
+constexpr u32 kHllBatch = 8;
+struct HllBatch {
+  u32 n;
+  HllParams s[kHllBatch];
+};
+static_assert(sizeof(HllBatch) <= 4096, "a sketch batch must fit in the kernel argument block");
+int launch_hll_batch(const HllBatch& b, u64 rows_hint, void* stream);
 int launch_dense_fwd(const float* in, u32 n, u32 din, const float* W, const float* b, u32 dout, float in_scale,
                      float* z, float* out, int relu, void* stream);
 int launch_mse(const float* yhat, const float* y, u32 n, float* dy, float* loss, void* stream);

@@ -255,135 +255,149 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
   ktime_end(p.ts);
 }
 
-// ------------------------------------------------------------------ single-pass join
-// Probe and write in one launch, for joins whose output buffer was presized
-// (by the cardinality predictor): no count pass, no scan scratch.  A wave
-// probes 64 rows, scans their run lengths in registers, then produces the
-// group's outputs 64 at a time (output n is found by a binary search over the
-// lanes' prefixes through cross-lane shuffles, so work stays balanced inside
-// the wave), and reserves room for each chunk's kept outputs with one atomic.
-// Outputs past the buffer are counted, not written, and raise the overflow
-// flag; the host then re-runs the round with count-then-write.
+// Presized one-pass join: a block takes a tile of kFusedTile probe rows, looks
+// their keys up, scans the match counts in LDS, reserves the tile's outputs
+// with one atomic and writes them output-balanced (each thread finds the probe
+// row of an output position by binary search over the tile's prefix).  With
+// write filters the outputs are compacted per chunk of kBlock instead, one
+// reservation per chunk.  Outputs past the buffer are counted, not written,
+// and raise the overflow flag (the round then runs again with count-then-
+// write joins).
+constexpr u32 kFusedItems = 4;
+constexpr u32 kFusedTile = kBlock * kFusedItems;
+
+// Output position <- the projected values of (probe row, build row).
+__device__ __forceinline__ void fused_put(const OutSpec& out, const u32* const* pcol, const u32* const* bcol, u64 pos,
+                                          u64 prow, u64 brow) {
+  if (out.packed) {
+    u64 key = 0;
+#pragma unroll
+    for (u32 c = 0; c < kMaxCols; ++c)
+      if (c < out.ncols) key |= u64(src_val(out.src[c], pcol, prow, bcol, brow)) << out.shift[c];
+    out.keys[pos] = key;
+  } else {
+#pragma unroll
+    for (u32 c = 0; c < kMaxCols; ++c)
+      if (c < out.ncols) out.cols[c][pos] = src_val(out.src[c], pcol, prow, bcol, brow);
+  }
+}
+
+// Tile index of output o: the last j with off[j] <= o (its count is > 0).
+__device__ __forceinline__ u32 fused_owner(const u64* off, u64 o) {
+  u32 lo = 0, hi = kFusedTile;
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (off[mid] <= o) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
+  __shared__ u64 s_off[kFusedTile + 1];
+  __shared__ u32 s_start[kFusedTile];
+  __shared__ u64 s_scan[kBlock / kWave + 1];
+  __shared__ u32 s_keep[kBlock / kWave + 1];
+  __shared__ u64 s_base;
   ktime_start(p.ts);
   u64 begin, n;
   source_range(p.src, begin, n);
-  const int lane = lane_id();
-  const u64 wave_id = (u64(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const u64 n_waves = u64(gridDim.x) * blockDim.x / kWave;
   u64 nbuild = 0;
   if (p.nkey == 0) nbuild = p.build_rows_ctr ? min_u64(*p.build_rows_ctr, p.build_cap) : p.build_rows;
-  u64 pre_total = 0, kept_total = 0;
-  // output position <- the projected values of (probe row, build row)
-  auto put = [&](u64 pos, u64 prow, u64 brow) {
-    if (p.out.packed) {
-      u64 key = 0;
+  u64 pre_total = 0, kept_total = 0;   // thread 0's tallies
+  const u64 ntiles = (n + kFusedTile - 1) / kFusedTile;
+  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const u64 t0 = tile * kFusedTile;
+    u32 st[kFusedItems], cnt[kFusedItems];
+    u64 mine = 0;
 #pragma unroll
-      for (u32 c = 0; c < kMaxCols; ++c)
-        if (c < p.out.ncols) key |= u64(src_val(p.out.src[c], p.pcol, prow, p.bcol, brow)) << p.out.shift[c];
-      p.out.keys[pos] = key;
-    } else {
-#pragma unroll
-      for (u32 c = 0; c < kMaxCols; ++c)
-        if (c < p.out.ncols) p.out.cols[c][pos] = src_val(p.out.src[c], p.pcol, prow, p.bcol, brow);
-    }
-  };
-  for (u64 g = wave_id; g * kWave < n; g += n_waves) {
-    const u64 r = g * kWave + lane;
-    u32 st = 0, cnt = 0;
-    u64 row = 0;
-    if (r < n) {
-      row = begin + r;
-      bool ok = true;
-      for (u32 f = 0; f < p.n_pf; ++f) {
-        const u32 a = probe_val(p.pf[f].a, p.pcol, row);
-        const u32 b = probe_val(p.pf[f].b, p.pcol, row);
-        ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
-      }
-      if (ok) {
-        if (p.nkey == 0) {
-          cnt = u32(nbuild);
-        } else {
-          const u32 a = probe_val(p.key[0], p.pcol, row);
-          const u32 b = p.nkey == 2 ? probe_val(p.key[1], p.pcol, row) : 0u;
-          u32 s0, c0;
-          if (index_find(p.table, p.mask, make_key(p.nkey, a, b), s0, c0)) { st = s0; cnt = c0; }
-        }
-      }
-    }
-    const u64 inc = wave_inclusive_sum<u64>(u64(cnt));
-    const u64 excl = inc - cnt;
-    const u64 tw = __shfl(inc, kWave - 1, kWave);
-    pre_total += tw;
-    if (tw == 0) continue;
-    if (p.n_filter == 0) {
-      // every output is kept: one reservation for the wave's outputs
-      u64 base = 0;
-      if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(p.out.count), (unsigned long long)tw);
-      base = __shfl(base, 0, kWave);
-      kept_total += tw;
-      if (base + tw > p.out.cap) {
-        if (lane == 0) *p.overflow = 1;
-        continue;
-      }
-      for (u64 c0 = 0; c0 < tw; c0 += kWave) {
-        const u64 o = c0 + lane;
-        int lo = 0;
-#pragma unroll
-        for (int step = kWave / 2; step >= 1; step >>= 1) {
-          const u64 e = __shfl(excl, lo + step, kWave);
-          if (o < tw && e <= o) lo += step;
-        }
-        const u64 ej = __shfl(excl, lo, kWave);
-        const u32 sj = __shfl(st, lo, kWave);
-        const u64 rowj = __shfl(row, lo, kWave);
-        if (o < tw) {
-          const u64 idx = u64(sj) + (o - ej);
-          put(base + o, rowj, p.perm ? u64(p.perm[idx]) : idx);
-        }
-      }
-      continue;
-    }
-    for (u64 c0 = 0; c0 < tw; c0 += kWave) {
-      const u64 o = c0 + lane;
-      bool keep = false;
-      // owner lane j: the last lane whose exclusive prefix is <= o
-      int lo = 0;
-#pragma unroll
-      for (int step = kWave / 2; step >= 1; step >>= 1) {
-        const u64 e = __shfl(excl, lo + step, kWave);
-        if (o < tw && e <= o) lo += step;
-      }
-      const u64 ej = __shfl(excl, lo, kWave);
-      const u32 sj = __shfl(st, lo, kWave);
-      const u64 rowj = __shfl(row, lo, kWave);
-      u64 brow = 0;
-      if (o < tw) {
-        const u64 idx = u64(sj) + (o - ej);
-        brow = p.perm ? u64(p.perm[idx]) : idx;
+    for (u32 k = 0; k < kFusedItems; ++k) {
+      st[k] = 0;
+      cnt[k] = 0;
+      const u64 r = t0 + threadIdx.x * kFusedItems + k;
+      if (r < n) {
+        const u64 row = begin + r;
         bool ok = true;
-        for (u32 f = 0; f < p.n_filter; ++f) {
-          const u32 a = src_val(p.filt[f].a, p.pcol, rowj, p.bcol, brow);
-          const u32 b = src_val(p.filt[f].b, p.pcol, rowj, p.bcol, brow);
-          ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
+        for (u32 f = 0; f < p.n_pf; ++f) {
+          const u32 a = probe_val(p.pf[f].a, p.pcol, row);
+          const u32 b = probe_val(p.pf[f].b, p.pcol, row);
+          ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
         }
-        keep = ok;
+        if (ok) {
+          if (p.nkey == 0) {
+            cnt[k] = u32(nbuild);
+          } else {
+            const u32 a = probe_val(p.key[0], p.pcol, row);
+            const u32 b = p.nkey == 2 ? probe_val(p.key[1], p.pcol, row) : 0u;
+            u32 s0, c0;
+            if (index_find(p.table, p.mask, make_key(p.nkey, a, b), s0, c0)) { st[k] = s0; cnt[k] = c0; }
+          }
+        }
       }
-      const u64 km = __ballot(keep);
-      const u32 kc = u32(__popcll(km));
-      if (kc == 0) continue;
-      u64 base = 0;
-      if (lane == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(p.out.count), (unsigned long long)kc);
-      base = __shfl(base, 0, kWave);
-      kept_total += kc;
-      if (base + kc > p.out.cap) {
-        if (lane == 0) *p.overflow = 1;
-        continue;
-      }
-      if (keep) put(base + u64(__popcll(km & ((1ull << lane) - 1))), rowj, brow);
+      mine += cnt[k];
     }
+    u64 tot;
+    u64 ex = block_exclusive_sum<kBlock>(mine, s_scan, &tot);
+#pragma unroll
+    for (u32 k = 0; k < kFusedItems; ++k) {
+      s_off[threadIdx.x * kFusedItems + k] = ex;
+      s_start[threadIdx.x * kFusedItems + k] = st[k];
+      ex += cnt[k];
+    }
+    if (threadIdx.x == 0) s_off[kFusedTile] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) pre_total += tot;
+    if (tot == 0) continue;   // block-uniform; nothing reads the tile's LDS
+    if (p.n_filter == 0) {
+      if (threadIdx.x == 0) s_base = atomicAdd(reinterpret_cast<unsigned long long*>(p.out.count), (unsigned long long)tot);
+      __syncthreads();
+      const u64 base = s_base;
+      if (threadIdx.x == 0) kept_total += tot;
+      if (base + tot > p.out.cap) {
+        if (threadIdx.x == 0) *p.overflow = 1;
+      } else {
+        for (u64 o = threadIdx.x; o < tot; o += kBlock) {
+          const u32 j = fused_owner(s_off, o);
+          const u64 idx = u64(s_start[j]) + (o - s_off[j]);
+          fused_put(p.out, p.pcol, p.bcol, base + o, begin + t0 + j, p.perm ? u64(p.perm[idx]) : idx);
+        }
+      }
+    } else {
+      for (u64 c0 = 0; c0 < tot; c0 += kBlock) {
+        const u64 o = c0 + threadIdx.x;
+        bool keep = false;
+        u64 prow = 0, brow = 0;
+        if (o < tot) {
+          const u32 j = fused_owner(s_off, o);
+          const u64 idx = u64(s_start[j]) + (o - s_off[j]);
+          prow = begin + t0 + j;
+          brow = p.perm ? u64(p.perm[idx]) : idx;
+          bool ok = true;
+          for (u32 f = 0; f < p.n_filter; ++f) {
+            const u32 a = src_val(p.filt[f].a, p.pcol, prow, p.bcol, brow);
+            const u32 b = src_val(p.filt[f].b, p.pcol, prow, p.bcol, brow);
+            ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
+          }
+          keep = ok;
+        }
+        u32 kc;
+        const u32 kpos = block_exclusive_sum<kBlock>(keep ? 1u : 0u, s_keep, &kc);
+        if (kc == 0) continue;   // block-uniform
+        if (threadIdx.x == 0) s_base = atomicAdd(reinterpret_cast<unsigned long long*>(p.out.count), (unsigned long long)kc);
+        __syncthreads();
+        const u64 base = s_base;
+        if (threadIdx.x == 0) kept_total += kc;
+        if (base + kc > p.out.cap) {
+          if (threadIdx.x == 0) *p.overflow = 1;
+        } else if (keep) {
+          fused_put(p.out, p.pcol, p.bcol, base + kpos, prow, brow);
+        }
+        __syncthreads();   // s_base and s_keep are reused by the next chunk
+      }
+    }
+    __syncthreads();   // the next tile overwrites s_off / s_start
   }
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     if (pre_total) atomicAdd(reinterpret_cast<unsigned long long*>(p.out_t), (unsigned long long)pre_total);
     if (kept_total && p.join_out_stat)
       atomicAdd(reinterpret_cast<unsigned long long*>(p.join_out_stat), (unsigned long long)kept_total);
@@ -552,9 +566,8 @@ int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream) {
 }
 
 int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream) {
-  const u64 waves = (rows_hint + kWave - 1) / kWave;
-  const u64 blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
-  hipLaunchKernelGGL(k_join_fused, dim3(grid_for(blocks, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+  const u64 tiles = (rows_hint + kFusedTile - 1) / kFusedTile;
+  hipLaunchKernelGGL(k_join_fused, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
   return int(hipGetLastError());
 }
 

@@ -19,9 +19,11 @@ constexpr int kHllM = 1 << kHllP;
 
 __device__ __forceinline__ u64 hll_hash(u64 v) { return mix64(v + 0x9E3779B97F4A7C15ull); }
 
-// registers of the keys of the rows that pass the probe filters, and their count
-__global__ __launch_bounds__(kBlock) void k_hll(HllParams p) {
+// Sketch blockIdx.y of the batch: registers of the keys of the rows that pass
+// the probe filters (kept as the maximum per register), and their count.
+__global__ __launch_bounds__(kBlock) void k_hll(HllBatch b) {
   __shared__ u32 s_reg[kHllM];
+  const HllParams& p = b.s[blockIdx.y];
   for (int i = threadIdx.x; i < kHllM; i += kBlock) s_reg[i] = 0;
   __syncthreads();
   u64 begin, n;
@@ -32,8 +34,8 @@ __global__ __launch_bounds__(kBlock) void k_hll(HllParams p) {
     bool ok = true;
     for (u32 f = 0; f < p.n_pf; ++f) {
       const u32 a = p.pf[f].a.kind == kSrcConst ? p.pf[f].a.v : p.col[p.pf[f].a.v][row];
-      const u32 b = p.pf[f].b.kind == kSrcConst ? p.pf[f].b.v : p.col[p.pf[f].b.v][row];
-      ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
+      const u32 c = p.pf[f].b.kind == kSrcConst ? p.pf[f].b.v : p.col[p.pf[f].b.v][row];
+      ok = ok && (p.pf[f].op == kEq ? a == c : a != c);
     }
     if (!ok) continue;
     ++kept;
@@ -51,15 +53,18 @@ __global__ __launch_bounds__(kBlock) void k_hll(HllParams p) {
     if (s_reg[i]) atomicMax(&p.regs[i], s_reg[i]);
 }
 
-// estimate -> *out (as a double's bits in a u64 counter slot)
-__global__ __launch_bounds__(kBlock) void k_hll_estimate(const u32* regs, u64* out) {
+// One block per sketch: the estimate (as a double's bits in a u64 counter
+// slot), then the registers are cleared for the sketch's next use.
+__global__ __launch_bounds__(kBlock) void k_hll_estimate(HllBatch b) {
   __shared__ double s_sum[kBlock];
   __shared__ u32 s_zero[kBlock];
+  const HllParams& p = b.s[blockIdx.x];
   double sum = 0;
   u32 zeros = 0;
   for (int i = threadIdx.x; i < kHllM; i += kBlock) {
-    sum += ldexp(1.0, -int(regs[i]));
-    zeros += regs[i] == 0;
+    const u32 r = p.regs[i];
+    sum += ldexp(1.0, -int(r));
+    zeros += r == 0;
   }
   s_sum[threadIdx.x] = sum;
   s_zero[threadIdx.x] = zeros;
@@ -73,18 +78,18 @@ __global__ __launch_bounds__(kBlock) void k_hll_estimate(const u32* regs, u64* o
     const double alpha = 0.7213 / (1.0 + 1.079 / m);
     double e = alpha * m * m / s_sum[0];
     if (e <= 2.5 * m && s_zero[0] > 0) e = m * log(m / double(s_zero[0]));
-    *out = __double_as_longlong(e);
+    *p.estimate = __double_as_longlong(e);
   }
+  for (int i = threadIdx.x; i < kHllM; i += kBlock) p.regs[i] = 0;
 }
 
-int launch_hll(const HllParams& p, u64 rows_hint, void* stream) {
+int launch_hll_batch(const HllBatch& b, u64 rows_hint, void* stream) {
+  if (b.n == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
-  launch_fill_u32(p.regs, u64(kHllM), 0u, stream);
-  launch_fill_u64(p.rows, 1, 0, stream);
-  const u64 b = (rows_hint + kBlock - 1) / kBlock;
-  const int g = int(b == 0 ? 1 : (b > 512 ? 512 : b));
-  hipLaunchKernelGGL(k_hll, dim3(g), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_hll_estimate, dim3(1), dim3(kBlock), 0, s, p.regs, p.estimate);
+  const u64 blocks = (rows_hint + kBlock - 1) / kBlock;
+  const u32 g = u32(blocks == 0 ? 1 : (blocks > 256 ? 256 : blocks));
+  hipLaunchKernelGGL(k_hll, dim3(g, b.n), dim3(kBlock), 0, s, b);
+  hipLaunchKernelGGL(k_hll_estimate, dim3(b.n), dim3(kBlock), 0, s, b);
   return int(hipGetLastError());
 }
 

@@ -71,3 +71,27 @@ def test_trained_predictor_on_plain_traces():
     got, stats, deltas, _ = fv.evaluate(program, edb, flags=fv.FV_LEARNED, relations=rels, predictor=params)
     assert np.array_equal(got["t"], ref["t"]) and deltas == ref.delta_sizes
     assert stats["predicted_joins"] > 0 and stats["qerror_median"] >= 1.0
+
+
+def test_trained_predictor_gains_over_plain_engine():
+    """What the network buys on an RDFS workload it never saw: the same
+    fixpoint with fewer join count passes (light joins run presized in one
+    pass) and no more re-run rounds than the plain engine's capacity guess."""
+    rows = []
+    for program, edb, rels in _cases()[:3]:
+        *_, trace = fv.evaluate(program, edb, flags=fv.FV_LOG_JOINS, relations=rels, with_trace=True)
+        rows.append(trace)
+    T = np.concatenate(rows)
+    params, _ = fv.mlp_train(T[:, :8], T[:, 8], steps=1500, lr=3e-3, seed=3)
+    w = W.config_rdfs(scale=0.02)
+    ref = oracle.evaluate(w.program, w.edb, relations=["t"])
+    runs = {}
+    for name, flags in (("plain", fv.FV_TRACE), ("learned", fv.FV_TRACE | fv.FV_LEARNED)):
+        got, stats, deltas, prof = fv.evaluate(w.program, w.edb, flags=flags, relations=["t"], predictor=params)
+        assert np.array_equal(got["t"], ref["t"]) and deltas == ref.delta_sizes, name
+        runs[name] = (stats, {k["name"]: k for k in prof})
+        print(name, stats["ms_total"], "ms, redo", stats["redo_rounds"], flush=True)
+    count_passes = {n: r[1].get("join_probe", {"launches": 0})["launches"] for n, r in runs.items()}
+    assert count_passes["learned"] < count_passes["plain"], count_passes
+    assert runs["learned"][1]["join_onepass"]["launches"] > 0
+    assert runs["learned"][0]["redo_rounds"] <= runs["plain"][0]["redo_rounds"]

@@ -319,6 +319,11 @@ def extras(fv, W, torch, np, args):
         "tuples_per_s_learned": round(lst["derived_tuples"] / (learned_ms * 1e-3), 1)}
     del rr
 
+    # --- one join at large sizes: per-kernel bandwidth where sizes are not
+    # latency-bound (probe 2^24..2^26 rows against 2^20..2^22 keys)
+    log("large-join sweep")
+    forms["large_join_sweep"] = join_sweep(fv, W, torch, np)
+
     # --- autotuned single-instance points-to
     log("autotuned form: points-to")
     pt = W.config_pointsto()
@@ -332,6 +337,28 @@ def extras(fv, W, torch, np, args):
                                    "derived_tuples": int(t_st["derived_tuples"]),
                                    "tuples_per_s_tuned": round(t_st["derived_tuples"] / (t_ms * 1e-3), 1)}
     return forms
+
+
+def join_sweep(fv, W, torch, np):
+    cases = []
+    for n_probe, n_keys, zipf_s in ((1 << 24, 1 << 20, 0.0), (1 << 26, 1 << 22, 0.0), (1 << 25, 1 << 21, 1.0)):
+        w = W.join_case(n_probe, n_keys, zipf_s)
+        r = Runner(fv, torch, np, w.program, w.edb, ["out"])
+        r.run_once(flags=fv.FV_TRACE)
+        st, prof, _ = r.run_once(flags=fv.FV_TRACE)
+        kernels = {}
+        for k in prof:
+            if not k["launches"] or k["ms"] <= 0:
+                continue
+            gbs = k["algo_bytes"] / (k["ms"] * 1e-3) / 1e9
+            kernels[k["name"]] = {"ms": round(k["ms"], 3), "launches": k["launches"], "GB_s": round(gbs, 1),
+                                  "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        cases.append({"case": w.name, "derived_tuples": int(st["derived_tuples"]),
+                      "ms_fixpoint": round(st["ms_total"], 3),
+                      "tuples_per_s": round(st["derived_tuples"] / (st["ms_total"] * 1e-3), 1), "kernels": kernels})
+        del r
+        torch.cuda.empty_cache()
+    return cases
 
 
 if __name__ == "__main__":

@@ -5,8 +5,9 @@
 // widths taken from the value domain, so a sort touches only the bits that
 // can be set.  One histogram pass counts the digits of every pass at once;
 // each pass is then a single read and write of the keys ("onesweep"): a tile
-// of 2048 keys is ranked stably in LDS (wave64 match masks built from one
-// ballot per digit bit, per-wave digit counters), the tile's per-digit counts
+// of 4096 keys (2048 with 11-bit digits or in the fused pass) is ranked stably
+// in LDS (wave64 match masks built from one ballot per digit bit, per-wave
+// digit counters), the tile's per-digit counts
 // are chained across tiles with a decoupled look-back, and the keys are staged
 // in LDS in digit order so that the global scatter writes contiguous runs.
 // Digits are 8 or 11 bits (a tuning knob).
@@ -21,7 +22,6 @@
 
 namespace fv {
 
-constexpr int kSortItems = kSortTile / kBlock;   // 8 keys per thread
 
 __device__ __forceinline__ u64 sort_n(const u64* n_ctr, u64 n_const, u64 cap) {
   return n_ctr ? min_u64(*n_ctr, cap) : n_const;
@@ -70,8 +70,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
                                                    FuseArgs fz) {
   constexpr int kRadix = 1 << kBits;
   constexpr int kWaves = kBlock / kWave;
+  // keys per thread: 16 for a plain pass with 8-bit digits, else 8 (11-bit
+  // digit counters take 8x the LDS; the fused pass, which also probes the
+  // tuple set, keeps more tiles in flight)
+  constexpr int kItems = (kBits <= 8 && !kFuse) ? 16 : 8;
+  constexpr u32 kTile = kBlock * kItems;
   constexpr int kDpt = kRadix > kBlock ? kRadix / kBlock : 1;   // digits owned per thread
-  __shared__ u64 s_keys[kSortTile];
+  __shared__ u64 s_keys[kTile];
   __shared__ u32 s_wcnt[kWaves][kRadix];
   __shared__ u32 s_tstart[kRadix + 1];
   __shared__ u64 s_base[kRadix];
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
   if (abort && *abort) return;
   const u32 epoch = launch_epoch(epoch_base, epoch_off);
   const u64 n = sort_n(n_ctr, n_const, cap);
-  const u32 ntiles = u32((n + kSortTile - 1) / kSortTile);
+  const u32 ntiles = u32((n + kTile - 1) / kTile);
   const int w = threadIdx.x / kWave;
   const int lane = lane_id();
   const u64 lt_mask = (1ull << lane) - 1;
@@ -114,28 +119,27 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     if (tile >= ntiles) break;
     for (int i = threadIdx.x; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
-    const u64 t0 = u64(tile) * kSortTile;
-    u64 key[kSortItems];
-    u32 dig[kSortItems];
-    u32 rank[kSortItems];
+    const u64 t0 = u64(tile) * kTile;
+    u64 key[kItems];
+    u32 rank[kItems];
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-      const u64 idx = t0 + u64(w) * (kWave * kSortItems) + u64(i) * kWave + lane;
+    for (int i = 0; i < kItems; ++i) {
+      const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
       const bool valid = idx < n;
       key[i] = valid ? in[idx] : 0;
-      dig[i] = valid ? u32((key[i] >> shift) & (kRadix - 1)) : 0u;
+      const u32 dig = valid ? u32((key[i] >> shift) & (kRadix - 1)) : 0u;
       u64 mask = __ballot(valid);
 #pragma unroll
       for (int b = 0; b < kBits; ++b) {
-        const bool bit = (dig[i] >> b) & 1u;
+        const bool bit = (dig >> b) & 1u;
         const u64 bb = __ballot(bit);
         mask &= bit ? bb : ~bb;
       }
       // lanes with equal digits read the old count, then the lowest of them
       // (the leader) adds the group size; LDS ops of one wave stay in order.
-      const u32 old = valid ? s_wcnt[w][dig[i]] : 0u;
+      const u32 old = valid ? s_wcnt[w][dig] : 0u;
       rank[i] = old + u32(__popcll(mask & lt_mask));
-      if (valid && (mask & lt_mask) == 0) s_wcnt[w][dig[i]] = old + u32(__popcll(mask));
+      if (valid && (mask & lt_mask) == 0) s_wcnt[w][dig] = old + u32(__popcll(mask));
     }
     __syncthreads();
     u32 tcount[kDpt];
@@ -199,15 +203,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kSortItems; ++i) {
-      const u64 idx = t0 + u64(w) * (kWave * kSortItems) + u64(i) * kWave + lane;
-      if (idx < n) s_keys[s_tstart[dig[i]] + s_wcnt[w][dig[i]] + rank[i]] = key[i];
+    for (int i = 0; i < kItems; ++i) {
+      const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
+      if (idx < n) {
+        const u32 dig = u32((key[i] >> shift) & (kRadix - 1));
+        s_keys[s_tstart[dig] + s_wcnt[w][dig] + rank[i]] = key[i];
+      }
     }
     __syncthreads();
-    const u32 tn = u32(min_u64(kSortTile, n - t0));
+    const u32 tn = u32(min_u64(kTile, n - t0));
     if (!kFuse) {
 #pragma unroll
-      for (int i = 0; i < kSortItems; ++i) {
+      for (int i = 0; i < kItems; ++i) {
         const u32 q = u32(i) * kBlock + threadIdx.x;
         if (q < tn) {
           const u64 k = s_keys[q];
@@ -218,11 +225,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     } else {
       // difference against full and append; consecutive LDS slots of one
       // digit hold consecutive keys of the sorted order
-      bool surv[kSortItems];
+      bool surv[kItems];
       u32 mine = 0;
 #pragma unroll
-      for (int i = 0; i < kSortItems; ++i) {
-        const u32 q = threadIdx.x * kSortItems + u32(i);
+      for (int i = 0; i < kItems; ++i) {
+        const u32 q = threadIdx.x * kItems + u32(i);
         surv[i] = false;
         if (q < tn) {
           const u64 k = s_keys[q];
@@ -243,9 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       __syncthreads();
       u64 pos = fbase + s_out + ex;
 #pragma unroll
-      for (int i = 0; i < kSortItems; ++i) {
+      for (int i = 0; i < kItems; ++i) {
         if (!surv[i]) continue;
-        const u64 k = s_keys[threadIdx.x * kSortItems + u32(i)];
+        const u64 k = s_keys[threadIdx.x * kItems + u32(i)];
         for (u32 c = 0; c < fz.arity; ++c) {
           const u64 m = fz.width[c] >= 32 ? 0xFFFFFFFFull : ((1ull << fz.width[c]) - 1);
           fz.cols[c][pos] = u32((k >> fz.shift[c]) & m);

@@ -409,3 +409,28 @@ def config_rdfs(seed: int = 1005, scale: float = 1.0) -> Workload:
                      seed=seed)
     return Workload(name=f"rdfs_{int(20_000_000 * scale)}", program=RDFS_PROGRAM, edb={"t": d["t"]},
                     idb=("t",), meta={"triples": int(20_000_000 * scale), **d["ids"], "seed": seed})
+
+
+# ---------------------------------------------------------------- join sweep
+JOIN_PROGRAM = """
+out(x, z) :- a(x, y), b(y, z).
+"""
+
+
+def join_case(n_probe: int, n_keys: int, zipf_s: float = 0.0, seed: int = 1006) -> Workload:
+    """One non-recursive join at large sizes: a(x, y) has n_probe rows with
+    distinct x and y drawn from n_keys keys (uniform, or Zipf(s) over a random
+    key ranking); b(y, z) has one row per key.  out has exactly n_probe
+    distinct tuples; the build side of the join is a's index on y, whose runs
+    follow the key distribution."""
+    rng = SplitMix64(seed)
+    x = np.arange(n_probe, dtype=np.uint32)
+    if zipf_s > 0:
+        y = _zipf_pick(n_keys, n_probe, zipf_s, rng).astype(np.uint32)
+    else:
+        y = rng.below(n_keys, n_probe).astype(np.uint32)
+    by = np.arange(n_keys, dtype=np.uint32)
+    bz = rng.below(1 << 30, n_keys).astype(np.uint32)
+    name = f"join_p{n_probe}_k{n_keys}_" + (f"zipf{zipf_s:g}" if zipf_s > 0 else "uniform")
+    return Workload(name=name, program=JOIN_PROGRAM, edb={"a": [x, y], "b": [by, bz]}, idb=("out",),
+                    meta={"probe_rows": n_probe, "keys": n_keys, "zipf_s": zipf_s, "seed": seed})

@@ -115,6 +115,12 @@ def test_autotune_picks_a_stored_tuning_with_the_same_fixpoint(tmp_path):
     _check(W.SG_PROGRAM, edb, relations=["sg"], tuning=best)
 
 
+@pytest.mark.parametrize("zipf_s", [0.0, 1.0])
+def test_join_case_small(zipf_s):
+    w = W.join_case(1 << 14, 1 << 10, zipf_s)
+    _check(w.program, w.edb, relations=["out"])
+
+
 def test_empty_and_duplicate_inputs():
     e0 = [np.zeros(0, np.uint32), np.zeros(0, np.uint32)]
     _check(W.TC_PROGRAM, {"edge": e0}, relations=["path", "edge"])

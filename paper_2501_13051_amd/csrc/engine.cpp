@@ -684,13 +684,22 @@ bool Engine::ensure_capacity() {
     // the index's full flag and the table is rebuilt larger before the next
     // round reads it; one measured far below its table (an index over a
     // selective filter, or a low-cardinality column) gets a smaller one.
+    // a derived relation's index before its first measurement also gets room
+    // for the rows the first rounds may add, scaled by the share of the
+    // relation's rows it keeps (all of them when the relation starts empty)
+    const u64 grow_rows = !R.used_as_head ? 0
+                          : R.n_full ? u64(double(ix.rows_hint) / double(R.n_full) * double(base_cap_ / 4))
+                                     : base_cap_ / 4;
     u64 keys;
     if (ix.keys_seen) keys = R.used_as_head ? 2 * std::max<u64>(ix.keys_seen, 512) : ix.keys_seen;
+    else if (ix.hinted && !R.used_as_head) keys = std::max<u64>(ix.keys_hint + ix.keys_hint / 4, 512);
+    else if (ix.hinted)
+      keys = std::max<u64>(2 * std::max<u64>(ix.keys_hint + ix.keys_hint / 4, 512), ix.keys_hint + grow_rows / 2);
     else keys = R.used_as_head ? R.n_full + std::max<u64>({3 * R.n_delta, base_cap_ / 4, 1024}) : R.n_full;
     keys = std::min<u64>(keys, rows + 1);
     u64 need = pow2_at_least(std::max<u64>(u64(double(keys) / tune_.index_load), 64));
     if (ix.grow) need = std::max<u64>(need, 4 * ix.cap);
-    const bool oversized = ix.keys_seen && ix.cap > 8 * need;
+    const bool oversized = (ix.keys_seen || ix.hinted) && ix.cap > 8 * need;
     if (ix.cap == 0 || ix.grow || double(keys) > 0.75 * double(ix.cap) || oversized) {
       release(ix.table);
       release(ix.dcnt);
@@ -711,9 +720,14 @@ bool Engine::ensure_capacity() {
     // round reads it.
     u64 want = rows;
     bool realloc_perm = ix.perm_cap < rows;
-    if (R.used_as_head && ix.rows_seen) {
-      want = std::min<u64>(rows, 4 * std::max<u64>(ix.rows_seen, 4096));
-      realloc_perm = 2 * ix.rows_seen > ix.perm_cap || ix.perm_cap > 16 * want;
+    const u64 have = ix.rows_seen ? ix.rows_seen : (ix.hinted ? ix.rows_hint : 0);
+    if (!R.used_as_head && ix.hinted) {
+      want = std::max<u64>(ix.rows_hint, 1);
+      realloc_perm = ix.perm_cap < want;
+    } else if (R.used_as_head && (have || ix.hinted)) {
+      want = std::min<u64>(rows, 4 * std::max<u64>(have, 4096));
+      if (!ix.rows_seen) want = std::min<u64>(rows, std::max<u64>(want, have + grow_rows));
+      realloc_perm = 2 * have > ix.perm_cap || ix.perm_cap > 16 * want || ix.perm_cap < have;
     }
     if (ix.perm_grow) {
       want = std::max<u64>(want, 2 * ix.perm_cap);
@@ -721,16 +735,24 @@ bool Engine::ensure_capacity() {
     }
     ix.perm_grow = false;
     if (ix.perm_cap == 0 || realloc_perm) {
-      for (Buf* b : {&ix.perm, &ix.pslot, &ix.perm2, &ix.pslot2}) release(*b);
+      // an intact index keeps its layout: the positions it holds move to the
+      // new arrays (a streaming copy) instead of a rebuild
+      const bool keep = !ix.dirty && ix.rows_seen && want >= ix.rows_seen && ix.perm.p && ix.pslot.p;
       const u64 n = std::max<u64>(want, 1) * 4;
-      ix.perm = alloc(n);
-      ix.pslot = alloc(n);
+      Buf np = alloc(n), ns = alloc(n);
+      if (keep) {
+        hip(hipMemcpyAsync(np.p, ix.perm.p, ix.rows_seen * 4, hipMemcpyDeviceToDevice, stream_), "index copy");
+        hip(hipMemcpyAsync(ns.p, ix.pslot.p, ix.rows_seen * 4, hipMemcpyDeviceToDevice, stream_), "index copy");
+      }
+      for (Buf* b : {&ix.perm, &ix.pslot, &ix.perm2, &ix.pslot2}) release(*b);
+      ix.perm = np;
+      ix.pslot = ns;
       if (R.used_as_head) {
         ix.perm2 = alloc(n);
         ix.pslot2 = alloc(n);
       }
       ix.perm_cap = want;
-      ix.dirty = true;
+      if (!keep) ix.dirty = true;
     }
     max_rows = std::max(max_rows, ix.cap);
   }
@@ -1419,8 +1441,13 @@ void Engine::run_round(bool initial) {
       // an index whose storage grew holds nothing yet: rebuild it over the
       // current full relation before any join reads it
       begin_phase();
-      for (auto& ix : indices_)
-        if (ix.dirty) build_index(ix);
+      std::vector<u32> built;
+      for (u32 i = 0; i < indices_.size(); ++i)
+        if (indices_[i].dirty) {
+          build_index(indices_[i]);
+          built.push_back(i);
+        }
+      verify_builds(built);
     }
     if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) begin_phase();   // clears status arrays
     bool replayed = false;
@@ -1500,6 +1527,95 @@ void Engine::run_round(bool initial) {
   deltas_.push_back(total);
 }
 
+// Before an index's first build: one sketch launch per batch of indices (the
+// index's key columns under its row filter) estimates the distinct keys and
+// counts the rows the index will hold, so that tables and row arrays start at
+// their size instead of the relation's (an index over a selective filter or a
+// low-cardinality column holds far fewer keys than its relation has rows).
+void Engine::presize_indices() {
+  std::vector<u32> todo;
+  for (u32 i = 0; i < indices_.size(); ++i)
+    if (!indices_[i].keys_seen && !indices_[i].hinted) todo.push_back(i);
+  if (todo.empty()) return;
+  Buf regs = alloc(size_t(kHllBatch) * kHllRegs * 4);
+  Buf out = alloc(todo.size() * 16);
+  launched(launch_fill_u32(regs.as<u32>(), u64(kHllBatch) * kHllRegs, 0u, stream_), "sketch clear");
+  launched(launch_fill_u64(out.as<u64>(), 2 * todo.size(), 0, stream_), "sketch clear");
+  for (size_t b0 = 0; b0 < todo.size(); b0 += kHllBatch) {
+    HllBatch batch{};
+    u64 rows_hint = 1;
+    for (size_t k = b0; k < todo.size() && batch.n < kHllBatch; ++k) {
+      const Index& ix = indices_[todo[k]];
+      const Relation& R = rels_[ix.rel];
+      HllParams& hp = batch.s[batch.n];
+      for (u32 c = 0; c < R.arity; ++c) hp.col[c] = R.col[c].as<u32>();
+      hp.c0 = ix.keycol[0];
+      hp.c1 = ix.nkey == 2 ? int(ix.keycol[1]) : -1;
+      hp.src.end_ctr = ctr(c_full0_ + int(ix.rel));
+      hp.src.cap = std::max<u64>(R.cap, 1);
+      hp.n_pf = ix.nfilt;
+      for (u32 f = 0; f < ix.nfilt; ++f)
+        hp.pf[f] = Filter{Src{kSrcProbe, ix.fcol[f]}, Src{kSrcConst, ix.fval[f]}, kEq};
+      hp.regs = regs.as<u32>() + size_t(batch.n) * kHllRegs;
+      hp.estimate = out.as<u64>() + 2 * k;
+      hp.rows = out.as<u64>() + 2 * k + 1;
+      rows_hint = std::max<u64>(rows_hint, R.n_full);
+      ++batch.n;
+    }
+    launched(launch_hll_batch(batch, rows_hint, stream_), "index sketch");
+  }
+  std::vector<u64> h(2 * todo.size());
+  hip(hipMemcpyAsync(h.data(), out.p, h.size() * 8, hipMemcpyDeviceToHost, stream_), "sketch readback");
+  sync();
+  for (size_t k = 0; k < todo.size(); ++k) {
+    Index& ix = indices_[todo[k]];
+    double est;
+    std::memcpy(&est, &h[2 * k], 8);
+    ix.keys_hint = std::min<u64>(u64(est > 0 ? est : 0) + 1, std::max<u64>(h[2 * k + 1], 1));
+    ix.rows_hint = h[2 * k + 1];
+    ix.hinted = true;
+  }
+  release(regs);
+  release(out);
+}
+
+// Builds that a round's joins are about to read must be complete: read their
+// flags back and rebuild any that ran out of slots or positions, larger,
+// until none does.  Their counts then size the next round.
+void Engine::verify_builds(std::vector<u32> built) {
+  for (int attempt = 0; attempt < 24 && !built.empty(); ++attempt) {
+    std::vector<u64> c(n_ctr_);
+    hip(hipMemcpyAsync(c.data(), ctr_dev_.p, size_t(n_ctr_) * 8, hipMemcpyDeviceToHost, stream_), "build check");
+    sync();
+    bool again = false;
+    for (u32 i : built) {
+      Index& ix = indices_[i];
+      const u64 full = c[ix.c_full];
+      if (full) {
+        if (full & 1) ix.grow = true;
+        if (full & 2) ix.perm_grow = true;
+        ix.keys_seen = ix.rows_seen = 0;
+        ix.hinted = false;   // outgrown its sketch: size from the relation instead
+        ix.dirty = true;
+        again = true;
+      } else if (c[ix.c_rows]) {   // an empty index says nothing about its size to come
+        ix.keys_seen = std::max<u64>(c[ix.c_ndv], 1);
+        ix.rows_seen = c[ix.c_rows];
+      }
+    }
+    if (!again) return;
+    ensure_capacity();
+    begin_phase();
+    built.clear();
+    for (u32 i = 0; i < indices_.size(); ++i)
+      if (indices_[i].dirty) {
+        build_index(indices_[i]);
+        built.push_back(i);
+      }
+  }
+  if (!built.empty()) throw Error(FV_ENOMEM, "a join index did not fit after repeated growth");
+}
+
 // After a round: the distinct-key counts of the indices just built size their
 // tables for the next round; an index whose build ran out of slots is
 // incomplete and is rebuilt larger before any join reads it.
@@ -1519,8 +1635,10 @@ void Engine::note_index_builds() {
       // relation's rows instead, so that it cannot fall short as well
       ix.rows_seen = 0;
       ix.keys_seen = 0;
+      ix.hinted = false;
       continue;
     }
+    if (!ctr_host_[ix.c_rows]) continue;   // empty: keep sizing from the relation
     ix.rows_seen = ctr_host_[ix.c_rows];
     ix.keys_seen = std::max<u64>(ctr_host_[ix.c_ndv], 1);
   }
@@ -1712,9 +1830,15 @@ void Engine::run(fv_stats* stats) {
   alloc_control();
   setup_learning();
   ingest();
+  presize_indices();
   ensure_capacity();
   begin_phase();
   build_indices(false);
+  {
+    std::vector<u32> all(indices_.size());
+    for (u32 i = 0; i < all.size(); ++i) all[i] = i;
+    verify_builds(all);
+  }
   if (log_joins_) {
     emit_sketches_and_prediction(true);
     read_counters();

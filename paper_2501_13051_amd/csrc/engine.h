@@ -81,6 +81,9 @@ struct Index {
   int c_rows_prev = -1;       // device counter: rows before the last update
   u64 keys_seen = 0;          // distinct keys found by the last complete build
   u64 rows_seen = 0;          // rows indexed by the last complete build or update
+  u64 keys_hint = 0;          // before the first build: estimated distinct keys (sketch)
+  u64 rows_hint = 0;          //   and the exact rows it will hold
+  bool hinted = false;
   bool grow = false;          // the last build ran out of slots: rebuild larger
   bool perm_grow = false;     // the last build ran out of positions: rebuild with more
   Buf table, perm, pslot;     // slots; row ids grouped by key; each position's slot
@@ -216,6 +219,8 @@ class Engine {
   void emit_sketches_and_prediction(bool initial);
   void size_from_predictions(bool initial);
   void note_index_builds();
+  void presize_indices();
+  void verify_builds(std::vector<u32> built);
   void update_index(Index& ix);
   void log_joins(bool initial);
   void exec_plan(Plan& p);

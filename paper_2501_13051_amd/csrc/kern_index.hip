@@ -113,6 +113,9 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
     for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
       const u32 c = m.cnt[e];
       if (!c) continue;
+      // once the table has overflowed the index is rebuilt larger anyway:
+      // later keys skip the (long) probe sequence of a full table
+      if (p.full && (__hip_atomic_load(p.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1)) continue;
       const u64 h = index_insert(p.table, mask, m.key[e]);
       if (h == kNoSlot) {
         if (p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
@@ -223,6 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
   const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
   u32* perm = kInc ? p.perm_out : p.perm;
   u32* pslot = kInc ? p.pslot_out : p.pslot;
+  if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
   if (*p.rows > p.perm_cap) {   // the runs would not fit: flag it, write nothing
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
     return;
@@ -267,6 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_idx_move(IndexParams p) {
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
   if (*p.rows > p.perm_cap) return;   // flagged by the fill
+  if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
   const u64 n = *p.rows_prev;
   for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
     const u32 s = p.pslot[i];

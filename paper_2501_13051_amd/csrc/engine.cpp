@@ -1740,12 +1740,30 @@ void Engine::size_from_predictions(bool initial) {
   for (auto& p : initial ? init_plans_ : delta_plans_) {
     const Relation& S = rels_[p.src_rel];
     if (!initial && S.n_delta == 0) continue;
-    for (auto& st : p.steps) {
+    double probe = 0;   // rows entering the current step (estimated past the first)
+    for (size_t k = 0; k < p.steps.size(); ++k) {
+      const Step& st = p.steps[k];
       u64 want;
-      if (st.select_only) want = initial ? S.n_full : S.n_delta;
-      // presize to 1.25x the prediction, within [1024, 2^27] rows: a join larger
-      // than that is served by the overflow fallback's exact count
-      else want = std::min<u64>(u64(double(ctr_host_[st.c_pred]) * 1.25) + 1024, u64(1) << 27);
+      if (k == 0)
+        probe = double(st.hll >= 0 ? ctr_host_[sketches_[st.hll].ctr_rows] : (initial ? S.n_full : S.n_delta));
+      if (st.select_only) {
+        want = initial ? S.n_full : S.n_delta;
+      } else {
+        // presize to 2x the larger of the prediction and the uniform-key
+        // estimate (probe rows x the build index's mean run), within
+        // [1024, 2^27] rows: a short buffer costs a re-run of the round, a
+        // long one only memory; a join larger than that is served by the
+        // overflow fallback's exact count
+        double uniform = probe;
+        if (st.index != kNoIndex) {
+          const Index& ix = indices_[st.index];
+          const double keys = double(std::max<u64>(ctr_host_[ix.c_ndv], 1));
+          uniform = probe * std::max(1.0, double(ctr_host_[ix.c_rows]) / keys);
+        }
+        const double est = std::max(double(ctr_host_[st.c_pred]), uniform);
+        want = u64(std::min(2.0 * est + 1024.0, double(u64(1) << 27)));
+        probe = est;
+      }
       if (st.out_buf >= 0) {
         Inter& I = inters_[st.out_buf];
         if (I.cap < want) I.cap = pow2_at_least(want);

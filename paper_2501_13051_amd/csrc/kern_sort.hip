@@ -5,7 +5,7 @@
 // widths taken from the value domain, so a sort touches only the bits that
 // can be set.  One histogram pass counts the digits of every pass at once;
 // each pass is then a single read and write of the keys ("onesweep"): a tile
-// of 4096 keys (2048 with 11-bit digits or in the fused pass) is ranked stably
+// of 2048 keys (4096 in plain 8-bit passes over large buffers) is ranked stably
 // in LDS (wave64 match masks built from one ballot per digit bit, per-wave
 // digit counters), the tile's per-digit counts
 // are chained across tiles with a decoupled look-back, and the keys are staged
@@ -62,7 +62,7 @@ struct FuseArgs {
   u64* ts;             // trace timing slot (nullable)
 };
 
-template <int kBits, bool kFuse>
+template <int kBits, bool kFuse, int kItems>
 __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, u64* __restrict__ out,
                                                    const u64* n_ctr, u64 n_const, u64 cap, u32 shift,
                                                    const u32* hist_p, u64* status, u32* ticket,
@@ -70,10 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
                                                    FuseArgs fz) {
   constexpr int kRadix = 1 << kBits;
   constexpr int kWaves = kBlock / kWave;
-  // keys per thread: 16 for a plain pass with 8-bit digits, else 8 (11-bit
-  // digit counters take 8x the LDS; the fused pass, which also probes the
-  // tuple set, keeps more tiles in flight)
-  constexpr int kItems = (kBits <= 8 && !kFuse) ? 16 : 8;
+  // kItems keys per thread (see launch_rs_pass for the choice)
   constexpr u32 kTile = kBlock * kItems;
   constexpr int kDpt = kRadix > kBlock ? kRadix / kBlock : 1;   // digits owned per thread
   __shared__ u64 s_keys[kTile];
@@ -328,13 +325,22 @@ int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 
   const u32 sh = pass * db;
   const u32* h = p.hist + (u64(pass) << db);
   hipStream_t s = (hipStream_t)stream;
-#define FV_PASS(B, F)                                                                                     \
-  hipLaunchKernelGGL((k_rs_pass<B, F>), dim3(pgrid), dim3(kBlock), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, sh, h, \
-                     p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
+  // Keys per thread: 16 (4096-key tiles, half the per-tile look-back and
+  // scan work) for a plain 8-bit pass over a buffer of at least 2^22 keys;
+  // 8 otherwise, where more, smaller tiles keep the chip busy (small sorts),
+  // 11-bit digit counters need the LDS, or the fused pass probes the set.
+  const bool wide = db == 8 && !fuse && p.cap >= (u64(1) << 22);
+#define FV_PASS(B, F, I)                                                                                     \
+  hipLaunchKernelGGL((k_rs_pass<B, F, I>), dim3(pgrid), dim3(kBlock), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, sh, \
+                     h, p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
   if (db == 11) {
-    if (fuse) FV_PASS(11, true); else FV_PASS(11, false);
+    if (fuse) FV_PASS(11, true, 8); else FV_PASS(11, false, 8);
+  } else if (fuse) {
+    FV_PASS(8, true, 8);
+  } else if (wide) {
+    FV_PASS(8, false, 16);
   } else {
-    if (fuse) FV_PASS(8, true); else FV_PASS(8, false);
+    FV_PASS(8, false, 8);
   }
 #undef FV_PASS
   return int(hipGetLastError());

@@ -83,6 +83,9 @@ typedef struct {
   uint32_t max_blocks;     /* grid cap of the look-back kernels, 256..8192 (0: 2048) */
   uint32_t index_rebuild;  /* 1: rebuild the join indices of derived relations from scratch every
                               round; 0: update them with the appended rows (default) */
+  uint32_t index_sort;     /* join-index construction: 0 (default) radix sort of the rows by key
+                              slot for builds of at least 2^20 rows, counting by hash below;
+                              1 counting for every build; 2 sorting for every build */
 } fv_tuning;
 
 typedef struct {
@@ -204,7 +207,7 @@ typedef fv_ctx* (*fv_make_ctx_fn)(const fv_options* opt, void* user);
 /* Autotuner.  Coordinate search over fv_tuning: starting from the defaults,
  * each knob in turn (radix_bits {8,11}, fuse_dedup {0,1}, set_load
  * {0.25,0.5}, index_load {0.25,0.5}, max_blocks {1024,2048,4096}, index_rebuild
- * {0,1}) is set to
+ * {0,1}, index_sort {0,1}) is set to
  * every candidate with the others at their best so far; a candidate is scored
  * by the median fv_run_fixpoint time of `reps` fresh contexts from make()
  * (reps 0 means 3).  The winner goes to *best and, if cache_path and key are

@@ -117,7 +117,8 @@ std::string render_cache(const std::map<std::string, Entry>& entries) {
 Entry to_entry(const fv_tuning& t, double ms) {
   return Entry{{"radix_bits", double(t.radix_bits)}, {"fuse_dedup", double(t.fuse_dedup)},
                {"set_load", double(t.set_load)},     {"index_load", double(t.index_load)},
-               {"max_blocks", double(t.max_blocks)}, {"index_rebuild", double(t.index_rebuild)}, {"ms", ms}};
+               {"max_blocks", double(t.max_blocks)}, {"index_rebuild", double(t.index_rebuild)},
+               {"index_sort", double(t.index_sort)},   {"ms", ms}};
 }
 
 fv_tuning from_entry(const Entry& e) {
@@ -129,6 +130,7 @@ fv_tuning from_entry(const Entry& e) {
   t.index_load = float(get("index_load", 0.5));
   t.max_blocks = uint32_t(get("max_blocks", 2048));
   t.index_rebuild = uint32_t(get("index_rebuild", 0));
+  t.index_sort = uint32_t(get("index_sort", 0));
   return t;
 }
 
@@ -189,9 +191,11 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
   if (cur_ms < 0) return FV_EINVAL;
   // coordinate search: each knob in turn, the others at their best so far
   const std::vector<double> radix = {8, 11}, fuse = {0, 1}, sload = {0.25, 0.5}, iload = {0.25, 0.5},
-                            blocks = {1024, 2048, 4096}, rebuild = {0, 1};
+                            blocks = {1024, 2048, 4096}, rebuild = {0, 1},
+                            isort = {0, 1};
   struct Knob { const std::vector<double>* vals; int which; };
-  const Knob knobs[] = {{&radix, 0}, {&fuse, 1}, {&sload, 2}, {&iload, 3}, {&blocks, 4}, {&rebuild, 5}};
+  const Knob knobs[] = {{&radix, 0}, {&fuse, 1}, {&sload, 2}, {&iload, 3}, {&blocks, 4}, {&rebuild, 5},
+                        {&isort, 6}};
   for (const Knob& k : knobs) {
     for (double v : *k.vals) {
       fv_tuning t = cur;
@@ -201,7 +205,8 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
         case 2: t.set_load = float(v); break;
         case 3: t.index_load = float(v); break;
         case 4: t.max_blocks = uint32_t(v); break;
-        default: t.index_rebuild = uint32_t(v); break;
+        case 5: t.index_rebuild = uint32_t(v); break;
+        default: t.index_sort = uint32_t(v); break;
       }
       if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
       const double ms = trial(make, user, base, t, reps);

@@ -49,6 +49,7 @@ Engine::Engine(const fv_options* opt) {
   if (!(tune_.index_load >= 0.1f && tune_.index_load <= 0.75f)) tune_.index_load = 0.5f;
   if (tune_.max_blocks < 256 || tune_.max_blocks > 8192) tune_.max_blocks = 2048;
   tune_.index_rebuild = tune_.index_rebuild ? 1 : 0;
+  if (tune_.index_sort > 2) tune_.index_sort = 0;
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
   trace_ = (opt_.flags & FV_TRACE) != 0;
@@ -89,6 +90,7 @@ Engine::~Engine() {
   release(stamps_dev_);
   release(m_row_); release(m_start_); release(m_off_);
   release(st_a_); release(st_b_); release(st_sort_);
+  release(ixk_a_); release(ixk_b_);
   for (auto& sk : sketches_) release(sk.regs);
   release(predictor_dev_); release(pspec_init_dev_); release(pspec_delta_dev_);
   if (ctr_host_) (void)hipHostFree(ctr_host_);
@@ -629,7 +631,7 @@ bool Engine::ensure_capacity() {
   // look-back status arrays and row-id scratch are sized for the largest
   // launch any round can make before capacities change again: a delta is at
   // most the previous round's new tuples, so new_cap bounds it
-  u64 max_probe = 1, max_rows = 1;
+  u64 max_probe = 1, max_rows = 1, sort_rows = 0;
   auto plan_probe = [&](const Plan& p, bool initial) {
     const Relation& S = rels_[p.src_rel];
     const u64 n0 = initial ? S.n_full : std::max<u64>(S.n_delta, S.new_cap);
@@ -755,7 +757,29 @@ bool Engine::ensure_capacity() {
       if (!keep) ix.dirty = true;
     }
     max_rows = std::max(max_rows, ix.cap);
+    // Construction: a large build sorts (row, slot) words by slot (no
+    // per-row atomics; see build_index), a small one counts by hashing.
+    // The slot bits (plus one for rows outside a filter) are sorted with
+    // 8-bit digits, and the row id sits above the last digit.
+    ix.sort_shift = 0;
+    if (tune_.index_sort == 2 || (tune_.index_sort == 0 && rows >= (u64(1) << 20))) {
+      const u32 slot_bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);   // cap is a power of two
+      const u32 shift = sort_passes(slot_bits, 8) * 8;
+      const u32 row_bits = bits_for(R.cap - 1);
+      if (shift + row_bits <= 64) {
+        ix.sort_shift = shift;
+        ix.sort_bits = slot_bits;
+        sort_rows = std::max(sort_rows, R.cap);
+      }
+    }
   }
+  if (ixk_cap_ < sort_rows) {
+    release(ixk_a_); release(ixk_b_);
+    ixk_a_ = alloc(sort_rows * 8);
+    ixk_b_ = alloc(sort_rows * 8);
+    ixk_cap_ = sort_rows;
+  }
+  max_rows = std::max(max_rows, sort_rows);
   for (auto& I : inters_) {
     if (I.cap == 0) I.cap = 1 << 16;
     for (u32 c = 0; c < I.ncols; ++c)
@@ -1223,7 +1247,33 @@ void Engine::build_index(Index& ix) {
   p.rows = ix.c_rows >= 0 ? ctr(ix.c_rows) : nullptr;
   const int kc = kclass("index_build");
   ev_begin(kc);
-  launched(launch_index_build(p, std::max<u64>(R.cap, 1), stream_), "index launch");
+  if (ix.sort_shift) {
+    // sorted build: (row, slot) words, a radix sort over the slot bits, runs
+    launched(launch_index_slotkeys(p, R.cap, ixk_a_.as<u64>(), ix.sort_shift, stream_), "index keys launch");
+    SortParams sp{};
+    sp.a = ixk_a_.as<u64>();
+    sp.b = ixk_b_.as<u64>();
+    sp.n_ctr = p.src.end_ctr;
+    sp.cap = R.cap;
+    sp.bits = ix.sort_bits;
+    sp.digit_bits = 8;
+    sp.max_blocks = tune_.max_blocks;
+    sp.hist = hist_dev_.as<u32>() + rels_.size() * kHistWords;
+    sp.status = st_sort_.as<u64>();
+    sp.ticket = ticket_dev_.as<u32>();
+    sp.epoch_base = epoch_base();
+    sp.abort = flags_dev_.as<u32>();
+    launched(launch_rs_hist(sp, stream_, true), "index hist launch");
+    u64* src = sp.a;
+    u64* dst = sp.b;
+    for (u32 pass = 0; pass < sort_passes(ix.sort_bits, 8); ++pass) {
+      launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_), "index sort pass launch");
+      std::swap(src, dst);
+    }
+    launched(launch_index_runs(p, R.cap, src, ix.sort_shift, stream_), "index runs launch");
+  } else {
+    launched(launch_index_build(p, std::max<u64>(R.cap, 1), stream_), "index launch");
+  }
   ev_end(kc, 0, 0);
   ix.dirty = false;
 }
@@ -1831,7 +1881,8 @@ void Engine::alloc_control() {
   ctr_dev_ = alloc(size_t(n_ctr_) * 8);
   flags_dev_ = alloc(16);
   ticket_dev_ = alloc(16);
-  hist_dev_ = alloc(std::max<size_t>(rels_.size(), 1) * kHistWords * 4);
+  // one histogram region per relation, and one for sorted index builds
+  hist_dev_ = alloc((rels_.size() + 1) * kHistWords * 4);
   hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
   hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
   hip(hipHostMalloc(reinterpret_cast<void**>(&ctr_host_), size_t(n_ctr_) * 8, hipHostMallocDefault), "pinned alloc");

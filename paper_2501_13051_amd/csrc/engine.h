@@ -92,6 +92,8 @@ struct Index {
   u64 cap = 0, perm_cap = 0;
   bool dirty = true;          // storage (re)allocated since the last build
   bool pending_swap = false;  // an update into perm2/pslot2 was enqueued this round
+  u32 sort_shift = 0;         // nonzero: built by sorting (row << sort_shift | slot) words
+  u32 sort_bits = 0;          //   over this many slot bits
 };
 
 // One join (or, with index == kNoIndex and brel == kNone, one selection):
@@ -265,6 +267,8 @@ class Engine {
   Buf m_row_, m_start_, m_off_;
   u64 m_cap_ = 0;
   Buf st_a_, st_b_, st_sort_;
+  Buf ixk_a_, ixk_b_;     // sorted index builds: (row, slot) words and the sort's second buffer
+  u64 ixk_cap_ = 0;
   u64 st_cap_ = 0, st_sort_tiles_ = 0;
   u32 epoch_off_ = 1;     // next look-back offset within the current phase
   u64 phases_ = 0;        // epoch-base advances since the status arrays were cleared

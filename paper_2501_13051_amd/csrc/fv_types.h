@@ -270,6 +270,14 @@ struct IndexParams {
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
 int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, void* stream);
+// Sorted build, in three steps on one stream: launch_index_slotkeys clears
+// the table and writes keys[r] = r << row_shift | slot for rows r < n of the
+// source (slot = cap for rows outside the filter); the caller radix-sorts
+// keys over bits [0, row_shift) (row_shift a multiple of the digit width);
+// launch_index_runs turns the sorted words into perm, pslot, counts and
+// starts.  keys holds rows_cap words.
+int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, void* stream);
+int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32 row_shift, void* stream);
 
 int launch_fill_u64(u64* p, u64 n, u64 value, void* stream);
 int launch_fill_u32(u32* p, u64 n, u32 value, void* stream);

@@ -128,11 +128,12 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
 }
 
 // Exclusive scan over the table in slot order (look-back across tiles).
-// Build: start <- prefix of counts, count <- 0 (it becomes the fill cursor).
+// Build: start <- prefix of counts, count <- 0 (it becomes the fill cursor),
+// or count kept (kKeep: the sorted build has already placed the rows).
 // Update (kInc): dsh <- prefix of the appended counts, start += dsh, dcnt <- 0;
 // count keeps the old rows, so the fill appends after them.  Both recompute
 // the distinct keys, longest run and rows of the result.
-template <bool kInc>
+template <bool kInc, bool kKeep = false>
 __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kBlock / kWave + 1];
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
           p.table[s0 + k].start += u32(run);
         } else {
           p.table[s0 + k].start = u32(run);
-          p.table[s0 + k].count = 0u;
+          if (!kKeep) p.table[s0 + k].count = 0u;
         }
       }
       run += c[k];
@@ -281,6 +282,82 @@ __global__ __launch_bounds__(kBlock) void k_idx_move(IndexParams p) {
   }
 }
 
+// ------------------------------------------------------------------ sorted build
+// The construction of Section 3 sorts the key column and run-length encodes
+// it.  Here every indexed row finds (or inserts) its key's slot with a plain
+// probe -- no per-row counter, so a hot key costs nothing extra -- and the
+// word (row << row_shift | slot) goes through a stable LSD radix sort over
+// the slot bits (launch_rs_hist / launch_rs_pass, run by the caller).  The
+// sorted words list the rows grouped by slot, runs in slot order and row ids
+// ascending inside a run: the layout the counting build produces, so the
+// incremental update applies to it unchanged.  A run's count comes from its
+// two boundaries (one atomic each, order-free modulo 2^32), and the table
+// scan turns counts into starts.  Rows outside the index's filter take the
+// slot value `cap`, which sorts after every real slot, and are dropped.
+
+// Find-or-insert with a plain first read: slots only go from empty to a key
+// during a build, so a stale read can only show "empty", which the CAS then
+// corrects (the same argument as for the tuple set).
+__device__ __forceinline__ u64 index_insert_probe(Slot* tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  for (u32 i = 0; i < kMaxProbe && i <= mask; ++i) {
+    const u64 cur = tab[h].key;
+    if (cur == key) return h;
+    if (cur == kEmptyKey) {
+      const u64 prev = atomic_cas_u64(&tab[h].key, kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) return h;
+    }
+    h = (h + 1) & mask;
+  }
+  return kNoSlot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_idx_slotkeys(IndexParams p, u64* keys, u32 row_shift) {
+  if (p.abort && *p.abort) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 mask = p.cap - 1;
+  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
+    u64 slot = p.cap;
+    if (row_indexed(p, begin + r)) {
+      // once the table has overflowed the index is rebuilt larger: later
+      // rows skip the long probe sequences of a full table
+      const bool full = p.full && (__hip_atomic_load(p.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1);
+      slot = full ? kNoSlot : index_insert_probe(p.table, mask, row_key(p, begin + r));
+      if (slot == kNoSlot) {
+        if (p.full && !full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
+        slot = 0;
+      }
+    }
+    keys[r] = (r << row_shift) | slot;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_idx_runs(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  if (p.abort && *p.abort) return;
+  if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  bool over = false;
+  for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
+    const u64 k = keys[i];
+    const u64 s = k & smask;
+    if (s >= p.cap) continue;   // outside the filter (sorted last)
+    if (i < p.perm_cap) {
+      p.perm[i] = u32(begin + (k >> row_shift));
+      p.pslot[i] = u32(s);
+    } else {
+      over = true;
+    }
+    const bool head = i == 0 || (keys[i - 1] & smask) != s;
+    const bool tail = i + 1 == n || (keys[i + 1] & smask) != s;
+    if (head || tail) atomicAdd(&p.table[s].count, (tail ? u32(i + 1) : 0u) - (head ? u32(i) : 0u));
+  }
+  // the runs would not fit: flag it (the host regrows the positions)
+  if (over && p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+}
+
 static int grid_rows(u64 n, int cap) {
   const u64 b = (n + kBlock - 1) / kBlock;
   return int(b == 0 ? 1 : (b > u64(cap) ? u64(cap) : b));
@@ -296,6 +373,22 @@ int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
   const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_idx_scan<false>, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
   hipLaunchKernelGGL(k_idx_fill<false>, dim3(row_grid), dim3(kBlock), 0, s, p);
+  return int(hipGetLastError());
+}
+
+int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv,
+                     p.maxrun, p.full, p.rows);
+  hipLaunchKernelGGL(k_idx_slotkeys, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, keys, row_shift);
+  return int(hipGetLastError());
+}
+
+int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32 row_shift, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_idx_runs, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, sorted, row_shift);
+  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL((k_idx_scan<false, true>), dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
   return int(hipGetLastError());
 }
 

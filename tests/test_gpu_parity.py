@@ -28,6 +28,8 @@ TUNINGS = {
     "radix11_fused_tight": {"radix_bits": 11, "fuse_dedup": 1, "set_load": 0.75, "index_load": 0.75,
                             "max_blocks": 256},
     "index_rebuild": {"index_rebuild": 1},
+    "index_sort": {"index_sort": 2},     # every join index built by sorting
+    "index_count": {"index_sort": 1},    # every join index built by counting
 }
 
 
@@ -115,10 +117,21 @@ def test_autotune_picks_a_stored_tuning_with_the_same_fixpoint(tmp_path):
     _check(W.SG_PROGRAM, edb, relations=["sg"], tuning=best)
 
 
+@pytest.mark.parametrize("tuning", ["default", "index_sort"])
 @pytest.mark.parametrize("zipf_s", [0.0, 1.0])
-def test_join_case_small(zipf_s):
+def test_join_case_small(zipf_s, tuning):
     w = W.join_case(1 << 14, 1 << 10, zipf_s)
-    _check(w.program, w.edb, relations=["out"])
+    _check(w.program, w.edb, relations=["out"], tuning=TUNINGS[tuning])
+
+
+@pytest.mark.parametrize("tuning", ["default", "index_count"])
+@pytest.mark.parametrize("zipf_s", [0.0, 1.5])
+def test_join_case_past_the_sorted_build_size(zipf_s, tuning):
+    # 2^21 probe rows: the default knobs build a's index by sorting (a build
+    # of at least 2^20 rows), index_count by hashing; same join either way
+    w = W.join_case(1 << 21, 1 << 16, zipf_s, seed=1010)
+    got, stats, ref = _check(w.program, w.edb, relations=["out"], tuning=TUNINGS[tuning])
+    assert stats["derived_tuples"] == 1 << 21
 
 
 def test_empty_and_duplicate_inputs():
@@ -188,7 +201,7 @@ def test_pointsto_small():
     _check(w.program, w.edb, relations=list(w.idb))
 
 
-@pytest.mark.parametrize("tuning", ["index_rebuild", "default"])
+@pytest.mark.parametrize("tuning", ["index_rebuild", "default", "index_sort"])
 def test_pointsto_full_size(tuning):
     w = W.config_pointsto()
     got, stats, ref = _check(w.program, w.edb, relations=list(w.idb), tuning=TUNINGS[tuning])
@@ -200,10 +213,10 @@ def test_rdfs_small():
     _check(W.RDFS_PROGRAM, {"t": d["t"]}, relations=["t"])
 
 
-def _batch_engines(instances):
+def _batch_engines(instances, tuning=None):
     engines = []
     for w in instances:
-        e = fv.Engine()
+        e = fv.Engine(tuning=tuning)
         for name, cols in w.edb.items():
             e.relation(name, len(cols))
         e.relation("path", 2)
@@ -214,10 +227,10 @@ def _batch_engines(instances):
     return engines
 
 
-@pytest.mark.parametrize("n_inst", [1, 7, 64])
-def test_batched_tc_matches_per_instance_oracle(n_inst):
+@pytest.mark.parametrize("n_inst,tuning", [(1, "default"), (7, "default"), (64, "default"), (7, "index_sort")])
+def test_batched_tc_matches_per_instance_oracle(n_inst, tuning):
     insts = W.batched_tc_instances(n_instances=n_inst, seed=77 + n_inst)
-    engines = _batch_engines(insts)
+    engines = _batch_engines(insts, TUNINGS[tuning])
     stats = fv.run_batch(engines)
     total = 0
     per_round = []

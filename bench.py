@@ -174,7 +174,8 @@ def main():
     for _ in range(3):
         _, prof, _ = sg.run_once(flags=fv.FV_TRACE, tuning=tuning)
         for k in prof:
-            per_class[k["name"]] = per_class.get(k["name"], 0.0) + k["ms"]
+            if not k["name"].startswith("host_"):   # host phases of a round are not kernels
+                per_class[k["name"]] = per_class.get(k["name"], 0.0) + k["ms"]
     dom_name = max(per_class, key=per_class.get)
 
     for _ in range(args.warmup):
@@ -348,7 +349,7 @@ def join_sweep(fv, W, torch, np):
         st, prof, _ = r.run_once(flags=fv.FV_TRACE)
         kernels = {}
         for k in prof:
-            if not k["launches"] or k["ms"] <= 0:
+            if not k["launches"] or k["ms"] <= 0 or k["name"].startswith("host_"):
                 continue
             gbs = k["algo_bytes"] / (k["ms"] * 1e-3) / 1e9
             kernels[k["name"]] = {"ms": round(k["ms"], 3), "launches": k["launches"], "GB_s": round(gbs, 1),

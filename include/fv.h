@@ -86,6 +86,9 @@ typedef struct {
   uint32_t index_sort;     /* join-index construction: 0 (default) radix sort of the rows by key
                               slot for builds of at least 2^20 rows, counting by hash below;
                               1 counting for every build; 2 sorting for every build */
+  uint32_t lookahead;      /* 0 (default): enqueue each plain eager round before the previous
+                              round's counters are read back, where the program allows it
+                              (no join reads an index of a derived relation); 1: never */
 } fv_tuning;
 
 typedef struct {
@@ -131,11 +134,17 @@ typedef struct {
   double qerror_max;
 } fv_stats;
 
-/* One kernel class in the profile returned by fv_profile (FV_TRACE only). */
+/* One kernel class in the profile returned by fv_profile (FV_TRACE only).
+ * Classes named host_* are not kernels but host phases of each round, timed
+ * on the host clock (launches = rounds): host_prepare (sizing, buffer growth,
+ * index rebuilds before the round's kernels are enqueued), host_enqueue,
+ * host_wait (counter read-back and stream sync) and host_finish; host_alloc
+ * counts the device allocations (launches) and the time spent in them.  They
+ * are not recorded when trace_only is set. */
 typedef struct {
   char name[32];
   uint64_t launches;
-  double ms;                   /* sum of HIP-event durations on the context's stream */
+  double ms;                   /* sum of kernel durations (device clock or HIP events) */
   double algo_bytes;           /* algorithmic HBM bytes these launches had to move */
   uint64_t items;              /* elements processed (rows, keys or output tuples) */
 } fv_kprof;
@@ -207,7 +216,7 @@ typedef fv_ctx* (*fv_make_ctx_fn)(const fv_options* opt, void* user);
 /* Autotuner.  Coordinate search over fv_tuning: starting from the defaults,
  * each knob in turn (radix_bits {8,11}, fuse_dedup {0,1}, set_load
  * {0.25,0.5}, index_load {0.25,0.5}, max_blocks {1024,2048,4096}, index_rebuild
- * {0,1}, index_sort {0,1}) is set to
+ * {0,1}, index_sort {0,1}, lookahead {0,1}) is set to
  * every candidate with the others at their best so far; a candidate is scored
  * by the median fv_run_fixpoint time of `reps` fresh contexts from make()
  * (reps 0 means 3).  The winner goes to *best and, if cache_path and key are

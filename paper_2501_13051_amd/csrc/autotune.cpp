@@ -118,7 +118,8 @@ Entry to_entry(const fv_tuning& t, double ms) {
   return Entry{{"radix_bits", double(t.radix_bits)}, {"fuse_dedup", double(t.fuse_dedup)},
                {"set_load", double(t.set_load)},     {"index_load", double(t.index_load)},
                {"max_blocks", double(t.max_blocks)}, {"index_rebuild", double(t.index_rebuild)},
-               {"index_sort", double(t.index_sort)},   {"ms", ms}};
+               {"index_sort", double(t.index_sort)},   {"lookahead", double(t.lookahead)},
+               {"ms", ms}};
 }
 
 fv_tuning from_entry(const Entry& e) {
@@ -131,6 +132,7 @@ fv_tuning from_entry(const Entry& e) {
   t.max_blocks = uint32_t(get("max_blocks", 2048));
   t.index_rebuild = uint32_t(get("index_rebuild", 0));
   t.index_sort = uint32_t(get("index_sort", 0));
+  t.lookahead = uint32_t(get("lookahead", 0));
   return t;
 }
 
@@ -192,10 +194,10 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
   // coordinate search: each knob in turn, the others at their best so far
   const std::vector<double> radix = {8, 11}, fuse = {0, 1}, sload = {0.25, 0.5}, iload = {0.25, 0.5},
                             blocks = {1024, 2048, 4096}, rebuild = {0, 1},
-                            isort = {0, 1};
+                            isort = {0, 1}, ahead = {0, 1};
   struct Knob { const std::vector<double>* vals; int which; };
   const Knob knobs[] = {{&radix, 0}, {&fuse, 1}, {&sload, 2}, {&iload, 3}, {&blocks, 4}, {&rebuild, 5},
-                        {&isort, 6}};
+                        {&isort, 6}, {&ahead, 7}};
   for (const Knob& k : knobs) {
     for (double v : *k.vals) {
       fv_tuning t = cur;
@@ -206,7 +208,8 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
         case 3: t.index_load = float(v); break;
         case 4: t.max_blocks = uint32_t(v); break;
         case 5: t.index_rebuild = uint32_t(v); break;
-        default: t.index_sort = uint32_t(v); break;
+        case 6: t.index_sort = uint32_t(v); break;
+        default: t.lookahead = uint32_t(v); break;
       }
       if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
       const double ms = trial(make, user, base, t, reps);

@@ -50,6 +50,7 @@ Engine::Engine(const fv_options* opt) {
   if (tune_.max_blocks < 256 || tune_.max_blocks > 8192) tune_.max_blocks = 2048;
   tune_.index_rebuild = tune_.index_rebuild ? 1 : 0;
   if (tune_.index_sort > 2) tune_.index_sort = 0;
+  tune_.lookahead = tune_.lookahead ? 1 : 0;
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
   trace_ = (opt_.flags & FV_TRACE) != 0;
@@ -86,15 +87,18 @@ Engine::~Engine() {
     release(ix.dcnt); release(ix.dsh);
   }
   for (auto& I : inters_) for (auto& b : I.col) release(b);
-  release(ctr_dev_); release(flags_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
+  flags_dev_ = Buf{};   // a view into ctr_dev_
+  release(ctr_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
   release(stamps_dev_);
   release(m_row_); release(m_start_); release(m_off_);
   release(st_a_); release(st_b_); release(st_sort_);
   release(ixk_a_); release(ixk_b_);
   for (auto& sk : sketches_) release(sk.regs);
   release(predictor_dev_); release(pspec_init_dev_); release(pspec_delta_dev_);
-  if (ctr_host_) (void)hipHostFree(ctr_host_);
-  if (flags_host_) (void)hipHostFree(flags_host_);
+  for (int i = 0; i < 2; ++i) {   // ctr_host_ and flags_host_ point into these
+    if (rb_host_[i]) (void)hipHostFree(rb_host_[i]);
+    if (rb_ev_[i]) (void)hipEventDestroy(rb_ev_[i]);
+  }
   for (auto e : ev_pool_) (void)hipEventDestroy(e);
   for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
 }
@@ -106,12 +110,14 @@ Buf Engine::alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
   bytes = (bytes + 255) & ~size_t(255);
   void* p = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
   if (opt_.dev_alloc) {
     p = opt_.dev_alloc(bytes, opt_.stream, opt_.user);
   } else if (hipMalloc(&p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     p = nullptr;
   }
+  host_time("host_alloc", t0);
   if (!p) {
     terminal = true;
     throw Error(FV_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
@@ -626,7 +632,7 @@ void Engine::plan_all() {
 }
 
 // ------------------------------------------------------------------ capacity
-bool Engine::ensure_capacity() {
+bool Engine::ensure_capacity(bool dry) {
   const u64 allocs_before = n_allocs_;
   // look-back status arrays and row-id scratch are sized for the largest
   // launch any round can make before capacities change again: a delta is at
@@ -642,11 +648,32 @@ bool Engine::ensure_capacity() {
   };
   for (auto& p : init_plans_) plan_probe(p, true);
   for (auto& p : delta_plans_) plan_probe(p, false);
+  // with look-ahead a relation may take two rounds of new tuples before the
+  // host sees the first
+  const u64 ahead_rounds = can_look_ahead() ? 2 : 1;
+  // growth of the last round over the one before (>= 1; 2 without history)
+  auto growth = [](u64 last, u64 prev) { return prev ? std::max(1.0, double(last) / double(prev)) : 2.0; };
+  if (dry) {
+    // a look-ahead round is sized before the round ahead of it is known:
+    // take it only while every buffer has room for two more rounds of the
+    // last round-over-round growth (and a quarter more), so that it rarely
+    // overflows and runs again
+    auto short_for = [&](u64 last, u64 prev, u64 cap) {
+      const double g = growth(last, prev);
+      return 1.25 * double(last) * g * g > double(cap);
+    };
+    if (deltas_.size() < 3) return true;   // no growth history yet
+    for (auto& R : rels_)
+      if (R.used_as_head && short_for(R.last_new, R.prev_new, R.new_cap)) return true;
+    for (auto& I : inters_)
+      if (short_for(I.last_used, I.prev_used, I.cap)) return true;
+  }
   for (auto& R : rels_) {
     max_rows = std::max(max_rows, R.new_cap);
     if (!R.used_as_head) continue;
-    const u64 need_full = R.n_full + R.new_cap;
+    const u64 need_full = R.n_full + ahead_rounds * R.new_cap;
     if (R.cap < need_full) {
+      if (dry) return true;
       const u64 nc = std::max<u64>(need_full, R.cap + R.cap / 2);
       for (u32 c = 0; c < R.arity; ++c) grow(R.col[c], nc * 4, R.n_full * 4);
       R.cap = nc;
@@ -657,9 +684,17 @@ bool Engine::ensure_capacity() {
     // happens a logarithmic number of times.
     // expected size after this round: full plus the new-tuple volume the
     // buffers were sized for (new_cap anticipates 4x the last round)
-    const u64 expect = R.n_full + std::max<u64>({3 * R.n_delta, R.new_cap / 4, R.staged, 1024});
+    // (new_cap anticipates 4x the last round, 8x with look-ahead)
+    // (new_cap anticipates 4x the last round; with look-ahead the set must
+    // also take two more rounds at the last growth rate)
+    u64 expect = R.n_full + std::max<u64>({3 * R.n_delta, R.new_cap / 4, R.staged, 1024});
+    if (ahead_rounds == 2) {
+      const double g = growth(R.last_new, R.prev_new);
+      expect = std::max<u64>(expect, R.n_full + u64(1.25 * double(R.last_new) * (g + g * g)));
+    }
     const u64 need_set = pow2_at_least(std::max<u64>(R.set_min, u64(double(expect) / tune_.set_load)));
     if (R.set_cap < R.set_min || R.set_cap < expect * 3 / 2 || R.set_stale) {
+      if (dry) return true;
       R.set_stale = false;
       release(R.set);
       R.set = alloc(need_set * 8);
@@ -670,6 +705,7 @@ bool Engine::ensure_capacity() {
                "set rebuild");
     }
     if (R.newk.bytes < R.new_cap * 8) {
+      if (dry) return true;
       release(R.newk);
       release(R.newk2);
       R.newk = alloc(R.new_cap * 8);
@@ -703,6 +739,7 @@ bool Engine::ensure_capacity() {
     if (ix.grow) need = std::max<u64>(need, 4 * ix.cap);
     const bool oversized = (ix.keys_seen || ix.hinted) && ix.cap > 8 * need;
     if (ix.cap == 0 || ix.grow || double(keys) > 0.75 * double(ix.cap) || oversized) {
+      if (dry) return true;
       release(ix.table);
       release(ix.dcnt);
       release(ix.dsh);
@@ -735,8 +772,9 @@ bool Engine::ensure_capacity() {
       want = std::max<u64>(want, 2 * ix.perm_cap);
       realloc_perm = true;
     }
-    ix.perm_grow = false;
-    if (ix.perm_cap == 0 || realloc_perm) {
+    if (dry && (ix.perm_cap == 0 || realloc_perm)) return true;
+    if (!dry) ix.perm_grow = false;
+    if (!dry && (ix.perm_cap == 0 || realloc_perm)) {
       // an intact index keeps its layout: the positions it holds move to the
       // new arrays (a streaming copy) instead of a rebuild
       const bool keep = !ix.dirty && ix.rows_seen && want >= ix.rows_seen && ix.perm.p && ix.pslot.p;
@@ -761,19 +799,24 @@ bool Engine::ensure_capacity() {
     // per-row atomics; see build_index), a small one counts by hashing.
     // The slot bits (plus one for rows outside a filter) are sorted with
     // 8-bit digits, and the row id sits above the last digit.
-    ix.sort_shift = 0;
+    u32 sort_shift = 0, sort_bits = 0;
     if (tune_.index_sort == 2 || (tune_.index_sort == 0 && rows >= (u64(1) << 20))) {
       const u32 slot_bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);   // cap is a power of two
       const u32 shift = sort_passes(slot_bits, 8) * 8;
       const u32 row_bits = bits_for(R.cap - 1);
       if (shift + row_bits <= 64) {
-        ix.sort_shift = shift;
-        ix.sort_bits = slot_bits;
+        sort_shift = shift;
+        sort_bits = slot_bits;
         sort_rows = std::max(sort_rows, R.cap);
       }
     }
+    if (!dry) {
+      ix.sort_shift = sort_shift;
+      ix.sort_bits = sort_bits;
+    }
   }
   if (ixk_cap_ < sort_rows) {
+    if (dry) return true;
     release(ixk_a_); release(ixk_b_);
     ixk_a_ = alloc(sort_rows * 8);
     ixk_b_ = alloc(sort_rows * 8);
@@ -781,11 +824,19 @@ bool Engine::ensure_capacity() {
   }
   max_rows = std::max(max_rows, sort_rows);
   for (auto& I : inters_) {
-    if (I.cap == 0) I.cap = 1 << 16;
+    if (I.cap == 0) {
+      if (dry) return true;
+      I.cap = 1 << 16;
+    }
     for (u32 c = 0; c < I.ncols; ++c)
-      if (I.col[c].bytes < I.cap * 4) { release(I.col[c]); I.col[c] = alloc(I.cap * 4); }
+      if (I.col[c].bytes < I.cap * 4) {
+        if (dry) return true;
+        release(I.col[c]);
+        I.col[c] = alloc(I.cap * 4);
+      }
   }
   if (m_cap_ < max_probe) {
+    if (dry) return true;
     const u64 nc = std::max<u64>(max_probe, m_cap_ * 2);
     release(m_row_); release(m_start_); release(m_off_);
     m_row_ = alloc(nc * 4);
@@ -795,6 +846,7 @@ bool Engine::ensure_capacity() {
   }
   const u64 tiles = (std::max(max_probe, max_rows) + 1023) / 1024 + 2;
   if (st_cap_ < tiles) {
+    if (dry) return true;
     const u64 nc = std::max<u64>(tiles, st_cap_ * 2);
     release(st_a_); release(st_b_);
     st_a_ = alloc(nc * 8);
@@ -805,6 +857,7 @@ bool Engine::ensure_capacity() {
   }
   const u64 stiles = (max_rows + kSortTile - 1) / kSortTile + 1;
   if (st_sort_tiles_ < stiles) {
+    if (dry) return true;
     const u64 nc = std::max<u64>(stiles, st_sort_tiles_ * 2);
     release(st_sort_);
     st_sort_ = alloc(nc * kMaxRadix * 8);
@@ -815,6 +868,13 @@ bool Engine::ensure_capacity() {
 }
 
 // ------------------------------------------------------------------ profiling
+void Engine::host_time(const char* name, std::chrono::steady_clock::time_point since) {
+  if (!trace_ || !trace_only_.empty()) return;
+  KClass& k = kprof_[kclass(name)];
+  k.launches += 1;
+  k.ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - since).count();
+}
+
 int Engine::kclass(const char* name) {
   for (size_t i = 0; i < kprof_.size(); ++i)
     if (kprof_[i].name == name) return int(i);
@@ -864,7 +924,7 @@ void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux
     e = pooled_event();
     hip(hipEventRecord(e, stream_), "event record");
   }
-  pending_.push_back(PendingEvent{cls, ev_open_, e, bytes, kind, ref0, ref1, aux, ev_stamp_});
+  pending_.push_back(PendingEvent{cls, ev_open_, e, bytes, kind, ref0, ref1, aux, ev_stamp_, emit_seq_});
   ev_open_ = nullptr;
   ev_stamp_ = -1;
 }
@@ -873,10 +933,16 @@ void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux
 // kind 1 probe: aux = probe rows (or ref0 counter), ref1 = matched counter
 // kind 2 write: ref0 = matched, ref1 = outputs; aux = bytes per output
 // kind 3 sort pass / kind 4 hist / kind 5 dedup: ref0 = rows counter, aux = cap or arity
-void Engine::collect_events() {
+void Engine::collect_events(u64 upto, bool discard) {
   if (!trace_) return;
-  std::vector<PendingEvent> all;
-  all.swap(pending_);
+  std::vector<PendingEvent> all, later;
+  for (auto& pe : pending_) (pe.seq <= upto ? all : later).push_back(pe);
+  pending_.swap(later);
+  if (discard) {   // launches of a look-ahead round that did nothing
+    for (auto& pe : all)
+      if (pe.stamp < 0) { ev_pool_.push_back(pe.a); ev_pool_.push_back(pe.b); }
+    return;
+  }
   const size_t n_eager = all.size();
   if (graph_replayed_) all.insert(all.end(), graph_events_.begin(), graph_events_.end());
   for (size_t idx = 0; idx < all.size(); ++idx) {
@@ -965,11 +1031,24 @@ void Engine::flush_stamps() {
 }
 
 // ------------------------------------------------------------------ execution
+// The end of a read-back is awaited by polling its event (the host thread has
+// nothing else to do; a blocking wait adds wake-up latency to every round).
+void Engine::wait_event(hipEvent_t e) {
+  for (;;) {
+    const hipError_t q = hipEventQuery(e);
+    if (q == hipSuccess) return;
+    if (q != hipErrorNotReady) hip(q, "round wait");
+  }
+}
+
 void Engine::read_counters() {
-  hip(hipMemcpyAsync(ctr_host_, ctr_dev_.p, size_t(n_ctr_) * 8, hipMemcpyDeviceToHost, stream_), "counter readback");
-  hip(hipMemcpyAsync(flags_host_, flags_dev_.p, 16, hipMemcpyDeviceToHost, stream_), "flag readback");
-  sync();
-  collect_events();
+  ctr_host_ = rb_host_[0];
+  flags_host_ = reinterpret_cast<u32*>(ctr_host_ + n_ctr_);
+  hip(hipMemcpyAsync(ctr_host_, ctr_dev_.p, size_t(n_ctr_) * 8 + 16, hipMemcpyDeviceToHost, stream_),
+      "counter readback");
+  hip(hipEventRecord(rb_ev_[0], stream_), "event record");
+  wait_event(rb_ev_[0]);
+  collect_events(emit_seq_, false);
   if (flags_host_[1]) {
     terminal = true;
     throw Error(FV_EINVAL, "internal: join scratch too small");
@@ -1137,6 +1216,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   sp.b = R.newk2.as<u64>();
   sp.n_ctr = ctr(c_new0_ + ri);
   sp.cap = R.new_cap;
+  sp.n_hint = R.last_new;
   sp.bits = R.bits;
   sp.digit_bits = tune_.radix_bits;
   sp.max_blocks = tune_.max_blocks;
@@ -1383,9 +1463,9 @@ void Engine::ingest() {
 // relation, and the rebuild of indices on derived relations.  `all_plans`
 // keeps plans whose delta is empty (a captured round must not depend on
 // host-side sizes).
-void Engine::emit_round(bool initial, bool all_plans) {
+void Engine::emit_round(bool initial, bool all_plans, bool sticky) {
   launched(launch_round_prologue(ctr(c_reset_begin_), u64(n_ctr_ - c_reset_begin_), flags_dev_.as<u32>(),
-                                 hist_dev_.as<u32>(), hist_dev_.bytes / 4, epoch_base(), stream_),
+                                 hist_dev_.as<u32>(), hist_dev_.bytes / 4, epoch_base(), stream_, sticky),
            "round prologue");
   epoch_off_ = 1;
   if (initial) {
@@ -1477,6 +1557,7 @@ void Engine::choose_join_algorithms(bool initial) {
 }
 
 void Engine::run_round(bool initial) {
+  auto th = std::chrono::steady_clock::now();
   start_ctr_.assign(ctr_host_, ctr_host_ + n_ctr_);
   use_fused_ = learned_;
   if (learned_) size_from_predictions(initial);
@@ -1500,6 +1581,7 @@ void Engine::run_round(bool initial) {
       verify_builds(built);
     }
     if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) begin_phase();   // clears status arrays
+    host_time("host_prepare", th);   // sizing, growth, index rebuilds: the GPU waits
     bool replayed = false;
     if (graph_exec_ && graph_fused_steps_ != fused_steps_) graph_dirty_ = true;
     if (!initial && use_graph_) {
@@ -1512,47 +1594,66 @@ void Engine::run_round(bool initial) {
         ++graph_replays_;
       }
     }
+    th = std::chrono::steady_clock::now();
     if (!replayed) emit_round(initial, false);
+    host_time("host_enqueue", th);
     ++phases_;
     graph_replayed_ = replayed;
+    th = std::chrono::steady_clock::now();
     read_counters();
+    host_time("host_wait", th);
+    th = std::chrono::steady_clock::now();
     if (!flags_host_[0] && !flags_host_[2]) break;
-    ++redo_;
-    bool any_fused = false;
-    for (bool f : fused_steps_) any_fused = any_fused || f;
-    if (any_fused && flags_host_[0]) {
-      // a presized one-pass join ran out of room: run the round again with
-      // exact count-then-write joins
-      ++overflows_;
-      use_fused_ = false;
-      choose_join_algorithms(initial);
-      graph_dirty_ = true;
-    }
-    if (flags_host_[2]) {
-      // a tuple set ran out of slots: the round committed nothing, but its
-      // difference passes may have inserted keys; rebuild every set, larger
-      for (auto& R : rels_)
-        if (R.used_as_head) { R.set_min = 2 * std::max<u64>(R.set_cap, 1); R.set_stale = true; }
-      graph_dirty_ = true;
-    }
-    // a buffer overflowed: grow whatever was short and run the round again
-    for (auto& R : rels_) {
-      if (!R.used_as_head) continue;
-      const u64 need = ctr_host_[c_new0_ + int(&R - &rels_[0])];
-      if (need > R.new_cap) R.new_cap = pow2_at_least(std::max<u64>(need + need / 4, R.new_cap * 2));
-    }
-    for (auto& I : inters_) {
-      const u64 need = ctr_host_[I.ctr];
-      if (need > I.cap) I.cap = pow2_at_least(std::max<u64>(need + need / 4, I.cap * 2));
-    }
+    grow_after_failure(initial);
   }
+  finish_round(initial, th);
+}
+
+// A round raised a flag: it committed nothing.  Grow what was short (or fall
+// back to exact joins) before the round runs again.
+void Engine::grow_after_failure(bool initial) {
+  ++redo_;
+  bool any_fused = false;
+  for (bool f : fused_steps_) any_fused = any_fused || f;
+  if (any_fused && flags_host_[0]) {
+    // a presized one-pass join ran out of room: run the round again with
+    // exact count-then-write joins
+    ++overflows_;
+    use_fused_ = false;
+    choose_join_algorithms(initial);
+    graph_dirty_ = true;
+  }
+  if (flags_host_[2]) {
+    // a tuple set ran out of slots: the round committed nothing, but its
+    // difference passes may have inserted keys; rebuild every set, larger
+    for (auto& R : rels_)
+      if (R.used_as_head) { R.set_min = 2 * std::max<u64>(R.set_cap, 1); R.set_stale = true; }
+    graph_dirty_ = true;
+  }
+  // a buffer overflowed: grow whatever was short and run the round again
+  for (auto& R : rels_) {
+    if (!R.used_as_head) continue;
+    const u64 need = ctr_host_[c_new0_ + int(&R - &rels_[0])];
+    if (need > R.new_cap) R.new_cap = pow2_at_least(std::max<u64>(need + need / 4, R.new_cap * 2));
+  }
+  for (auto& I : inters_) {
+    const u64 need = ctr_host_[I.ctr];
+    if (need > I.cap) I.cap = pow2_at_least(std::max<u64>(need + need / 4, I.cap * 2));
+  }
+}
+
+// A round that raised no flag: size the next one from it and take over its
+// counters (full, delta, derived) on the host.
+void Engine::finish_round(bool initial, std::chrono::steady_clock::time_point th) {
   if (log_joins_) log_joins(initial);
   if (!learned_) {
     // size the next round from this one: outputs tend to grow round over
     // round, and a buffer that overflows costs a whole re-run of the round
     // (4x while small, 2x past 2^24 rows, where memory rather than a re-run
     // is the scarcer resource)
-    auto ahead = [](u64 used) { return used < (u64(1) << 24) ? 4 * used : 2 * used; };
+    // (twice that with look-ahead, whose rounds are sized a round earlier)
+    const u64 f = can_look_ahead() ? 2 : 1;
+    auto ahead = [f](u64 used) { return f * (used < (u64(1) << 24) ? 4 * used : 2 * used); };
     for (auto& R : rels_) {
       if (!R.used_as_head) continue;
       const u64 want = ahead(ctr_host_[c_new0_ + int(&R - &rels_[0])]);
@@ -1562,6 +1663,15 @@ void Engine::run_round(bool initial) {
       const u64 want = ahead(ctr_host_[I.ctr]);
       if (want > I.cap) I.cap = pow2_at_least(want);
     }
+  }
+  for (auto& R : rels_)
+    if (R.used_as_head) {
+      R.prev_new = R.last_new;
+      R.last_new = ctr_host_[c_new0_ + int(&R - &rels_[0])];
+    }
+  for (auto& I : inters_) {
+    I.prev_used = I.last_used;
+    I.last_used = ctr_host_[I.ctr];
   }
   note_index_builds();
   u64 total = 0;
@@ -1575,6 +1685,97 @@ void Engine::run_round(bool initial) {
   }
   join_out_ = ctr_host_[c_joinout_];
   deltas_.push_back(total);
+  host_time("host_finish", th);
+}
+
+// Rounds with one round of look-ahead.  The next round is enqueued before
+// this one's counters are back on the host, so that the host's read-back,
+// sizing and launches overlap the GPU's work instead of separating rounds.
+// Every kernel takes its sizes from device counters and every buffer was
+// sized for two rounds ahead (the look-ahead is only taken when nothing has
+// to grow), so the early round computes what it would have computed later.
+// It runs all delta plans (an empty delta costs a launch that finds nothing),
+// and its prologue is sticky: if the round before it raises a flag, the
+// look-ahead round does nothing, and both are discarded and re-run as usual.
+// A round after the fixpoint (empty delta) finds nothing and is dropped.
+// Applies to eager plain rounds whose joins read no index of a derived
+// relation (those indices are updated between rounds on the host's word).
+bool Engine::can_look_ahead() const {
+  if (tune_.lookahead || learned_ || log_joins_ || use_graph_) return false;
+  for (auto& ix : indices_)
+    if (rels_[ix.rel].used_as_head) return false;
+  return true;
+}
+
+void Engine::run_with_look_ahead() {
+  using clk = std::chrono::steady_clock;
+  constexpr u64 kPhaseLimit = (kEpochMask + 1) / kEpochStride - 96;
+  if (!rb_host_[1]) {
+    hip(hipHostMalloc(reinterpret_cast<void**>(&rb_host_[1]), size_t(n_ctr_) * 8 + 16, hipHostMallocDefault),
+        "pinned alloc");
+    hip(hipEventCreateWithFlags(&rb_ev_[1], hipEventDisableTiming), "event create");
+  }
+  choose_join_algorithms(false);
+  int slot = 0;
+  auto emit = [&](bool sticky, u64& seq) {
+    const int s = slot;
+    slot ^= 1;
+    seq = ++emit_seq_;
+    emit_round(false, true, sticky);
+    ++phases_;
+    hip(hipMemcpyAsync(rb_host_[s], ctr_dev_.p, size_t(n_ctr_) * 8 + 16, hipMemcpyDeviceToHost, stream_),
+        "counter readback");
+    hip(hipEventRecord(rb_ev_[s], stream_), "event record");
+    return s;
+  };
+  auto drop = [&](int s, u64 seq) {   // a look-ahead round that did nothing
+    wait_event(rb_ev_[s]);
+    collect_events(seq, true);
+  };
+  int cur = -1, nxt = -1;
+  u64 cur_seq = 0, nxt_seq = 0;
+  for (;;) {
+    auto th = clk::now();
+    if (cur < 0) {
+      ensure_capacity();
+      if (phases_ + 2 >= kPhaseLimit) begin_phase();   // clears status arrays
+      host_time("host_prepare", th);
+      th = clk::now();
+      cur = emit(false, cur_seq);
+      host_time("host_enqueue", th);
+    }
+    if (nxt < 0 && phases_ + 3 < kPhaseLimit && !ensure_capacity(true)) {
+      th = clk::now();
+      nxt = emit(true, nxt_seq);
+      host_time("host_enqueue", th);
+    }
+    th = clk::now();
+    wait_event(rb_ev_[cur]);
+    ctr_host_ = rb_host_[cur];
+    flags_host_ = reinterpret_cast<u32*>(ctr_host_ + n_ctr_);
+    collect_events(cur_seq, false);
+    host_time("host_wait", th);
+    if (flags_host_[1]) {
+      terminal = true;
+      throw Error(FV_EINVAL, "internal: join scratch too small");
+    }
+    th = clk::now();
+    if (flags_host_[0] || flags_host_[2]) {
+      if (nxt >= 0) drop(nxt, nxt_seq);
+      nxt = -1;
+      grow_after_failure(false);
+      cur = -1;
+      continue;
+    }
+    finish_round(false, th);
+    if (deltas_.back() == 0) {
+      if (nxt >= 0) drop(nxt, nxt_seq);
+      break;
+    }
+    cur = nxt;
+    cur_seq = nxt_seq;
+    nxt = -1;
+  }
 }
 
 // Before an index's first build: one sketch launch per batch of indices (the
@@ -1878,15 +2079,21 @@ void Engine::log_joins(bool initial) {
 
 void Engine::alloc_control() {
   if (n_ctr_ < 8) n_ctr_ = 8;
-  ctr_dev_ = alloc(size_t(n_ctr_) * 8);
-  flags_dev_ = alloc(16);
+  // the counters and the four flag words are one buffer (and one pinned
+  // host copy), so that a round's read-back is a single copy
+  ctr_dev_ = alloc(size_t(n_ctr_) * 8 + 16);
+  flags_dev_.p = static_cast<char*>(ctr_dev_.p) + size_t(n_ctr_) * 8;
+  flags_dev_.bytes = 16;
   ticket_dev_ = alloc(16);
   // one histogram region per relation, and one for sorted index builds
   hist_dev_ = alloc((rels_.size() + 1) * kHistWords * 4);
   hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
   hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
-  hip(hipHostMalloc(reinterpret_cast<void**>(&ctr_host_), size_t(n_ctr_) * 8, hipHostMallocDefault), "pinned alloc");
-  hip(hipHostMalloc(reinterpret_cast<void**>(&flags_host_), 16, hipHostMallocDefault), "pinned alloc");
+  hip(hipHostMalloc(reinterpret_cast<void**>(&rb_host_[0]), size_t(n_ctr_) * 8 + 16, hipHostMallocDefault),
+      "pinned alloc");
+  ctr_host_ = rb_host_[0];
+  flags_host_ = reinterpret_cast<u32*>(ctr_host_ + n_ctr_);
+  hip(hipEventCreateWithFlags(&rb_ev_[0], hipEventDisableTiming), "event create");
 }
 
 void Engine::run(fv_stats* stats) {
@@ -1914,7 +2121,10 @@ void Engine::run(fv_stats* stats) {
   }
   deltas_.clear();
   run_round(true);
-  while (deltas_.back() != 0) run_round(false);
+  if (deltas_.back() != 0) {
+    if (can_look_ahead()) run_with_look_ahead();
+    else while (deltas_.back() != 0) run_round(false);
+  }
   const auto t1 = std::chrono::steady_clock::now();
   flush_stamps();
   if (stats) {

@@ -55,6 +55,8 @@ struct Relation {
   // new tuples of a round as packed keys, plus the sort's second buffer
   Buf newk, newk2;
   u64 new_cap = 0;
+  u64 last_new = 0;          // new tuples of the last finished round
+  u64 prev_new = 0;          //   and of the round before it
   // tuple set of full, for the difference operator
   Buf set;
   u64 set_cap = 0;
@@ -139,6 +141,8 @@ struct Inter {
   Buf col[kMaxCols];
   u64 cap = 0;
   int ctr = -1;
+  u64 last_used = 0;   // rows of the last finished round
+  u64 prev_used = 0;   //   and of the round before it
 };
 
 struct KClass {
@@ -156,6 +160,7 @@ struct PendingEvent {
   int ref0, ref1; // counter references
   u64 aux;
   int stamp = -1;  // >= 0: timed by the kernel's own stamps in this slot
+  u64 seq = 0;     // the round it belongs to (emit_seq_ when enqueued)
 };
 
 class Engine;
@@ -211,7 +216,9 @@ class Engine {
   Plan plan_rule(u32 rule, int delta_pos);
   u32 get_index(u32 rel, u32 nkey, const u32* keycol, u32 nfilt, const u32* fcol, const u32* fval);
   void ingest();
-  bool ensure_capacity();   // true if any buffer was reallocated
+  // true if any buffer was (dry: would be) reallocated; with look-ahead every
+  // derived relation is sized for two rounds of new tuples
+  bool ensure_capacity(bool dry = false);
   void build_indices(bool idb_only);
   void build_index(Index& ix);
 
@@ -231,16 +238,23 @@ class Engine {
   void read_counters();
   u32 next_epoch();
   void begin_phase();
-  void emit_round(bool initial, bool all_plans);
+  void emit_round(bool initial, bool all_plans, bool sticky = false);
+  void grow_after_failure(bool initial);
+  void finish_round(bool initial, std::chrono::steady_clock::time_point th);
+  bool can_look_ahead() const;
+  void run_with_look_ahead();
+  void wait_event(hipEvent_t e);
   bool capture_round();
   void drop_graph();
 
   // profiling
   int kclass(const char* name);
+  // traces: host time of one round phase, as a class of its own
+  void host_time(const char* name, std::chrono::steady_clock::time_point since);
   u64* ev_begin(int cls, bool single = false);
   hipEvent_t pooled_event();
   void ev_end(int cls, double bytes, int kind = 0, int ref0 = -1, int ref1 = -1, u64 aux = 0);
-  void collect_events();
+  void collect_events(u64 upto, bool discard);   // launches of rounds up to `upto`
 
   u64* ctr(int i) { return ctr_dev_.as<u64>() + i; }
   u32* epoch_base() { return flags_dev_.as<u32>() + 3; }
@@ -311,6 +325,9 @@ class Engine {
   std::vector<KClass> kprof_;
   std::vector<PendingEvent> pending_;
   std::vector<hipEvent_t> ev_pool_;
+  u64* rb_host_[2] = {nullptr, nullptr};    // pinned counter read-backs (two with look-ahead)
+  hipEvent_t rb_ev_[2] = {nullptr, nullptr};
+  u64 emit_seq_ = 0;                        // rounds enqueued so far
   hipEvent_t ev_open_ = nullptr;
   bool ev_is_open_ = false;
   int ev_stamp_ = -1;

@@ -103,6 +103,21 @@ __device__ __forceinline__ u64 index_slot_of(const Slot* tab, u64 mask, u64 key)
   return kNoSlot;
 }
 
+// Continuations for callers that read the home slots of several keys at once
+// (independent loads in flight, then one resolution per key): probing goes on
+// after home slot h, which the caller found holding another key, within the
+// same kMaxProbe window.
+__device__ __forceinline__ bool index_find_after(const Slot* __restrict__ tab, u64 mask, u64 key, u64 h,
+                                                 u32& start, u32& count) {
+  for (u32 i = 1; i < kMaxProbe && i <= mask; ++i) {
+    h = (h + 1) & mask;
+    const Slot s = tab[h];
+    if (s.key == key) { start = s.start; count = s.count; return true; }
+    if (s.key == kEmptyKey) return false;
+  }
+  return false;
+}
+
 // Tuple set insert-if-absent over 8-byte slots.  Returns 1 if the key was
 // new, 0 if present, -1 if kMaxProbe slots were all taken (the table is too
 // full; the caller flags it and the host grows the set).  Slots only ever go
@@ -121,6 +136,53 @@ __device__ __forceinline__ int set_insert(u64* tab, u64 mask, u64 key) {
     h = (h + 1) & mask;
   }
   return -1;
+}
+
+// set_insert after home slot h, which the caller found (or made, by a failed
+// CAS) holding another key.
+__device__ __forceinline__ int set_insert_after(u64* tab, u64 mask, u64 key, u64 h) {
+  for (u32 i = 1; i < kMaxProbe; ++i) {
+    h = (h + 1) & mask;
+    const u64 cur = tab[h];
+    if (cur == key) return 0;
+    if (cur == kEmptyKey) {
+      const u64 prev = atomic_cas_u64(&tab[h], kEmptyKey, key);
+      if (prev == kEmptyKey) return 1;
+      if (prev == key) return 0;
+    }
+  }
+  return -1;
+}
+
+// Insert-if-absent of up to kN keys per thread with their home-slot reads and
+// CASes issued together: res[i] receives set_insert's result for the keys
+// with act[i] set.
+template <int kN>
+__device__ __forceinline__ void set_insert_many(u64* tab, u64 mask, const u64* key, const bool* act, int* res) {
+  u64 h[kN], cur[kN], prev[kN];
+  bool cas[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    h[i] = mix64(key[i]) & mask;
+    cur[i] = act[i] ? tab[h[i]] : key[i];
+  }
+  // every test reads the loads first, then the CASes are issued back to
+  // back (their results are read only below)
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    cas[i] = act[i] && cur[i] == kEmptyKey;
+    prev[i] = cur[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kN; ++i)
+    if (cas[i]) prev[i] = atomic_cas_u64(&tab[h[i]], kEmptyKey, key[i]);
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    res[i] = 0;
+    if (!act[i]) continue;
+    if (cas[i] && prev[i] == kEmptyKey) res[i] = 1;   // inserted it
+    else if (prev[i] != key[i]) res[i] = set_insert_after(tab, mask, key[i], h[i]);
+  }
 }
 
 // --------------------------------------------------------------- wave / block scans

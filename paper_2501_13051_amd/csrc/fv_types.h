@@ -190,7 +190,9 @@ int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream);
 int launch_commit(const CommitParams& p, void* stream);
 // Zero n_ctr counters, n_hist histogram words and (if flag) the overflow and
 // set-full flags (flag[0], flag[2]), and advance the epoch base by kEpochStride.
-int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base, void* stream);
+// sticky: a look-ahead round, which does nothing if a flag is already raised
+int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base, void* stream,
+                          bool sticky = false);
 
 // LSD radix sort of n packed u64 keys (n from *n_ctr clamped to cap, or
 // n_const) on the low `bits` bits, digit_bits (8 or 11) per pass:
@@ -203,6 +205,7 @@ struct SortParams {
   const u64* n_ctr;
   u64 n_const;
   u64 cap;
+  u64 n_hint;            // expected keys (0: cap), for the choice of tile size
   u32 bits;
   u32 digit_bits;        // 8 or 11
   u32 max_blocks;        // grid cap of a pass (0: 2048)

@@ -317,19 +317,41 @@ __global__ __launch_bounds__(kBlock) void k_idx_slotkeys(IndexParams p, u64* key
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
-  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
-    u64 slot = p.cap;
-    if (row_indexed(p, begin + r)) {
-      // once the table has overflowed the index is rebuilt larger: later
-      // rows skip the long probe sequences of a full table
-      const bool full = p.full && (__hip_atomic_load(p.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1);
-      slot = full ? kNoSlot : index_insert_probe(p.table, mask, row_key(p, begin + r));
-      if (slot == kNoSlot) {
-        if (p.full && !full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
-        slot = 0;
-      }
+  // kS rows per thread and step: their keys, then their home slots, are
+  // read together; only a key whose home slot is taken by another key (or
+  // still empty) goes on to the find-or-insert
+  constexpr int kS = 4;
+  const u64 stride = u64(gridDim.x) * kBlock;
+  for (u64 r0 = u64(blockIdx.x) * kBlock + threadIdx.x; r0 < n; r0 += stride * kS) {
+    bool in[kS];
+    u64 key[kS];
+#pragma unroll
+    for (int j = 0; j < kS; ++j) {
+      const u64 r = min_u64(r0 + j * stride, n - 1);   // reads stay in bounds, unconditionally
+      in[j] = r0 + j * stride < n && row_indexed(p, begin + r);
+      key[j] = row_key(p, begin + r);
     }
-    keys[r] = (r << row_shift) | slot;
+    // once the table has overflowed the index is rebuilt larger: later rows
+    // skip the long probe sequences of a full table
+    const bool full = p.full && (__hip_atomic_load(p.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1);
+    u64 home[kS];
+#pragma unroll
+    for (int j = 0; j < kS; ++j) home[j] = (in[j] && !full) ? p.table[mix64(key[j]) & mask].key : kEmptyKey;
+#pragma unroll
+    for (int j = 0; j < kS; ++j) {
+      const u64 r = r0 + j * stride;
+      if (r >= n) break;
+      u64 slot = p.cap;   // rows outside the filter sort after every slot
+      if (in[j]) {
+        slot = full ? kNoSlot
+                    : home[j] == key[j] ? (mix64(key[j]) & mask) : index_insert_probe(p.table, mask, key[j]);
+        if (slot == kNoSlot) {
+          if (p.full && !full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
+          slot = 0;
+        }
+      }
+      keys[r] = (r << row_shift) | slot;
+    }
   }
 }
 

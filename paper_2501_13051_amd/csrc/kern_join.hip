@@ -42,6 +42,62 @@ __device__ __forceinline__ u64 make_key(u32 nkey, u32 a, u32 b) {
   return nkey == 2 ? ((u64(a) << 32) | u64(b)) : u64(a);
 }
 
+// Probe rows r0 + k * step (k < kN) of a source: want[k] when the row exists
+// and passes the probe filters, key[k] its join key.
+template <int kN>
+__device__ __forceinline__ void probe_keys(const u32* const* pcol, u32 n_pf, const Filter* pf, u32 nkey,
+                                           const Src* keysrc, u64 begin, u64 r0, u64 step, u64 n, bool* want,
+                                           u64* key) {
+#pragma unroll
+  for (int k = 0; k < kN; ++k) {
+    const u64 r = r0 + u64(k) * step;
+    want[k] = false;
+    key[k] = 0;
+    if (r < n) {
+      const u64 row = begin + r;
+      bool ok = true;
+      for (u32 f = 0; f < n_pf; ++f) {
+        const u32 a = probe_val(pf[f].a, pcol, row);
+        const u32 b = probe_val(pf[f].b, pcol, row);
+        ok = ok && (pf[f].op == kEq ? a == b : a != b);
+      }
+      want[k] = ok;
+      if (ok && nkey) {
+        const u32 a = probe_val(keysrc[0], pcol, row);
+        const u32 b = nkey == 2 ? probe_val(keysrc[1], pcol, row) : 0u;
+        key[k] = make_key(nkey, a, b);
+      }
+    }
+  }
+}
+
+// Runs (start, count) of kN keys: the home slots are read together (one
+// round trip for the batch), and only a key whose home slot holds another
+// key probes on.  A cross product (nkey 0) matches all nbuild build rows.
+template <int kN>
+__device__ __forceinline__ void lookup_many(const Slot* __restrict__ tab, u64 mask, u32 nkey, u32 nbuild,
+                                            const bool* want, const u64* key, u32* st, u32* cnt) {
+  Slot hs[kN];
+#pragma unroll
+  for (int k = 0; k < kN; ++k)
+    if (want[k] && nkey) hs[k] = tab[mix64(key[k]) & mask];
+#pragma unroll
+  for (int k = 0; k < kN; ++k) {
+    st[k] = 0;
+    cnt[k] = 0;
+    if (!want[k]) continue;
+    if (nkey == 0) {
+      cnt[k] = nbuild;
+    } else if (hs[k].key == key[k]) {
+      st[k] = hs[k].start;
+      cnt[k] = hs[k].count;
+    } else if (hs[k].key != kEmptyKey) {
+      u32 s, c;
+      if (index_find_after(tab, mask, key[k], mix64(key[k]) & mask, s, c)) { st[k] = s; cnt[k] = c; }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ probe
 __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
   __shared__ u32 s_ticket;
@@ -68,32 +124,13 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
     u32 st[kProbeItems], cnt[kProbeItems];
     u32 matched = 0;
     u64 tsum = 0;
+    bool want[kProbeItems];
+    u64 key[kProbeItems];
+    probe_keys<kProbeItems>(p.pcol, p.n_pf, p.pf, p.nkey, p.key, begin, r0, 1, n, want, key);
+    lookup_many<kProbeItems>(p.table, p.mask, p.nkey, u32(nbuild), want, key, st, cnt);
 #pragma unroll
-    for (int k = 0; k < kProbeItems; ++k) {
-      st[k] = 0;
-      cnt[k] = 0;
-      const u64 r = r0 + k;
-      if (r < n) {
-        const u64 row = begin + r;
-        bool ok = true;
-        for (u32 f = 0; f < p.n_pf; ++f) {
-          const u32 a = probe_val(p.pf[f].a, p.pcol, row);
-          const u32 b = probe_val(p.pf[f].b, p.pcol, row);
-          ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
-        }
-        if (ok) {
-          if (p.nkey == 0) {
-            cnt[k] = u32(nbuild);
-          } else {
-            const u32 a = probe_val(p.key[0], p.pcol, row);
-            const u32 b = p.nkey == 2 ? probe_val(p.key[1], p.pcol, row) : 0u;
-            u32 s, c;
-            if (index_find(p.table, p.mask, make_key(p.nkey, a, b), s, c)) { st[k] = s; cnt[k] = c; }
-          }
-        }
-      }
+    for (int k = 0; k < kProbeItems; ++k)
       if (cnt[k]) { ++matched; tsum += cnt[k]; }
-    }
     u32 mtot;
     u64 ttot;
     const u32 mex = block_exclusive_sum<kBlock>(matched, s_m, &mtot);
@@ -220,35 +257,55 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
       s_off[i] = (j0 + i < M) ? p.m_off[j0 + i] : T;
     __syncthreads();
 
-    bool keep[kWriteItems];
+    // Each step below goes out for all of the thread's outputs before the
+    // next one waits: the run search (LDS), then the run's probe row and
+    // start, then the build row id, then the gathered columns -- a few
+    // round trips per tile instead of a few per output.
+    bool keep[kWriteItems], live[kWriteItems];
     OutVals vals[kWriteItems];
+    u32 jl[kWriteItems];
+    u64 prow[kWriteItems], idx[kWriteItems], brow[kWriteItems];
 #pragma unroll
     for (int k = 0; k < kWriteItems; ++k) {
       const u64 nn = n0 + u64(threadIdx.x) * kWriteItems + k;
-      keep[k] = false;
-      if (nn >= T) continue;
+      live[k] = nn < T;
       u32 lo = 0, hi = kWriteTile + 1;         // last jl with s_off[jl] <= nn
       while (lo < hi) {
         const u32 mid = (lo + hi) >> 1;
         if (s_off[mid] <= nn) lo = mid + 1; else hi = mid;
       }
-      const u32 jl = lo - 1;
-      const u64 j = j0 + jl;
-      const u64 prow = p.m_row[j];
-      const u64 idx = u64(p.m_start[j]) + (nn - s_off[jl]);
-      const u64 brow = p.perm ? u64(p.perm[idx]) : idx;
-      bool ok = true;
-      for (u32 f = 0; f < p.n_filter; ++f) {
-        const u32 a = src_val(p.filt[f].a, p.pcol, prow, p.bcol, brow);
-        const u32 b = src_val(p.filt[f].b, p.pcol, prow, p.bcol, brow);
-        ok = ok && (p.filt[f].op == kEq ? a == b : a != b);
-      }
-      keep[k] = ok;
-      if (ok) {
+      // an output past the end reads the tile's first run (which exists:
+      // n0 < T), so every load below is in bounds and none is conditional
+      jl[k] = live[k] ? lo - 1 : 0;
+    }
 #pragma unroll
-        for (u32 c = 0; c < kMaxCols; ++c)
-          if (c < p.out.ncols) vals[k].v[c] = src_val(p.out.src[c], p.pcol, prow, p.bcol, brow);
+    for (int k = 0; k < kWriteItems; ++k) {
+      const u64 nn = n0 + u64(threadIdx.x) * kWriteItems + k;
+      const u64 j = j0 + jl[k];
+      prow[k] = u64(p.m_row[j]);
+      idx[k] = u64(p.m_start[j]) + (live[k] ? nn - s_off[jl[k]] : 0);
+    }
+#pragma unroll
+    for (int k = 0; k < kWriteItems; ++k) brow[k] = p.perm ? u64(p.perm[idx[k]]) : idx[k];
+    // filters and columns term by term, each term for all outputs at once
+    // (a term's source is uniform, so the outputs' loads go out together)
+#pragma unroll
+    for (int k = 0; k < kWriteItems; ++k) keep[k] = live[k];
+    for (u32 f = 0; f < p.n_filter; ++f) {
+      u32 a[kWriteItems], b[kWriteItems];
+#pragma unroll
+      for (int k = 0; k < kWriteItems; ++k) {
+        a[k] = src_val(p.filt[f].a, p.pcol, prow[k], p.bcol, brow[k]);
+        b[k] = src_val(p.filt[f].b, p.pcol, prow[k], p.bcol, brow[k]);
       }
+#pragma unroll
+      for (int k = 0; k < kWriteItems; ++k) keep[k] = keep[k] && (p.filt[f].op == kEq ? a[k] == b[k] : a[k] != b[k]);
+    }
+#pragma unroll
+    for (u32 c = 0; c < kMaxCols; ++c) {
+      if (c >= p.out.ncols) break;
+#pragma unroll
+      for (int k = 0; k < kWriteItems; ++k) vals[k].v[c] = src_val(p.out.src[c], p.pcol, prow[k], p.bcol, brow[k]);
     }
     append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
   }
@@ -282,6 +339,21 @@ __device__ __forceinline__ void fused_put(const OutSpec& out, const u32* const* 
   }
 }
 
+// Output position <- already gathered values.
+__device__ __forceinline__ void put_vals(const OutSpec& out, u64 pos, const OutVals& v) {
+  if (out.packed) {
+    u64 key = 0;
+#pragma unroll
+    for (u32 c = 0; c < kMaxCols; ++c)
+      if (c < out.ncols) key |= u64(v.v[c]) << out.shift[c];
+    out.keys[pos] = key;
+  } else {
+#pragma unroll
+    for (u32 c = 0; c < kMaxCols; ++c)
+      if (c < out.ncols) out.cols[c][pos] = v.v[c];
+  }
+}
+
 // Tile index of output o: the last j with off[j] <= o (its count is > 0).
 __device__ __forceinline__ u32 fused_owner(const u64* off, u64 o) {
   u32 lo = 0, hi = kFusedTile;
@@ -310,32 +382,13 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
     const u64 t0 = tile * kFusedTile;
     u32 st[kFusedItems], cnt[kFusedItems];
     u64 mine = 0;
+    bool want[kFusedItems];
+    u64 key[kFusedItems];
+    probe_keys<kFusedItems>(p.pcol, p.n_pf, p.pf, p.nkey, p.key, begin, t0 + u64(threadIdx.x) * kFusedItems, 1, n,
+                            want, key);
+    lookup_many<kFusedItems>(p.table, p.mask, p.nkey, u32(nbuild), want, key, st, cnt);
 #pragma unroll
-    for (u32 k = 0; k < kFusedItems; ++k) {
-      st[k] = 0;
-      cnt[k] = 0;
-      const u64 r = t0 + threadIdx.x * kFusedItems + k;
-      if (r < n) {
-        const u64 row = begin + r;
-        bool ok = true;
-        for (u32 f = 0; f < p.n_pf; ++f) {
-          const u32 a = probe_val(p.pf[f].a, p.pcol, row);
-          const u32 b = probe_val(p.pf[f].b, p.pcol, row);
-          ok = ok && (p.pf[f].op == kEq ? a == b : a != b);
-        }
-        if (ok) {
-          if (p.nkey == 0) {
-            cnt[k] = u32(nbuild);
-          } else {
-            const u32 a = probe_val(p.key[0], p.pcol, row);
-            const u32 b = p.nkey == 2 ? probe_val(p.key[1], p.pcol, row) : 0u;
-            u32 s0, c0;
-            if (index_find(p.table, p.mask, make_key(p.nkey, a, b), s0, c0)) { st[k] = s0; cnt[k] = c0; }
-          }
-        }
-      }
-      mine += cnt[k];
-    }
+    for (u32 k = 0; k < kFusedItems; ++k) mine += cnt[k];
     u64 tot;
     u64 ex = block_exclusive_sum<kBlock>(mine, s_scan, &tot);
 #pragma unroll
@@ -356,10 +409,37 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
       if (base + tot > p.out.cap) {
         if (threadIdx.x == 0) *p.overflow = 1;
       } else {
-        for (u64 o = threadIdx.x; o < tot; o += kBlock) {
-          const u32 j = fused_owner(s_off, o);
-          const u64 idx = u64(s_start[j]) + (o - s_off[j]);
-          fused_put(p.out, p.pcol, p.bcol, base + o, begin + t0 + j, p.perm ? u64(p.perm[idx]) : idx);
+        // kFusedItems outputs per thread and step: their build row ids are
+        // read together, then their columns
+        for (u64 o0 = 0; o0 < tot; o0 += u64(kBlock) * kFusedItems) {
+          u32 j[kFusedItems];
+          u64 idx[kFusedItems], brow[kFusedItems];
+#pragma unroll
+          for (u32 k = 0; k < kFusedItems; ++k) {
+            const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
+            j[k] = o < tot ? fused_owner(s_off, o) : 0u;
+            idx[k] = o < tot ? u64(s_start[j[k]]) + (o - s_off[j[k]]) : 0;
+          }
+#pragma unroll
+          for (u32 k = 0; k < kFusedItems; ++k) {
+            const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
+            brow[k] = (o < tot && p.perm) ? u64(p.perm[idx[k]]) : idx[k];
+          }
+          OutVals v[kFusedItems];
+#pragma unroll
+          for (u32 c = 0; c < kMaxCols; ++c) {
+            if (c >= p.out.ncols) break;
+#pragma unroll
+            for (u32 k = 0; k < kFusedItems; ++k) {
+              const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
+              v[k].v[c] = o < tot ? src_val(p.out.src[c], p.pcol, begin + t0 + j[k], p.bcol, brow[k]) : 0u;
+            }
+          }
+#pragma unroll
+          for (u32 k = 0; k < kFusedItems; ++k) {
+            const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
+            if (o < tot) put_vals(p.out, base + o, v[k]);
+          }
         }
       }
     } else {
@@ -460,25 +540,34 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
     if (tile >= ntiles) break;
     const u64 r0 = u64(tile) * kDedupTile + u64(threadIdx.x) * kDedupItems;
     u64 key[kDedupItems];
-    bool surv[kDedupItems];
-    u32 mine = 0;
+    bool surv[kDedupItems], first[kDedupItems];
 #pragma unroll
     for (int k = 0; k < kDedupItems; ++k) {
       const u64 r = r0 + k;
-      surv[k] = false;
       key[k] = 0;
+      first[k] = false;
       if (r < n) {
         key[k] = p.keys[begin + r];
-        const bool first = (r == 0) || (p.keys[begin + r - 1] != key[k]);
-        if (first && p.set) {
-          const int ins = set_insert(p.set, p.set_mask, key[k]);
-          if (ins < 0) *p.set_full = 1;   // never the flag this kernel checks on entry
-          surv[k] = ins > 0;
-        } else {
-          surv[k] = first;
-        }
+        first[k] = (r == 0) || (p.keys[begin + r - 1] != key[k]);
       }
-      mine += surv[k] ? 1u : 0u;
+    }
+    u32 mine = 0;
+    if (p.set) {
+      // the thread's set probes go out together (one round trip, not kDedupItems)
+      int ins[kDedupItems];
+      set_insert_many<kDedupItems>(p.set, p.set_mask, key, first, ins);
+#pragma unroll
+      for (int k = 0; k < kDedupItems; ++k) {
+        if (ins[k] < 0) *p.set_full = 1;   // never the flag this kernel checks on entry
+        surv[k] = first[k] && ins[k] > 0;
+        mine += surv[k] ? 1u : 0u;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kDedupItems; ++k) {
+        surv[k] = first[k];
+        mine += surv[k] ? 1u : 0u;
+      }
     }
     u32 tot;
     const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
@@ -529,9 +618,18 @@ __global__ void k_commit(CommitParams p) {
 
 // Start of a round: zero the round's counters, the overflow flag and the
 // radix histograms in one launch.
-__global__ void k_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base) {
+__global__ void k_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base,
+                                 int sticky) {
   const u64 i0 = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   const u64 stride = u64(gridDim.x) * blockDim.x;
+  // A round enqueued behind one that may still fail: if that one raised a
+  // flag, this round must do nothing at all (its counters, histograms and
+  // epoch stay as the failed round left them) -- raising the overflow flag
+  // makes every later kernel of the round return at entry.
+  if (sticky && flag && (flag[0] || flag[2])) {
+    if (i0 == 0) flag[0] = 1;
+    return;
+  }
   for (u64 i = i0; i < n_ctr; i += stride) ctr[i] = 0;
   for (u64 i = i0; i < n_hist; i += stride) hist[i] = 0;
   if (i0 == 0) {
@@ -541,9 +639,10 @@ __global__ void k_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 
 }
 
 // ------------------------------------------------------------------ launchers
-int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base, void* stream) {
+int launch_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 n_hist, u32* epoch_base, void* stream,
+                          bool sticky) {
   hipLaunchKernelGGL(k_round_prologue, dim3(8), dim3(256), 0, (hipStream_t)stream, ctr, n_ctr, flag, hist, n_hist,
-                     epoch_base);
+                     epoch_base, int(sticky));
   return int(hipGetLastError());
 }
 

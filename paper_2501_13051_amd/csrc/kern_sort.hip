@@ -37,9 +37,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const u64* keys, const u64* 
   const u64 n = sort_n(n_ctr, n_const, cap);
   for (u32 i = threadIdx.x; i < passes * kRadix; i += kBlock) s_h[i] = 0;
   __syncthreads();
-  for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
-    const u64 k = keys[i];
-    for (u32 p = 0; p < passes; ++p) atomicAdd(&s_h[p * kRadix + ((k >> (p * kBits)) & (kRadix - 1))], 1u);
+  // kH keys per thread and step, loaded before any is counted
+  constexpr int kH = 8;
+  const u64 stride = u64(gridDim.x) * kBlock;
+  for (u64 i0 = u64(blockIdx.x) * kBlock + threadIdx.x; i0 < n; i0 += stride * kH) {
+    u64 k[kH];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) k[j] = i0 + j * stride < n ? keys[i0 + j * stride] : 0;
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+      if (i0 + j * stride >= n) continue;
+      for (u32 p = 0; p < passes; ++p) atomicAdd(&s_h[p * kRadix + ((k[j] >> (p * kBits)) & (kRadix - 1))], 1u);
+    }
   }
   __syncthreads();
   for (u32 i = threadIdx.x; i < passes * kRadix; i += kBlock) {
@@ -119,11 +128,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     const u64 t0 = u64(tile) * kTile;
     u64 key[kItems];
     u32 rank[kItems];
+    // all of the tile's loads go out before the ranking (whose ballots and
+    // LDS counters would otherwise hold each load back until the last one
+    // returned)
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
+      key[i] = idx < n ? in[idx] : 0;
+    }
 #pragma unroll
     for (int i = 0; i < kItems; ++i) {
       const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
       const bool valid = idx < n;
-      key[i] = valid ? in[idx] : 0;
       const u32 dig = valid ? u32((key[i] >> shift) & (kRadix - 1)) : 0u;
       u64 mask = __ballot(valid);
 #pragma unroll
@@ -222,22 +238,27 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     } else {
       // difference against full and append; consecutive LDS slots of one
       // digit hold consecutive keys of the sorted order
-      bool surv[kItems];
-      u32 mine = 0;
+      bool surv[kItems], first[kItems];
+      u64 kk[kItems];
 #pragma unroll
       for (int i = 0; i < kItems; ++i) {
         const u32 q = threadIdx.x * kItems + u32(i);
-        surv[i] = false;
+        first[i] = false;
+        kk[i] = 0;
         if (q < tn) {
-          const u64 k = s_keys[q];
-          const u32 dq = u32((k >> shift) & (kRadix - 1));
-          const bool first = q == s_tstart[dq] || s_keys[q - 1] != k;
-          if (first) {
-            const int ins = set_insert(fz.set, fz.set_mask, k);
-            if (ins < 0) *fz.set_full = 1;
-            surv[i] = ins > 0;
-          }
+          kk[i] = s_keys[q];
+          const u32 dq = u32((kk[i] >> shift) & (kRadix - 1));
+          first[i] = q == s_tstart[dq] || s_keys[q - 1] != kk[i];
         }
+      }
+      // the tile's set probes go out together (one round trip, not kItems)
+      int ins[kItems];
+      set_insert_many<kItems>(fz.set, fz.set_mask, kk, first, ins);
+      u32 mine = 0;
+#pragma unroll
+      for (int i = 0; i < kItems; ++i) {
+        if (ins[i] < 0) *fz.set_full = 1;
+        surv[i] = first[i] && ins[i] > 0;
         mine += surv[i] ? 1u : 0u;
       }
       u32 tot;
@@ -326,10 +347,11 @@ int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 
   const u32* h = p.hist + (u64(pass) << db);
   hipStream_t s = (hipStream_t)stream;
   // Keys per thread: 16 (4096-key tiles, half the per-tile look-back and
-  // scan work) for a plain 8-bit pass over a buffer of at least 2^22 keys;
+  // scan work) for a plain 8-bit pass over at least 2^22 keys (expected, or
+  // the buffer's capacity);
   // 8 otherwise, where more, smaller tiles keep the chip busy (small sorts),
   // 11-bit digit counters need the LDS, or the fused pass probes the set.
-  const bool wide = db == 8 && !fuse && p.cap >= (u64(1) << 22);
+  const bool wide = db == 8 && !fuse && (p.n_hint ? p.n_hint : p.cap) >= (u64(1) << 22);
 #define FV_PASS(B, F, I)                                                                                     \
   hipLaunchKernelGGL((k_rs_pass<B, F, I>), dim3(pgrid), dim3(kBlock), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, sh, \
                      h, p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)

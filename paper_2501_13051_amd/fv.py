@@ -40,7 +40,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 class Tuning(ctypes.Structure):
     _fields_ = [("radix_bits", ctypes.c_uint32), ("fuse_dedup", ctypes.c_uint32), ("set_load", ctypes.c_float),
                 ("index_load", ctypes.c_float), ("max_blocks", ctypes.c_uint32), ("index_rebuild", ctypes.c_uint32),
-                ("index_sort", ctypes.c_uint32)]
+                ("index_sort", ctypes.c_uint32), ("lookahead", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

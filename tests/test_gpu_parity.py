@@ -30,6 +30,7 @@ TUNINGS = {
     "index_rebuild": {"index_rebuild": 1},
     "index_sort": {"index_sort": 2},     # every join index built by sorting
     "index_count": {"index_sort": 1},    # every join index built by counting
+    "no_lookahead": {"lookahead": 1},    # every round waits for the one before
 }
 
 

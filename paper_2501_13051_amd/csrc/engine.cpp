@@ -650,7 +650,7 @@ bool Engine::ensure_capacity(bool dry) {
   for (auto& p : delta_plans_) plan_probe(p, false);
   // with look-ahead a relation may take two rounds of new tuples before the
   // host sees the first
-  const u64 ahead_rounds = can_look_ahead() ? 2 : 1;
+  const u64 ahead_rounds = ahead_active_ ? 2 : 1;
   // growth of the last round over the one before (>= 1; 2 without history)
   auto growth = [](u64 last, u64 prev) { return prev ? std::max(1.0, double(last) / double(prev)) : 2.0; };
   if (dry) {
@@ -1646,13 +1646,14 @@ void Engine::grow_after_failure(bool initial) {
 // counters (full, delta, derived) on the host.
 void Engine::finish_round(bool initial, std::chrono::steady_clock::time_point th) {
   if (log_joins_) log_joins(initial);
-  if (!learned_) {
+  // (a program without recursive rules derives nothing after round 0)
+  if (!learned_ && !delta_plans_.empty()) {
     // size the next round from this one: outputs tend to grow round over
     // round, and a buffer that overflows costs a whole re-run of the round
     // (4x while small, 2x past 2^24 rows, where memory rather than a re-run
     // is the scarcer resource)
     // (twice that with look-ahead, whose rounds are sized a round earlier)
-    const u64 f = can_look_ahead() ? 2 : 1;
+    const u64 f = ahead_active_ ? 2 : 1;
     auto ahead = [f](u64 used) { return f * (used < (u64(1) << 24) ? 4 * used : 2 * used); };
     for (auto& R : rels_) {
       if (!R.used_as_head) continue;
@@ -1701,7 +1702,7 @@ void Engine::finish_round(bool initial, std::chrono::steady_clock::time_point th
 // Applies to eager plain rounds whose joins read no index of a derived
 // relation (those indices are updated between rounds on the host's word).
 bool Engine::can_look_ahead() const {
-  if (tune_.lookahead || learned_ || log_joins_ || use_graph_) return false;
+  if (tune_.lookahead || learned_ || log_joins_ || use_graph_ || delta_plans_.empty()) return false;
   for (auto& ix : indices_)
     if (rels_[ix.rel].used_as_head) return false;
   return true;
@@ -1716,6 +1717,7 @@ void Engine::run_with_look_ahead() {
     hip(hipEventCreateWithFlags(&rb_ev_[1], hipEventDisableTiming), "event create");
   }
   choose_join_algorithms(false);
+  ahead_active_ = true;   // buffers are sized for two rounds from here on
   int slot = 0;
   auto emit = [&](bool sticky, u64& seq) {
     const int s = slot;

@@ -328,6 +328,7 @@ class Engine {
   u64* rb_host_[2] = {nullptr, nullptr};    // pinned counter read-backs (two with look-ahead)
   hipEvent_t rb_ev_[2] = {nullptr, nullptr};
   u64 emit_seq_ = 0;                        // rounds enqueued so far
+  bool ahead_active_ = false;               // rounds run with look-ahead (run_with_look_ahead)
   hipEvent_t ev_open_ = nullptr;
   bool ev_is_open_ = false;
   int ev_stamp_ = -1;

@@ -810,9 +810,21 @@ bool Engine::ensure_capacity(bool dry) {
         sort_rows = std::max(sort_rows, R.cap);
       }
     }
+    // an update sorts the appended rows the same way when the last round
+    // appended at least 2^20 (their words fit in new_cap words of scratch)
+    u32 upd_shift = 0;
+    if (R.used_as_head && (tune_.index_sort == 2 || (tune_.index_sort == 0 && R.n_delta >= (u64(1) << 20)))) {
+      const u32 slot_bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);
+      const u32 shift = sort_passes(slot_bits, 8) * 8;
+      if (shift + bits_for(std::max<u64>(R.new_cap, 1) - 1) <= 64) {
+        upd_shift = shift;
+        sort_rows = std::max(sort_rows, R.new_cap);
+      }
+    }
     if (!dry) {
       ix.sort_shift = sort_shift;
       ix.sort_bits = sort_bits;
+      ix.upd_shift = upd_shift;
     }
   }
   if (ixk_cap_ < sort_rows) {
@@ -1396,8 +1408,36 @@ void Engine::update_index(Index& ix) {
   p.rows_prev = ctr(ix.c_rows_prev);
   const int kc = kclass("index_update");
   ev_begin(kc);
-  launched(launch_index_update(p, std::max<u64>(R.new_cap, 1), std::max<u64>(ix.perm_cap, 1), stream_),
-           "index update launch");
+  if (ix.upd_shift) {
+    // sorted update: the appended rows' (row, slot) words, sorted by slot
+    const u64 dcap = std::max<u64>(R.new_cap, 1);
+    launched(launch_index_update_keys(p, dcap, ixk_a_.as<u64>(), ix.upd_shift, stream_), "index keys launch");
+    SortParams sp{};
+    sp.a = ixk_a_.as<u64>();
+    sp.b = ixk_b_.as<u64>();
+    sp.n_ctr = ctr(c_delta0_ + int(ix.rel));   // rows appended by the commit
+    sp.cap = dcap;
+    sp.bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);
+    sp.digit_bits = 8;
+    sp.max_blocks = tune_.max_blocks;
+    sp.hist = hist_dev_.as<u32>() + rels_.size() * kHistWords;
+    sp.status = st_sort_.as<u64>();
+    sp.ticket = ticket_dev_.as<u32>();
+    sp.epoch_base = epoch_base();
+    sp.abort = flags_dev_.as<u32>();
+    launched(launch_rs_hist(sp, stream_, true), "index hist launch");
+    u64* src = sp.a;
+    u64* dst = sp.b;
+    for (u32 pass = 0; pass < sort_passes(sp.bits, 8); ++pass) {
+      launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_), "index sort pass launch");
+      std::swap(src, dst);
+    }
+    launched(launch_index_update_runs(p, dcap, std::max<u64>(ix.perm_cap, 1), src, ix.upd_shift, stream_),
+             "index update launch");
+  } else {
+    launched(launch_index_update(p, std::max<u64>(R.new_cap, 1), std::max<u64>(ix.perm_cap, 1), stream_),
+             "index update launch");
+  }
   ev_end(kc, 0, 0);
   ix.pending_swap = true;
 }
@@ -1787,8 +1827,14 @@ void Engine::run_with_look_ahead() {
 // low-cardinality column holds far fewer keys than its relation has rows).
 void Engine::presize_indices() {
   std::vector<u32> todo;
-  for (u32 i = 0; i < indices_.size(); ++i)
-    if (!indices_[i].keys_seen && !indices_[i].hinted) todo.push_back(i);
+  for (u32 i = 0; i < indices_.size(); ++i) {
+    const Index& ix = indices_[i];
+    const Relation& R = rels_[ix.rel];
+    // a small loaded relation is sized from its rows: a table a few times
+    // too large costs less than the sketch launch and its read-back
+    if (!R.used_as_head && R.n_full < (u64(1) << 18)) continue;
+    if (!ix.keys_seen && !ix.hinted) todo.push_back(i);
+  }
   if (todo.empty()) return;
   Buf regs = alloc(size_t(kHllBatch) * kHllRegs * 4);
   Buf out = alloc(todo.size() * 16);

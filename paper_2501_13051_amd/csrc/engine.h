@@ -96,6 +96,7 @@ struct Index {
   bool pending_swap = false;  // an update into perm2/pslot2 was enqueued this round
   u32 sort_shift = 0;         // nonzero: built by sorting (row << sort_shift | slot) words
   u32 sort_bits = 0;          //   over this many slot bits
+  u32 upd_shift = 0;          // nonzero: updated by sorting the appended rows' (row << upd_shift | slot) words
 };
 
 // One join (or, with index == kNoIndex and brel == kNone, one selection):

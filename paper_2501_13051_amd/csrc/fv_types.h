@@ -281,6 +281,13 @@ int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_c
 // starts.  keys holds rows_cap words.
 int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, void* stream);
 int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32 row_shift, void* stream);
+// Sorted update, the same way: launch_index_update_keys writes the words of
+// the appended rows (relative row ids) without clearing anything; the caller
+// sorts them; launch_index_update_runs counts, shifts the old runs and
+// places the appended rows into perm_out / pslot_out.
+int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, void* stream);
+int launch_index_update_runs(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, const u64* sorted,
+                             u32 row_shift, void* stream);
 
 int launch_fill_u64(u64* p, u64 n, u64 value, void* stream);
 int launch_fill_u32(u32* p, u64 n, u32 value, void* stream);

@@ -130,9 +130,10 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
 // Exclusive scan over the table in slot order (look-back across tiles).
 // Build: start <- prefix of counts, count <- 0 (it becomes the fill cursor),
 // or count kept (kKeep: the sorted build has already placed the rows).
-// Update (kInc): dsh <- prefix of the appended counts, start += dsh, dcnt <- 0;
-// count keeps the old rows, so the fill appends after them.  Both recompute
-// the distinct keys, longest run and rows of the result.
+// Update (kInc): dsh <- prefix of the appended counts, start += dsh, dcnt <- 0
+// (kept with kKeep: the sorted update still needs it); count keeps the old
+// rows, so the fill appends after them.  Both recompute the distinct keys,
+// longest run and rows of the result.
 template <bool kInc, bool kKeep = false>
 __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
   __shared__ u32 s_ticket;
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
       if (s0 + k < p.cap) {
         if (kInc) {
           p.dsh[s0 + k] = u32(run);
-          p.dcnt[s0 + k] = 0u;
+          if (!kKeep) p.dcnt[s0 + k] = 0u;
           p.table[s0 + k].start += u32(run);
         } else {
           p.table[s0 + k].start = u32(run);
@@ -380,6 +381,79 @@ __global__ __launch_bounds__(kBlock) void k_idx_runs(IndexParams p, const u64* _
   if (over && p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
 }
 
+// ------------------------------------------------------------------ sorted update
+// An update over many appended rows sorts them by slot as the sorted build
+// does (k_idx_slotkeys over the appended range, then the radix sort), so
+// that no appended row needs a per-row atomic: the boundaries of each slot's
+// run give its appended count, the update scan shifts the old runs, and the
+// appended rows are written after each key's old rows at their rank in the
+// run.  After that pass each slot's count takes its appended rows and the
+// per-slot counter is cleared for the next update.
+
+__global__ __launch_bounds__(kBlock) void k_idx_druns(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *p.rows_prev = *p.rows;
+    *p.rows = 0;
+    *p.ndv = 0;
+    *p.maxrun = 0;
+  }
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
+    const u64 s = keys[j] & smask;
+    if (s >= p.cap) continue;   // outside the filter (sorted last)
+    const bool head = j == 0 || (keys[j - 1] & smask) != s;
+    const bool tail = j + 1 == n || (keys[j + 1] & smask) != s;
+    if (head || tail) atomicAdd(&p.dcnt[s], (tail ? u32(j + 1) : 0u) - (head ? u32(j) : 0u));
+  }
+}
+
+// Appended row j of slot s goes to start(s) + count(s) + (j - dsh(s)): its
+// key's new run start, past the key's old rows, at its rank among the key's
+// appended rows (dsh(s) is where that key's rows begin in the sorted words).
+__global__ __launch_bounds__(kBlock) void k_idx_dfill(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  if (p.full && (*p.full & 1)) return;
+  if (*p.rows > p.perm_cap) {   // the runs would not fit: flag it, write nothing
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+    return;
+  }
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
+    const u64 k = keys[j];
+    const u64 s = k & smask;
+    if (s >= p.cap) continue;
+    const u64 pos = u64(p.table[s].start) + p.table[s].count + (j - p.dsh[s]);
+    p.perm_out[pos] = u32(begin + (k >> row_shift));
+    p.pslot_out[pos] = u32(s);
+  }
+}
+
+// count += appended rows, appended counter cleared: one thread per slot (the
+// head of its run), after every read of both.
+__global__ __launch_bounds__(kBlock) void k_idx_dfinish(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  if (p.full && (*p.full & 1)) return;   // nothing was counted
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
+    const u64 s = keys[j] & smask;
+    if (s >= p.cap) continue;
+    if (j != 0 && (keys[j - 1] & smask) == s) continue;
+    p.table[s].count += p.dcnt[s];
+    p.dcnt[s] = 0u;
+  }
+}
+
 static int grid_rows(u64 n, int cap) {
   const u64 b = (n + kBlock - 1) / kBlock;
   return int(b == 0 ? 1 : (b > u64(cap) ? u64(cap) : b));
@@ -403,6 +477,25 @@ int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row
   hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv,
                      p.maxrun, p.full, p.rows);
   hipLaunchKernelGGL(k_idx_slotkeys, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, keys, row_shift);
+  return int(hipGetLastError());
+}
+
+int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, void* stream) {
+  hipLaunchKernelGGL(k_idx_slotkeys, dim3(grid_rows(delta_rows_cap, 8192)), dim3(kBlock), 0, (hipStream_t)stream, p,
+                     keys, row_shift);
+  return int(hipGetLastError());
+}
+
+int launch_index_update_runs(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, const u64* sorted,
+                             u32 row_shift, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const int dgrid = grid_rows(delta_rows_cap, 8192);
+  hipLaunchKernelGGL(k_idx_druns, dim3(dgrid), dim3(kBlock), 0, s, p, sorted, row_shift);
+  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL((k_idx_scan<true, true>), dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_move, dim3(grid_rows(old_rows_cap, 8192)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_dfill, dim3(dgrid), dim3(kBlock), 0, s, p, sorted, row_shift);
+  hipLaunchKernelGGL(k_idx_dfinish, dim3(dgrid), dim3(kBlock), 0, s, p, sorted, row_shift);
   return int(hipGetLastError());
 }
 

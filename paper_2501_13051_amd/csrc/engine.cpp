@@ -811,9 +811,13 @@ bool Engine::ensure_capacity(bool dry) {
       }
     }
     // an update sorts the appended rows the same way when the last round
-    // appended at least 2^20 (their words fit in new_cap words of scratch)
+    // appended at least 2^20 and the index keeps all of them (a filtered
+    // index takes a fraction of the rows, which the counting update skips
+    // for free while a sort would still pass over all of them); the words
+    // fit in new_cap words of scratch
     u32 upd_shift = 0;
-    if (R.used_as_head && (tune_.index_sort == 2 || (tune_.index_sort == 0 && R.n_delta >= (u64(1) << 20)))) {
+    if (R.used_as_head &&
+        (tune_.index_sort == 2 || (tune_.index_sort == 0 && ix.nfilt == 0 && R.n_delta >= (u64(1) << 20)))) {
       const u32 slot_bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);
       const u32 shift = sort_passes(slot_bits, 8) * 8;
       if (shift + bits_for(std::max<u64>(R.new_cap, 1) - 1) <= 64) {

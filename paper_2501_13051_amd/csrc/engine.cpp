@@ -329,6 +329,7 @@ void Engine::domain_analysis() {
       throw Error(FV_ENOTSUP, "relation " + R.name + " needs " + std::to_string(R.bits) + " bits per packed tuple");
     u32 s = 0;
     for (int c = int(R.arity) - 1; c >= 0; --c) { R.shift[c] = s; s += R.width[c]; }
+    R.set32 = R.bits <= 32;
   }
 }
 
@@ -575,6 +576,7 @@ void Engine::plan_all() {
   for (auto& ix : indices_) ix.c_full = next++;
   for (auto& ix : indices_) ix.c_rows = next++;
   for (auto& ix : indices_) ix.c_rows_prev = next++;
+  for (auto& Rl : rels_) Rl.c_ones = next++;
   c_hll0_ = next;
   sketches_.clear();
   if (log_joins_) {
@@ -697,11 +699,18 @@ bool Engine::ensure_capacity(bool dry) {
       if (dry) return true;
       R.set_stale = false;
       release(R.set);
-      R.set = alloc(need_set * 8);
+      R.set = alloc(need_set * (R.set32 ? 4 : 8));
       R.set_cap = need_set;
-      launched(launch_fill_u64(R.set.as<u64>(), need_set, kEmptyKey, stream_), "set clear");
+      if (R.set32) {
+        launched(launch_fill_u32(R.set.as<u32>(), need_set, kEmptyKey32, stream_), "set clear");
+        launched(launch_fill_u64(ctr(R.c_ones), 1, 0, stream_), "set clear");
+      } else {
+        launched(launch_fill_u64(R.set.as<u64>(), need_set, kEmptyKey, stream_), "set clear");
+      }
       const u32* cols[3] = {R.col[0].as<u32>(), R.col[1].as<u32>(), R.col[2].as<u32>()};
-      launched(launch_set_insert_rows(cols, R.arity, R.shift, R.n_full, R.set.as<u64>(), need_set - 1, stream_),
+      launched(launch_set_insert_rows(cols, R.arity, R.shift, R.n_full, R.set32 ? nullptr : R.set.as<u64>(),
+                                      need_set - 1, stream_, R.set32 ? R.set.as<u32>() : nullptr,
+                                      R.set32 ? ctr(R.c_ones) : nullptr),
                "set rebuild");
     }
     if (R.newk.bytes < R.new_cap * 8) {
@@ -1254,7 +1263,9 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   const int kfused = kclass("sort_pass_dedup");
   SortFuse fz{};
   if (fuse) {
-    fz.set = R.set.as<u64>();
+    fz.set = R.set32 ? nullptr : R.set.as<u64>();
+    fz.set32 = R.set32 ? R.set.as<u32>() : nullptr;
+    fz.ones = R.set32 ? ctr(R.c_ones) : nullptr;
     fz.set_mask = R.set_cap - 1;
     fz.set_full = flags + 2;
     for (u32 c = 0; c < R.arity; ++c) {
@@ -1280,7 +1291,9 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.keys = src;
   dp.src.end_ctr = ctr(c_new0_ + ri);
   dp.src.cap = R.new_cap;
-  dp.set = R.idb ? R.set.as<u64>() : nullptr;
+  dp.set = R.idb && !R.set32 ? R.set.as<u64>() : nullptr;
+  dp.set32 = R.idb && R.set32 ? R.set.as<u32>() : nullptr;
+  dp.ones = R.idb && R.set32 ? ctr(R.c_ones) : nullptr;
   dp.set_mask = R.set_cap ? R.set_cap - 1 : 0;
   dp.set_full = flags + 2;
   for (u32 c = 0; c < R.arity; ++c) {

@@ -185,6 +185,70 @@ __device__ __forceinline__ void set_insert_many(u64* tab, u64 mask, const u64* k
   }
 }
 
+// Tuple sets of relations whose packed tuples fit in 32 bits use 4-byte slots
+// (half the footprint, so more of the set stays in cache), empty = all ones.
+// The one key equal to that marker (kEmptyKey32) is kept out of the table: a
+// flag word records whether it is in the set.
+
+__device__ __forceinline__ int set32_insert_after(u32* tab, u64 mask, u32 key, u64 h) {
+  for (u32 i = 1; i < kMaxProbe; ++i) {
+    h = (h + 1) & mask;
+    const u32 cur = tab[h];
+    if (cur == key) return 0;
+    if (cur == kEmptyKey32) {
+      const u32 prev = atomicCAS(&tab[h], kEmptyKey32, key);
+      if (prev == kEmptyKey32) return 1;
+      if (prev == key) return 0;
+    }
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int set32_insert(u32* tab, u64 mask, u32 key, u64* ones) {
+  if (key == kEmptyKey32) return atomicExch(reinterpret_cast<unsigned long long*>(ones), 1ull) == 0 ? 1 : 0;
+  const u64 h = mix64(key) & mask;
+  const u32 cur = tab[h];
+  if (cur == key) return 0;
+  if (cur == kEmptyKey32) {
+    const u32 prev = atomicCAS(&tab[h], kEmptyKey32, key);
+    if (prev == kEmptyKey32) return 1;
+    if (prev == key) return 0;
+  }
+  return set32_insert_after(tab, mask, key, h);
+}
+
+// set_insert_many over a 32-bit set (keys given as u64, all below 2^32).
+template <int kN>
+__device__ __forceinline__ void set32_insert_many(u32* tab, u64 mask, const u64* key64, const bool* act, int* res,
+                                                  u64* ones) {
+  u64 h[kN];
+  u32 key[kN], cur[kN], prev[kN];
+  bool tabled[kN], cas[kN];
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    key[i] = u32(key64[i]);
+    tabled[i] = act[i] && key[i] != kEmptyKey32;
+    h[i] = mix64(key[i]) & mask;
+    cur[i] = tabled[i] ? tab[h[i]] : key[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    cas[i] = tabled[i] && cur[i] == kEmptyKey32;
+    prev[i] = cur[i];
+  }
+#pragma unroll
+  for (int i = 0; i < kN; ++i)
+    if (cas[i]) prev[i] = atomicCAS(&tab[h[i]], kEmptyKey32, key[i]);
+#pragma unroll
+  for (int i = 0; i < kN; ++i) {
+    res[i] = 0;
+    if (!act[i]) continue;
+    if (!tabled[i]) res[i] = atomicExch(reinterpret_cast<unsigned long long*>(ones), 1ull) == 0 ? 1 : 0;
+    else if (cas[i] && prev[i] == kEmptyKey32) res[i] = 1;
+    else if (prev[i] != key[i]) res[i] = set32_insert_after(tab, mask, key[i], h[i]);
+  }
+}
+
 // --------------------------------------------------------------- wave / block scans
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

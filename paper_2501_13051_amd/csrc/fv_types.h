@@ -12,6 +12,7 @@ using u32 = uint32_t;
 using u64 = uint64_t;
 
 constexpr u64 kEmptyKey = ~0ull;         // empty hash slot (0xFFFFFFFF is a reserved value)
+constexpr u32 kEmptyKey32 = 0xFFFFFFFFu; // empty slot of a 32-bit tuple set
 constexpr u32 kEpochMask = (1u << 22) - 1;
 // Each phase of work (a round, an ingest, an index build) first advances a
 // device-resident epoch base by kEpochStride; a look-back launch inside the
@@ -152,7 +153,9 @@ struct SelectParams {
 struct DedupParams {
   const u64* keys;       // sorted packed tuples
   RowRange src;          // [0, n)
-  u64* set;              // tuple set of full (null: only drop adjacent repeats)
+  u64* set;              // tuple set of full (null with set32 null: only drop adjacent repeats)
+  u32* set32;            // 32-bit tuple set instead of set (keys below 2^32), and its all-ones flag
+  u64* ones;
   u64 set_mask;
   u32* set_full;         // raised (with the overflow flag) when an insert finds no slot
   u32* cols[3];          // full columns to append to
@@ -218,6 +221,8 @@ struct SortParams {
 };
 struct SortFuse {
   u64* set;
+  u32* set32;            // 32-bit set instead of set (keys below 2^32), and its all-ones flag
+  u64* ones;
   u64 set_mask;
   u32* set_full;
   u32* cols[3];
@@ -296,9 +301,10 @@ int launch_colmax(const u32* col, u64 n, u32* out_max, void* stream);
 int launch_pack(const u32* const* cols, u32 arity, const u32* shift, u64 n, u64* keys, void* stream);
 int launch_unpack(const u64* keys, u64 n, u32 arity, const u32* shift, const u32* width,
                   u32* const* cols, void* stream);
-// Re-insert rows [0, n) of full into a tuple set.
+// Re-insert rows [0, n) of full into a tuple set (the 64-bit set, or with
+// set32 non-null the 32-bit one and its all-ones flag word).
 int launch_set_insert_rows(const u32* const* cols, u32 arity, const u32* shift, u64 n,
-                           u64* set, u64 mask, void* stream);
+                           u64* set, u64 mask, void* stream, u32* set32 = nullptr, u64* ones = nullptr);
 
 struct GatherDesc {
   const u32* src[3];

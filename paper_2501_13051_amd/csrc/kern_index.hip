@@ -571,6 +571,14 @@ __global__ void k_set_rows(PackArgs a, u64 n, u64* set, u64 mask) {
   }
 }
 
+__global__ void k_set_rows32(PackArgs a, u64 n, u32* set, u64 mask, u64* ones) {
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x) {
+    u64 k = 0;
+    for (u32 c = 0; c < a.arity; ++c) k |= u64(a.cols[c][i]) << a.shift[c];
+    (void)set32_insert(set, mask, u32(k), ones);
+  }
+}
+
 static PackArgs pack_args(const u32* const* cols, u32 arity, const u32* shift, const u32* width) {
   PackArgs a{};
   a.arity = arity;
@@ -645,10 +653,14 @@ int launch_gather_relabel(const GatherDesc* d, u32 n_src, u32 arity, u32* const*
 }
 
 int launch_set_insert_rows(const u32* const* cols, u32 arity, const u32* shift, u64 n, u64* set, u64 mask,
-                           void* stream) {
+                           void* stream, u32* set32, u64* ones) {
   if (n == 0) return 0;
-  hipLaunchKernelGGL(k_set_rows, dim3(grid_rows(n, 4096)), dim3(kBlock), 0, (hipStream_t)stream,
-                     pack_args(cols, arity, shift, nullptr), n, set, mask);
+  if (set32)
+    hipLaunchKernelGGL(k_set_rows32, dim3(grid_rows(n, 4096)), dim3(kBlock), 0, (hipStream_t)stream,
+                       pack_args(cols, arity, shift, nullptr), n, set32, mask, ones);
+  else
+    hipLaunchKernelGGL(k_set_rows, dim3(grid_rows(n, 4096)), dim3(kBlock), 0, (hipStream_t)stream,
+                       pack_args(cols, arity, shift, nullptr), n, set, mask);
   return int(hipGetLastError());
 }
 

@@ -552,10 +552,11 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
       }
     }
     u32 mine = 0;
-    if (p.set) {
+    if (p.set || p.set32) {
       // the thread's set probes go out together (one round trip, not kDedupItems)
       int ins[kDedupItems];
-      set_insert_many<kDedupItems>(p.set, p.set_mask, key, first, ins);
+      if (p.set32) set32_insert_many<kDedupItems>(p.set32, p.set_mask, key, first, ins, p.ones);
+      else set_insert_many<kDedupItems>(p.set, p.set_mask, key, first, ins);
 #pragma unroll
       for (int k = 0; k < kDedupItems; ++k) {
         if (ins[k] < 0) *p.set_full = 1;   // never the flag this kernel checks on entry

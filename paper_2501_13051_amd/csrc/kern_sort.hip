@@ -60,6 +60,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const u64* keys, const u64* 
 // Parameters of the fused difference + append (last pass only).
 struct FuseArgs {
   u64* set;
+  u32* set32;          // 32-bit set (instead of set), with its all-ones flag word
+  u64* ones;
   u64 set_mask;
   u32* set_full;
   u32* cols[3];
@@ -253,7 +255,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       }
       // the tile's set probes go out together (one round trip, not kItems)
       int ins[kItems];
-      set_insert_many<kItems>(fz.set, fz.set_mask, kk, first, ins);
+      if (fz.set32) set32_insert_many<kItems>(fz.set32, fz.set_mask, kk, first, ins, fz.ones);
+      else set_insert_many<kItems>(fz.set, fz.set_mask, kk, first, ins);
       u32 mine = 0;
 #pragma unroll
       for (int i = 0; i < kItems; ++i) {
@@ -332,6 +335,8 @@ int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 
   fz.ts = p.ts;
   if (fuse) {
     fz.set = fuse->set;
+    fz.set32 = fuse->set32;
+    fz.ones = fuse->ones;
     fz.set_mask = fuse->set_mask;
     fz.set_full = fuse->set_full;
     for (int c = 0; c < 3; ++c) {

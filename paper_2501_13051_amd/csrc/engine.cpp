@@ -676,7 +676,9 @@ bool Engine::ensure_capacity(bool dry) {
     const u64 need_full = R.n_full + ahead_rounds * R.new_cap;
     if (R.cap < need_full) {
       if (dry) return true;
-      const u64 nc = std::max<u64>(need_full, R.cap + R.cap / 2);
+      // doubling: each growth copies full and (with look-ahead) stops the
+      // overlap of two rounds, so it should happen a logarithmic number of times
+      const u64 nc = std::max<u64>(need_full, 2 * R.cap);
       for (u32 c = 0; c < R.arity; ++c) grow(R.col[c], nc * 4, R.n_full * 4);
       R.cap = nc;
     }

@@ -1123,6 +1123,10 @@ void Engine::exec_plan(Plan& p) {
       o.keys = H.newk.as<u64>();
       o.count = ctr(c_new0_ + int(s.head_rel));
       o.cap = H.new_cap;
+      if (H.hist_by_writers) {
+        o.hist = hist_dev_.as<u32>() + size_t(s.head_rel) * kHistWords;
+        o.hist_passes = sort_passes(H.bits, 8);
+      }
     }
     if (s.select_only) {
       SelectParams sp{};
@@ -1255,10 +1259,12 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   const u32 passes = sort_passes(R.bits, tune_.radix_bits);
   // the last radix pass can take the difference itself when there is a set
   const bool fuse = tune_.fuse_dedup && R.idb && passes > 0;
-  const int kh = kclass("sort_hist");
-  ev_begin(kh);
-  launched(launch_rs_hist(sp, stream_, !in_round), "hist launch");
-  ev_end(kh, 0, 4, c_new0_ + ri, -1, R.new_cap);
+  if (!(in_round && R.hist_by_writers)) {   // else the writers counted the digits
+    const int kh = kclass("sort_hist");
+    ev_begin(kh);
+    launched(launch_rs_hist(sp, stream_, !in_round), "hist launch");
+    ev_end(kh, 0, 4, c_new0_ + ri, -1, R.new_cap);
+  }
   u64* src = sp.a;
   u64* dst = sp.b;
   const int kpass = kclass("sort_pass");
@@ -1527,6 +1533,13 @@ void Engine::emit_round(bool initial, bool all_plans, bool sticky) {
                                  hist_dev_.as<u32>(), hist_dev_.bytes / 4, epoch_base(), stream_, sticky),
            "round prologue");
   epoch_off_ = 1;
+  // the writers of a relation's new keys count the sort's 8-bit digits as
+  // they write (no histogram pass), unless a one-pass join writes some of them
+  for (auto& R : rels_) R.hist_by_writers = R.used_as_head && tune_.radix_bits == 8;
+  for (auto* plans : {&init_plans_, &delta_plans_})
+    for (auto& p : *plans)
+      for (auto& s : p.steps)
+        if (s.out_buf < 0 && s.fused) rels_[s.head_rel].hist_by_writers = false;
   if (initial) {
     for (auto& p : init_plans_) exec_plan(p);
   } else {

@@ -63,6 +63,7 @@ struct Relation {
   u64 set_min = 0;           // lower bound on the next set size (after a set-full round)
   bool set_stale = false;    // holds keys of an aborted round: rebuild before the next one
   bool set32 = false;        // packed tuples fit in 32 bits: 4-byte set slots
+  bool hist_by_writers = false;  // this round's writers of new keys count their sort digits
   int c_ones = -1;           // device counter: the 32-bit set holds the all-ones key
   u32 width[3] = {0, 0, 0}, shift[3] = {0, 0, 0}, bits = 0;
   u32 exp_shift[3] = {0, 0, 0};   // lexicographic packing for export

@@ -65,6 +65,11 @@ struct OutSpec {
   u64* keys;
   u64* count;            // device counter: tuples written (may exceed cap)
   u64 cap;
+  // packed outputs into a relation's new keys may also count the 8-bit
+  // digits of every radix pass of those keys ([pass][256] words, added to),
+  // so that the sort needs no histogram pass of its own
+  u32* hist;
+  u32 hist_passes;
 };
 
 struct ProbeParams {

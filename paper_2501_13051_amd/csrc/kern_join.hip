@@ -192,9 +192,27 @@ struct OutVals {
   u32 v[kMaxCols];
 };
 
+// Digit counts of the keys a block writes (see OutSpec::hist): an LDS copy
+// for all passes, cleared before the block's first tile and added to the
+// relation's histogram after its last.
+constexpr u32 kOutHistWords = 8 * 256;
+__device__ __forceinline__ void out_hist_clear(const OutSpec& o, u32* s_hist) {
+  if (!o.hist) return;
+  for (u32 i = threadIdx.x; i < o.hist_passes * 256; i += kBlock) s_hist[i] = 0;
+  __syncthreads();
+}
+__device__ __forceinline__ void out_hist_flush(const OutSpec& o, u32* s_hist) {
+  if (!o.hist) return;
+  __syncthreads();
+  for (u32 i = threadIdx.x; i < o.hist_passes * 256; i += kBlock) {
+    const u32 c = s_hist[i];
+    if (c) atomicAdd(&o.hist[i], c);
+  }
+}
+
 template <int kItems>
 __device__ __forceinline__ void append_tile(const OutSpec& o, const bool* keep, const OutVals* vals,
-                                            u32* s_cnt, u64* s_base, u32* overflow, u64* stat) {
+                                            u32* s_cnt, u64* s_base, u32* overflow, u64* stat, u32* s_hist) {
   u32 mine = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) mine += keep[k] ? 1u : 0u;
@@ -219,6 +237,8 @@ __device__ __forceinline__ void append_tile(const OutSpec& o, const bool* keep, 
         for (u32 c = 0; c < kMaxCols; ++c)
           if (c < o.ncols) key |= u64(vals[k].v[c]) << o.shift[c];
         o.keys[pos] = key;
+        if (o.hist)
+          for (u32 q = 0; q < o.hist_passes; ++q) atomicAdd(&s_hist[q * 256 + u32((key >> (8 * q)) & 255)], 1u);
       } else {
 #pragma unroll
         for (u32 c = 0; c < kMaxCols; ++c)
@@ -236,8 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
   __shared__ u64 s_j0;
   __shared__ u32 s_cnt[kBlock / kWave + 1];
   __shared__ u64 s_base;
+  __shared__ u32 s_hist[kOutHistWords];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
+  out_hist_clear(p.out, s_hist);
   const u64 M = min_u64(*p.in_m, p.m_cap);
   const u64 T = *p.in_t;
   const u64 ntiles = (T + kWriteTile - 1) / kWriteTile;
@@ -307,8 +329,9 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
 #pragma unroll
       for (int k = 0; k < kWriteItems; ++k) vals[k].v[c] = src_val(p.out.src[c], p.pcol, prow[k], p.bcol, brow[k]);
     }
-    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
+    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat, s_hist);
   }
+  out_hist_flush(p.out, s_hist);
   ktime_end(p.ts);
 }
 
@@ -489,8 +512,10 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
 __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
   __shared__ u32 s_cnt[kBlock / kWave + 1];
   __shared__ u64 s_base;
+  __shared__ u32 s_hist[kOutHistWords];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
+  out_hist_clear(p.out, s_hist);
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 ntiles = (n + kWriteTile - 1) / kWriteTile;
@@ -516,8 +541,9 @@ __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
           if (c < p.out.ncols) vals[k].v[c] = probe_val(p.out.src[c], p.pcol, row);
       }
     }
-    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat);
+    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat, s_hist);
   }
+  out_hist_flush(p.out, s_hist);
   ktime_end(p.ts);
 }
 

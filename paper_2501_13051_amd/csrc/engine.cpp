@@ -682,15 +682,12 @@ bool Engine::ensure_capacity(bool dry) {
       for (u32 c = 0; c < R.arity; ++c) grow(R.col[c], nc * 4, R.n_full * 4);
       R.cap = nc;
     }
-    // sized for the expected size at load <= 2/3; a round that still runs out
+    // Sized for the expected size at load <= 2/3; a round that still runs out
     // of slots (bounded probing) is re-run with a larger set.  Growth is 4x
     // past the target so that the rebuild (a re-insert of all of full)
-    // happens a logarithmic number of times.
-    // expected size after this round: full plus the new-tuple volume the
-    // buffers were sized for (new_cap anticipates 4x the last round)
-    // (new_cap anticipates 4x the last round, 8x with look-ahead)
-    // (new_cap anticipates 4x the last round; with look-ahead the set must
-    // also take two more rounds at the last growth rate)
+    // happens a logarithmic number of times.  Expected size: full plus the
+    // new-tuple volume the buffers were sized for (new_cap anticipates 4x the
+    // last round); with look-ahead also two more rounds at the last growth rate.
     u64 expect = R.n_full + std::max<u64>({3 * R.n_delta, R.new_cap / 4, R.staged, 1024});
     if (ahead_rounds == 2) {
       const double g = growth(R.last_new, R.prev_new);

@@ -233,7 +233,7 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
 fv_status fv_tuning_load(const char* cache_path, const char* key, fv_tuning* out);
 
 /* Error text of the last failed call that has no context (fv_autotune,
- * fv_tuning_load, fv_mlp_*). */
+ * fv_tuning_load, fv_mlp_*, fv_hll_ndv). */
 const char* fv_global_error(void);
 
 /* The join-cardinality predictor: an MLP 8 -> 64 -> 64 -> 1 with ReLU whose
@@ -241,30 +241,50 @@ const char* fv_global_error(void);
  * b2[64] W3[1][64] b3[1] (row-major, output index first).  Inputs are the
  * 8 features of a join (see fv_join_trace), scaled by 1/16 before the first
  * layer; the output predicts log2(1 + join output size) / 16.  X is n x 8
- * row-major host memory, y has n entries.  These run on the current device. */
+ * row-major host memory, y has n entries.  These calls take no context: they
+ * run on the current device, on opt->stream, and take their device memory
+ * from opt's allocator hooks (opt may be NULL: null stream, hipMalloc).  The
+ * memory is released before the call returns.  Errors: FV_EINVAL (null
+ * argument, n == 0), FV_ENOMEM, FV_EHIP; fv_global_error() tells which. */
 #define FV_MLP_PARAMS 4801u
 
 /* Mean-squared-error loss of the network on (X, y) and its gradient with
  * respect to every parameter (same layout), in FP32 on the GPU. */
-fv_status fv_mlp_grad(const float* X, const float* y, uint32_t n, const float* params, float* grads,
-                      float* loss);
+fv_status fv_mlp_grad(const fv_options* opt, const float* X, const float* y, uint32_t n, const float* params,
+                      float* grads, float* loss);
 
 /* Full-batch training with Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) for
  * `steps` steps on the GPU.  init != 0 starts from He-uniform weights drawn from
  * SplitMix64(seed) and zero biases; otherwise from *params.  Writes the
  * trained parameters to params and the final loss to *loss (nullable). */
-fv_status fv_mlp_train(const float* X, const float* y, uint32_t n, uint32_t steps, float lr, uint64_t seed,
-                       int init, float* params, float* loss);
+fv_status fv_mlp_train(const fv_options* opt, const float* X, const float* y, uint32_t n, uint32_t steps, float lr,
+                       uint64_t seed, int init, float* params, float* loss);
 
 /* Inference with BF16 weights and activations (round to nearest even) and
  * FP32 accumulation: yhat[i] for each row of X. */
-fv_status fv_mlp_predict(const float* X, uint32_t n, const float* params, float* yhat);
+fv_status fv_mlp_predict(const fv_options* opt, const float* X, uint32_t n, const float* params, float* yhat);
+
+/* Distinct-value estimates of n_cols uint32 columns of n_rows values each:
+ * one HyperLogLog sketch per column (Flajolet, Fusy, Gandouet and Meunier
+ * 2007, the algorithm and its estimator as that paper states them; 2^12
+ * registers, standard error about 1.04 / 64 = 1.6%), the same sketch kernels
+ * that give the learned predictor its probe-key feature.  A value v is
+ * hashed as MurmurHash3's 64-bit finalizer of v + 0x9E3779B97F4A7C15; the top
+ * 12 bits pick a register, which keeps the largest 1 + (leading zeros of the
+ * other 52 bits).  cols holds n_cols column pointers (device pointers if
+ * on_device != 0, else host memory, copied in); estimates receives n_cols
+ * doubles (host memory).  Stream, allocator and errors as for the MLP calls
+ * above. */
+fv_status fv_hll_ndv(const fv_options* opt, const uint32_t* const* cols, uint32_t n_cols, uint64_t n_rows,
+                     int on_device, double* estimates);
 
 /* Number of tuples currently in a relation (after the fixpoint: its full
  * version; before: the rows loaded so far, duplicates included). */
 fv_status fv_relation_size(fv_ctx* ctx, fv_rel rel, uint64_t* n_rows);
 
-/* Copy a relation out, sorted lexicographically by (col0, col1, col2).
+/* Copy a relation out, sorted lexicographically by (col0, col1, col2): the
+ * intensional facts derived by the fixpoint (Section 2), or a relation's
+ * loaded facts, as a set.
  * cols_out holds `arity` column pointers of capacity rows each (device
  * pointers if on_device != 0).  cols_out == NULL only writes *n_rows_out.
  * If capacity < size nothing is written and FV_ETRUNC is returned with

@@ -17,6 +17,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 
@@ -72,6 +73,21 @@ Engine::Engine(const fv_options* opt) {
   opt_.predictor = nullptr;
   if (opt_.trace_only) trace_only_ = opt_.trace_only;
   opt_.trace_only = nullptr;
+  // Test hooks (fault injection for the redo paths), read once per context:
+  // FV_TEST_FAIL_ROUNDS="3,5" makes the 3rd and 5th enqueued rounds fail once
+  // as if a join had overflowed; FV_TEST_SMALL_CAPS=1 starts every new-tuple
+  // and intermediate buffer at 256 rows, so that the first rounds overflow
+  // and grow.
+  if (const char* f = std::getenv("FV_TEST_FAIL_ROUNDS")) {
+    for (const char* q = f; *q;) {
+      char* end = nullptr;
+      const unsigned long v = std::strtoul(q, &end, 10);
+      if (end == q) { ++q; continue; }
+      fail_rounds_.insert(u64(v));
+      q = end;
+    }
+  }
+  if (const char* c = std::getenv("FV_TEST_SMALL_CAPS")) small_caps_ = std::atoi(c) != 0;
 }
 
 Engine::~Engine() {
@@ -1068,7 +1084,7 @@ void Engine::wait_event(hipEvent_t e) {
 void Engine::read_counters() {
   ctr_host_ = rb_host_[0];
   flags_host_ = reinterpret_cast<u32*>(ctr_host_ + n_ctr_);
-  hip(hipMemcpyAsync(ctr_host_, ctr_dev_.p, size_t(n_ctr_) * 8 + 16, hipMemcpyDeviceToHost, stream_),
+  hip(hipMemcpyAsync(ctr_host_, ctr_dev_.p, size_t(n_ctr_) * 8 + kFlagBytes, hipMemcpyDeviceToHost, stream_),
       "counter readback");
   hip(hipEventRecord(rb_ev_[0], stream_), "event record");
   wait_event(rb_ev_[0]);
@@ -1133,7 +1149,7 @@ void Engine::exec_plan(Plan& p) {
       for (u32 f = 0; f < sp.n_filter; ++f) sp.filt[f] = s.pf[f];
       sp.out = o;
       sp.join_out_stat = ctr(c_joinout_);
-      sp.abort = nullptr;
+      sp.abort = flags + kFlagVoid;
       sp.overflow = flags;
       const int kc = kclass("select");
       sp.ts = ev_begin(kc, true);
@@ -1167,6 +1183,7 @@ void Engine::exec_plan(Plan& p) {
       fp.out = o;
       fp.out_t = ctr(s.c_t);
       fp.join_out_stat = ctr(c_joinout_);
+      fp.abort = flags + kFlagVoid;
       fp.overflow = flags;
       const int kf = kclass("join_onepass");
       fp.ts = ev_begin(kf, true);
@@ -1201,8 +1218,8 @@ void Engine::exec_plan(Plan& p) {
     pp.ticket = ticket;
     pp.epoch_base = epoch_base();
     pp.epoch_off = next_epoch();
-    pp.abort = nullptr;
-    pp.fatal = flags + 1;
+    pp.abort = flags + kFlagVoid;
+    pp.fatal = flags + kFlagFatal;
     const int kp = kclass("join_probe");
     pp.ts = ev_begin(kp, true);
     launched(launch_probe(pp, std::max<u64>(probe_bound, 1), 0, stream_), "probe launch");
@@ -1222,7 +1239,8 @@ void Engine::exec_plan(Plan& p) {
     for (u32 f = 0; f < wp.n_filter; ++f) wp.filt[f] = s.wf[f];
     wp.out = o;
     wp.join_out_stat = ctr(c_joinout_);
-    wp.abort = flags + 1;   // the probe ran out of scratch: write nothing
+    wp.abort = flags + kFlagFatal;   // the probe ran out of scratch: write nothing
+    wp.abort2 = flags + kFlagVoid;
     wp.overflow = flags;
     u32 nbuild = 0;
     for (auto& sc : s.out) nbuild += sc.kind == kSrcBuild ? 1 : 0;
@@ -1477,7 +1495,7 @@ void Engine::build_indices(bool idb_only) {
 void Engine::ingest() {
   u64 total = 0;
   for (auto& R : rels_) total += R.staged;
-  const u64 base_cap = pow2_at_least(std::max<u64>(1 << 16, 2 * total));
+  const u64 base_cap = small_caps_ ? 256 : pow2_at_least(std::max<u64>(1 << 16, 2 * total));
   base_cap_ = base_cap;
   for (auto& R : rels_) {
     R.new_cap = std::max<u64>(R.staged, R.used_as_head ? base_cap : 1);
@@ -1491,7 +1509,7 @@ void Engine::ingest() {
   for (auto& I : inters_) I.cap = base_cap;
   ensure_capacity();
   hip(hipMemsetAsync(ctr_dev_.p, 0, size_t(n_ctr_) * 8, stream_), "counter clear");
-  hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
+  hip(hipMemsetAsync(flags_dev_.p, 0, kFlagBytes, stream_), "flag clear");
   phases_ = 0;
   begin_phase();
   for (auto& R : rels_) {
@@ -1542,6 +1560,13 @@ void Engine::emit_round(bool initial, bool all_plans, bool sticky) {
   } else {
     for (auto& p : delta_plans_)
       if (all_plans || rels_[p.src_rel].n_delta > 0) exec_plan(p);
+  }
+  // test hook: this emission fails as if a join had overflowed (before any
+  // sort, difference or commit), so the round runs again
+  if (!capturing_) {
+    ++emitted_;
+    if (fail_rounds_.count(emitted_))
+      launched(launch_fill_u32(flags_dev_.as<u32>() + kFlagOverflow, 1, 1u, stream_), "test failure");
   }
   // every relation's difference first, then the commits: a round that runs
   // out of set space commits nothing
@@ -1781,7 +1806,7 @@ void Engine::run_with_look_ahead() {
   using clk = std::chrono::steady_clock;
   constexpr u64 kPhaseLimit = (kEpochMask + 1) / kEpochStride - 96;
   if (!rb_host_[1]) {
-    hip(hipHostMalloc(reinterpret_cast<void**>(&rb_host_[1]), size_t(n_ctr_) * 8 + 16, hipHostMallocDefault),
+    hip(hipHostMalloc(reinterpret_cast<void**>(&rb_host_[1]), size_t(n_ctr_) * 8 + kFlagBytes, hipHostMallocDefault),
         "pinned alloc");
     hip(hipEventCreateWithFlags(&rb_ev_[1], hipEventDisableTiming), "event create");
   }
@@ -1794,7 +1819,7 @@ void Engine::run_with_look_ahead() {
     seq = ++emit_seq_;
     emit_round(false, true, sticky);
     ++phases_;
-    hip(hipMemcpyAsync(rb_host_[s], ctr_dev_.p, size_t(n_ctr_) * 8 + 16, hipMemcpyDeviceToHost, stream_),
+    hip(hipMemcpyAsync(rb_host_[s], ctr_dev_.p, size_t(n_ctr_) * 8 + kFlagBytes, hipMemcpyDeviceToHost, stream_),
         "counter readback");
     hip(hipEventRecord(rb_ev_[s], stream_), "event record");
     return s;
@@ -1866,7 +1891,13 @@ void Engine::presize_indices() {
   }
   if (todo.empty()) return;
   Buf regs = alloc(size_t(kHllBatch) * kHllRegs * 4);
-  Buf out = alloc(todo.size() * 16);
+  Buf out;
+  try {
+    out = alloc(todo.size() * 16);
+  } catch (...) {
+    release(regs);
+    throw;
+  }
   launched(launch_fill_u32(regs.as<u32>(), u64(kHllBatch) * kHllRegs, 0u, stream_), "sketch clear");
   launched(launch_fill_u64(out.as<u64>(), 2 * todo.size(), 0, stream_), "sketch clear");
   for (size_t b0 = 0; b0 < todo.size(); b0 += kHllBatch) {
@@ -2158,15 +2189,15 @@ void Engine::alloc_control() {
   if (n_ctr_ < 8) n_ctr_ = 8;
   // the counters and the four flag words are one buffer (and one pinned
   // host copy), so that a round's read-back is a single copy
-  ctr_dev_ = alloc(size_t(n_ctr_) * 8 + 16);
+  ctr_dev_ = alloc(size_t(n_ctr_) * 8 + kFlagBytes);
   flags_dev_.p = static_cast<char*>(ctr_dev_.p) + size_t(n_ctr_) * 8;
-  flags_dev_.bytes = 16;
+  flags_dev_.bytes = kFlagBytes;
   ticket_dev_ = alloc(16);
   // one histogram region per relation, and one for sorted index builds
   hist_dev_ = alloc((rels_.size() + 1) * kHistWords * 4);
   hip(hipMemsetAsync(ticket_dev_.p, 0, 16, stream_), "ticket clear");
-  hip(hipMemsetAsync(flags_dev_.p, 0, 16, stream_), "flag clear");
-  hip(hipHostMalloc(reinterpret_cast<void**>(&rb_host_[0]), size_t(n_ctr_) * 8 + 16, hipHostMallocDefault),
+  hip(hipMemsetAsync(flags_dev_.p, 0, kFlagBytes, stream_), "flag clear");
+  hip(hipHostMalloc(reinterpret_cast<void**>(&rb_host_[0]), size_t(n_ctr_) * 8 + kFlagBytes, hipHostMallocDefault),
       "pinned alloc");
   ctr_host_ = rb_host_[0];
   flags_host_ = reinterpret_cast<u32*>(ctr_host_ + n_ctr_);
@@ -2257,9 +2288,11 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
     return;
   }
   // shifts already give lexicographic (col0, col1, col2) order: pack, sort, unpack
-  Buf a = alloc(n * 8), b = alloc(n * 8);
+  Buf a, b;
   Buf tmp[3];
   try {
+    a = alloc(n * 8);
+    b = alloc(n * 8);
     const u32* in[3] = {R.col[0].as<u32>(), R.col[1].as<u32>(), R.col[2].as<u32>()};
     launched(launch_pack(in, R.arity, R.shift, n, a.as<u64>(), stream_), "pack launch");
     const u64 stiles = (n + kSortTile - 1) / kSortTile + 1;

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <map>
 #include <memory>
+#include <set>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -261,7 +262,7 @@ class Engine {
   void collect_events(u64 upto, bool discard);   // launches of rounds up to `upto`
 
   u64* ctr(int i) { return ctr_dev_.as<u64>() + i; }
-  u32* epoch_base() { return flags_dev_.as<u32>() + 3; }
+  u32* epoch_base() { return flags_dev_.as<u32>() + kFlagEpoch; }
 
   fv_options opt_{};
   fv_tuning tune_{};
@@ -304,6 +305,10 @@ class Engine {
 
   std::vector<u64> deltas_;
   u32 redo_ = 0;
+  // test hooks (see the constructor)
+  std::set<u64> fail_rounds_;   // enqueued rounds (1-based) made to fail once
+  u64 emitted_ = 0;             // rounds enqueued so far (captures excluded)
+  bool small_caps_ = false;
   // learned predictor
   bool learned_ = false, log_joins_ = false, use_fused_ = false;
   u64 base_cap_ = 0;   // new-tuple capacity set at ingest (2x the loaded facts, at least 2^16)

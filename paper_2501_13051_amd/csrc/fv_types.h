@@ -19,6 +19,12 @@ constexpr u32 kEpochMask = (1u << 22) - 1;
 // phase uses base + its own offset (1 .. kEpochStride-1), so replaying a
 // captured graph never meets status words of an earlier replay.
 constexpr u32 kEpochStride = 1024;
+// Flag words after the counter block: [0] overflow (a round must run again),
+// [1] fatal (join scratch too small), [2] a tuple set ran out of slots,
+// [3] the epoch base, [4] void (a look-ahead round queued behind a failed
+// one: every kernel of that round returns at entry).  Words 5..7 are spare.
+constexpr u32 kFlagOverflow = 0, kFlagFatal = 1, kFlagSetFull = 2, kFlagEpoch = 3, kFlagVoid = 4;
+constexpr size_t kFlagBytes = 32;
 constexpr u32 kStampWords = 65;   // per timed launch (traces): start, then 64 end words
 constexpr int kMaxCols = 6;              // columns of an intermediate result
 constexpr int kMaxFilters = 8;
@@ -115,6 +121,7 @@ struct WriteParams {
   OutSpec out;
   u64* join_out_stat;    // running total of tuples written by joins
   const u32* abort;
+  const u32* abort2;     // second cancel word (a voided round), nullable
   u32* overflow;
   u64* ts;               // trace timing slot (see ktime_start), nullable
 };
@@ -139,6 +146,7 @@ struct FusedJoinParams {
   OutSpec out;
   u64* out_t;            // join output size before filters (added per wave)
   u64* join_out_stat;
+  const u32* abort;      // nonzero: return at entry (a voided round), nullable
   u32* overflow;
   u64* ts;               // trace timing slot (see ktime_start), nullable
 };

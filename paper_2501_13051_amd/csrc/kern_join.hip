@@ -259,6 +259,7 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
   __shared__ u32 s_hist[kOutHistWords];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
   out_hist_clear(p.out, s_hist);
   const u64 M = min_u64(*p.in_m, p.m_cap);
   const u64 T = *p.in_t;
@@ -395,6 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
   __shared__ u32 s_keep[kBlock / kWave + 1];
   __shared__ u64 s_base;
   ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
   u64 begin, n;
   source_range(p.src, begin, n);
   u64 nbuild = 0;
@@ -651,16 +653,19 @@ __global__ void k_round_prologue(u64* ctr, u64 n_ctr, u32* flag, u32* hist, u64 
   const u64 stride = u64(gridDim.x) * blockDim.x;
   // A round enqueued behind one that may still fail: if that one raised a
   // flag, this round must do nothing at all (its counters, histograms and
-  // epoch stay as the failed round left them) -- raising the overflow flag
-  // makes every later kernel of the round return at entry.
-  if (sticky && flag && (flag[0] || flag[2])) {
-    if (i0 == 0) flag[0] = 1;
+  // epoch stay as the failed round left them).  The void word makes every
+  // join and selection of the round return at entry (their look-back would
+  // otherwise meet the failed round's status words under the same epoch),
+  // and the overflow flag stops the sorts, differences, commits and index
+  // work.
+  if (sticky && flag && (flag[kFlagOverflow] || flag[kFlagSetFull])) {
+    if (i0 == 0) { flag[kFlagOverflow] = 1; flag[kFlagVoid] = 1; }
     return;
   }
   for (u64 i = i0; i < n_ctr; i += stride) ctr[i] = 0;
   for (u64 i = i0; i < n_hist; i += stride) hist[i] = 0;
   if (i0 == 0) {
-    if (flag) { flag[0] = 0; flag[2] = 0; }
+    if (flag) { flag[kFlagOverflow] = 0; flag[kFlagSetFull] = 0; flag[kFlagVoid] = 0; }
     *epoch_base += kEpochStride;
   }
 }

@@ -31,7 +31,8 @@ TRACE_COLS = 10
 EXPORTED = ("fv_ctx_create", "fv_ctx_destroy", "fv_last_error", "fv_relation_create", "fv_relation_find",
             "fv_load_columns", "fv_add_rule", "fv_run_fixpoint", "fv_relation_size", "fv_export",
             "fv_delta_sizes", "fv_profile", "fv_run_batch", "fv_autotune", "fv_tuning_load",
-            "fv_global_error", "fv_mlp_grad", "fv_mlp_train", "fv_mlp_predict", "fv_join_trace")
+            "fv_global_error", "fv_mlp_grad", "fv_mlp_train", "fv_mlp_predict", "fv_join_trace",
+            "fv_hll_ndv")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -127,9 +128,11 @@ def lib():
         L.fv_tuning_load.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(Tuning)]
         L.fv_global_error.argtypes = []
         L.fv_global_error.restype = ctypes.c_char_p
-        L.fv_mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp]
-        L.fv_mlp_train.argtypes = [vp, vp, u32, u32, ctypes.c_float, u64, ctypes.c_int, vp, vp]
-        L.fv_mlp_predict.argtypes = [vp, u32, vp, vp]
+        opt = ctypes.POINTER(Options)
+        L.fv_mlp_grad.argtypes = [opt, vp, vp, u32, vp, vp, vp]
+        L.fv_mlp_train.argtypes = [opt, vp, vp, u32, u32, ctypes.c_float, u64, ctypes.c_int, vp, vp]
+        L.fv_mlp_predict.argtypes = [opt, vp, u32, vp, vp]
+        L.fv_hll_ndv.argtypes = [opt, ctypes.POINTER(vp), u32, u64, ctypes.c_int, vp]
         L.fv_join_trace.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
         for name in EXPORTED:
             if name not in ("fv_ctx_destroy", "fv_last_error", "fv_global_error"):
@@ -485,6 +488,39 @@ def autotune(make_engine, key: str = None, cache_path: str = None, reps: int = 3
 
 
 MLP_PARAMS = 4801
+_call_opts = {}
+
+
+def _call_options():
+    """fv_options for the context-free calls: the current device's engine
+    stream and torch's caching allocator (kept alive per device)."""
+    import torch
+    dev = torch.cuda.current_device()
+    if dev not in _call_opts:
+        s = _engine_stream(torch, dev)
+        handle = s.cuda_stream
+
+        def _alloc(nbytes, stream, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, handle)
+            except Exception:
+                return None
+
+        delete = torch.cuda.caching_allocator_delete
+
+        def _free(ptr, stream, user):
+            if ptr:
+                try:
+                    delete(ptr)
+                except (AttributeError, TypeError):
+                    pass
+
+        o = Options()
+        o.stream = ctypes.c_void_p(handle)
+        a, f = ALLOC_FN(_alloc), FREE_FN(_free)
+        o.dev_alloc, o.dev_free = a, f
+        _call_opts[dev] = (o, a, f, s)
+    return ctypes.byref(_call_opts[dev][0])
 
 
 def _mlp_check(rc):
@@ -504,8 +540,8 @@ def mlp_grad(X, y, params):
     X, y, P = _f32(X, (-1, 8)), _f32(y, (-1,)), _f32(params, (MLP_PARAMS,))
     g = np.zeros(MLP_PARAMS, np.float32)
     loss = np.zeros(1, np.float32)
-    _mlp_check(lib().fv_mlp_grad(X.ctypes.data, y.ctypes.data, len(y), P.ctypes.data, g.ctypes.data,
-                                 loss.ctypes.data))
+    _mlp_check(lib().fv_mlp_grad(_call_options(), X.ctypes.data, y.ctypes.data, len(y), P.ctypes.data,
+                                 g.ctypes.data, loss.ctypes.data))
     return float(loss[0]), g
 
 
@@ -514,7 +550,7 @@ def mlp_train(X, y, steps=2000, lr=1e-3, seed=1, params=None):
     X, y = _f32(X, (-1, 8)), _f32(y, (-1,))
     P = np.zeros(MLP_PARAMS, np.float32) if params is None else _f32(params, (MLP_PARAMS,)).copy()
     loss = np.zeros(1, np.float32)
-    _mlp_check(lib().fv_mlp_train(X.ctypes.data, y.ctypes.data, len(y), steps, lr, seed,
+    _mlp_check(lib().fv_mlp_train(_call_options(), X.ctypes.data, y.ctypes.data, len(y), steps, lr, seed,
                                   1 if params is None else 0, P.ctypes.data, loss.ctypes.data))
     return P, float(loss[0])
 
@@ -523,7 +559,36 @@ def mlp_predict(X, params):
     """BF16 inference of the predictor on the GPU."""
     X, P = _f32(X, (-1, 8)), _f32(params, (MLP_PARAMS,))
     out = np.zeros(len(X), np.float32)
-    _mlp_check(lib().fv_mlp_predict(X.ctypes.data, len(X), P.ctypes.data, out.ctypes.data))
+    _mlp_check(lib().fv_mlp_predict(_call_options(), X.ctypes.data, len(X), P.ctypes.data, out.ctypes.data))
+    return out
+
+
+def hll_ndv(cols):
+    """HyperLogLog distinct-value estimate of each column (numpy uint32 on
+    the host, or torch 32-bit tensors on the device), one sketch per column."""
+    import torch
+    cols = list(cols)
+    if not cols:
+        return np.zeros(0)
+    n = len(cols[0])
+    on_device = isinstance(cols[0], torch.Tensor) and cols[0].is_cuda
+    keep, ptrs = [], (ctypes.c_void_p * len(cols))()
+    for c, col in enumerate(cols):
+        if len(col) != n:
+            raise ValueError("columns differ in length")
+        if on_device:
+            t = col.contiguous()
+            if t.element_size() != 4:
+                raise ValueError("device columns must be 32-bit")
+            _engine_stream(torch, torch.cuda.current_device()).wait_stream(torch.cuda.current_stream())
+            keep.append(t)
+            ptrs[c] = t.data_ptr()
+        else:
+            a = np.ascontiguousarray(np.asarray(col), dtype=np.uint32)
+            keep.append(a)
+            ptrs[c] = a.ctypes.data
+    out = np.zeros(len(cols), np.float64)
+    _mlp_check(lib().fv_hll_ndv(_call_options(), ptrs, len(cols), n, 1 if on_device else 0, out.ctypes.data))
     return out
 
 

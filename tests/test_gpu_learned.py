@@ -59,15 +59,124 @@ def test_stub_predictors_leave_the_fixpoint_unchanged(stub):
         assert overflows == 0
 
 
+def _true_sizes(trace):
+    """Join output sizes recorded in a trace (column 8 holds log2(1 + m) / 16)."""
+    return np.exp2(trace[:, 8].astype(np.float64) * 16) - 1
+
+
 def test_join_trace_records_true_sizes():
     program, edb, rels = _cases()[1]
     got, stats, deltas, _, trace = fv.evaluate(program, edb, flags=fv.FV_LOG_JOINS, relations=rels,
                                                with_trace=True)
     assert trace.shape[1] == fv.TRACE_COLS and len(trace) >= 2 * (len(deltas) - 1)
     assert np.all(trace[:, 9] == -1)
-    # every round's join outputs add up to what the joins wrote before filters
     assert np.all(trace[:, 8] >= 0)
     assert stats["join_output_tuples"] > 0
+
+
+def test_join_trace_sizes_equal_nested_loop_counts():
+    """A chain of three atoms: the trace's two joins must report |a join b|
+    and |(a join b) join c| before any filter, as bags, counted here by
+    nested loops over the distinct rows (the relations are sets)."""
+    rng = np.random.default_rng(21)
+
+    def rel(n, hi0, hi1):
+        r = np.unique(np.stack([rng.integers(0, hi0, n), rng.integers(0, hi1, n)], 1).astype(np.uint32), axis=0)
+        return r
+
+    a, b, c = rel(300, 200, 40), rel(900, 40, 60), rel(2500, 60, 500)   # |a| < |b| < |c|: a is probed first
+    prog = "out(x, w) :- a(x, y), b(y, z), c(z, w)."
+    edb = {k: [v[:, 0].copy(), v[:, 1].copy()] for k, v in (("a", a), ("b", b), ("c", c))}
+    m1 = sum(1 for (_, y) in a for (y2, _) in b if y == y2)
+    m2 = sum(1 for (_, y) in a for (y2, z) in b if y == y2 for (z2, _) in c if z == z2)
+    *_, trace = fv.evaluate(prog, edb, flags=fv.FV_LOG_JOINS, relations=["out"], with_trace=True)
+    steps = trace[:, 7]
+    got1 = _true_sizes(trace[steps == 0])
+    got2 = _true_sizes(trace[steps == 1])
+    assert len(got1) == 1 and len(got2) == 1, trace
+    assert abs(got1[0] - m1) <= 1e-4 * m1 + 0.5, (got1, m1)
+    assert abs(got2[0] - m2) <= 1e-4 * m2 + 0.5, (got2, m2)
+
+
+def test_recursive_join_trace_sizes_follow_shortest_path_layers():
+    """Transitive closure path(x, z) :- path(x, y), edge(y, z): round j joins
+    the pairs first derived in round j - 1 -- the pairs at shortest walk
+    length exactly j -- with edge, so it outputs the sum of out-degree(y)
+    over those pairs (computed here from boolean matrix powers)."""
+    n = 300
+    edge = W.er_graph(n, 600, seed=12)
+    A = np.zeros((n, n), np.int64)
+    A[edge[0], edge[1]] = 1
+    outdeg = A.sum(1)
+    seen = A.astype(bool)
+    layer = A.astype(bool)           # pairs at shortest length exactly 1
+    expect = [0]                     # round 0 joins the still empty path relation
+    while layer.any():
+        expect.append(int((layer * outdeg[None, :]).sum()))
+        nxt = (layer.astype(np.int64) @ A) > 0
+        layer = nxt & ~seen
+        seen |= nxt
+    *_, trace = fv.evaluate(W.TC_PROGRAM, {"edge": edge}, flags=fv.FV_LOG_JOINS, relations=["path"],
+                            with_trace=True)
+    got = np.rint(_true_sizes(trace)).astype(np.int64).tolist()
+    assert got == expect, (got, expect)
+
+
+def _predictor_rows(program, edb, rels, params):
+    *_, trace = fv.evaluate(program, edb, flags=fv.FV_LEARNED, relations=rels, predictor=params, with_trace=True)
+    return trace
+
+
+def _bf16_sizes(X, params):
+    from oracle import mlp
+    y = mlp.forward_bf16(X, params).astype(np.float64)
+    return np.exp2(16 * y) - 1
+
+
+def test_on_device_predictions_equal_the_bf16_reference():
+    """k_predict (the inference the engine runs every round) against the
+    FP64-structured BF16 reference on the same features.  First-step joins
+    only: a later step's probe size is the previous prediction on the device
+    but the true intermediate size in the trace.  A hand-built network
+    predicts (1 + probe)^0.898 - 1, below every join's worst case (probe rows
+    x longest build run), so no prediction is clamped and each must equal the
+    reference's, truncated to an integer."""
+    hand = np.zeros(fv.MLP_PARAMS, np.float32)
+    hand[0] = 1.0                       # W1[0][0]: hidden unit 0 = probe feature
+    hand[64 * 8 + 64 + 0] = 1.0         # W2[0][0]
+    hand[64 * 8 + 64 + 64 * 64 + 64 + 0] = 0.9   # W3[0]
+    checked = 0
+    for program, edb, rels in _cases():
+        T = _predictor_rows(program, edb, rels, hand)
+        sel = (T[:, 7] == 0) & (T[:, 1] > 0)
+        ref = _bf16_sizes(T[sel, :8], hand)
+        got = T[sel, 9].astype(np.float64)
+        assert np.all(np.abs(got - np.floor(ref)) <= 1 + 1e-5 * ref), np.c_[got, ref][:10]
+        checked += int(sel.sum())
+    assert checked > 20
+
+
+def test_trained_predictions_within_the_bf16_reference():
+    rows = []
+    for program, edb, rels in _cases()[:3]:
+        *_, trace = fv.evaluate(program, edb, flags=fv.FV_LOG_JOINS, relations=rels, with_trace=True)
+        rows.append(trace)
+    T0 = np.concatenate(rows)
+    params, _ = fv.mlp_train(T0[:, :8], T0[:, 8], steps=800, lr=3e-3, seed=5)
+    exact_rows = 0
+    for program, edb, rels in _cases():
+        T = _predictor_rows(program, edb, rels, params)
+        sel = T[:, 7] == 0
+        ref = _bf16_sizes(T[sel, :8], params)
+        got = T[sel, 9].astype(np.float64)
+        probe = np.exp2(T[sel, 0].astype(np.float64)) - 1
+        # clamping to the worst case only lowers a prediction
+        assert np.all(got <= ref * (1 + 1e-4) + 1), np.c_[got, ref][:10]
+        # a prediction at most the probe rows is never clamped (longest run >= 1)
+        unclamped = (ref <= probe) & (T[sel, 1] > 0)
+        assert np.all(np.abs(got[unclamped] - np.floor(ref[unclamped])) <= 1 + 1e-4 * ref[unclamped])
+        exact_rows += int(unclamped.sum())
+    assert exact_rows > 0
 
 
 def test_trained_predictor_on_plain_traces():

@@ -34,10 +34,11 @@ TUNINGS = {
 }
 
 
-def _check(program, edb, relations=None, flags=fv.FV_PLAIN, tuning=None):
+def _check(program, edb, relations=None, flags=fv.FV_PLAIN, tuning=None, predictor=None):
     ref = oracle.evaluate(program, edb)
     names = relations or list(ref.relations)
-    got, stats, deltas, _ = fv.evaluate(program, edb, flags=flags, relations=names, tuning=tuning)
+    got, stats, deltas, _ = fv.evaluate(program, edb, flags=flags, relations=names, tuning=tuning,
+                                        predictor=predictor)
     for n in names:
         assert got[n].shape == ref[n].shape, (n, got[n].shape, ref[n].shape)
         assert np.array_equal(got[n], ref[n]), n
@@ -214,10 +215,10 @@ def test_rdfs_small():
     _check(W.RDFS_PROGRAM, {"t": d["t"]}, relations=["t"])
 
 
-def _batch_engines(instances, tuning=None):
+def _batch_engines(instances, tuning=None, flags=fv.FV_PLAIN):
     engines = []
     for w in instances:
-        e = fv.Engine(tuning=tuning)
+        e = fv.Engine(tuning=tuning, flags=flags)
         for name, cols in w.edb.items():
             e.relation(name, len(cols))
         e.relation("path", 2)
@@ -271,18 +272,230 @@ def test_batched_rejects_constants_and_disconnected_bodies():
             e.close()
 
 
-def test_batched_config_full_size():
+@pytest.mark.parametrize("flags", [fv.FV_PLAIN, fv.FV_GRAPH], ids=["eager", "graph"])
+def test_batched_config_full_size(flags):
+    """All 512 instances of the batched workload, each against its own oracle
+    fixpoint (eager rounds, and the recursive round captured as a graph)."""
     insts = W.batched_tc_instances()
-    engines = _batch_engines(insts)
+    engines = _batch_engines(insts, flags=flags)
     stats = fv.run_batch(engines)
-    rng = np.random.default_rng(0)
-    picks = sorted(set(rng.choice(len(insts), 24, replace=False).tolist()) | {0, len(insts) - 1})
     total = 0
     for k, (w, e) in enumerate(zip(insts, engines)):
-        if k in picks:
-            ref = oracle.evaluate(w.program, w.edb)
-            assert np.array_equal(e.export("path"), ref["path"]), k
-        total += e.size("path")
+        ref = oracle.evaluate(w.program, w.edb)
+        assert np.array_equal(e.export("path"), ref["path"]), k
+        total += len(ref["path"])
     assert stats["derived_tuples"] == total
+    if flags == fv.FV_GRAPH:
+        assert stats["graph_captures"] >= 1 and stats["graph_replays"] >= 1, stats
     for e in engines:
         e.close()
+
+
+# ------------------------------------------------------------------ captured rounds
+@pytest.mark.parametrize("case", ["tc_chain", "tc_er", "sg", "pointsto", "rdfs"])
+def test_graph_rounds_match_oracle(case):
+    """FV_GRAPH: the recursive round captured once as a HIP graph and replayed
+    (re-captured when a buffer grows)."""
+    if case == "tc_chain":
+        prog, edb, rels = W.TC_PROGRAM, {"edge": W.chain(300)}, ["path"]
+    elif case == "tc_er":
+        prog, edb, rels = W.TC_PROGRAM, {"edge": W.er_graph(700, 1400, seed=5)}, ["path"]
+    elif case == "sg":
+        prog, edb, rels = W.SG_PROGRAM, {"edge": W.forest(8, 256, 0.05, seed=1002)}, ["sg"]
+    elif case == "pointsto":
+        w = W.config_pointsto(scale=0.05)
+        prog, edb, rels = w.program, w.edb, list(w.idb)
+    else:
+        d = W.rdfs_triples(n_triples=60_000, class_depth=5, n_entities=8_000, trans_tree=32, seed=9)
+        prog, edb, rels = W.RDFS_PROGRAM, {"t": d["t"]}, ["t"]
+    _, stats, _ = _check(prog, edb, relations=rels, flags=fv.FV_GRAPH)
+    assert stats["graph_replays"] >= 1, stats
+
+
+@pytest.mark.parametrize("seed", range(30, 38))
+def test_graph_random_programs(seed):
+    rnd = random.Random(seed)
+    prog = random_program(rnd)
+    _check(prog, random_edb(rnd), flags=fv.FV_GRAPH)
+
+
+@pytest.mark.parametrize("n_inst", [7, 64])
+def test_batched_graph_matches_per_instance_oracle(n_inst):
+    insts = W.batched_tc_instances(n_instances=n_inst, seed=77 + n_inst)
+    engines = _batch_engines(insts, flags=fv.FV_GRAPH)
+    stats = fv.run_batch(engines)
+    for w, e in zip(insts, engines):
+        assert np.array_equal(e.export("path"), oracle.evaluate(w.program, w.edb)["path"])
+        e.close()
+    assert stats["graph_replays"] >= 1
+
+
+# ------------------------------------------------------------------ fault injection
+def _workload(case):
+    if case == "tc":
+        return W.TC_PROGRAM, {"edge": W.er_graph(700, 1400, seed=5)}, ["path"]
+    if case == "sg":
+        return W.SG_PROGRAM, {"edge": W.forest(8, 256, 0.05, seed=1002)}, ["sg"]
+    if case == "pointsto":
+        w = W.config_pointsto(scale=0.05)
+        return w.program, w.edb, list(w.idb)
+    d = W.rdfs_triples(n_triples=60_000, class_depth=5, n_entities=8_000, trans_tree=32, seed=9)
+    return W.RDFS_PROGRAM, {"t": d["t"]}, ["t"]
+
+
+@pytest.mark.parametrize("case", ["tc", "sg", "pointsto", "rdfs"])
+def test_rounds_that_fail_run_again(case, monkeypatch):
+    """Rounds made to fail (test hook: as if a join had overflowed) commit
+    nothing and run again.  TC and SG run with look-ahead, so a round fails
+    while the next one is already queued: that one must do nothing at all."""
+    prog, edb, rels = _workload(case)
+    monkeypatch.setenv("FV_TEST_FAIL_ROUNDS", "1,2,4,5,6,9,10,13,17")
+    _, stats, _ = _check(prog, edb, relations=rels)
+    assert stats["redo_rounds"] >= 3, stats
+
+
+@pytest.mark.parametrize("case", ["tc", "sg", "pointsto", "rdfs"])
+def test_learned_rounds_that_fail_fall_back(case, monkeypatch):
+    prog, edb, rels = _workload(case)
+    monkeypatch.setenv("FV_TEST_FAIL_ROUNDS", "1,3,4,7")
+    params = np.zeros(fv.MLP_PARAMS, np.float32)
+    _, stats, _ = _check(prog, edb, relations=rels, flags=fv.FV_LEARNED, predictor=params)
+    assert stats["redo_rounds"] >= 2, stats
+
+
+@pytest.mark.parametrize("case", ["tc", "sg", "pointsto", "rdfs"])
+@pytest.mark.parametrize("flags", [fv.FV_PLAIN, fv.FV_GRAPH], ids=["eager", "graph"])
+def test_tiny_initial_capacities_grow(case, flags, monkeypatch):
+    """Every new-tuple and intermediate buffer starts at 256 rows (test hook):
+    rounds overflow, buffers grow, rounds run again."""
+    prog, edb, rels = _workload(case)
+    monkeypatch.setenv("FV_TEST_SMALL_CAPS", "1")
+    _, stats, _ = _check(prog, edb, relations=rels, flags=flags)
+    assert stats["redo_rounds"] >= 1, stats
+
+
+@pytest.mark.parametrize("seed", range(38, 46))
+def test_random_programs_with_failures_and_tiny_capacities(seed, monkeypatch):
+    rnd = random.Random(seed)
+    prog = random_program(rnd)
+    monkeypatch.setenv("FV_TEST_SMALL_CAPS", "1")
+    monkeypatch.setenv("FV_TEST_FAIL_ROUNDS", "2,3,5")
+    _check(prog, random_edb(rnd))
+
+
+def test_batched_with_failures(monkeypatch):
+    insts = W.batched_tc_instances(n_instances=16, seed=91)
+    monkeypatch.setenv("FV_TEST_FAIL_ROUNDS", "2,3,6")
+    monkeypatch.setenv("FV_TEST_SMALL_CAPS", "1")
+    engines = _batch_engines(insts)
+    stats = fv.run_batch(engines)
+    for w, e in zip(insts, engines):
+        assert np.array_equal(e.export("path"), oracle.evaluate(w.program, w.edb)["path"])
+        e.close()
+    assert stats["redo_rounds"] >= 3
+
+
+def _raw_tc_context(L, opt):
+    """A TC program set up through the C ABI directly; returns the handle,
+    the path relation, the edges and the first failing status (0 if none)."""
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = L.fv_ctx_create(ctypes.byref(h), ctypes.byref(opt) if opt is not None else None)
+    assert rc == 0
+    e, p = ctypes.c_uint32(), ctypes.c_uint32()
+    assert L.fv_relation_create(h, b"edge", 2, ctypes.byref(e)) == 0
+    assert L.fv_relation_create(h, b"path", 2, ctypes.byref(p)) == 0
+    edge = W.er_graph(500, 1000, seed=3)
+    cols = [np.ascontiguousarray(c, np.uint32) for c in edge]
+    ptrs = (ctypes.c_void_p * 2)(cols[0].ctypes.data, cols[1].ctypes.data)
+    rc = L.fv_load_columns(h, e.value, ptrs, len(cols[0]), 0)
+    keep = []
+    for head, body, neq in fv.parse_program(W.TC_PROGRAM):
+        def atom(a):
+            name, ts = a
+            arr = (fv.Term * len(ts))(*[fv.Term(v, 1 if k == "c" else 0) for k, v in ts])
+            keep.append(arr)
+            return fv.Atom(e.value if name == "edge" else p.value, len(ts), arr)
+        r = fv.Rule()
+        r.head = atom(head)
+        r.body = (fv.Atom * len(body))(*[atom(b) for b in body])
+        keep.append(r.body)
+        r.n_body = len(body)
+        r.n_neq = 0
+        assert L.fv_add_rule(h, ctypes.byref(r)) == 0
+    return h, p.value, edge, rc
+
+
+def test_allocator_failure_is_enomem_and_the_context_stays_destroyable():
+    """The allocator hook returns NULL from its k-th call on: the call that
+    needed the memory returns FV_ENOMEM, later calls refuse, and the context
+    can still be destroyed (everything it did allocate is handed back)."""
+    import ctypes
+    import torch
+    L = fv.lib()
+    dev = torch.cuda.current_device()
+    stream = torch.cuda.Stream()
+
+    def run(fail_after):
+        count, live = [0], set()
+
+        def _alloc(nbytes, s, user):
+            count[0] += 1
+            if count[0] > fail_after:
+                return None
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream.cuda_stream)
+            live.add(ptr)
+            return ptr
+
+        def _free(ptr, s, user):
+            live.discard(ptr)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        a, f = fv.ALLOC_FN(_alloc), fv.FREE_FN(_free)
+        opt = fv.Options()
+        opt.stream = ctypes.c_void_p(stream.cuda_stream)
+        opt.dev_alloc, opt.dev_free = a, f
+        h, path, _, rc = _raw_tc_context(L, opt)
+        if rc == 0:
+            st = fv.Stats()
+            rc = L.fv_run_fixpoint(h, ctypes.byref(st))
+        err = L.fv_last_error(h)
+        if rc != 0:
+            n = ctypes.c_uint64()
+            assert L.fv_export(h, path, None, 0, ctypes.byref(n), 0) != 0   # a failed context refuses
+        L.fv_ctx_destroy(h)
+        assert not live, f"{len(live)} allocations not handed back"
+        return rc, count[0], err
+
+    rc, total, _ = run(10 ** 9)
+    assert rc == 0 and total > 10
+    for k in (0, 2, total // 3, total // 2, total - 1):
+        rc, _, err = run(k)
+        assert rc == -2, (k, rc, err)          # FV_ENOMEM
+        assert b"allocation" in err, err
+    # the device is still fine afterwards
+    _check(W.TC_PROGRAM, {"edge": W.chain(50)})
+
+
+def test_export_into_a_short_buffer_is_etrunc():
+    import ctypes
+    L = fv.lib()
+    h, path, edge, rc = _raw_tc_context(L, None)
+    assert rc == 0
+    try:
+        st = fv.Stats()
+        assert L.fv_run_fixpoint(h, ctypes.byref(st)) == 0
+        n = ctypes.c_uint64()
+        assert L.fv_export(h, path, None, 0, ctypes.byref(n), 0) == 0
+        ref = oracle.evaluate(W.TC_PROGRAM, {"edge": edge})["path"]
+        assert n.value == len(ref)
+        bufs = [np.full(n.value, 7, np.uint32) for _ in range(2)]
+        ptrs = (ctypes.c_void_p * 2)(bufs[0].ctypes.data, bufs[1].ctypes.data)
+        m = ctypes.c_uint64()
+        assert L.fv_export(h, path, ptrs, n.value - 1, ctypes.byref(m), 0) == -8   # FV_ETRUNC
+        assert m.value == n.value and np.all(bufs[0] == 7)                          # nothing written
+        assert L.fv_export(h, path, ptrs, n.value, ctypes.byref(m), 0) == 0
+        assert np.array_equal(np.stack(bufs, 1), ref)
+        assert L.fv_run_fixpoint(h, ctypes.byref(st)) == -5                         # FV_ESTATE: ran already
+    finally:
+        L.fv_ctx_destroy(h)

@@ -27,6 +27,37 @@ def test_reference_gradient_matches_finite_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
 
 
+def _f32(bits):
+    return np.array([bits], np.uint32).view(np.float32)
+
+
+# (float32 bits in, BF16 bits out) derived by hand from round-to-nearest-even
+# on the 16 dropped bits: below half rounds down, above half up, exactly half
+# to the neighbour whose last kept bit is 0.
+RNE_CASES = [
+    (0x3F800000, 0x3F800000),   # 1.0 is exact
+    (0x3F807FFF, 0x3F800000),   # just below the half-way point
+    (0x3F808000, 0x3F800000),   # tie, kept last bit 0 (even): stays (round-half-up would go up)
+    (0x3F808001, 0x3F810000),   # just above the tie: up (truncation would stay)
+    (0x3F818000, 0x3F820000),   # tie, kept last bit 1 (odd): up to even (truncation stays)
+    (0xBF818000, 0xBF820000),   # the same tie negative: magnitude rounds up
+    (0xBF808000, 0xBF800000),   # negative tie to even: magnitude stays
+    (0xBF80FFFF, 0xBF810000),   # negative, above half: magnitude up
+    (0x7F7E8000, 0x7F7E0000),   # tie just under the largest BF16: even, stays
+    (0x7F7F7FFF, 0x7F7F0000),   # rounds to the largest finite BF16
+    (0x7F7F8000, 0x7F800000),   # tie at the largest BF16 (odd): overflows to +inf
+    (0x00008000, 0x00000000),   # subnormal tie to even zero
+    (0x00018000, 0x00020000),   # subnormal tie, odd: up
+    (0x80000000, 0x80000000),   # -0.0 stays
+]
+
+
+@pytest.mark.parametrize("bits_in,bits_out", RNE_CASES, ids=[f"{a:08x}" for a, _ in RNE_CASES])
+def test_bf16_rounds_to_nearest_even(bits_in, bits_out):
+    got = mlp.bf16(_f32(bits_in)).view(np.uint32)[0]
+    assert got == bits_out, f"{bits_in:08x} -> {got:08x}, expected {bits_out:08x}"
+
+
 def test_bf16_reference_within_rounding_bound():
     X, y, p = _data(3)
     exact = mlp.forward(X, p)[-1]

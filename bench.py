@@ -1,21 +1,27 @@
 """Benchmark: derived tuples/s to fixpoint on one MI355X.
 
-Headline (`value`): whole fixpoints of the same-generation program over a
-random forest of 64 trees x 1,024 nodes with 5% extra forward edges (68,736
-edges, 9,594,866 derived tuples).  One step = one fv_run_fixpoint: ingest of
-the EDB, index builds and every round of join / radix sort / difference /
-merge to the fixpoint, from the call until the stream is synchronized.  Inputs
-are generated and copied to the device, and each step's context is created
-and loaded from those resident columns, before its timed region (the metric
-excludes the load); the K timed regions are summed.  The engine's knobs come
-from its own autotuner, run on this workload before timing.
+Headline (`value`): whole fixpoints of RDFS reasoning over the 20M-triple
+synthetic triple table (class hierarchy of 8 levels with fan-out 6, 200
+properties in a 4-level sub-property tree, domain and range axioms on half of
+them, 10 transitive properties, Zipf-distributed entities and types; 102.5M
+derived triples) with the learned join-cardinality predictor on: an MLP
+trained at the start of the run, on this GPU, by the library's own kernels
+from join traces the plain engine logs on the transitive-closure,
+same-generation, points-to and batched transitive-closure workloads.  One
+step = one fv_run_fixpoint: ingest of the EDB, index builds and every round of
+join / radix sort / difference / merge to the fixpoint, from the call until the
+stream is synchronized.  Inputs are generated and copied to the device, and
+each step's context is created and loaded from those resident columns, before
+its timed region (the metric excludes the load); the K timed regions are
+summed.  The engine's knobs come from its own autotuner (stored choice).
 
 The JSON line also carries: the roofline of the dominant kernel class
 (algorithmic bytes over its kernels' device-clock time inside the timed
-region, against 8 TB/s), the oracle timed on the host, and the engine's other forms measured
-against the plain engine -- 512 batched transitive-closure instances vs the
-same instances run one after another, the learned predictor on the 20M-triple
-RDFS workload, and the autotuned points-to workload.
+region, against 8 TB/s), the same workload run by the plain engine and with a
+zero predictor (what the trained network adds), the oracle timed on one host
+core on a bounded sample of the same workload, and the engine's other forms --
+same generation, 512 batched transitive-closure instances vs the same
+instances run one after another, a large single join, and autotuned points-to.
 """
 from __future__ import annotations
 
@@ -133,6 +139,45 @@ class Runner:
         return sorted(ms)[len(ms) // 2], st
 
 
+def collect_traces(fv, W, torch, np):
+    """Join traces (features, true sizes) the plain engine logs on the
+    transitive-closure, same-generation, points-to and batched
+    transitive-closure workloads: the predictor's training data."""
+    rows = []
+    for wl, rels in ((W.config_tc(), ["path"]), (W.config_sg(), ["sg"]), (W.config_pointsto(), None)):
+        r = Runner(fv, torch, np, wl.program, wl.edb, rels or list(wl.idb))
+        _, _, trace = r.run_once(flags=fv.FV_LOG_JOINS)
+        rows.append(trace)
+    insts = W.batched_tc_instances()
+    es = []
+    for x in insts:
+        e = fv.Engine(flags=fv.FV_LOG_JOINS)
+        e.relation("edge", 2)
+        e.relation("path", 2)
+        e.load("edge", x.edb["edge"])
+        e.program(x.program)
+        es.append(e)
+    fv.run_batch(es)
+    rows.append(es[0].join_trace())   # the merged run's trace is reported on the first instance
+    for e in es:
+        e.close()
+    return np.concatenate(rows)
+
+
+def qerror_by_step(trace, np):
+    """Median and max q-error (max(m/p, p/m) on sizes + 1) per position in
+    the join chain, from a learned run's trace."""
+    out = {}
+    m = np.exp2(trace[:, 8].astype(np.float64) * 16) - 1
+    p = trace[:, 9].astype(np.float64)
+    for step in sorted(set(trace[:, 7].astype(int).tolist())):
+        sel = trace[:, 7] == step
+        q = np.maximum((m[sel] + 1) / (p[sel] + 1), (p[sel] + 1) / (m[sel] + 1))
+        out[f"step{step}"] = {"joins": int(sel.sum()), "median": round(float(np.median(q)), 3),
+                              "max": round(float(q.max()), 3)}
+    return out
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -149,17 +194,26 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    w = W.config_sg()
-    sg = Runner(fv, torch, np, w.program, w.edb, ["sg"])
+
+    # the predictor: trained here, on this GPU, from the plain engine's traces
+    log("collecting join traces of the plain engine (TC, SG, points-to, batched TC)")
+    T = collect_traces(fv, W, torch, np)
+    params, train_loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
+    log(f"trained the predictor on {len(T)} join records, loss {train_loss:.5f}")
+
+    w = W.config_rdfs()
+    rd = Runner(fv, torch, np, w.program, w.edb, ["t"])
+    learned = dict(flags=fv.FV_LEARNED, predictor=params)
 
     tuning, tuning_source = None, "defaults"
     if not args.no_autotune:
-        key = "sg_forest_t64_n1024"
+        key = "rdfs_t20000000_learned"
         tuning = None if args.retune or not os.path.exists(args.tuning_cache) else fv.tuning_load(args.tuning_cache, key)
         tuning_source = "autotuner cache"
         if tuning is None:
-            log("autotuning the engine on the same-generation workload")
-            tuning = fv.autotune(lambda t: sg.make(tuning=t), key=key, cache_path=args.tuning_cache, reps=3)
+            log("autotuning the engine on the learned RDFS workload")
+            tuning = fv.autotune(lambda t: rd.make(tuning=t, **learned), key=key, cache_path=args.tuning_cache,
+                                 reps=3)
             tuning_source = "autotuner (this run)"
         log(f"tuning {tuning} ({tuning_source})")
     if args.copy_probe_mb > 0:
@@ -174,24 +228,26 @@ def main():
     # dominant kernel class: most time over three traced passes (outside the timed region)
     per_class = {}
     for _ in range(3):
-        _, prof, _ = sg.run_once(flags=fv.FV_TRACE, tuning=tuning)
+        _, prof, _ = rd.run_once(flags=fv.FV_TRACE | fv.FV_LEARNED, predictor=params, tuning=tuning)
         for k in prof:
             if not k["name"].startswith("host_"):   # host phases of a round are not kernels
                 per_class[k["name"]] = per_class.get(k["name"], 0.0) + k["ms"]
     dom_name = max(per_class, key=per_class.get)
+    log(f"dominant kernel class: {dom_name}")
 
+    traced = dict(flags=fv.FV_TRACE | fv.FV_LEARNED, predictor=params, tuning=tuning, trace_only=dom_name)
     for _ in range(args.warmup):
-        sg.run_once(flags=fv.FV_TRACE, tuning=tuning, trace_only=dom_name)
+        rd.run_once(**traced)
     # A step is one fixpoint (fv_run_fixpoint: EDB ingest, index builds and
     # every round to the fixpoint).  Each step's context is created and loaded
     # from the resident EDB before its timed region, as the metric excludes
     # the load, and read and closed after it; the timed regions are summed.
     log(f"timing {args.steps} steps")
     dom = {"launches": 0, "ms": 0.0, "algo_bytes": 0.0, "items": 0}
-    derived = iters = None
+    derived = iters = st = trace = None
     elapsed = 0.0
     for _ in range(args.steps):
-        e = sg.make(flags=fv.FV_TRACE, tuning=tuning, trace_only=dom_name)
+        e = rd.make(**traced)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st = e.run()
@@ -202,6 +258,7 @@ def main():
             if k["name"] == dom_name:
                 for f in dom:
                     dom[f] += k[f]
+        trace = e.join_trace()
         e.close()
     ms_per_step = elapsed * 1000.0 / max(args.steps, 1)
     value = derived * args.steps / elapsed if elapsed > 0 else 0.0
@@ -213,6 +270,24 @@ def main():
                 "avg_launch_ms": round(dom["ms"] / max(dom["launches"], 1), 5),
                 "launches_per_step": dom["launches"] / max(args.steps, 1),
                 "algo_bytes_per_launch": round(dom["algo_bytes"] / max(dom["launches"], 1), 1)}
+
+    # the same workload and knobs without the network: the plain engine, and
+    # the learned path with a zero predictor (presizing from the uniform-key
+    # estimate alone), untraced, median of three fixpoints each
+    reps = max(3, args.steps // 3)
+    plain_ms, plain_st = rd.time_runs(reps, tuning=tuning)
+    zero_ms, zero_st = rd.time_runs(reps, tuning=tuning, flags=fv.FV_LEARNED,
+                                    predictor=np.zeros(fv.MLP_PARAMS, np.float32))
+    trained_ms, trained_st = rd.time_runs(reps, tuning=tuning, **learned)
+    learned_form = {
+        "train_records": int(len(T)), "train_loss": round(train_loss, 6),
+        "plain_ms": round(plain_ms, 2), "zero_predictor_ms": round(zero_ms, 2), "trained_ms": round(trained_ms, 2),
+        "speedup_vs_plain": round(plain_ms / trained_ms, 3), "speedup_vs_zero_predictor": round(zero_ms / trained_ms, 3),
+        "plain_redo_rounds": plain_st["redo_rounds"], "zero_predictor_redo_rounds": zero_st["redo_rounds"],
+        "zero_predictor_overflow_fallbacks": zero_st["overflows"],
+        "trained_redo_rounds": trained_st["redo_rounds"], "trained_overflow_fallbacks": trained_st["overflows"],
+        "predicted_joins": trained_st["predicted_joins"], "qerror_median": round(trained_st["qerror_median"], 3),
+        "qerror_max": round(trained_st["qerror_max"], 3), "qerror_by_chain_step": qerror_by_step(trace, np)}
 
     out = {
         "metric": "derived tuples/s to fixpoint",
@@ -227,40 +302,73 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": "same-generation fixpoint, random forest 64 trees x 1024 nodes, "
-                               "5% extra in-tree forward edges, seed 1002",
-                   "edges": w.meta["edges"], "derived_tuples": derived, "rounds": iters,
-                   "engine": "plain semi-naive (count-then-write joins, one sync per round), autotuned knobs",
-                   "tuning": tuning, "tuning_source": tuning_source},
+        "config": {"workload": "RDFS reasoning to fixpoint over 20M synthetic triples (class tree of 8 levels x "
+                               "fan-out 6, 200 properties in 4 levels, domain/range on every second property, 10 "
+                               "transitive properties, Zipf(1) entities, types and properties), seed 1005, learned "
+                               "join-cardinality MLP on",
+                   "triples": w.meta["triples"], "derived_tuples": derived, "rounds": iters,
+                   "engine": "semi-naive, learned presizing with exact count-then-write fallback, autotuned knobs",
+                   "tuning": tuning, "tuning_source": tuning_source,
+                   "redo_rounds": st["redo_rounds"], "overflow_fallbacks": st["overflows"]},
         "roofline": roofline,
         "cpu_baseline": None,
+        "learned_vs_plain": learned_form,
     }
-
-    # the same workload with the default knobs, for reference
-    plain_ms, _ = sg.time_runs(max(3, args.steps // 2))
-    out["config"]["default_knobs_ms_per_fixpoint"] = round(plain_ms, 3)
 
     if not args.no_extras:
         out["forms"] = extras(fv, W, torch, np, args)
 
     if not args.no_cpu_baseline:
-        import oracle
-        log("timing the oracle")
-        secs, n_out = [], None
-        for _ in range(max(1, args.cpu_reps)):
-            r = oracle.evaluate(w.program, w.edb, relations=["sg"])
-            secs.append(r.seconds)
-            n_out = len(r["sg"])
-        s = sorted(secs)[len(secs) // 2]
-        out["cpu_baseline"] = {"value": round(n_out / s, 1), "unit": "tuples/s", "cores": 1, "kind": "oracle",
-                               "sample": f"the whole workload, {len(secs)} runs, median fixpoint time {s:.3f} s "
-                                         f"(single-threaded sorted-vector semi-naive; {os.cpu_count()} host "
-                                         f"cores visible)"}
+        out["cpu_baseline"] = cpu_baseline(W)
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W):
+    """The oracle (single-threaded sorted-vector semi-naive) on the same
+    workload at 1/20 scale, pinned to one host core, once."""
+    import oracle
+    log("timing the oracle on a 1/20-scale sample of the RDFS workload")
+    sample = W.config_rdfs(scale=0.05)
+    old = os.sched_getaffinity(0)
+    core = min(old)
+    try:
+        os.sched_setaffinity(0, {core})
+        r = oracle.evaluate(sample.program, sample.edb, relations=["t"])
+    finally:
+        os.sched_setaffinity(0, old)
+    derived = sum(r.delta_sizes)
+    return {"value": round(derived / r.seconds, 1), "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"the RDFS generator at 1/20 scale ({sample.meta['triples']} triples, same rules and "
+                      f"hierarchies): {derived} derived tuples in {r.seconds:.2f} s, one run pinned to host core "
+                      f"{core} ({cpu_model()}; {len(old)} cores available to the process)"}
 
 
 def extras(fv, W, torch, np, args):
     forms = {}
+    # --- same generation (the round-1 headline), autotuned knobs
+    log("same-generation form")
+    wsg = W.config_sg()
+    sg = Runner(fv, torch, np, wsg.program, wsg.edb, ["sg"])
+    key = "sg_forest_t64_n1024"
+    sg_tune = fv.tuning_load(args.tuning_cache, key) if os.path.exists(args.tuning_cache) else None
+    sg.run_once(tuning=sg_tune)
+    sg_ms, sg_st = sg.time_runs(max(5, args.steps), tuning=sg_tune)
+    forms["sg_forest_64x1024"] = {"ms_per_fixpoint": round(sg_ms, 3), "derived_tuples": int(sg_st["derived_tuples"]),
+                                  "tuples_per_s": round(sg_st["derived_tuples"] / (sg_ms * 1e-3), 1),
+                                  "rounds": sg_st["iterations"], "tuning": sg_tune}
+    del sg
+
     # --- batched: 512 independent TC instances, one fixpoint vs 512 fixpoints
     log("batched form: 512 transitive-closure instances")
     insts = W.batched_tc_instances()
@@ -294,40 +402,14 @@ def extras(fv, W, torch, np, args):
     ts, tot = serial()
     batched(0)
     tb, stb = batched(0)
+    batched(fv.FV_GRAPH)
     tg, stg = batched(fv.FV_GRAPH)
     forms["batched_tc_512"] = {
         "derived_tuples": int(tot), "serial_plain_ms": round(ts * 1e3, 2), "batched_ms": round(tb * 1e3, 2),
-        "batched_graph_ms": round(tg * 1e3, 2), "speedup": round(ts / tb, 2),
+        "batched_graph_ms": round(tg * 1e3, 2), "speedup": round(ts / min(tb, tg), 2),
         "rounds": stb["iterations"], "graph_replays": stg["graph_replays"],
-        "tuples_per_s_batched": round(tot / tb, 1)}
+        "tuples_per_s_batched": round(tot / min(tb, tg), 1)}
     del runners
-
-    # --- learned predictor: train on plain-engine traces of TC, SG, points-to
-    # and the batched TC run, apply to the RDFS workload
-    log("learned form: collecting join traces")
-    rows = []
-    sources = [(W.config_tc(), ["path"]), (W.config_sg(), ["sg"]), (W.config_pointsto(), None)]
-    for wl, rels in sources:
-        r = Runner(fv, torch, np, wl.program, wl.edb, rels or list(wl.idb))
-        _, _, trace = r.run_once(flags=fv.FV_LOG_JOINS)
-        rows.append(trace)
-    T = np.concatenate(rows)
-    params, loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
-    log(f"trained on {len(T)} join records, loss {loss:.5f}")
-    rd = W.config_rdfs()
-    rr = Runner(fv, torch, np, rd.program, rd.edb, ["t"])
-    rr.run_once()
-    plain_ms, plain_st = rr.time_runs(3)
-    rr.run_once(flags=fv.FV_LEARNED, predictor=params)
-    learned_ms, lst = rr.time_runs(3, flags=fv.FV_LEARNED, predictor=params)
-    forms["learned_rdfs_20M"] = {
-        "train_records": int(len(T)), "train_loss": round(loss, 6), "plain_ms": round(plain_ms, 2),
-        "learned_ms": round(learned_ms, 2), "speedup": round(plain_ms / learned_ms, 3),
-        "derived_tuples": int(lst["derived_tuples"]), "plain_redo_rounds": plain_st["redo_rounds"],
-        "overflow_fallbacks": lst["overflows"], "predicted_joins": lst["predicted_joins"],
-        "qerror_median": round(lst["qerror_median"], 3), "qerror_max": round(lst["qerror_max"], 3),
-        "tuples_per_s_learned": round(lst["derived_tuples"] / (learned_ms * 1e-3), 1)}
-    del rr
 
     # --- one join at large sizes: per-kernel bandwidth where sizes are not
     # latency-bound (probe 2^24..2^26 rows against 2^20..2^22 keys)
@@ -340,7 +422,10 @@ def extras(fv, W, torch, np, args):
     pr = Runner(fv, torch, np, pt.program, pt.edb, list(pt.idb))
     pr.run_once()
     p_ms, p_st = pr.time_runs(3)
-    tune = fv.autotune(lambda t: pr.make(tuning=t), key="pointsto_n200000", reps=3)
+    key = "pointsto_n200000"
+    tune = fv.tuning_load(args.tuning_cache, key) if os.path.exists(args.tuning_cache) and not args.retune else None
+    if tune is None:
+        tune = fv.autotune(lambda t: pr.make(tuning=t), key=key, cache_path=args.tuning_cache, reps=3)
     t_ms, t_st = pr.time_runs(3, tuning=tune)
     forms["autotuned_pointsto"] = {"plain_ms": round(p_ms, 2), "tuned_ms": round(t_ms, 2),
                                    "speedup": round(p_ms / t_ms, 3), "tuning": tune,

@@ -65,6 +65,14 @@ typedef enum {
 #define FV_GRAPH      8u   /* capture the recursive round as a HIP graph and replay it,
                               recapturing when a buffer grows (needs a stream other than
                               the legacy null stream; ignored with FV_TRACE) */
+#define FV_HOST      32u   /* evaluate on host threads instead of the GPU: the same plans and
+                              operators (hash-index joins counted then written, radix sort,
+                              difference by a tuple set, eager append) over host memory, as the
+                              paper's CPU variant of its engine (Section 5.3, Table 3).  Chosen
+                              only by this flag, never as a fallback.  Loads and exports accept
+                              host or device pointers; with FV_LEARNED, FV_GRAPH or FV_LOG_JOINS
+                              fv_ctx_create fails (FV_EINVAL); FV_TRACE is ignored; fv_run_batch
+                              refuses it (FV_ENOTSUP) */
 
 /* Device allocator hooks.  dev_alloc returns device memory of at least
  * `bytes` bytes usable on `stream`, or NULL on failure; dev_free releases a
@@ -91,6 +99,11 @@ typedef struct {
   uint32_t lookahead;      /* 0 (default): enqueue each plain eager round before the previous
                               round's counters are read back, where the program allows it
                               (no join reads an index of a derived relation); 1: never */
+  uint32_t dedup_ranges;   /* 0 (default): the difference against full probes a hash set of full's
+                              packed tuples; 1: Algorithm 2 -- per-column indices of full (the
+                              join indices' layout, kept up to date every round), a new tuple's
+                              value ranges in them, an empty range or an empty intersection of
+                              the ranges proving it new; no tuple set is kept */
 } fv_tuning;
 
 typedef struct {
@@ -218,7 +231,7 @@ typedef fv_ctx* (*fv_make_ctx_fn)(const fv_options* opt, void* user);
 /* Autotuner.  Coordinate search over fv_tuning: starting from the defaults,
  * each knob in turn (radix_bits {8,11}, fuse_dedup {0,1}, set_load
  * {0.25,0.5}, index_load {0.25,0.5}, max_blocks {1024,2048,4096}, index_rebuild
- * {0,1}, index_sort {0,1}, lookahead {0,1}) is set to
+ * {0,1}, index_sort {0,1}, lookahead {0,1}, dedup_ranges {0,1}) is set to
  * every candidate with the others at their best so far; a candidate is scored
  * by the median fv_run_fixpoint time of `reps` fresh contexts from make()
  * (reps 0 means 3).  The winner goes to *best and, if cache_path and key are

@@ -119,7 +119,7 @@ Entry to_entry(const fv_tuning& t, double ms) {
                {"set_load", double(t.set_load)},     {"index_load", double(t.index_load)},
                {"max_blocks", double(t.max_blocks)}, {"index_rebuild", double(t.index_rebuild)},
                {"index_sort", double(t.index_sort)},   {"lookahead", double(t.lookahead)},
-               {"ms", ms}};
+               {"dedup_ranges", double(t.dedup_ranges)}, {"ms", ms}};
 }
 
 fv_tuning from_entry(const Entry& e) {
@@ -133,6 +133,7 @@ fv_tuning from_entry(const Entry& e) {
   t.index_rebuild = uint32_t(get("index_rebuild", 0));
   t.index_sort = uint32_t(get("index_sort", 0));
   t.lookahead = uint32_t(get("lookahead", 0));
+  t.dedup_ranges = uint32_t(get("dedup_ranges", 0));
   return t;
 }
 
@@ -194,10 +195,10 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
   // coordinate search: each knob in turn, the others at their best so far
   const std::vector<double> radix = {8, 11}, fuse = {0, 1}, sload = {0.25, 0.5}, iload = {0.25, 0.5},
                             blocks = {1024, 2048, 4096}, rebuild = {0, 1},
-                            isort = {0, 1}, ahead = {0, 1};
+                            isort = {0, 1}, ahead = {0, 1}, ranges = {0, 1};
   struct Knob { const std::vector<double>* vals; int which; };
   const Knob knobs[] = {{&radix, 0}, {&fuse, 1}, {&sload, 2}, {&iload, 3}, {&blocks, 4}, {&rebuild, 5},
-                        {&isort, 6}, {&ahead, 7}};
+                        {&isort, 6}, {&ahead, 7}, {&ranges, 8}};
   for (const Knob& k : knobs) {
     for (double v : *k.vals) {
       fv_tuning t = cur;
@@ -209,7 +210,8 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
         case 4: t.max_blocks = uint32_t(v); break;
         case 5: t.index_rebuild = uint32_t(v); break;
         case 6: t.index_sort = uint32_t(v); break;
-        default: t.lookahead = uint32_t(v); break;
+        case 7: t.lookahead = uint32_t(v); break;
+        default: t.dedup_ranges = uint32_t(v); break;
       }
       if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
       const double ms = trial(make, user, base, t, reps);

@@ -52,8 +52,16 @@ Engine::Engine(const fv_options* opt) {
   tune_.index_rebuild = tune_.index_rebuild ? 1 : 0;
   if (tune_.index_sort > 2) tune_.index_sort = 0;
   tune_.lookahead = tune_.lookahead ? 1 : 0;
+  tune_.dedup_ranges = tune_.dedup_ranges ? 1 : 0;
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
+  host_mode_ = (opt_.flags & FV_HOST) != 0;
+  if (host_mode_) {
+    if (opt_.flags & (FV_LEARNED | FV_GRAPH | FV_LOG_JOINS))
+      throw Error(FV_EINVAL, "FV_HOST runs the plain engine only (no FV_LEARNED, FV_GRAPH or FV_LOG_JOINS)");
+    opt_.flags &= ~u32(FV_TRACE);
+    host_threads_ = host_threads();
+  }
   trace_ = (opt_.flags & FV_TRACE) != 0;
   if (trace_) {   // the constant-rate clock the kernels stamp (kHz)
     int dev = 0, khz = 0;
@@ -228,6 +236,7 @@ void Engine::load_columns(u32 rel, const u32* const* cols, u64 n, bool on_device
   Relation& R = rels_[rel];
   for (u32 c = 0; c < R.arity; ++c)
     if (!cols[c]) throw Error(FV_EINVAL, "null column pointer");
+  if (host_mode_) { host_load(rel, cols, n, on_device); return; }
   if (!maxv_dev_.p) maxv_dev_ = alloc(64);
   if (R.staged + n > R.stage_cap) {
     const u64 cap = std::max<u64>(R.staged + n, R.stage_cap * 2);
@@ -576,6 +585,12 @@ void Engine::plan_all() {
       if (rels_[rules_[ri].body[i].rel].idb) delta_plans_.push_back(plan_rule(ri, int(i)));
   }
   for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
+  // Algorithm 2's difference reads an index of full on every column of a
+  // derived relation (shared with any join that keys on that column alone)
+  if (tune_.dedup_ranges)
+    for (u32 ri = 0; ri < rels_.size(); ++ri)
+      if (rels_[ri].used_as_head)
+        for (u32 c = 0; c < rels_[ri].arity; ++c) rels_[ri].dix[c] = get_index(ri, 1, &c, 0, nullptr, nullptr);
   // counter layout: [derived, join_out] [full_n x R] [d_begin x R]
   //   [index distinct keys] [index longest runs] [index full flags] [index rows] [HLL estimate, rows]
   //   [predicted join sizes]                                          (kept across rounds)
@@ -710,7 +725,7 @@ bool Engine::ensure_capacity(bool dry) {
       expect = std::max<u64>(expect, R.n_full + u64(1.25 * double(R.last_new) * (g + g * g)));
     }
     const u64 need_set = pow2_at_least(std::max<u64>(R.set_min, u64(double(expect) / tune_.set_load)));
-    if (R.set_cap < R.set_min || R.set_cap < expect * 3 / 2 || R.set_stale) {
+    if (!tune_.dedup_ranges && (R.set_cap < R.set_min || R.set_cap < expect * 3 / 2 || R.set_stale)) {
       if (dry) return true;
       R.set_stale = false;
       release(R.set);
@@ -1273,7 +1288,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   sp.abort = flags;
   const u32 passes = sort_passes(R.bits, tune_.radix_bits);
   // the last radix pass can take the difference itself when there is a set
-  const bool fuse = tune_.fuse_dedup && R.idb && passes > 0;
+  const bool fuse = tune_.fuse_dedup && R.idb && passes > 0 && !tune_.dedup_ranges;
   if (!(in_round && R.hist_by_writers)) {   // else the writers counted the digits
     const int kh = kclass("sort_hist");
     ev_begin(kh);
@@ -1314,9 +1329,21 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.keys = src;
   dp.src.end_ctr = ctr(c_new0_ + ri);
   dp.src.cap = R.new_cap;
-  dp.set = R.idb && !R.set32 ? R.set.as<u64>() : nullptr;
-  dp.set32 = R.idb && R.set32 ? R.set.as<u32>() : nullptr;
-  dp.ones = R.idb && R.set32 ? ctr(R.c_ones) : nullptr;
+  const bool use_set = R.idb && !tune_.dedup_ranges;
+  dp.set = use_set && !R.set32 ? R.set.as<u64>() : nullptr;
+  dp.set32 = use_set && R.set32 ? R.set.as<u32>() : nullptr;
+  dp.ones = use_set && R.set32 ? ctr(R.c_ones) : nullptr;
+  if (tune_.dedup_ranges && in_round && R.used_as_head) {
+    // full is empty before the first round (ingest), so only rounds need the test
+    dp.rd.ncol = R.arity;
+    for (u32 c = 0; c < R.arity; ++c) {
+      const Index& ix = indices_[R.dix[c]];
+      dp.rd.table[c] = ix.table.as<Slot>();
+      dp.rd.mask[c] = ix.cap - 1;
+      dp.rd.perm[c] = ix.perm.as<u32>();
+      dp.rd.fcol[c] = R.col[c].as<u32>();
+    }
+  }
   dp.set_mask = R.set_cap ? R.set_cap - 1 : 0;
   dp.set_full = flags + 2;
   for (u32 c = 0; c < R.arity; ++c) {
@@ -2208,6 +2235,7 @@ void Engine::run(fv_stats* stats) {
   if (ran_) throw Error(FV_ESTATE, "the fixpoint already ran on this context");
   if (terminal) throw Error(FV_ESTATE, "context is in an error state");
   ran_ = true;
+  if (host_mode_) { run_host(stats); return; }
   const auto t0 = std::chrono::steady_clock::now();
   domain_analysis();
   plan_all();
@@ -2271,6 +2299,7 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
   if (n == 0) return;
   for (u32 c = 0; c < R.arity; ++c)
     if (!cols[c]) throw Error(FV_EINVAL, "null output column");
+  if (host_mode_) { host_export(rel, cols, n, on_device); return; }
   if (batch_) {   // this instance's run of the batch result, shifted back to its own ids
     Engine& M = *batch_->merged;
     const u64 b = batch_->bounds[rel][inst_];
@@ -2362,6 +2391,7 @@ void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
     const Engine& E = *es[k];
     if (!es[k]) throw Error(FV_EINVAL, "null context in batch");
     if (E.ran_ || E.terminal) throw Error(FV_ESTATE, "every batched context must be fresh");
+    if (E.host_mode_) throw Error(FV_ENOTSUP, "the batched form runs on the GPU only");
     if (E.rels_.size() != E0.rels_.size() || E.rules_.size() != E0.rules_.size())
       throw Error(FV_EINVAL, "batched contexts must hold the same program");
     for (size_t r = 0; r < E.rels_.size(); ++r)

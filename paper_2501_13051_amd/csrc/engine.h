@@ -66,6 +66,7 @@ struct Relation {
   bool set32 = false;        // packed tuples fit in 32 bits: 4-byte set slots
   bool hist_by_writers = false;  // this round's writers of new keys count their sort digits
   int c_ones = -1;           // device counter: the 32-bit set holds the all-ones key
+  u32 dix[3] = {kNoIndex, kNoIndex, kNoIndex};   // per-column indices of full (Algorithm 2 difference)
   u32 width[3] = {0, 0, 0}, shift[3] = {0, 0, 0}, bits = 0;
   u32 exp_shift[3] = {0, 0, 0};   // lexicographic packing for export
   // host mirrors of device counters (valid after each sync)
@@ -169,6 +170,7 @@ struct PendingEvent {
 };
 
 class Engine;
+struct HostState;   // host evaluator state (host_engine.cpp)
 
 // Result of a batched fixpoint, shared by the instance contexts: every
 // relation sorted lexicographically in the merged id space, plus where each
@@ -305,6 +307,17 @@ class Engine {
 
   std::vector<u64> deltas_;
   u32 redo_ = 0;
+  // FV_HOST: the same plans evaluated on host threads (host_engine.cpp)
+  bool host_mode_ = false;
+  u32 host_threads_ = 1;
+  std::shared_ptr<HostState> host_;
+  static u32 host_threads();
+  void host_load(u32 rel, const u32* const* cols, u64 n, bool on_device);
+  void host_build_index(u32 i);
+  void host_exec_plan(Plan& p);
+  u64 host_finish_relation(u32 ri);
+  void run_host(fv_stats* stats);
+  void host_export(u32 rel, u32* const* cols, u64 n, bool on_device);
   // test hooks (see the constructor)
   std::set<u64> fail_rounds_;   // enqueued rounds (1-based) made to fail once
   u64 emitted_ = 0;             // rounds enqueued so far (captures excluded)

@@ -163,6 +163,21 @@ struct SelectParams {
   u64* ts;               // trace timing slot (see ktime_start), nullable
 };
 
+// The difference by Algorithm 2 (Section 4, "Union and Deduplication"): a new
+// tuple is already in full iff the ranges of its values in the per-column
+// indices of full (Section 3's hybrid index: one slot per distinct value, its
+// run of row ids) share a row id.  An empty range proves the tuple new; else
+// the row ids of the shortest range are checked against the other columns'
+// values (an id lies in the range of value v in column c iff full's column c
+// holds v at that row), which is the intersection of the ranges.
+struct RangeDedup {
+  u32 ncol;              // 0: off
+  const Slot* table[3];  // per column of full: the index table, its mask, its row ids
+  u64 mask[3];
+  const u32* perm[3];
+  const u32* fcol[3];    // full's columns
+};
+
 struct DedupParams {
   const u64* keys;       // sorted packed tuples
   RowRange src;          // [0, n)
@@ -183,6 +198,7 @@ struct DedupParams {
   u32 epoch_off;
   const u32* abort;
   u64* ts;               // trace timing slot (see ktime_start), nullable
+  RangeDedup rd;         // with rd.ncol > 0 (and no set): the difference by per-column ranges
 };
 
 struct CommitParams {

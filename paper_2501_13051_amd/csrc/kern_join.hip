@@ -550,6 +550,56 @@ __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
 }
 
 // ------------------------------------------------------------------ dedup + append
+// Algorithm 2's membership test for kN sorted new tuples (act[k]: the first
+// of a run of equal keys): present[k] when some row of full holds the tuple.
+// Every column's range lookup goes out together; then each tuple scans the
+// row ids of its shortest range and compares the other columns.
+template <int kN>
+__device__ __forceinline__ void ranges_present(const RangeDedup& rd, const u32* shift, const u32* width,
+                                               const u64* key, const bool* act, bool* present) {
+  u32 v[3][kN], st[3][kN], cnt[3][kN];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const bool on = u32(c) < rd.ncol;
+    const u64 m = width[c] >= 32 ? 0xFFFFFFFFull : ((1ull << width[c]) - 1);
+    u64 ck[kN];
+    bool want[kN];
+#pragma unroll
+    for (int k = 0; k < kN; ++k) {
+      v[c][k] = on ? u32((key[k] >> shift[c]) & m) : 0u;
+      ck[k] = u64(v[c][k]);
+      want[k] = on && act[k];
+    }
+    if (on) {
+      lookup_many<kN>(rd.table[c], rd.mask[c], 1, 0, want, ck, st[c], cnt[c]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < kN; ++k) { st[c][k] = 0; cnt[c][k] = 0xFFFFFFFFu; }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kN; ++k) {
+    present[k] = false;
+    if (!act[k]) continue;
+    // the shortest range (columns past ncol count as all ones: never chosen)
+    const u32 c01 = cnt[1][k] < cnt[0][k] ? 1u : 0u;
+    const u32 n01 = c01 ? cnt[1][k] : cnt[0][k];
+    const u32 best = cnt[2][k] < n01 ? 2u : c01;
+    if (cnt[0][k] == 0 || cnt[1][k] == 0 || cnt[2][k] == 0) continue;   // a value full never holds there
+    const u32 s0 = best == 0 ? st[0][k] : best == 1 ? st[1][k] : st[2][k];
+    const u32 n = best == 0 ? cnt[0][k] : best == 1 ? cnt[1][k] : cnt[2][k];
+    const u32* perm = rd.perm[best];
+    for (u32 i = 0; i < n; ++i) {
+      const u32 r = perm[s0 + i];
+      bool all = true;
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (u32(c) < rd.ncol && u32(c) != best) all = all && rd.fcol[c][r] == v[c][k];
+      if (all) { present[k] = true; break; }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kBlock / kWave + 1];
@@ -589,6 +639,14 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
       for (int k = 0; k < kDedupItems; ++k) {
         if (ins[k] < 0) *p.set_full = 1;   // never the flag this kernel checks on entry
         surv[k] = first[k] && ins[k] > 0;
+        mine += surv[k] ? 1u : 0u;
+      }
+    } else if (p.rd.ncol) {
+      bool present[kDedupItems];
+      ranges_present<kDedupItems>(p.rd, p.shift, p.width, key, first, present);
+#pragma unroll
+      for (int k = 0; k < kDedupItems; ++k) {
+        surv[k] = first[k] && !present[k];
         mine += surv[k] ? 1u : 0u;
       }
     } else {

@@ -26,6 +26,7 @@ FV_LEARNED = 2
 FV_TRACE = 4
 FV_GRAPH = 8
 FV_LOG_JOINS = 16
+FV_HOST = 32
 TRACE_COLS = 10
 
 EXPORTED = ("fv_ctx_create", "fv_ctx_destroy", "fv_last_error", "fv_relation_create", "fv_relation_find",
@@ -41,7 +42,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 class Tuning(ctypes.Structure):
     _fields_ = [("radix_bits", ctypes.c_uint32), ("fuse_dedup", ctypes.c_uint32), ("set_load", ctypes.c_float),
                 ("index_load", ctypes.c_float), ("max_blocks", ctypes.c_uint32), ("index_rebuild", ctypes.c_uint32),
-                ("index_sort", ctypes.c_uint32), ("lookahead", ctypes.c_uint32)]
+                ("index_sort", ctypes.c_uint32), ("lookahead", ctypes.c_uint32), ("dedup_ranges", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -249,13 +250,19 @@ class Engine:
         self._torch = torch
         L = lib()
         self._L = L
-        self._device = torch.cuda.current_device()
-        # a stream of its own (default priority): the engine captures its
-        # recursive round as a graph, which the legacy null stream cannot do
-        s = stream if stream is not None else _engine_stream(torch, self._device)
-        self._stream_obj = s
+        self._host = bool(flags & FV_HOST)
         opt = Options()
-        opt.stream = ctypes.c_void_p(s.cuda_stream)
+        if self._host:
+            # the host evaluator needs no device, stream or device allocator
+            self._device, self._stream_obj = None, None
+            use_torch_allocator = False
+        else:
+            self._device = torch.cuda.current_device()
+            # a stream of its own (default priority): the engine captures its
+            # recursive round as a graph, which the legacy null stream cannot do
+            s = stream if stream is not None else _engine_stream(torch, self._device)
+            self._stream_obj = s
+            opt.stream = ctypes.c_void_p(s.cuda_stream)
         opt.flags = flags
         if tuning is not None:
             self._tuning = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
@@ -270,7 +277,7 @@ class Engine:
             opt.predictor = self._predictor.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
         self._live = {}
         if use_torch_allocator:
-            dev, handle = self._device, s.cuda_stream
+            dev, handle = self._device, self._stream_obj.cuda_stream
 
             def _alloc(nbytes, stream, user):
                 try:
@@ -342,8 +349,10 @@ class Engine:
             if len(col) != n:
                 raise ValueError("columns differ in length")
             if on_device:
-                if c == 0:   # the columns were produced on the caller's stream
+                if c == 0 and self._stream_obj is not None:   # produced on the caller's stream
                     self._stream_obj.wait_stream(torch.cuda.current_stream())
+                elif c == 0:
+                    torch.cuda.current_stream().synchronize()
                 t = col.contiguous()
                 if t.element_size() != 4:
                     raise ValueError("device columns must be 32-bit")

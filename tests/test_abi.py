@@ -101,7 +101,7 @@ def test_tuning_cache_roundtrip_on_host(tmp_path):
                  '"set_load": 0.5, "index_load": 0.25, "max_blocks": 4096, "ms": 3.5}}}')
     t = fv.tuning_load(str(p), "sg")
     assert t == {"radix_bits": 11, "fuse_dedup": 1, "set_load": 0.5, "index_load": 0.25, "max_blocks": 4096,
-                 "index_rebuild": 0, "index_sort": 0, "lookahead": 0}
+                 "index_rebuild": 0, "index_sort": 0, "lookahead": 0, "dedup_ranges": 0}
     assert fv.tuning_load(str(p), "other") is None
     assert fv.tuning_load(str(tmp_path / "missing.json"), "sg") is None
 

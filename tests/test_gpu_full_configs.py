@@ -22,12 +22,15 @@ def _digest(rows):
     return hashlib.sha256(np.ascontiguousarray(rows, dtype="<u4").tobytes()).hexdigest()
 
 
+MODES = {"plain": None, "tuned": {"radix_bits": 11, "fuse_dedup": 1}, "ranges": {"dedup_ranges": 1}}
+
+
 @pytest.mark.parametrize("name", sorted(MAKERS))
-@pytest.mark.parametrize("mode", ["plain", "tuned"])
+@pytest.mark.parametrize("mode", sorted(MODES))
 def test_full_size_matches_oracle_digest(name, mode):
     w = MAKERS[name]()
     ref = DIGESTS[name]
-    tuning = {"radix_bits": 11, "fuse_dedup": 1} if mode == "tuned" else None
+    tuning = MODES[mode]
     got, stats, deltas, _ = fv.evaluate(w.program, w.edb, relations=list(w.idb), tuning=tuning)
     for rel, d in ref["relations"].items():
         assert len(got[rel]) == d["count"], rel

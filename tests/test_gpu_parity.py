@@ -31,6 +31,8 @@ TUNINGS = {
     "index_sort": {"index_sort": 2},     # every join index built by sorting
     "index_count": {"index_sort": 1},    # every join index built by counting
     "no_lookahead": {"lookahead": 1},    # every round waits for the one before
+    "ranges": {"dedup_ranges": 1},       # Algorithm 2's difference over per-column indices of full
+    "ranges_count": {"dedup_ranges": 1, "index_sort": 1},
 }
 
 

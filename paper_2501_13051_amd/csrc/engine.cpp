@@ -818,7 +818,13 @@ bool Engine::ensure_capacity(bool dry) {
       // new arrays (a streaming copy) instead of a rebuild
       const bool keep = !ix.dirty && ix.rows_seen && want >= ix.rows_seen && ix.perm.p && ix.pslot.p;
       const u64 n = std::max<u64>(want, 1) * 4;
-      Buf np = alloc(n), ns = alloc(n);
+      Buf np = alloc(n), ns;
+      try {
+        ns = alloc(n);
+      } catch (...) {
+        release(np);
+        throw;
+      }
       if (keep) {
         hip(hipMemcpyAsync(np.p, ix.perm.p, ix.rows_seen * 4, hipMemcpyDeviceToDevice, stream_), "index copy");
         hip(hipMemcpyAsync(ns.p, ix.pslot.p, ix.rows_seen * 4, hipMemcpyDeviceToDevice, stream_), "index copy");
@@ -2306,12 +2312,17 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
     const u32 back = u32(0u - u32(u64(inst_) * batch_->stride));
     for (u32 c = 0; c < R.arity; ++c) {
       Buf t = M.alloc(n * 4);
-      M.hip(hipMemcpyAsync(t.p, batch_->cols[rel][c].as<u32>() + b, n * 4, hipMemcpyDeviceToDevice, M.stream_),
-            "slice copy");
-      M.launched(launch_add_u32(t.as<u32>(), n, back, M.stream_), "relabel back");
-      M.hip(hipMemcpyAsync(cols[c], t.p, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                           M.stream_), "export copy");
-      M.sync();
+      try {
+        M.hip(hipMemcpyAsync(t.p, batch_->cols[rel][c].as<u32>() + b, n * 4, hipMemcpyDeviceToDevice, M.stream_),
+              "slice copy");
+        M.launched(launch_add_u32(t.as<u32>(), n, back, M.stream_), "relabel back");
+        M.hip(hipMemcpyAsync(cols[c], t.p, n * 4, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             M.stream_), "export copy");
+        M.sync();
+      } catch (...) {
+        M.release(t);
+        throw;
+      }
       M.release(t);
     }
     return;
@@ -2384,6 +2395,13 @@ namespace fv {
 // to instance k's range is instance k's fixpoint.  Every operator then runs
 // as one launch over all instances, and an instance whose delta is empty
 // simply contributes no rows.
+BatchResult::~BatchResult() {
+  if (!merged) return;
+  if (merged->touched_device_) (void)hipStreamSynchronize(merged->stream_);
+  for (auto& rc : cols)
+    for (auto& b : rc) merged->release(b);
+}
+
 void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
   if (n == 0 || !es || !es[0]) throw Error(FV_EINVAL, "empty batch");
   Engine& E0 = *es[0];
@@ -2450,26 +2468,31 @@ void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
   // one gather launch per relation concatenates every instance's staged facts
   std::vector<GatherDesc> desc(n);
   Buf ddesc = M.alloc(size_t(n) * sizeof(GatherDesc));
-  for (size_t r = 0; r < M.rels_.size(); ++r) {
-    Relation& D = M.rels_[r];
-    u64 total = 0;
-    for (u32 k = 0; k < n; ++k) {
-      const Relation& S = es[k]->rels_[r];
-      desc[k] = GatherDesc{{S.stage[0].as<u32>(), S.stage[1].as<u32>(), S.stage[2].as<u32>()}, S.staged, total,
-                           u32(k * stride), 0};
-      total += S.staged;
+  try {
+    for (size_t r = 0; r < M.rels_.size(); ++r) {
+      Relation& D = M.rels_[r];
+      u64 total = 0;
+      for (u32 k = 0; k < n; ++k) {
+        const Relation& S = es[k]->rels_[r];
+        desc[k] = GatherDesc{{S.stage[0].as<u32>(), S.stage[1].as<u32>(), S.stage[2].as<u32>()}, S.staged, total,
+                             u32(k * stride), 0};
+        total += S.staged;
+      }
+      if (!total) continue;
+      for (u32 k = 0; k < n; ++k) es[k]->sync();   // instance copies are ordered on their own streams
+      for (u32 c = 0; c < D.arity; ++c) D.stage[c] = M.alloc(total * 4);
+      M.hip(hipMemcpyAsync(ddesc.p, desc.data(), size_t(n) * sizeof(GatherDesc), hipMemcpyHostToDevice, M.stream_),
+            "descriptor copy");
+      u32* outs[3] = {D.stage[0].as<u32>(), D.stage[1].as<u32>(), D.stage[2].as<u32>()};
+      M.launched(launch_gather_relabel(ddesc.as<GatherDesc>(), n, D.arity, outs, M.stream_), "gather");
+      M.sync();   // the descriptor buffer is reused by the next relation
+      D.staged = D.stage_cap = total;
+      D.has_rows = true;
+      for (u32 c = 0; c < D.arity; ++c) D.maxv[c] = u32(stride * n - 1);
     }
-    if (!total) continue;
-    for (u32 k = 0; k < n; ++k) es[k]->sync();   // instance copies are ordered on their own streams
-    for (u32 c = 0; c < D.arity; ++c) D.stage[c] = M.alloc(total * 4);
-    M.hip(hipMemcpyAsync(ddesc.p, desc.data(), size_t(n) * sizeof(GatherDesc), hipMemcpyHostToDevice, M.stream_),
-          "descriptor copy");
-    u32* outs[3] = {D.stage[0].as<u32>(), D.stage[1].as<u32>(), D.stage[2].as<u32>()};
-    M.launched(launch_gather_relabel(ddesc.as<GatherDesc>(), n, D.arity, outs, M.stream_), "gather");
-    M.sync();   // the descriptor buffer is reused by the next relation
-    D.staged = D.stage_cap = total;
-    D.has_rows = true;
-    for (u32 c = 0; c < D.arity; ++c) D.maxv[c] = u32(stride * n - 1);
+  } catch (...) {
+    M.release(ddesc);
+    throw;
   }
   M.release(ddesc);
   M.rules_ = E0.rules_;
@@ -2480,23 +2503,28 @@ void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
   // every relation sorted once in the merged id space; instance k's rows are
   // the run whose first column lies in [k * stride, (k + 1) * stride)
   Buf bounds = M.alloc((size_t(n) + 1) * 8);
-  B->cols.resize(M.rels_.size());
-  B->bounds.resize(M.rels_.size());
-  for (size_t r = 0; r < M.rels_.size(); ++r) {
-    Relation& R = M.rels_[r];
-    const u64 total = R.n_full;
-    u32* outc[3] = {nullptr, nullptr, nullptr};
-    for (u32 c = 0; c < R.arity; ++c) {
-      B->cols[r].push_back(M.alloc(std::max<u64>(total, 1) * 4));
-      outc[c] = B->cols[r][c].as<u32>();
+  try {
+    B->cols.resize(M.rels_.size());
+    B->bounds.resize(M.rels_.size());
+    for (size_t r = 0; r < M.rels_.size(); ++r) {
+      Relation& R = M.rels_[r];
+      const u64 total = R.n_full;
+      u32* outc[3] = {nullptr, nullptr, nullptr};
+      for (u32 c = 0; c < R.arity; ++c) {
+        B->cols[r].push_back(M.alloc(std::max<u64>(total, 1) * 4));
+        outc[c] = B->cols[r][c].as<u32>();
+      }
+      u64 got = 0;
+      if (total) M.export_rel(u32(r), outc, total, &got, true);
+      B->bounds[r].assign(size_t(n) + 1, 0);
+      M.launched(launch_bounds(outc[0], total, u32(stride), n, bounds.as<u64>(), M.stream_), "bounds");
+      M.hip(hipMemcpyAsync(B->bounds[r].data(), bounds.p, (size_t(n) + 1) * 8, hipMemcpyDeviceToHost, M.stream_),
+            "bounds readback");
+      M.sync();
     }
-    u64 got = 0;
-    if (total) M.export_rel(u32(r), outc, total, &got, true);
-    B->bounds[r].assign(size_t(n) + 1, 0);
-    M.launched(launch_bounds(outc[0], total, u32(stride), n, bounds.as<u64>(), M.stream_), "bounds");
-    M.hip(hipMemcpyAsync(B->bounds[r].data(), bounds.p, (size_t(n) + 1) * 8, hipMemcpyDeviceToHost, M.stream_),
-          "bounds readback");
-    M.sync();
+  } catch (...) {
+    M.release(bounds);
+    throw;
   }
   M.release(bounds);
   for (u32 k = 0; k < n; ++k) {

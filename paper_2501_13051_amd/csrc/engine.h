@@ -178,12 +178,15 @@ struct HostState;   // host evaluator state (host_engine.cpp)
 struct BatchResult {
   std::shared_ptr<Engine> merged;
   u64 stride = 0;
-  std::vector<std::vector<Buf>> cols;       // [relation][column], owned by `merged`
+  std::vector<std::vector<Buf>> cols;       // [relation][column], from `merged`'s allocator
   std::vector<std::vector<u64>> bounds;     // [relation][instance + 1]
   std::vector<u64> deltas;
+  ~BatchResult();                           // hands cols back through `merged`
 };
 
 class Engine {
+  friend struct BatchResult;
+
  public:
   explicit Engine(const fv_options* opt);
   ~Engine();

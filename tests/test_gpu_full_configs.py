@@ -38,3 +38,41 @@ def test_full_size_matches_oracle_digest(name, mode):
     assert deltas == ref["deltas"]
     # the per-round deltas count derived tuples only (input facts are seeds)
     assert stats["derived_tuples"] == sum(ref["deltas"])
+
+
+def _plain_traces():
+    """Join traces the plain engine logs on the transitive-closure,
+    same-generation, points-to and batched transitive-closure workloads --
+    the predictor's training data, as the benchmark collects it."""
+    rows = []
+    for w in (W.config_tc(), W.config_sg(), W.config_pointsto()):
+        *_, trace = fv.evaluate(w.program, w.edb, flags=fv.FV_LOG_JOINS, relations=list(w.idb), with_trace=True)
+        rows.append(trace)
+    engines = []
+    for x in W.batched_tc_instances():
+        e = fv.Engine(flags=fv.FV_LOG_JOINS)
+        e.relation("edge", 2)
+        e.relation("path", 2)
+        e.load("edge", x.edb["edge"])
+        e.program(x.program)
+        engines.append(e)
+    fv.run_batch(engines)
+    rows.append(engines[0].join_trace())
+    for e in engines:
+        e.close()
+    return np.concatenate(rows)
+
+
+def test_rdfs_full_size_learned_mode_matches_oracle_digest():
+    """Config 5 in its stated mode: the learned predictor on, trained (on the
+    GPU) from the plain engine's traces of the other four configurations."""
+    T = _plain_traces()
+    params, loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
+    assert np.isfinite(loss)
+    w = W.config_rdfs()
+    ref = DIGESTS["rdfs_20000000"]
+    got, stats, deltas, _ = fv.evaluate(w.program, w.edb, relations=["t"], flags=fv.FV_LEARNED, predictor=params)
+    assert len(got["t"]) == ref["relations"]["t"]["count"]
+    assert _digest(got["t"]) == ref["relations"]["t"]["sha256"]
+    assert deltas == ref["deltas"]
+    assert stats["derived_tuples"] == sum(ref["deltas"]) and stats["predicted_joins"] > 0

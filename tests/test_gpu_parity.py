@@ -385,6 +385,27 @@ def test_random_programs_with_failures_and_tiny_capacities(seed, monkeypatch):
     _check(prog, random_edb(rnd))
 
 
+def test_device_memory_is_handed_back():
+    """Contexts, including a batch's merged result, return every allocation
+    to the caller's allocator when they are destroyed."""
+    import gc
+    import torch
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    _check(W.SG_PROGRAM, {"edge": W.forest(4, 128, 0.05, seed=3)}, relations=["sg"])
+    insts = W.batched_tc_instances(n_instances=9, seed=5)
+    engines = _batch_engines(insts)
+    fv.run_batch(engines)
+    for w, e in zip(insts, engines):
+        assert np.array_equal(e.export("path"), oracle.evaluate(w.program, w.edb)["path"])
+    for e in engines:
+        e.close()
+    del engines
+    gc.collect()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+
+
 def test_batched_with_failures(monkeypatch):
     insts = W.batched_tc_instances(n_instances=16, seed=91)
     monkeypatch.setenv("FV_TEST_FAIL_ROUNDS", "2,3,6")
@@ -399,7 +420,8 @@ def test_batched_with_failures(monkeypatch):
 
 def _raw_tc_context(L, opt):
     """A TC program set up through the C ABI directly; returns the handle,
-    the path relation, the edges and the first failing status (0 if none)."""
+    the path relation, the edges, the status of the load (0 if it worked)
+    and the error text the load left."""
     import ctypes
     h = ctypes.c_void_p()
     rc = L.fv_ctx_create(ctypes.byref(h), ctypes.byref(opt) if opt is not None else None)
@@ -411,6 +433,7 @@ def _raw_tc_context(L, opt):
     cols = [np.ascontiguousarray(c, np.uint32) for c in edge]
     ptrs = (ctypes.c_void_p * 2)(cols[0].ctypes.data, cols[1].ctypes.data)
     rc = L.fv_load_columns(h, e.value, ptrs, len(cols[0]), 0)
+    err = L.fv_last_error(h)          # valid until the next call on the context
     keep = []
     for head, body, neq in fv.parse_program(W.TC_PROGRAM):
         def atom(a):
@@ -425,7 +448,7 @@ def _raw_tc_context(L, opt):
         r.n_body = len(body)
         r.n_neq = 0
         assert L.fv_add_rule(h, ctypes.byref(r)) == 0
-    return h, p.value, edge, rc
+    return h, p.value, edge, rc, err
 
 
 def test_allocator_failure_is_enomem_and_the_context_stays_destroyable():
@@ -457,11 +480,11 @@ def test_allocator_failure_is_enomem_and_the_context_stays_destroyable():
         opt = fv.Options()
         opt.stream = ctypes.c_void_p(stream.cuda_stream)
         opt.dev_alloc, opt.dev_free = a, f
-        h, path, _, rc = _raw_tc_context(L, opt)
+        h, path, _, rc, err = _raw_tc_context(L, opt)
         if rc == 0:
             st = fv.Stats()
             rc = L.fv_run_fixpoint(h, ctypes.byref(st))
-        err = L.fv_last_error(h)
+            err = L.fv_last_error(h)
         if rc != 0:
             n = ctypes.c_uint64()
             assert L.fv_export(h, path, None, 0, ctypes.byref(n), 0) != 0   # a failed context refuses
@@ -482,7 +505,7 @@ def test_allocator_failure_is_enomem_and_the_context_stays_destroyable():
 def test_export_into_a_short_buffer_is_etrunc():
     import ctypes
     L = fv.lib()
-    h, path, edge, rc = _raw_tc_context(L, None)
+    h, path, edge, rc, _ = _raw_tc_context(L, None)
     assert rc == 0
     try:
         st = fv.Stats()

@@ -291,6 +291,23 @@ fv_status fv_mlp_predict(const fv_options* opt, const float* X, uint32_t n, cons
 fv_status fv_hll_ndv(const fv_options* opt, const uint32_t* const* cols, uint32_t n_cols, uint64_t n_rows,
                      int on_device, double* estimates);
 
+/* fv_hll_ndv for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same sketch kernels, with their registers and counters in a static device
+ * array of 128.1 KiB that each GPU the library runs on holds until the
+ * process ends.  cols is a host array of n_cols device column pointers
+ * (n_cols <= FV_HLL_NOALLOC_MAX_COLS, else FV_EINVAL), estimates a device
+ * array of n_cols doubles that receives the estimates.  Work is enqueued on
+ * `stream` (a hipStream_t; NULL = null stream) and not waited for: read the
+ * estimates after synchronising it.  The call allocates nothing, clears the
+ * array with kernels (never a memset) and may be captured into a graph.
+ * Calls on one GPU share its array, so calls that overlap on one GPU (two
+ * streams, or two graphs in flight) race; serialise them.  Errors: FV_EINVAL,
+ * FV_EHIP (fv_global_error() tells which). */
+#define FV_HLL_NOALLOC_MAX_COLS 8u
+fv_status fv_hll_ndv_noalloc(const uint32_t* const* cols, uint32_t n_cols, uint64_t n_rows, double* estimates,
+                             void* stream);
+
 /* Number of tuples currently in a relation (after the fixpoint: its full
  * version; before: the rows loaded so far, duplicates included). */
 fv_status fv_relation_size(fv_ctx* ctx, fv_rel rel, uint64_t* n_rows);

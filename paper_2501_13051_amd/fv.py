@@ -33,7 +33,7 @@ EXPORTED = ("fv_ctx_create", "fv_ctx_destroy", "fv_last_error", "fv_relation_cre
             "fv_load_columns", "fv_add_rule", "fv_run_fixpoint", "fv_relation_size", "fv_export",
             "fv_delta_sizes", "fv_profile", "fv_run_batch", "fv_autotune", "fv_tuning_load",
             "fv_global_error", "fv_mlp_grad", "fv_mlp_train", "fv_mlp_predict", "fv_join_trace",
-            "fv_hll_ndv")
+            "fv_hll_ndv", "fv_hll_ndv_noalloc")
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -134,6 +134,7 @@ def lib():
         L.fv_mlp_train.argtypes = [opt, vp, vp, u32, u32, ctypes.c_float, u64, ctypes.c_int, vp, vp]
         L.fv_mlp_predict.argtypes = [opt, vp, u32, vp, vp]
         L.fv_hll_ndv.argtypes = [opt, ctypes.POINTER(vp), u32, u64, ctypes.c_int, vp]
+        L.fv_hll_ndv_noalloc.argtypes = [ctypes.POINTER(vp), u32, u64, vp, vp]
         L.fv_join_trace.argtypes = [vp, vp, u32, ctypes.POINTER(u32)]
         for name in EXPORTED:
             if name not in ("fv_ctx_destroy", "fv_last_error", "fv_global_error"):
@@ -599,6 +600,26 @@ def hll_ndv(cols):
     out = np.zeros(len(cols), np.float64)
     _mlp_check(lib().fv_hll_ndv(_call_options(), ptrs, len(cols), n, 1 if on_device else 0, out.ctypes.data))
     return out
+
+
+HLL_NOALLOC_MAX_COLS = 8
+
+
+def hll_ndv_noalloc(cols, out, stream=None):
+    """fv_hll_ndv_noalloc: sketch up to 8 device columns (torch 32-bit
+    tensors) into `out`, a float64 device tensor of len(cols), on `stream`
+    (default: the current stream).  Nothing is allocated and nothing waits."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    ptrs = (ctypes.c_void_p * max(1, len(cols)))()
+    n = len(cols[0]) if cols else 0
+    for c, col in enumerate(cols):
+        if len(col) != n or col.element_size() != 4 or not col.is_contiguous():
+            raise ValueError("columns must be contiguous 32-bit tensors of one length")
+        ptrs[c] = col.data_ptr()
+    if out.dtype != torch.float64 or out.numel() < len(cols):
+        raise ValueError("out must be a float64 tensor with one entry per column")
+    _mlp_check(lib().fv_hll_ndv_noalloc(ptrs, len(cols), n, out.data_ptr(), s.cuda_stream))
 
 
 def tuning_load(cache_path: str, key: str):

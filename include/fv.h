@@ -92,10 +92,9 @@ typedef struct {
   uint32_t index_rebuild;  /* 1: rebuild the join indices of derived relations from scratch every
                               round; 0: update them with the appended rows (default) */
   uint32_t index_sort;     /* join-index construction: 0 (default) radix sort of the rows by key
-                              slot for builds of at least 2^20 rows (and for updates of an index
-                              without row filter after a round that appended at least 2^20),
-                              counting by hash otherwise; 1 counting for every build and update;
-                              2 sorting for every build and update */
+                              slot for builds of at least 2^20 rows, counting by hash otherwise;
+                              1 counting for every build; 2 sorting for every build (updates of
+                              the indices of derived relations always count) */
   uint32_t lookahead;      /* 0 (default): enqueue each plain eager round before the previous
                               round's counters are read back, where the program allows it
                               (no join reads an index of a derived relation); 1: never */

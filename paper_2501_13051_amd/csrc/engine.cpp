@@ -107,9 +107,9 @@ Engine::~Engine() {
     release(R.newk); release(R.newk2); release(R.set);
   }
   for (auto& ix : indices_) {
-    release(ix.table); release(ix.perm); release(ix.pslot); release(ix.perm2); release(ix.pslot2);
-    release(ix.dcnt); release(ix.dsh);
+    release(ix.table); release(ix.perm); release(ix.pcap); release(ix.dcnt); release(ix.wl);
   }
+  release(moves_);
   for (auto& I : inters_) for (auto& b : I.col) release(b);
   flags_dev_ = Buf{};   // a view into ctr_dev_
   release(ctr_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
@@ -606,7 +606,7 @@ void Engine::plan_all() {
   for (auto& ix : indices_) ix.c_maxrun = next++;
   for (auto& ix : indices_) ix.c_full = next++;
   for (auto& ix : indices_) ix.c_rows = next++;
-  for (auto& ix : indices_) ix.c_rows_prev = next++;
+  for (auto& ix : indices_) ix.c_top = next++;
   for (auto& Rl : rels_) Rl.c_ones = next++;
   c_hll0_ = next;
   sketches_.clear();
@@ -657,8 +657,9 @@ void Engine::plan_all() {
   for (auto* plans : {&init_plans_, &delta_plans_})
     for (auto& p : *plans)
       for (auto& s : p.steps)
-        if (!s.select_only) { s.c_m = next++; s.c_t = next++; }
+        if (!s.select_only) { s.c_m = next++; s.c_t = next++; s.c_n = next++; }
   for (auto& I : inters_) I.ctr = next++;
+  for (auto& ix : indices_) { ix.c_wl = next++; ix.c_moves = next++; ix.c_mrows = next++; }
   // rows passing a sketch's filters: counted afresh by every sketch launch
   for (auto& sk : sketches_) sk.ctr_rows = next++;
   n_ctr_ = next;
@@ -670,7 +671,7 @@ bool Engine::ensure_capacity(bool dry) {
   // look-back status arrays and row-id scratch are sized for the largest
   // launch any round can make before capacities change again: a delta is at
   // most the previous round's new tuples, so new_cap bounds it
-  u64 max_probe = 1, max_rows = 1, sort_rows = 0;
+  u64 max_probe = 1, max_rows = 1, sort_rows = 0, moves_need = 0;
   auto plan_probe = [&](const Plan& p, bool initial) {
     const Relation& S = rels_[p.src_rel];
     const u64 n0 = initial ? S.n_full : std::max<u64>(S.n_delta, S.new_cap);
@@ -779,66 +780,83 @@ bool Engine::ensure_capacity(bool dry) {
     const bool oversized = (ix.keys_seen || ix.hinted) && ix.cap > 8 * need;
     if (ix.cap == 0 || ix.grow || double(keys) > 0.75 * double(ix.cap) || oversized) {
       if (dry) return true;
-      release(ix.table);
-      release(ix.dcnt);
-      release(ix.dsh);
-      ix.table = alloc(need * sizeof(Slot));
-      ix.dcnt = alloc(need * 4);
-      ix.dsh = alloc(need * 4);
-      launched(launch_fill_u32(ix.dcnt.as<u32>(), need, 0u, stream_), "index delta counts clear");
+      // an intact index of a derived relation that outgrows its table moves
+      // into a larger one (keys re-inserted with their runs; perm stays), a
+      // build is needed otherwise
+      const bool rehash = R.used_as_head && !ix.dirty && !ix.grow && ix.cap && ix.pcap.p && need > ix.cap &&
+                          !tune_.index_rebuild && !use_graph_;
+      Buf nt = alloc(need * sizeof(Slot)), np, nd, nw;
+      try {
+        if (R.used_as_head) {   // updated every round: region sizes, appended counts, work list
+          np = alloc(need * 4);
+          nd = alloc(need * 4);
+          nw = alloc(need * 4);
+        }
+      } catch (...) {
+        for (Buf* b : {&nt, &np, &nd}) release(*b);
+        throw;
+      }
+      if (rehash) {
+        launched(launch_index_rehash(ix.table.as<Slot>(), ix.pcap.as<u32>(), ix.cap, nt.as<Slot>(), np.as<u32>(), need,
+                                     ctr(ix.c_full), stream_),
+                 "index rehash");
+        rehashed_.push_back(u32(&ix - &indices_[0]));
+      }
+      for (Buf* b : {&ix.table, &ix.pcap, &ix.dcnt, &ix.wl}) release(*b);
+      ix.table = nt;
+      ix.pcap = np;
+      ix.dcnt = nd;
+      ix.wl = nw;
+      if (nd.p) launched(launch_fill_u32(ix.dcnt.as<u32>(), need, 0u, stream_), "index delta counts clear");
       ix.cap = need;
-      ix.dirty = true;
+      if (!rehash) ix.dirty = true;
       ix.grow = false;
     }
-    // Positions: the rows the index may hold after this round.  A derived
-    // relation's index gets 4x its last measured row count once it passes
-    // half its positions (or sits far below them), and every row the
-    // relation may hold before its first build; an update that still
-    // overflows raises the full flag and is rebuilt with more before the next
-    // round reads it.
+    // Positions.  A loaded relation's index holds exactly its rows.  A
+    // derived relation's index keeps each run in a region with room to grow
+    // and moves a run that outgrows it to fresh positions (twice its size),
+    // so it gets 4x the rows it may hold after this round: its measured rows
+    // plus its share of the round's new tuples.  When the positions in use
+    // pass half of it, it moves to an array of twice the size (the regions
+    // keep their place) or, when the index must be rebuilt anyway, the build
+    // packs the runs again.  An update that still runs out raises the full
+    // flag and the index is rebuilt with more before the next round reads it.
     u64 want = rows;
     bool realloc_perm = ix.perm_cap < rows;
     const u64 have = ix.rows_seen ? ix.rows_seen : (ix.hinted ? ix.rows_hint : 0);
     if (!R.used_as_head && ix.hinted) {
       want = std::max<u64>(ix.rows_hint, 1);
       realloc_perm = ix.perm_cap < want;
-    } else if (R.used_as_head && (have || ix.hinted)) {
-      want = std::min<u64>(rows, 4 * std::max<u64>(have, 4096));
-      if (!ix.rows_seen) want = std::min<u64>(rows, std::max<u64>(want, have + grow_rows));
-      realloc_perm = 2 * have > ix.perm_cap || ix.perm_cap > 16 * want || ix.perm_cap < have;
+    } else if (R.used_as_head) {
+      const double share =
+          ix.rows_seen && R.n_full ? std::min(1.0, double(ix.rows_seen) / double(R.n_full)) : 1.0;
+      const u64 base = ix.rows_seen ? ix.rows_seen : (have ? have + grow_rows : rows);
+      const u64 after = base + u64(share * double(R.new_cap));
+      want = 4 * std::max<u64>(after, 4096);
+      const u64 used = std::max(ix.top_seen, after);
+      realloc_perm = ix.perm_cap < 2 * used || ix.perm_cap > 32 * std::max<u64>(used, 4096);
     }
     if (ix.perm_grow) {
       want = std::max<u64>(want, 2 * ix.perm_cap);
       realloc_perm = true;
     }
+    want = std::min<u64>(want, u64(0xFFFFFFFFu));   // positions are 32-bit
     if (dry && (ix.perm_cap == 0 || realloc_perm)) return true;
     if (!dry) ix.perm_grow = false;
     if (!dry && (ix.perm_cap == 0 || realloc_perm)) {
-      // an intact index keeps its layout: the positions it holds move to the
-      // new arrays (a streaming copy) instead of a rebuild
-      const bool keep = !ix.dirty && ix.rows_seen && want >= ix.rows_seen && ix.perm.p && ix.pslot.p;
-      const u64 n = std::max<u64>(want, 1) * 4;
-      Buf np = alloc(n), ns;
-      try {
-        ns = alloc(n);
-      } catch (...) {
-        release(np);
-        throw;
-      }
-      if (keep) {
-        hip(hipMemcpyAsync(np.p, ix.perm.p, ix.rows_seen * 4, hipMemcpyDeviceToDevice, stream_), "index copy");
-        hip(hipMemcpyAsync(ns.p, ix.pslot.p, ix.rows_seen * 4, hipMemcpyDeviceToDevice, stream_), "index copy");
-      }
-      for (Buf* b : {&ix.perm, &ix.pslot, &ix.perm2, &ix.pslot2}) release(*b);
+      // an intact index keeps its layout: the positions in use move to the
+      // new array (a streaming copy) instead of a rebuild
+      const u64 used = R.used_as_head ? ix.top_seen : ix.rows_seen;
+      const bool keep = !ix.dirty && ix.rows_seen && ix.perm.p && used <= want;
+      Buf np = alloc(std::max<u64>(want, 1) * 4);
+      if (keep && used)
+        hip(hipMemcpyAsync(np.p, ix.perm.p, used * 4, hipMemcpyDeviceToDevice, stream_), "index copy");
+      release(ix.perm);
       ix.perm = np;
-      ix.pslot = ns;
-      if (R.used_as_head) {
-        ix.perm2 = alloc(n);
-        ix.pslot2 = alloc(n);
-      }
       ix.perm_cap = want;
       if (!keep) ix.dirty = true;
     }
+    if (R.used_as_head) moves_need = std::max<u64>(moves_need, ix.perm_cap / 32 + 1024);
     max_rows = std::max(max_rows, ix.cap);
     // Construction: a large build sorts (row, slot) words by slot (no
     // per-row atomics; see build_index), a small one counts by hashing.
@@ -855,14 +873,19 @@ bool Engine::ensure_capacity(bool dry) {
         sort_rows = std::max(sort_rows, R.cap);
       }
     }
-    // an update sorts the appended rows the same way when the last round
-    // appended at least 2^20 and the index keeps all of them (a filtered
-    // index takes a fraction of the rows, which the counting update skips
-    // for free while a sort would still pass over all of them); the words
-    // fit in new_cap words of scratch
+    // An update sorts the appended rows by slot when the last round appended
+    // at least 2^20 rows and the index keeps a good share of them (at least a
+    // quarter of the relation's rows; the counting update skips the rows
+    // outside a selective filter for free, while the sort would still pass
+    // over them): mostly distinct keys then cost random table and counter
+    // accesses per row, and a few hot keys serialise the counting update's
+    // atomics, where the sorted words are walked in slot order.  The words fit
+    // in new_cap words of scratch.
     u32 upd_shift = 0;
+    const double share = ix.rows_seen && R.n_full ? double(ix.rows_seen) / double(R.n_full) : 1.0;
     if (R.used_as_head &&
-        (tune_.index_sort == 2 || (tune_.index_sort == 0 && ix.nfilt == 0 && R.n_delta >= (u64(1) << 20)))) {
+        (tune_.index_sort == 2 ||
+         (tune_.index_sort == 0 && R.n_delta >= (u64(1) << 20) && (ix.nfilt == 0 || share >= 0.25)))) {
       const u32 slot_bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);
       const u32 shift = sort_passes(slot_bits, 8) * 8;
       if (shift + bits_for(std::max<u64>(R.new_cap, 1) - 1) <= 64) {
@@ -875,6 +898,12 @@ bool Engine::ensure_capacity(bool dry) {
       ix.sort_bits = sort_bits;
       ix.upd_shift = upd_shift;
     }
+  }
+  if (moves_cap_ < moves_need) {
+    if (dry) return true;
+    release(moves_);
+    moves_ = alloc(moves_need * sizeof(RunMove));
+    moves_cap_ = moves_need;
   }
   if (ixk_cap_ < sort_rows) {
     if (dry) return true;
@@ -977,6 +1006,14 @@ u64* Engine::ev_begin(int cls, bool single) {
   return nullptr;
 }
 
+// Drop a timing opened by ev_begin (a launch that will not be timed).
+void Engine::ev_cancel() {
+  if (ev_open_) ev_pool_.push_back(ev_open_);
+  ev_open_ = nullptr;
+  ev_is_open_ = false;
+  ev_stamp_ = -1;
+}
+
 void Engine::ev_end(int cls, double bytes, int kind, int ref0, int ref1, u64 aux) {
   if (!trace_ || !ev_is_open_) return;
   ev_is_open_ = false;
@@ -1055,6 +1092,52 @@ void Engine::collect_events(u64 upto, bool discard) {
         items = n;
         break;
       }
+      case 14: {   // index build: key columns read (in pe.bytes with the table), row ids written
+        items = C(pe.ref0);
+        bytes = pe.bytes + 4.0 * double(items);
+        break;
+      }
+      case 15: {   // update keys: key columns read, slot found, word written per appended row
+        const u64 appended = C(c_delta0_ + pe.ref0);
+        bytes = double(appended) * (4.0 * double(pe.aux) + 16 + 8);
+        items = appended;
+        break;
+      }
+      case 16: case 17: case 18: case 19: {   // sorted update steps: words in slot order
+        const u64 appended = C(c_delta0_ + pe.ref0);
+        if (pe.kind == 16) {          // runs: words read (with a neighbour), counters at run ends
+          bytes = double(appended) * 8;
+          items = appended;
+        } else if (pe.kind == 17) {   // reserve: words read; slot, counters, region per run head
+          bytes = double(appended) * 8;
+          items = appended;
+        } else if (pe.kind == 18) {   // move: listed old rows read and written
+          items = C(int(pe.aux & 0xFFFFFFFFu));
+          bytes = double(items) * 8;
+        } else {                      // fill: word read, slot and counters (in slot order), row id written
+          bytes = double(appended) * (8 + 4);
+          items = appended;
+        }
+        break;
+      }
+      case 10: case 11: case 12: case 13: {   // index update steps (see update_index)
+        const u64 appended = C(c_delta0_ + pe.ref0), touched = C(pe.ref1);
+        const double cols = double(pe.aux >> 32);
+        if (pe.kind == 10) {          // count: key columns of every appended row; per touched key slot + counters
+          bytes = double(appended) * 4 * cols + double(touched) * 24;
+          items = appended;
+        } else if (pe.kind == 11) {   // reserve: work list, counters, slot, region size per touched key
+          bytes = double(touched) * 36;
+          items = touched;
+        } else if (pe.kind == 12) {   // move: listed old rows read and written
+          items = C(int(pe.aux & 0xFFFFFFFFu));
+          bytes = double(items) * 8;
+        } else {                      // fill: key columns again, row id written; slot per touched key
+          bytes = double(appended) * (4 * cols + 4) + double(touched) * 16;
+          items = appended;
+        }
+        break;
+      }
       case 5: {   // difference + append: key read, set probe, column writes of survivors
         const u64 n = C(pe.ref0), d = C(pe.ref1);
         bytes = double(n) * 16 + double(d) * 4 * double(pe.aux);
@@ -1125,7 +1208,6 @@ void Engine::exec_plan(Plan& p) {
     const u32* pcol[kMaxCols] = {};
     RowRange src{};
     u64 probe_bound;
-    int probe_ctr = -1;
     if (k == 0) {
       const Relation& S = rels_[p.src_rel];
       for (u32 c = 0; c < S.arity; ++c) pcol[c] = S.col[c].as<u32>();
@@ -1140,7 +1222,6 @@ void Engine::exec_plan(Plan& p) {
       src.end_ctr = ctr(I.ctr);
       src.cap = I.cap;
       probe_bound = I.cap;
-      probe_ctr = I.ctr;
     }
     OutSpec o{};
     o.ncols = u32(s.out.size());
@@ -1203,13 +1284,14 @@ void Engine::exec_plan(Plan& p) {
       for (u32 f = 0; f < fp.n_filter; ++f) fp.filt[f] = s.wf[f];
       fp.out = o;
       fp.out_t = ctr(s.c_t);
+      fp.out_n = ctr(s.c_n);
       fp.join_out_stat = ctr(c_joinout_);
       fp.abort = flags + kFlagVoid;
       fp.overflow = flags;
       const int kf = kclass("join_onepass");
       fp.ts = ev_begin(kf, true);
       launched(launch_join_fused(fp, std::max<u64>(probe_bound, 1), stream_), "one-pass join launch");
-      ev_end(kf, 0, 7, probe_ctr, s.c_t, probe_bound);
+      ev_end(kf, 0, 7, s.c_n, s.c_t, probe_bound);
       continue;
     }
     ProbeParams pp{};
@@ -1234,6 +1316,7 @@ void Engine::exec_plan(Plan& p) {
     pp.m_cap = m_cap_;
     pp.out_m = ctr(s.c_m);
     pp.out_t = ctr(s.c_t);
+    pp.out_n = ctr(s.c_n);
     pp.st_m = st_a_.as<u64>();
     pp.st_t = st_b_.as<u64>();
     pp.ticket = ticket;
@@ -1244,7 +1327,7 @@ void Engine::exec_plan(Plan& p) {
     const int kp = kclass("join_probe");
     pp.ts = ev_begin(kp, true);
     launched(launch_probe(pp, std::max<u64>(probe_bound, 1), 0, stream_), "probe launch");
-    ev_end(kp, 0, 1, probe_ctr, s.c_m, probe_bound);
+    ev_end(kp, 0, 1, s.c_n, s.c_m, probe_bound);
 
     WriteParams wp{};
     for (int c = 0; c < kMaxCols; ++c) wp.pcol[c] = pcol[c];
@@ -1399,7 +1482,6 @@ void Engine::build_index(Index& ix) {
   p.table = ix.table.as<Slot>();
   p.cap = ix.cap;
   p.perm = ix.perm.as<u32>();
-  p.pslot = ix.pslot.as<u32>();
   p.perm_cap = ix.perm_cap;
   p.status = st_a_.as<u64>();
   p.ticket = ticket_dev_.as<u32>();
@@ -1410,6 +1492,10 @@ void Engine::build_index(Index& ix) {
   p.maxrun = ix.c_maxrun >= 0 ? ctr(ix.c_maxrun) : nullptr;
   p.full = ix.c_full >= 0 ? ctr(ix.c_full) : nullptr;
   p.rows = ix.c_rows >= 0 ? ctr(ix.c_rows) : nullptr;
+  if (R.used_as_head) {   // regions of exactly their runs, bump pointer past the last
+    p.pcap = ix.pcap.as<u32>();
+    p.top = ctr(ix.c_top);
+  }
   const int kc = kclass("index_build");
   ev_begin(kc);
   if (ix.sort_shift) {
@@ -1439,14 +1525,16 @@ void Engine::build_index(Index& ix) {
   } else {
     launched(launch_index_build(p, std::max<u64>(R.cap, 1), stream_), "index launch");
   }
-  ev_end(kc, 0, 0);
+  // algorithmic bytes: every row's key (and filter) columns read once, each
+  // indexed row id written once, the table cleared and scanned
+  ev_end(kc, double(R.n_full) * 4.0 * (ix.nkey + ix.nfilt) + double(ix.cap) * 32.0, 14, ix.c_rows);
   ix.dirty = false;
 }
 
 // Bring the join indices of derived relations up to date with the rows the
-// round appended: an update of the existing layout where the index is intact
-// and the round runs eagerly (a replayed graph cannot swap buffers), a full
-// build otherwise.
+// round appended (launch_index_update): only the keys that got rows are
+// touched.  Used for intact indices in eager rounds; a captured round
+// rebuilds them instead (a replayed graph cannot know which keys it touches).
 void Engine::update_index(Index& ix) {
   const Relation& R = rels_[ix.rel];
   IndexParams p{};
@@ -1462,63 +1550,85 @@ void Engine::update_index(Index& ix) {
   p.table = ix.table.as<Slot>();
   p.cap = ix.cap;
   p.perm = ix.perm.as<u32>();
-  p.pslot = ix.pslot.as<u32>();
   p.perm_cap = ix.perm_cap;
-  p.perm_out = ix.perm2.as<u32>();
-  p.pslot_out = ix.pslot2.as<u32>();
-  p.dcnt = ix.dcnt.as<u32>();
-  p.dsh = ix.dsh.as<u32>();
-  p.status = st_a_.as<u64>();
-  p.ticket = ticket_dev_.as<u32>();
-  p.epoch_base = epoch_base();
-  p.epoch_off = next_epoch();
   p.abort = flags_dev_.as<u32>();
-  p.abort2 = flags_dev_.as<u32>() + 2;
+  p.abort2 = flags_dev_.as<u32>() + kFlagSetFull;
   p.ndv = ctr(ix.c_ndv);
   p.maxrun = ctr(ix.c_maxrun);
   p.full = ctr(ix.c_full);
   p.rows = ctr(ix.c_rows);
-  p.rows_prev = ctr(ix.c_rows_prev);
-  const int kc = kclass("index_update");
-  ev_begin(kc);
-  if (ix.upd_shift) {
-    // sorted update: the appended rows' (row, slot) words, sorted by slot
-    const u64 dcap = std::max<u64>(R.new_cap, 1);
-    launched(launch_index_update_keys(p, dcap, ixk_a_.as<u64>(), ix.upd_shift, stream_), "index keys launch");
-    SortParams sp{};
-    sp.a = ixk_a_.as<u64>();
-    sp.b = ixk_b_.as<u64>();
-    sp.n_ctr = ctr(c_delta0_ + int(ix.rel));   // rows appended by the commit
-    sp.cap = dcap;
-    sp.bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);
-    sp.digit_bits = 8;
-    sp.max_blocks = tune_.max_blocks;
-    sp.hist = hist_dev_.as<u32>() + rels_.size() * kHistWords;
-    sp.status = st_sort_.as<u64>();
-    sp.ticket = ticket_dev_.as<u32>();
-    sp.epoch_base = epoch_base();
-    sp.abort = flags_dev_.as<u32>();
-    launched(launch_rs_hist(sp, stream_, true), "index hist launch");
-    u64* src = sp.a;
-    u64* dst = sp.b;
-    for (u32 pass = 0; pass < sort_passes(sp.bits, 8); ++pass) {
-      launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_), "index sort pass launch");
-      std::swap(src, dst);
+  p.pcap = ix.pcap.as<u32>();
+  p.top = ctr(ix.c_top);
+  p.dcnt = ix.dcnt.as<u32>();
+  p.wl = ix.wl.as<u32>();
+  p.wl_n = ctr(ix.c_wl);
+  p.moves = moves_.as<RunMove>();
+  p.moves_n = ctr(ix.c_moves);
+  p.moves_cap = moves_cap_;
+  p.moved_rows = ctr(ix.c_mrows);
+  const u64 dcap = std::max<u64>(R.new_cap, 1);
+  // each step is its own kernel class, timed by its own stamps (a step that
+  // gets no stamp slot goes untimed)
+  auto stamps = [&](const char* const* names, int kind0, u64* ts) {
+    for (int k = 0; k < 4; ++k) {
+      const int cls = kclass(names[k]);
+      ts[k] = reinterpret_cast<u64>(ev_begin(cls, true));
+      if (ts[k]) ev_end(cls, 0, kind0 + k, int(ix.rel), ix.c_wl, (u64(ix.nkey + ix.nfilt) << 32) | u64(ix.c_mrows));
+      else ev_cancel();
     }
-    launched(launch_index_update_runs(p, dcap, std::max<u64>(ix.perm_cap, 1), src, ix.upd_shift, stream_),
-             "index update launch");
-  } else {
-    launched(launch_index_update(p, std::max<u64>(R.new_cap, 1), std::max<u64>(ix.perm_cap, 1), stream_),
-             "index update launch");
+  };
+  u64 tsv[4];
+  u64* ts[4];
+  if (!ix.upd_shift) {
+    const char* names[4] = {"index_upd_count", "index_upd_reserve", "index_upd_move", "index_upd_fill"};
+    stamps(names, 10, tsv);
+    for (int k = 0; k < 4; ++k) ts[k] = reinterpret_cast<u64*>(tsv[k]);
+    launched(launch_index_update(p, dcap, ix.cap, ts, stream_), "index update launch");
+    return;
   }
-  ev_end(kc, 0, 0);
-  ix.pending_swap = true;
+  // many appended rows with short runs: sort the appended rows by slot first
+  {
+    const int kc = kclass("index_upd_keys");
+    ev_begin(kc);
+    launched(launch_index_update_keys(p, dcap, ixk_a_.as<u64>(), ix.upd_shift, stream_), "index keys launch");
+    ev_end(kc, 0, 15, int(ix.rel), -1, u64(ix.nkey + ix.nfilt));
+  }
+  SortParams sp{};
+  sp.a = ixk_a_.as<u64>();
+  sp.b = ixk_b_.as<u64>();
+  sp.n_ctr = ctr(c_delta0_ + int(ix.rel));   // rows appended by the commit
+  sp.cap = dcap;
+  sp.bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);
+  sp.digit_bits = 8;
+  sp.max_blocks = tune_.max_blocks;
+  sp.hist = hist_dev_.as<u32>() + rels_.size() * kHistWords;
+  sp.status = st_sort_.as<u64>();
+  sp.ticket = ticket_dev_.as<u32>();
+  sp.epoch_base = epoch_base();
+  sp.abort = flags_dev_.as<u32>();
+  const int kh = kclass("sort_hist");
+  ev_begin(kh);
+  launched(launch_rs_hist(sp, stream_, true), "index hist launch");
+  ev_end(kh, 0, 4, c_delta0_ + int(ix.rel), -1, dcap);
+  u64* src = sp.a;
+  u64* dst = sp.b;
+  const int kpass = kclass("sort_pass");
+  for (u32 pass = 0; pass < sort_passes(sp.bits, 8); ++pass) {
+    sp.ts = ev_begin(kpass, true);
+    launched(launch_rs_pass(sp, pass, src, dst, next_epoch(), stream_), "index sort pass launch");
+    ev_end(kpass, 0, 3, c_delta0_ + int(ix.rel), -1, dcap);
+    std::swap(src, dst);
+  }
+  const char* names[4] = {"index_upds_runs", "index_upds_reserve", "index_upd_move", "index_upds_fill"};
+  stamps(names, 16, tsv);
+  for (int k = 0; k < 4; ++k) ts[k] = reinterpret_cast<u64*>(tsv[k]);
+  launched(launch_index_update_sorted(p, dcap, src, ix.upd_shift, ts, stream_), "index update launch");
 }
 
 void Engine::build_indices(bool idb_only) {
   for (auto& ix : indices_) {
     if (idb_only && !rels_[ix.rel].used_as_head) continue;
-    if (idb_only && !tune_.index_rebuild && !use_graph_ && !capturing_ && !ix.dirty && ix.perm2.p) update_index(ix);
+    if (idb_only && !tune_.index_rebuild && !use_graph_ && !capturing_ && !ix.dirty && ix.pcap.p) update_index(ix);
     else build_index(ix);
   }
 }
@@ -1690,16 +1800,17 @@ void Engine::run_round(bool initial) {
   if (learned_) size_from_predictions(initial);
   choose_join_algorithms(initial);
   for (;;) {
-    for (auto& ix : indices_) ix.pending_swap = false;   // a failed attempt updated nothing
     if (ensure_capacity()) graph_dirty_ = true;
     if (phases_ + 2 >= (kEpochMask + 1) / kEpochStride - 96) graph_dirty_ = true;
-    bool any_dirty = false;
+    bool any_dirty = !rehashed_.empty();
     for (auto& ix : indices_) any_dirty = any_dirty || ix.dirty;
     if (any_dirty) {
       // an index whose storage grew holds nothing yet: rebuild it over the
-      // current full relation before any join reads it
+      // current full relation before any join reads it (and check that the
+      // indices moved to larger tables kept every key)
       begin_phase();
       std::vector<u32> built;
+      built.swap(rehashed_);
       for (u32 i = 0; i < indices_.size(); ++i)
         if (indices_[i].dirty) {
           build_index(indices_[i]);
@@ -1994,11 +2105,13 @@ void Engine::verify_builds(std::vector<u32> built) {
         ix.keys_seen = std::max<u64>(c[ix.c_ndv], 1);
         ix.rows_seen = c[ix.c_rows];
       }
+      ix.top_seen = c[ix.c_top];
     }
     if (!again) return;
     ensure_capacity();
     begin_phase();
     built.clear();
+    built.swap(rehashed_);
     for (u32 i = 0; i < indices_.size(); ++i)
       if (indices_[i].dirty) {
         build_index(indices_[i]);
@@ -2013,11 +2126,7 @@ void Engine::verify_builds(std::vector<u32> built) {
 // incomplete and is rebuilt larger before any join reads it.
 void Engine::note_index_builds() {
   for (auto& ix : indices_) {
-    if (ix.pending_swap) {   // the round's update wrote the new layout into the second buffers
-      std::swap(ix.perm, ix.perm2);
-      std::swap(ix.pslot, ix.pslot2);
-      ix.pending_swap = false;
-    }
+    ix.top_seen = ctr_host_[ix.c_top];
     const u64 full = ctr_host_[ix.c_full];
     if (full) {
       if (full & 1) ix.grow = true;

@@ -85,7 +85,10 @@ struct Index {
   int c_maxrun = -1;          // device counter: rows of the most frequent key
   int c_full = -1;            // device counter: 1 if the last build ran out of slots
   int c_rows = -1;            // device counter: rows the last build indexed
-  int c_rows_prev = -1;       // device counter: rows before the last update
+  int c_top = -1;             // device counter: first position of perm no run region uses
+  int c_wl = -1;              // device counter: slots an update touched (cleared every round)
+  int c_moves = -1;           // device counter: old-run chunks an update listed (cleared every round)
+  int c_mrows = -1;           // device counter: rows in those chunks (cleared every round)
   u64 keys_seen = 0;          // distinct keys found by the last complete build
   u64 rows_seen = 0;          // rows indexed by the last complete build or update
   u64 keys_hint = 0;          // before the first build: estimated distinct keys (sketch)
@@ -93,12 +96,11 @@ struct Index {
   bool hinted = false;
   bool grow = false;          // the last build ran out of slots: rebuild larger
   bool perm_grow = false;     // the last build ran out of positions: rebuild with more
-  Buf table, perm, pslot;     // slots; row ids grouped by key; each position's slot
-  Buf perm2, pslot2;          // targets of an incremental update (swapped in after it)
-  Buf dcnt, dsh;              // per slot: rows appended this round, and their prefix
+  Buf table, perm;            // slots; row ids grouped by key (runs in regions of perm)
+  Buf pcap, dcnt, wl;         // per slot: region size, rows appended this round; touched slots
   u64 cap = 0, perm_cap = 0;
+  u64 top_seen = 0;           // host mirror of the bump pointer after the last round
   bool dirty = true;          // storage (re)allocated since the last build
-  bool pending_swap = false;  // an update into perm2/pslot2 was enqueued this round
   u32 sort_shift = 0;         // nonzero: built by sorting (row << sort_shift | slot) words
   u32 sort_bits = 0;          //   over this many slot bits
   u32 upd_shift = 0;          // nonzero: updated by sorting the appended rows' (row << upd_shift | slot) words
@@ -118,6 +120,7 @@ struct Step {
   int out_buf = -1;           // intermediate id, or -1: head relation's new keys
   u32 head_rel = 0;
   int c_m = -1, c_t = -1;     // device counters for this join's sizes
+  int c_n = -1;               // device counter: probe rows the join read (traces)
   int c_pred = -1;            // device counter: predicted output size (learned mode)
   int hll = -1;               // HLL sketch of the probe key (step 0, learned/logging modes)
   bool fused = false;         // this round runs it as a presized one-pass join
@@ -264,6 +267,7 @@ class Engine {
   u64* ev_begin(int cls, bool single = false);
   hipEvent_t pooled_event();
   void ev_end(int cls, double bytes, int kind = 0, int ref0 = -1, int ref1 = -1, u64 aux = 0);
+  void ev_cancel();
   void collect_events(u64 upto, bool discard);   // launches of rounds up to `upto`
 
   u64* ctr(int i) { return ctr_dev_.as<u64>() + i; }
@@ -292,6 +296,9 @@ class Engine {
   u64 m_cap_ = 0;
   Buf st_a_, st_b_, st_sort_;
   Buf ixk_a_, ixk_b_;     // sorted index builds: (row, slot) words and the sort's second buffer
+  std::vector<u32> rehashed_;   // indices moved to larger tables, to be checked before a round reads them
+  Buf moves_;             // index updates: old-run chunks to copy (shared, updates run one by one)
+  u64 moves_cap_ = 0;
   u64 ixk_cap_ = 0;
   u64 st_cap_ = 0, st_sort_tiles_ = 0;
   u32 epoch_off_ = 1;     // next look-back offset within the current phase

@@ -360,6 +360,7 @@ __device__ __forceinline__ u32 take_ticket(u32* ticket, u32 ntiles, u32* lds_slo
 }
 
 __device__ __forceinline__ u64 min_u64(u64 a, u64 b) { return a < b ? a : b; }
+__device__ __forceinline__ u32 min_u32(u32 a, u32 b) { return a < b ? a : b; }
 
 __device__ __forceinline__ u32 launch_epoch(const u32* base, u32 off) { return (*base + off) & kEpochMask; }
 

@@ -96,6 +96,7 @@ struct ProbeParams {
   u64 m_cap;
   u64* out_m;            // matched probe rows
   u64* out_t;            // join output size before filters
+  u64* out_n;            // probe rows in the source range (nullable; traces)
   u64* st_m;             // look-back status arrays
   u64* st_t;
   u32* ticket;
@@ -145,6 +146,7 @@ struct FusedJoinParams {
   Filter filt[kMaxFilters];
   OutSpec out;
   u64* out_t;            // join output size before filters (added per wave)
+  u64* out_n;            // probe rows in the source range (nullable; traces)
   u64* join_out_stat;
   const u32* abort;      // nonzero: return at entry (a voided round), nullable
   u32* overflow;
@@ -269,6 +271,11 @@ constexpr u32 kHistWords = 6 * 2048;   // per relation: enough for 8 passes of 8
 constexpr u32 kMaxRadix = 2048;
 constexpr u32 kSortTile = 2048;
 
+// A run of perm positions moving to a fresh region (see launch_index_update).
+struct RunMove {
+  u32 from, to, count;
+};
+
 // Index build over rows [0, n) of a relation's columns: table of distinct
 // keys with runs into perm (the sorted-id array of Section 3, grouped by key).
 struct IndexParams {
@@ -291,37 +298,58 @@ struct IndexParams {
   u32 nfilt;             // rows indexed: only those with col[fcol[i]] == fval[i], i < nfilt
   u32 fcol[2];
   u32 fval[2];
-  // Every indexed position also records the slot of its key (pslot), so
-  // that an incremental update can shift old runs without looking keys up.
-  u32* pslot;
-  u64 perm_cap;          // positions available in perm / pslot (and their update copies)
-  // Incremental update (launch_index_update): `src` is the range of rows
-  // appended since the last build or update; the old layout (perm, pslot)
-  // is rewritten into (perm_out, pslot_out) with room for the new rows.
-  u32* perm_out;
-  u32* pslot_out;
-  u32* dcnt;             // per slot: appended rows (zero between updates)
-  u32* dsh;              // per slot: appended rows of all earlier slots
-  u64* rows_prev;        // rows indexed before the update
+  u64 perm_cap;          // positions available in perm
+  // Incremental updates (launch_index_update; derived relations): `src` is
+  // the range of rows appended by the round.  Each slot's run lives in a
+  // region of pcap[s] positions; the appended rows go after the run's old
+  // rows, and a run that outgrows its region moves to a fresh region at the
+  // bump pointer *top (the old region is left unused until the next build).
+  u32* pcap;             // per slot: positions of its region (a build sets the run's count)
+  u64* top;              // first position of perm no region uses (set by a build)
+  u32* dcnt;             // per slot: rows appended this round (zero between updates)
+  u32* wl;               // slots that got rows this round (the update's work list)
+  u64* wl_n;             // its length (zero before the update)
+  RunMove* moves;        // old runs to copy into their new regions, in chunks
+  u64* moves_n;          // chunks listed (zero before the update)
+  u64 moves_cap;
+  u64* moved_rows;       // rows in the listed chunks (nullable; traces)
   const u32* abort2;     // a second flag that cancels an update (set-full round)
+  u64* ts;               // trace timing slot of the launch (see ktime_start), nullable
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
-int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, void* stream);
+// Incremental update over the appended rows, four launches on one stream:
+// count the appended rows per key (inserting new keys) and list the touched
+// slots; give every touched run room for its appended rows (a run that
+// outgrows its region gets one of twice its new size at the bump pointer,
+// short runs copied on the spot, long ones listed in chunks); copy the listed
+// chunks; place the appended rows after each key's old rows.  No slot or row
+// that the round did not touch is read or written.  ts[0..3] time the four
+// launches (nullable).
+int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 wl_cap, u64* const* ts, void* stream);
+// The same update for many appended rows with mostly distinct keys, after
+// sorting them by slot: launch_index_update_keys writes the appended rows'
+// words (row - begin) << row_shift | slot (inserting new keys); the caller
+// radix-sorts them over the slot bits; launch_index_update_sorted derives
+// per-slot counts from run boundaries, reserves room per run head, copies
+// listed old runs, places the appended rows and clears the counts, walking
+// the table in slot order.  ts[0..3] time the runs, reserve, move and fill
+// launches (nullable).
+int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, void* stream);
+// Move an index into a larger table (tab, pcap of cap slots, cleared here):
+// keys, runs and regions carried over, perm untouched; bit 0 of *full (also
+// cleared here) reports a key that found no slot.
+int launch_index_rehash(const Slot* old_tab, const u32* old_pcap, u64 old_cap, Slot* tab, u32* pcap, u64 cap,
+                        u64* full, void* stream);
+int launch_index_update_sorted(const IndexParams& p, u64 delta_rows_cap, const u64* sorted, u32 row_shift,
+                               u64* const* ts, void* stream);
 // Sorted build, in three steps on one stream: launch_index_slotkeys clears
 // the table and writes keys[r] = r << row_shift | slot for rows r < n of the
 // source (slot = cap for rows outside the filter); the caller radix-sorts
 // keys over bits [0, row_shift) (row_shift a multiple of the digit width);
-// launch_index_runs turns the sorted words into perm, pslot, counts and
-// starts.  keys holds rows_cap words.
+// launch_index_runs turns the sorted words into perm, counts and starts.
+// keys holds rows_cap words.
 int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, void* stream);
 int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32 row_shift, void* stream);
-// Sorted update, the same way: launch_index_update_keys writes the words of
-// the appended rows (relative row ids) without clearing anything; the caller
-// sorts them; launch_index_update_runs counts, shifts the old runs and
-// places the appended rows into perm_out / pslot_out.
-int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, void* stream);
-int launch_index_update_runs(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, const u64* sorted,
-                             u32 row_shift, void* stream);
 
 int launch_fill_u64(u64* p, u64 n, u64 value, void* stream);
 int launch_fill_u32(u32* p, u64 n, u32 value, void* stream);

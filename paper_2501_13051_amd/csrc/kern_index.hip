@@ -1,14 +1,16 @@
-// Join-index construction and column utilities.
+// Join-index construction and maintenance, and column utilities.
 //
 // The join index of a relation on a key (one or two columns) is the hybrid
 // index of Section 3: an open-addressing table that holds each distinct key
 // once (run-length encoding of the key column, which keeps repeated values
 // from piling into long collision chains) with the value (start, count) into
-// a row-id array in which the rows of one key are contiguous.  It is built
-// without a sort: count rows per distinct key in the table, exclusive-scan the
-// counts over the table to get each run's start, then scatter row ids into
-// their runs.  Row order inside a run is unspecified, which joins do not
-// observe.
+// a row-id array (perm) in which the rows of one key are contiguous.  A build
+// either counts rows per distinct key in the table, exclusive-scans the counts
+// over the table to get each run's start and scatters the row ids into their
+// runs, or (large builds) sorts (row, slot) words by slot as Section 3 sorts
+// its key column.  Row order inside a run is unspecified, which joins do not
+// observe.  Indices of derived relations are then updated every round with
+// the rows the round appended, touching only the keys that got rows.
 #include "fv_device.h"
 
 namespace fv {
@@ -27,6 +29,10 @@ __device__ __forceinline__ u64 row_key(const IndexParams& p, u64 row) {
   const u32 a = p.col[p.keycol[0]][row];
   if (p.nkey == 2) return (u64(a) << 32) | u64(p.col[p.keycol[1]][row]);
   return u64(a);
+}
+
+__global__ void k_fill_u32_idx(u32* p, u64 n) {
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += u64(gridDim.x) * blockDim.x) p[i] = 0u;
 }
 
 __global__ void k_idx_clear(Slot* tab, u64 cap, const u32* abort, u64* ndv, u64* maxrun, u64* full, u64* rows) {
@@ -80,19 +86,23 @@ __device__ __forceinline__ u32 lds_map_add(IdxLds& m, u64 key, u32& rank) {
   return h;
 }
 
-// kInc: an update over the appended rows, counting into dcnt; block 0 also
-// saves the old row count and clears the statistics the scan recomputes.
-template <bool kInc>
+// Group the indexed rows of a tile by key in the block's map.
+__device__ __forceinline__ void map_tile(const IndexParams& p, IdxLds& m, u64 begin, u64 n, u64 tile,
+                                         u32* ent, u32* rank) {
+  const u64 r0 = tile * kIdxTile + threadIdx.x;
+#pragma unroll
+  for (u32 k = 0; k < kIdxItems; ++k) {
+    const u64 r = r0 + u64(k) * kBlock;
+    ent[k] = ~0u;
+    rank[k] = 0;
+    if (r < n && row_indexed(p, begin + r)) ent[k] = lds_map_add(m, row_key(p, begin + r), rank[k]);
+  }
+}
+
+// Build, step 1: rows per distinct key, counted into the table.
 __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
   __shared__ IdxLds m;
   if (p.abort && *p.abort) return;
-  if (kInc && p.abort2 && *p.abort2) return;
-  if (kInc && blockIdx.x == 0 && threadIdx.x == 0) {
-    *p.rows_prev = *p.rows;
-    *p.rows = 0;
-    *p.ndv = 0;
-    *p.maxrun = 0;
-  }
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
@@ -100,15 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
   for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     lds_map_clear(m);
     __syncthreads();
-    const u64 r0 = tile * kIdxTile + threadIdx.x;
-#pragma unroll
-    for (u32 k = 0; k < kIdxItems; ++k) {
-      const u64 r = r0 + u64(k) * kBlock;
-      if (r < n && row_indexed(p, begin + r)) {
-        u32 rank;
-        (void)lds_map_add(m, row_key(p, begin + r), rank);
-      }
-    }
+    u32 ent[kIdxItems], rank[kIdxItems];
+    map_tile(p, m, begin, n, tile, ent, rank);
     __syncthreads();
     for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
       const u32 c = m.cnt[e];
@@ -121,26 +124,23 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
         if (p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
         continue;
       }
-      atomicAdd(kInc ? &p.dcnt[h] : &p.table[h].count, c);
+      atomicAdd(&p.table[h].count, c);
     }
     __syncthreads();
   }
 }
 
-// Exclusive scan over the table in slot order (look-back across tiles).
-// Build: start <- prefix of counts, count <- 0 (it becomes the fill cursor),
-// or count kept (kKeep: the sorted build has already placed the rows).
-// Update (kInc): dsh <- prefix of the appended counts, start += dsh, dcnt <- 0
-// (kept with kKeep: the sorted update still needs it); count keeps the old
-// rows, so the fill appends after them.  Both recompute the distinct keys,
-// longest run and rows of the result.
-template <bool kInc, bool kKeep = false>
+// Build, step 2: exclusive scan over the table in slot order (look-back
+// across tiles): start <- prefix of counts, and count <- 0 (it becomes the
+// fill cursor) or kept (kKeep: the sorted build has already placed the rows).
+// Each run's region is exactly its rows (pcap), the bump pointer starts past
+// the last run, and the distinct keys, longest run and rows are recomputed.
+template <bool kKeep>
 __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kBlock / kWave + 1];
   __shared__ u64 s_excl;
   if (p.abort && *p.abort) return;
-  if (kInc && p.abort2 && *p.abort2) return;
   const u32 epoch = launch_epoch(p.epoch_base, p.epoch_off);
   const u32 ntiles = u32((p.cap + kScanTile - 1) / kScanTile);
   if (blockIdx.x >= participants(ntiles)) return;
@@ -149,24 +149,20 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
     if (tile >= ntiles) break;
     const u64 s0 = u64(tile) * kScanTile + u64(threadIdx.x) * 4;
     u32 c[4];
-    u32 mine = 0, keys = 0, longest = 0, total = 0;
+    u32 mine = 0, keys = 0, longest = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const bool in = s0 + k < p.cap;
-      const u32 old = in ? p.table[s0 + k].count : 0u;
-      c[k] = kInc ? (in ? p.dcnt[s0 + k] : 0u) : old;
-      const u32 all = kInc ? old + c[k] : old;
+      c[k] = s0 + k < p.cap ? p.table[s0 + k].count : 0u;
       mine += c[k];
-      total += all;
-      keys += all ? 1u : 0u;
-      longest = all > longest ? all : longest;
+      keys += c[k] ? 1u : 0u;
+      longest = c[k] > longest ? c[k] : longest;
     }
     if (p.ndv) {
       const u32 wk = wave_sum(keys);
       if (lane_id() == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
     }
     if (p.rows) {
-      const u64 wr = wave_sum(u64(total));
+      const u64 wr = wave_sum(u64(mine));
       if (lane_id() == 0 && wr) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wr);
     }
     if (p.maxrun) {
@@ -199,35 +195,28 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       if (s0 + k < p.cap) {
-        if (kInc) {
-          p.dsh[s0 + k] = u32(run);
-          if (!kKeep) p.dcnt[s0 + k] = 0u;
-          p.table[s0 + k].start += u32(run);
-        } else {
-          p.table[s0 + k].start = u32(run);
-          if (!kKeep) p.table[s0 + k].count = 0u;
-        }
+        p.table[s0 + k].start = u32(run);
+        if (!kKeep) p.table[s0 + k].count = 0u;
+        if (p.pcap) p.pcap[s0 + k] = c[k];
       }
       run += c[k];
     }
+    if (tile == ntiles - 1 && threadIdx.x == 0 && p.top) *p.top = s_excl + tot;
     __syncthreads();
   }
 }
 
-// Scatter row ids into their key's run: the tile's rows are grouped in the
-// LDS map again, one global atomic per distinct key reserves the group's
-// places in the run, and each row takes the place of its rank in the group.
-template <bool kInc>
+// Build, step 3: scatter row ids into their key's run: the tile's rows are
+// grouped in the LDS map again, one global atomic per distinct key reserves
+// the group's places in the run, and each row takes the place of its rank in
+// the group.
 __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
   __shared__ IdxLds m;
   if (p.abort && *p.abort) return;
-  if (kInc && p.abort2 && *p.abort2) return;
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
   const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
-  u32* perm = kInc ? p.perm_out : p.perm;
-  u32* pslot = kInc ? p.pslot_out : p.pslot;
   if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
   if (*p.rows > p.perm_cap) {   // the runs would not fit: flag it, write nothing
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
@@ -236,15 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
   for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     lds_map_clear(m);
     __syncthreads();
-    const u64 r0 = tile * kIdxTile + threadIdx.x;
     u32 ent[kIdxItems], rank[kIdxItems];
-#pragma unroll
-    for (u32 k = 0; k < kIdxItems; ++k) {
-      const u64 r = r0 + u64(k) * kBlock;
-      ent[k] = ~0u;
-      rank[k] = 0;
-      if (r < n && row_indexed(p, begin + r)) ent[k] = lds_map_add(m, row_key(p, begin + r), rank[k]);
-    }
+    map_tile(p, m, begin, n, tile, ent, rank);
     __syncthreads();
     for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
       const u32 c = m.cnt[e];
@@ -252,7 +234,6 @@ __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
       const u64 h = index_slot_of(p.table, mask, m.key[e]);
       // a key whose insert failed has no run: the host rebuilds a larger table
       m.pos[e] = h == kNoSlot ? ~0u : p.table[h].start + atomicAdd(&p.table[h].count, c);
-      m.key[e] = h;   // the slot, for pslot (the map is not probed again)
     }
     __syncthreads();
 #pragma unroll
@@ -260,26 +241,365 @@ __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
       if (ent[k] == ~0u) continue;
       const u32 base = m.pos[ent[k]];
       if (base == ~0u) continue;
-      perm[base + rank[k]] = u32(begin + r0 + u64(k) * kBlock);
-      pslot[base + rank[k]] = u32(m.key[ent[k]]);
+      p.perm[base + rank[k]] = u32(begin + tile * kIdxTile + threadIdx.x + u64(k) * kBlock);
     }
     __syncthreads();
   }
 }
 
-// Update: old position i of slot s moves to i + dsh[s] (runs keep their
-// order and shift right by the rows appended to earlier slots).
-__global__ __launch_bounds__(kBlock) void k_idx_move(IndexParams p) {
+// A larger table for an intact index of a derived relation: every key of the
+// old table is inserted again with its run and region (the runs stay where
+// they are in perm), so the index need not be rebuilt.  A key that finds no
+// slot raises bit 0 of the full flag (the index is then rebuilt).
+__global__ __launch_bounds__(kBlock) void k_idx_rehash(const Slot* __restrict__ old_tab,
+                                                        const u32* __restrict__ old_pcap, u64 old_cap, Slot* tab,
+                                                        u32* pcap, u64 cap, u64* full) {
+  const u64 mask = cap - 1;
+  for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < old_cap; i += u64(gridDim.x) * kBlock) {
+    const Slot sl = old_tab[i];
+    if (sl.key == kEmptyKey) continue;
+    const u64 h = index_insert(tab, mask, sl.key);
+    if (h == kNoSlot) {
+      atomicOr(reinterpret_cast<unsigned long long*>(full), 1ull);
+      continue;
+    }
+    tab[h].start = sl.start;
+    tab[h].count = sl.count;
+    pcap[h] = old_pcap[i];
+  }
+}
+
+// ------------------------------------------------------------------ update
+// Update, step 1: the appended rows per key, grouped per tile in LDS, added
+// to dcnt (new keys are inserted into the table with an empty run); a slot
+// whose dcnt was zero joins the work list (one atomic per wave).
+__global__ __launch_bounds__(kBlock) void k_upd_count(IndexParams p) {
+  __shared__ IdxLds m;
+  ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
-  if (*p.rows > p.perm_cap) return;   // flagged by the fill
-  if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
-  const u64 n = *p.rows_prev;
-  for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
-    const u32 s = p.pslot[i];
-    const u64 j = i + p.dsh[s];
-    p.perm_out[j] = p.perm[i];
-    p.pslot_out[j] = s;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 mask = p.cap - 1;
+  const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
+  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    lds_map_clear(m);
+    __syncthreads();
+    u32 ent[kIdxItems], rank[kIdxItems];
+    map_tile(p, m, begin, n, tile, ent, rank);
+    __syncthreads();
+    // kLdsMap / kBlock steps for every thread: the wave's ballot below
+    // always has all its lanes
+    for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
+      const u32 c = m.cnt[e];
+      bool push = false;
+      u64 h = kNoSlot;
+      if (c && !(__hip_atomic_load(p.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1)) {
+        h = index_insert(p.table, mask, m.key[e]);
+        if (h == kNoSlot) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
+        else push = atomicAdd(&p.dcnt[h], c) == 0u;
+      }
+      const u64 ball = __ballot(push);
+      if (ball) {
+        u64 base = 0;
+        if (lane_id() == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(p.wl_n), (unsigned long long)__popcll(ball));
+        base = __shfl(base, 0, kWave);
+        const u64 at = base + __popcll(ball & ((1ull << lane_id()) - 1));
+        if (push && at < p.cap) p.wl[at] = u32(h);
+      }
+    }
+    __syncthreads();
+  }
+  ktime_end(p.ts);
+}
+
+// Copy the old runs of the lanes that want one (at most kInlineCopy rows
+// each) with the whole wave: one run at a time, its rows spread over the
+// lanes, so each copy is one coalesced load and store.  Every lane of the
+// wave must call this.
+constexpr u32 kInlineCopy = 64;
+__device__ __forceinline__ void wave_copy_runs(u32* perm, bool want, u32 from, u64 to, u32 count) {
+  u64 ball = __ballot(want);
+  while (ball) {
+    const int l = __ffsll((unsigned long long)ball) - 1;
+    ball &= ball - 1;
+    const u32 f = __shfl(from, l, kWave);
+    const u64 t = __shfl(to, l, kWave);
+    const u32 c = __shfl(count, l, kWave);
+    if (u32(lane_id()) < c) perm[t + lane_id()] = perm[f + lane_id()];
+  }
+}
+
+// Update, step 2: per touched slot, room for its appended rows.  A run whose
+// old rows plus appended rows exceed its region moves to a region of twice
+// that size taken from the bump pointer (one atomic per wave); its old rows
+// are copied right away when there are at most kInlineCopy of them, else
+// listed in chunks of kMoveChunk for step 3.  The slot's appended count is
+// cleared (also when the update fails, so that the rebuild finds it zero),
+// and the index statistics grow by the round's rows and keys.
+constexpr u32 kMoveChunk = 1u << 16;
+__global__ __launch_bounds__(kBlock) void k_upd_reserve(IndexParams p) {
+  ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  const u64 n = min_u64(*p.wl_n, p.cap);   // the work list holds at most one entry per slot
+  const bool failed = (*p.full & 1) != 0;   // keys missing: the index is rebuilt, only clear dcnt
+  // every thread of a block runs the same number of steps (the wave
+  // operations below need all lanes)
+  for (u64 b0 = u64(blockIdx.x) * kBlock; b0 < n; b0 += u64(gridDim.x) * kBlock) {
+    const u64 i = b0 + threadIdx.x;
+    const bool valid = i < n;
+    u32 s = 0, d = 0, c_old = 0;
+    u64 need = 0, newcap = 0;
+    if (valid) {
+      s = p.wl[i];
+      d = p.dcnt[s];
+      p.dcnt[s] = 0u;
+      c_old = p.table[s].count;
+      need = u64(c_old) + d;
+      if (!failed && need > p.pcap[s]) newcap = need < 8 ? 16 : 2 * need;
+    }
+    // bump allocation of the new regions, one atomic per wave
+    const u64 incl = wave_inclusive_sum(newcap);
+    const u64 wtot = __shfl(incl, kWave - 1, kWave);
+    u64 wbase = 0;
+    if (lane_id() == 0 && wtot) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(p.top), (unsigned long long)wtot);
+    wbase = __shfl(wbase, 0, kWave);
+    const u64 start_new = wbase + incl - newcap;
+    const bool fits = newcap && start_new + newcap <= p.perm_cap;
+    const u32 from = fits ? p.table[s].start : 0u;
+    wave_copy_runs(p.perm, fits && c_old <= kInlineCopy, from, start_new, c_old);
+    if (newcap) {
+      if (!fits) {
+        atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);   // rebuilt with more positions
+      } else {
+        if (c_old > kInlineCopy) {
+          const u32 chunks = (c_old + kMoveChunk - 1) / kMoveChunk;
+          const u64 at = atomicAdd(reinterpret_cast<unsigned long long*>(p.moves_n), (unsigned long long)chunks);
+          if (at + chunks > p.moves_cap) {
+            atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+          } else {
+            if (p.moved_rows) atomicAdd(reinterpret_cast<unsigned long long*>(p.moved_rows), (unsigned long long)c_old);
+            for (u32 q = 0; q < chunks; ++q) {
+              const u32 off = q * kMoveChunk;
+              p.moves[at + q] = RunMove{from + off, u32(start_new) + off, min_u32(kMoveChunk, c_old - off)};
+            }
+          }
+        }
+        p.table[s].start = u32(start_new);
+        p.pcap[s] = u32(newcap);
+      }
+    }
+    // statistics of the updated index
+    const u64 wd = wave_sum(u64(valid && !failed ? d : 0u));
+    const u64 wk = wave_sum(u64(valid && !failed && c_old == 0 ? 1u : 0u));
+    u64 longest = valid && !failed ? need : 0;
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+      const u64 x = __shfl_xor(longest, o, kWave);
+      longest = x > longest ? x : longest;
+    }
+    if (lane_id() == 0) {
+      if (wd) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wd);
+      if (wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
+      if (longest) atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)longest);
+    }
+  }
+  ktime_end(p.ts);
+}
+
+// Update, step 3: the listed old runs into their new regions, one chunk per
+// block step.
+__global__ __launch_bounds__(kBlock) void k_upd_move(IndexParams p) {
+  ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  if (*p.full & 3) return;   // the index is rebuilt
+  const u64 n = min_u64(*p.moves_n, p.moves_cap);
+  for (u64 k = blockIdx.x; k < n; k += gridDim.x) {
+    const RunMove mv = p.moves[k];
+    for (u32 j = threadIdx.x; j < mv.count; j += kBlock) p.perm[u64(mv.to) + j] = p.perm[u64(mv.from) + j];
+  }
+  ktime_end(p.ts);
+}
+
+// Update, step 4: each appended row goes after its key's old rows, at its
+// rank among the key's appended rows (one atomic per key and tile on the
+// run's count, which ends as old + appended rows).
+__global__ __launch_bounds__(kBlock) void k_upd_fill(IndexParams p) {
+  __shared__ IdxLds m;
+  ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  if (*p.full & 3) return;   // keys or positions missing: the index is rebuilt
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 mask = p.cap - 1;
+  const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
+  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    lds_map_clear(m);
+    __syncthreads();
+    u32 ent[kIdxItems], rank[kIdxItems];
+    map_tile(p, m, begin, n, tile, ent, rank);
+    __syncthreads();
+    for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
+      const u32 c = m.cnt[e];
+      if (!c) continue;
+      const u64 h = index_slot_of(p.table, mask, m.key[e]);
+      m.pos[e] = h == kNoSlot ? ~0u : p.table[h].start + atomicAdd(&p.table[h].count, c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (u32 k = 0; k < kIdxItems; ++k) {
+      if (ent[k] == ~0u) continue;
+      const u32 base = m.pos[ent[k]];
+      if (base == ~0u) continue;
+      p.perm[base + rank[k]] = u32(begin + tile * kIdxTile + threadIdx.x + u64(k) * kBlock);
+    }
+    __syncthreads();
+  }
+  ktime_end(p.ts);
+}
+
+// ------------------------------------------------------------------ sorted update
+// An update over many appended rows whose keys are mostly distinct (where the
+// per-tile grouping above saves nothing and every row would cost random
+// accesses to the table and the counters) first sorts the appended rows'
+// (row, slot) words by slot, as the sorted build does (k_idx_slotkeys over the
+// appended range, then the radix sort).  Every per-slot access below then
+// walks the table in slot order: run boundaries give each touched slot's
+// appended count and where its rows begin among the words (wl doubles as that
+// per-slot position), the run head reserves room as k_upd_reserve does, and
+// appended word j of slot s goes to start(s) + old count(s) + (j - head(s)).
+
+__device__ __forceinline__ bool run_head(const u64* keys, u64 j, u64 smask) {
+  return j == 0 || (keys[j - 1] & smask) != (keys[j] & smask);
+}
+
+// Sorted update, step 1: appended count and head position per touched slot.
+__global__ __launch_bounds__(kBlock) void k_upds_runs(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
+    const u64 s = keys[j] & smask;
+    if (s >= p.cap) continue;   // outside the filter (sorted last)
+    const bool head = run_head(keys, j, smask);
+    const bool tail = j + 1 == n || (keys[j + 1] & smask) != s;
+    if (head) p.wl[s] = u32(j);
+    if (head || tail) atomicAdd(&p.dcnt[s], (tail ? u32(j + 1) : 0u) - (head ? u32(j) : 0u));
+  }
+  ktime_end(p.ts);
+}
+
+// Sorted update, step 2: k_upd_reserve's work, done by each run's head word;
+// the slot's count becomes old + appended rows (dcnt keeps the appended
+// count for the placement, which then clears it).
+__global__ __launch_bounds__(kBlock) void k_upds_reserve(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  const bool failed = (*p.full & 1) != 0;   // keys missing: the index is rebuilt
+  for (u64 b0 = u64(blockIdx.x) * kBlock; b0 < n; b0 += u64(gridDim.x) * kBlock) {
+    const u64 j = b0 + threadIdx.x;
+    u64 s = 0;
+    bool act = false;
+    if (j < n) {
+      s = keys[j] & smask;
+      act = s < p.cap && run_head(keys, j, smask) && !failed;
+    }
+    u32 d = 0, c_old = 0;
+    u64 need = 0, newcap = 0;
+    if (act) {
+      d = p.dcnt[s];
+      c_old = p.table[s].count;
+      need = u64(c_old) + d;
+      if (need > p.pcap[s]) newcap = need < 8 ? 16 : 2 * need;
+    }
+    const u64 incl = wave_inclusive_sum(newcap);
+    const u64 wtot = __shfl(incl, kWave - 1, kWave);
+    u64 wbase = 0;
+    if (lane_id() == 0 && wtot) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(p.top), (unsigned long long)wtot);
+    wbase = __shfl(wbase, 0, kWave);
+    const u64 start_new = wbase + incl - newcap;
+    const bool fits = newcap && start_new + newcap <= p.perm_cap;
+    const u32 from = fits ? p.table[s].start : 0u;
+    wave_copy_runs(p.perm, fits && c_old <= kInlineCopy, from, start_new, c_old);
+    if (newcap) {
+      if (!fits) {
+        atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+      } else {
+        if (c_old > kInlineCopy) {
+          const u32 chunks = (c_old + kMoveChunk - 1) / kMoveChunk;
+          const u64 at = atomicAdd(reinterpret_cast<unsigned long long*>(p.moves_n), (unsigned long long)chunks);
+          if (at + chunks > p.moves_cap) {
+            atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+          } else {
+            if (p.moved_rows) atomicAdd(reinterpret_cast<unsigned long long*>(p.moved_rows), (unsigned long long)c_old);
+            for (u32 q = 0; q < chunks; ++q) {
+              const u32 off = q * kMoveChunk;
+              p.moves[at + q] = RunMove{from + off, u32(start_new) + off, min_u32(kMoveChunk, c_old - off)};
+            }
+          }
+        }
+        p.table[s].start = u32(start_new);
+        p.pcap[s] = u32(newcap);
+      }
+    }
+    if (act) p.table[s].count = u32(need);
+    const u64 wd = wave_sum(u64(act ? d : 0u));
+    const u64 wk = wave_sum(u64(act && c_old == 0 ? 1u : 0u));
+    u64 longest = act ? need : 0;
+    for (int o = kWave / 2; o >= 1; o >>= 1) {
+      const u64 x = __shfl_xor(longest, o, kWave);
+      longest = x > longest ? x : longest;
+    }
+    if (lane_id() == 0) {
+      if (wd) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wd);
+      if (wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
+      if (longest) atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)longest);
+    }
+  }
+  ktime_end(p.ts);
+}
+
+// Sorted update, step 3: appended word j of slot s to its place after the
+// key's old rows.
+__global__ __launch_bounds__(kBlock) void k_upds_fill(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  if (*p.full & 3) return;   // keys or positions missing: the index is rebuilt
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
+    const u64 k = keys[j];
+    const u64 s = k & smask;
+    if (s >= p.cap) continue;
+    const Slot sl = p.table[s];
+    const u64 pos = u64(sl.start) + (sl.count - p.dcnt[s]) + (j - p.wl[s]);
+    p.perm[pos] = u32(begin + (k >> row_shift));
+  }
+  ktime_end(p.ts);
+}
+
+// Sorted update, step 4: the appended counts cleared for the next update
+// (also after a failed update, so that the rebuild finds them zero).
+__global__ __launch_bounds__(kBlock) void k_upds_clear(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
+    const u64 s = keys[j] & smask;
+    if (s < p.cap && run_head(keys, j, smask)) p.dcnt[s] = 0u;
   }
 }
 
@@ -291,7 +611,7 @@ __global__ __launch_bounds__(kBlock) void k_idx_move(IndexParams p) {
 // the slot bits (launch_rs_hist / launch_rs_pass, run by the caller).  The
 // sorted words list the rows grouped by slot, runs in slot order and row ids
 // ascending inside a run: the layout the counting build produces, so the
-// incremental update applies to it unchanged.  A run's count comes from its
+// incremental update applies to either.  A run's count comes from its
 // two boundaries (one atomic each, order-free modulo 2^32), and the table
 // scan turns counts into starts.  Rows outside the index's filter take the
 // slot value `cap`, which sorts after every real slot, and are dropped.
@@ -369,7 +689,6 @@ __global__ __launch_bounds__(kBlock) void k_idx_runs(IndexParams p, const u64* _
     if (s >= p.cap) continue;   // outside the filter (sorted last)
     if (i < p.perm_cap) {
       p.perm[i] = u32(begin + (k >> row_shift));
-      p.pslot[i] = u32(s);
     } else {
       over = true;
     }
@@ -381,94 +700,28 @@ __global__ __launch_bounds__(kBlock) void k_idx_runs(IndexParams p, const u64* _
   if (over && p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
 }
 
-// ------------------------------------------------------------------ sorted update
-// An update over many appended rows sorts them by slot as the sorted build
-// does (k_idx_slotkeys over the appended range, then the radix sort), so
-// that no appended row needs a per-row atomic: the boundaries of each slot's
-// run give its appended count, the update scan shifts the old runs, and the
-// appended rows are written after each key's old rows at their rank in the
-// run.  After that pass each slot's count takes its appended rows and the
-// per-slot counter is cleared for the next update.
-
-__global__ __launch_bounds__(kBlock) void k_idx_druns(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
-  if (p.abort && *p.abort) return;
-  if (p.abort2 && *p.abort2) return;
-  if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *p.rows_prev = *p.rows;
-    *p.rows = 0;
-    *p.ndv = 0;
-    *p.maxrun = 0;
-  }
-  u64 begin, n;
-  source_range(p.src, begin, n);
-  const u64 smask = (u64(1) << row_shift) - 1;
-  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
-    const u64 s = keys[j] & smask;
-    if (s >= p.cap) continue;   // outside the filter (sorted last)
-    const bool head = j == 0 || (keys[j - 1] & smask) != s;
-    const bool tail = j + 1 == n || (keys[j + 1] & smask) != s;
-    if (head || tail) atomicAdd(&p.dcnt[s], (tail ? u32(j + 1) : 0u) - (head ? u32(j) : 0u));
-  }
-}
-
-// Appended row j of slot s goes to start(s) + count(s) + (j - dsh(s)): its
-// key's new run start, past the key's old rows, at its rank among the key's
-// appended rows (dsh(s) is where that key's rows begin in the sorted words).
-__global__ __launch_bounds__(kBlock) void k_idx_dfill(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
-  if (p.abort && *p.abort) return;
-  if (p.abort2 && *p.abort2) return;
-  if (p.full && (*p.full & 1)) return;
-  if (*p.rows > p.perm_cap) {   // the runs would not fit: flag it, write nothing
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
-    return;
-  }
-  u64 begin, n;
-  source_range(p.src, begin, n);
-  const u64 smask = (u64(1) << row_shift) - 1;
-  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
-    const u64 k = keys[j];
-    const u64 s = k & smask;
-    if (s >= p.cap) continue;
-    const u64 pos = u64(p.table[s].start) + p.table[s].count + (j - p.dsh[s]);
-    p.perm_out[pos] = u32(begin + (k >> row_shift));
-    p.pslot_out[pos] = u32(s);
-  }
-}
-
-// count += appended rows, appended counter cleared: one thread per slot (the
-// head of its run), after every read of both.
-__global__ __launch_bounds__(kBlock) void k_idx_dfinish(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
-  if (p.abort && *p.abort) return;
-  if (p.abort2 && *p.abort2) return;
-  if (p.full && (*p.full & 1)) return;   // nothing was counted
-  u64 begin, n;
-  source_range(p.src, begin, n);
-  const u64 smask = (u64(1) << row_shift) - 1;
-  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
-    const u64 s = keys[j] & smask;
-    if (s >= p.cap) continue;
-    if (j != 0 && (keys[j - 1] & smask) == s) continue;
-    p.table[s].count += p.dcnt[s];
-    p.dcnt[s] = 0u;
-  }
-}
-
 static int grid_rows(u64 n, int cap) {
   const u64 b = (n + kBlock - 1) / kBlock;
   return int(b == 0 ? 1 : (b > u64(cap) ? u64(cap) : b));
+}
+
+static int grid_tiles(u64 rows) {
+  const u64 t = (rows + kIdxTile - 1) / kIdxTile;
+  return int(t == 0 ? 1 : (t > 4096 ? 4096 : t));
+}
+
+static int grid_scan(u64 cap) {
+  const u64 t = (cap + kScanTile - 1) / kScanTile;
+  return int(t == 0 ? 1 : (t > 2048 ? 2048 : t));
 }
 
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv,
                      p.maxrun, p.full, p.rows);
-  const u64 row_tiles = (rows_cap + kIdxTile - 1) / kIdxTile;
-  const int row_grid = int(row_tiles == 0 ? 1 : (row_tiles > 4096 ? 4096 : row_tiles));
-  hipLaunchKernelGGL(k_idx_count<false>, dim3(row_grid), dim3(kBlock), 0, s, p);
-  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_idx_scan<false>, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_idx_fill<false>, dim3(row_grid), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_count, dim3(grid_tiles(rows_cap)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_scan<false>, dim3(grid_scan(p.cap)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_fill, dim3(grid_tiles(rows_cap)), dim3(kBlock), 0, s, p);
   return int(hipGetLastError());
 }
 
@@ -480,42 +733,59 @@ int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row
   return int(hipGetLastError());
 }
 
+int launch_index_rehash(const Slot* old_tab, const u32* old_pcap, u64 old_cap, Slot* tab, u32* pcap, u64 cap,
+                        u64* full, void* stream) {
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(cap, 4096)), dim3(kBlock), 0, s, tab, cap, nullptr, nullptr, nullptr,
+                     full, nullptr);
+  hipLaunchKernelGGL(k_fill_u32_idx, dim3(grid_rows(cap, 4096)), dim3(kBlock), 0, s, pcap, cap);
+  hipLaunchKernelGGL(k_idx_rehash, dim3(grid_rows(old_cap, 8192)), dim3(kBlock), 0, s, old_tab, old_pcap, old_cap, tab,
+                     pcap, cap, full);
+  return int(hipGetLastError());
+}
+
 int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, void* stream) {
   hipLaunchKernelGGL(k_idx_slotkeys, dim3(grid_rows(delta_rows_cap, 8192)), dim3(kBlock), 0, (hipStream_t)stream, p,
                      keys, row_shift);
   return int(hipGetLastError());
 }
 
-int launch_index_update_runs(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, const u64* sorted,
-                             u32 row_shift, void* stream) {
+int launch_index_update_sorted(const IndexParams& p, u64 delta_rows_cap, const u64* sorted, u32 row_shift,
+                               u64* const* ts, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  const int dgrid = grid_rows(delta_rows_cap, 8192);
-  hipLaunchKernelGGL(k_idx_druns, dim3(dgrid), dim3(kBlock), 0, s, p, sorted, row_shift);
-  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL((k_idx_scan<true, true>), dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_idx_move, dim3(grid_rows(old_rows_cap, 8192)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_idx_dfill, dim3(dgrid), dim3(kBlock), 0, s, p, sorted, row_shift);
-  hipLaunchKernelGGL(k_idx_dfinish, dim3(dgrid), dim3(kBlock), 0, s, p, sorted, row_shift);
+  const int g = grid_rows(delta_rows_cap, 8192);
+  IndexParams q = p;
+  q.ts = ts ? ts[0] : nullptr;
+  hipLaunchKernelGGL(k_upds_runs, dim3(g), dim3(kBlock), 0, s, q, sorted, row_shift);
+  q.ts = ts ? ts[1] : nullptr;
+  hipLaunchKernelGGL(k_upds_reserve, dim3(grid_rows(delta_rows_cap, 4096)), dim3(kBlock), 0, s, q, sorted, row_shift);
+  q.ts = ts ? ts[2] : nullptr;
+  hipLaunchKernelGGL(k_upd_move, dim3(2048), dim3(kBlock), 0, s, q);
+  q.ts = ts ? ts[3] : nullptr;
+  hipLaunchKernelGGL(k_upds_fill, dim3(g), dim3(kBlock), 0, s, q, sorted, row_shift);
+  q.ts = nullptr;
+  hipLaunchKernelGGL(k_upds_clear, dim3(g), dim3(kBlock), 0, s, q, sorted, row_shift);
   return int(hipGetLastError());
 }
 
 int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32 row_shift, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_idx_runs, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, sorted, row_shift);
-  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL((k_idx_scan<false, true>), dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
+  hipLaunchKernelGGL(k_idx_scan<true>, dim3(grid_scan(p.cap)), dim3(kBlock), 0, s, p);
   return int(hipGetLastError());
 }
 
-int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 old_rows_cap, void* stream) {
+int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 wl_cap, u64* const* ts, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  const u64 row_tiles = (delta_rows_cap + kIdxTile - 1) / kIdxTile;
-  const int row_grid = int(row_tiles == 0 ? 1 : (row_tiles > 4096 ? 4096 : row_tiles));
-  hipLaunchKernelGGL(k_idx_count<true>, dim3(row_grid), dim3(kBlock), 0, s, p);
-  const u64 tiles = (p.cap + kScanTile - 1) / kScanTile;
-  hipLaunchKernelGGL(k_idx_scan<true>, dim3(int(tiles > 2048 ? 2048 : tiles)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_idx_move, dim3(grid_rows(old_rows_cap, 8192)), dim3(kBlock), 0, s, p);
-  hipLaunchKernelGGL(k_idx_fill<true>, dim3(row_grid), dim3(kBlock), 0, s, p);
+  IndexParams q = p;
+  q.ts = ts ? ts[0] : nullptr;
+  hipLaunchKernelGGL(k_upd_count, dim3(grid_tiles(delta_rows_cap)), dim3(kBlock), 0, s, q);
+  q.ts = ts ? ts[1] : nullptr;
+  hipLaunchKernelGGL(k_upd_reserve, dim3(grid_rows(wl_cap, 4096)), dim3(kBlock), 0, s, q);
+  q.ts = ts ? ts[2] : nullptr;
+  hipLaunchKernelGGL(k_upd_move, dim3(2048), dim3(kBlock), 0, s, q);
+  q.ts = ts ? ts[3] : nullptr;
+  hipLaunchKernelGGL(k_upd_fill, dim3(grid_tiles(delta_rows_cap)), dim3(kBlock), 0, s, q);
   return int(hipGetLastError());
 }
 

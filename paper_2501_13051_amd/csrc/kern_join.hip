@@ -109,6 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
   u64 begin, n;
   source_range(p.src, begin, n);
   const u32 ntiles = u32((n + kProbeTile - 1) / kProbeTile);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && p.out_n) *p.out_n = n;
   if (ntiles == 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0) { *p.out_m = 0; *p.out_t = 0; }
   }
@@ -403,6 +404,7 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
   if (p.nkey == 0) nbuild = p.build_rows_ctr ? min_u64(*p.build_rows_ctr, p.build_cap) : p.build_rows;
   u64 pre_total = 0, kept_total = 0;   // thread 0's tallies
   const u64 ntiles = (n + kFusedTile - 1) / kFusedTile;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && p.out_n) *p.out_n = n;
   for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const u64 t0 = tile * kFusedTile;
     u32 st[kFusedItems], cnt[kFusedItems];

@@ -52,6 +52,12 @@ def parse_args():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once before timing (a known-size kernel for "
                          "calibrating HBM byte counters)")
+    ap.add_argument("--save-predictor", default=None, help="write the trained predictor's parameters here (.npy)")
+    ap.add_argument("--load-predictor", default=None,
+                    help="use these parameters (.npy written by --save-predictor) instead of training, so that a "
+                         "profiled run holds only the headline workload's kernels")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain and zero-predictor runs beside the headline")
     return ap.parse_args()
 
 
@@ -60,7 +66,10 @@ def parse_args():
 KERNEL_SOURCES = {"sort_pass": "kern_sort.hip", "sort_pass_dedup": "kern_sort.hip", "sort_hist": "kern_sort.hip",
                   "join_probe": "kern_join.hip", "join_write": "kern_join.hip", "dedup_append": "kern_join.hip",
                   "join_onepass": "kern_join.hip", "select": "kern_join.hip", "index_build": "kern_index.hip",
-                  "index_update": "kern_index.hip"}
+                  "index_upd_count": "kern_index.hip", "index_upd_reserve": "kern_index.hip",
+                  "index_upd_move": "kern_index.hip", "index_upd_fill": "kern_index.hip",
+                  "index_upd_keys": "kern_index.hip", "index_upds_runs": "kern_index.hip",
+                  "index_upds_reserve": "kern_index.hip", "index_upds_fill": "kern_index.hip"}
 
 
 def source_digest(kernel_class):
@@ -178,6 +187,25 @@ def qerror_by_step(trace, np):
     return out
 
 
+def compare_learned(fv, np, rd, args, tuning, learned, T, train_loss, trace, reps):
+    """The headline workload and knobs without the network: the plain engine,
+    and the learned path with a zero predictor (presizing from the
+    uniform-key estimate alone), untraced, median of `reps` fixpoints each."""
+    plain_ms, plain_st = rd.time_runs(reps, tuning=tuning)
+    zero_ms, zero_st = rd.time_runs(reps, tuning=tuning, flags=fv.FV_LEARNED,
+                                    predictor=np.zeros(fv.MLP_PARAMS, np.float32))
+    trained_ms, trained_st = rd.time_runs(reps, tuning=tuning, **learned)
+    return {
+        "train_records": int(len(T)), "train_loss": round(train_loss, 6),
+        "plain_ms": round(plain_ms, 2), "zero_predictor_ms": round(zero_ms, 2), "trained_ms": round(trained_ms, 2),
+        "speedup_vs_plain": round(plain_ms / trained_ms, 3), "speedup_vs_zero_predictor": round(zero_ms / trained_ms, 3),
+        "plain_redo_rounds": plain_st["redo_rounds"], "zero_predictor_redo_rounds": zero_st["redo_rounds"],
+        "zero_predictor_overflow_fallbacks": zero_st["overflows"],
+        "trained_redo_rounds": trained_st["redo_rounds"], "trained_overflow_fallbacks": trained_st["overflows"],
+        "predicted_joins": trained_st["predicted_joins"], "qerror_median": round(trained_st["qerror_median"], 3),
+        "qerror_max": round(trained_st["qerror_max"], 3), "qerror_by_chain_step": qerror_by_step(trace, np)}
+
+
 def main():
     args = parse_args()
     if args.gpus != 1:
@@ -196,10 +224,17 @@ def main():
     torch.cuda.set_device(0)
 
     # the predictor: trained here, on this GPU, from the plain engine's traces
-    log("collecting join traces of the plain engine (TC, SG, points-to, batched TC)")
-    T = collect_traces(fv, W, torch, np)
-    params, train_loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
-    log(f"trained the predictor on {len(T)} join records, loss {train_loss:.5f}")
+    if args.load_predictor:
+        params = np.load(args.load_predictor).astype(np.float32)
+        T, train_loss = np.zeros((0, 10), np.float32), float("nan")
+        log(f"predictor parameters from {args.load_predictor}")
+    else:
+        log("collecting join traces of the plain engine (TC, SG, points-to, batched TC)")
+        T = collect_traces(fv, W, torch, np)
+        params, train_loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
+        log(f"trained the predictor on {len(T)} join records, loss {train_loss:.5f}")
+    if args.save_predictor:
+        np.save(args.save_predictor, params)
 
     w = W.config_rdfs()
     rd = Runner(fv, torch, np, w.program, w.edb, ["t"])
@@ -275,19 +310,9 @@ def main():
     # the learned path with a zero predictor (presizing from the uniform-key
     # estimate alone), untraced, median of three fixpoints each
     reps = max(3, args.steps // 3)
-    plain_ms, plain_st = rd.time_runs(reps, tuning=tuning)
-    zero_ms, zero_st = rd.time_runs(reps, tuning=tuning, flags=fv.FV_LEARNED,
-                                    predictor=np.zeros(fv.MLP_PARAMS, np.float32))
-    trained_ms, trained_st = rd.time_runs(reps, tuning=tuning, **learned)
-    learned_form = {
-        "train_records": int(len(T)), "train_loss": round(train_loss, 6),
-        "plain_ms": round(plain_ms, 2), "zero_predictor_ms": round(zero_ms, 2), "trained_ms": round(trained_ms, 2),
-        "speedup_vs_plain": round(plain_ms / trained_ms, 3), "speedup_vs_zero_predictor": round(zero_ms / trained_ms, 3),
-        "plain_redo_rounds": plain_st["redo_rounds"], "zero_predictor_redo_rounds": zero_st["redo_rounds"],
-        "zero_predictor_overflow_fallbacks": zero_st["overflows"],
-        "trained_redo_rounds": trained_st["redo_rounds"], "trained_overflow_fallbacks": trained_st["overflows"],
-        "predicted_joins": trained_st["predicted_joins"], "qerror_median": round(trained_st["qerror_median"], 3),
-        "qerror_max": round(trained_st["qerror_max"], 3), "qerror_by_chain_step": qerror_by_step(trace, np)}
+    learned_form = None
+    if not args.no_compare:
+        learned_form = compare_learned(fv, np, rd, args, tuning, learned, T, train_loss, trace, reps)
 
     out = {
         "metric": "derived tuples/s to fixpoint",

@@ -1492,9 +1492,10 @@ void Engine::build_index(Index& ix) {
   p.maxrun = ix.c_maxrun >= 0 ? ctr(ix.c_maxrun) : nullptr;
   p.full = ix.c_full >= 0 ? ctr(ix.c_full) : nullptr;
   p.rows = ix.c_rows >= 0 ? ctr(ix.c_rows) : nullptr;
-  if (R.used_as_head) {   // regions of exactly their runs, bump pointer past the last
+  if (R.used_as_head) {   // regions with room to grow, bump pointer past the last
     p.pcap = ix.pcap.as<u32>();
     p.top = ctr(ix.c_top);
+    p.wl = ix.wl.as<u32>();   // the sorted build notes each run's first word here
   }
   const int kc = kclass("index_build");
   ev_begin(kc);

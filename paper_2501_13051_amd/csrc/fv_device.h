@@ -270,6 +270,40 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Block-wide sum and maximum (every thread gets the result); `lds` must hold
+// kBlock / kWave entries.  Used to give a whole block one atomic on a shared
+// counter instead of one per wave: counters that every wave of a large launch
+// adds to serialise on their address otherwise.
+template <int kBlock, typename T>
+__device__ __forceinline__ T block_sum(T v, T* lds) {
+  constexpr int kWaves = kBlock / kWave;
+  T w = wave_sum(v);
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = w;
+  __syncthreads();
+  T t = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) t += lds[i];
+  __syncthreads();
+  return t;
+}
+
+template <int kBlock, typename T>
+__device__ __forceinline__ T block_max(T v, T* lds) {
+  constexpr int kWaves = kBlock / kWave;
+#pragma unroll
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const T o = __shfl_xor(v, d, kWave);
+    v = o > v ? o : v;
+  }
+  if (lane_id() == 0) lds[threadIdx.x / kWave] = v;
+  __syncthreads();
+  T t = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) t = lds[i] > t ? lds[i] : t;
+  __syncthreads();
+  return t;
+}
+
 // Block-wide exclusive scan; `lds` must hold kBlock / kWave + 1 entries.
 // Returns the exclusive prefix of v; *total receives the block sum.
 template <int kBlock, typename T>

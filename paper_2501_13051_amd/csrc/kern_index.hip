@@ -131,47 +131,40 @@ __global__ __launch_bounds__(kBlock) void k_idx_count(IndexParams p) {
 }
 
 // Build, step 2: exclusive scan over the table in slot order (look-back
-// across tiles): start <- prefix of counts, and count <- 0 (it becomes the
-// fill cursor) or kept (kKeep: the sorted build has already placed the rows).
-// Each run's region is exactly its rows (pcap), the bump pointer starts past
-// the last run, and the distinct keys, longest run and rows are recomputed.
+// across tiles): start <- prefix of the regions, and count <- 0 (it becomes
+// the fill cursor) or kept (kKeep: the sorted build places the rows after
+// this scan, or has placed them).  A loaded relation's index packs its runs
+// (region = count); a derived relation's index (pcap set) gives each run a
+// region of twice its rows, so that the next updates mostly append in place,
+// records the regions in pcap and starts the bump pointer past the last one.
+// The distinct keys, longest run and rows are recomputed; regions past the
+// positions available raise bit 1 of the full flag.
 template <bool kKeep>
 __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kBlock / kWave + 1];
   __shared__ u64 s_excl;
+  __shared__ u64 s_red[kBlock / kWave];
   if (p.abort && *p.abort) return;
   const u32 epoch = launch_epoch(p.epoch_base, p.epoch_off);
   const u32 ntiles = u32((p.cap + kScanTile - 1) / kScanTile);
   if (blockIdx.x >= participants(ntiles)) return;
+  // the statistics go to their counters once per block, after the last tile
+  u64 keys_acc = 0, rows_acc = 0, longest_acc = 0;
   for (;;) {
     const u32 tile = take_ticket(p.ticket, ntiles, &s_ticket);
     if (tile >= ntiles) break;
     const u64 s0 = u64(tile) * kScanTile + u64(threadIdx.x) * 4;
     u32 c[4];
-    u32 mine = 0, keys = 0, longest = 0;
+    u32 mine = 0;
+    const u32 slack = p.pcap ? 2u : 1u;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       c[k] = s0 + k < p.cap ? p.table[s0 + k].count : 0u;
-      mine += c[k];
-      keys += c[k] ? 1u : 0u;
-      longest = c[k] > longest ? c[k] : longest;
-    }
-    if (p.ndv) {
-      const u32 wk = wave_sum(keys);
-      if (lane_id() == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
-    }
-    if (p.rows) {
-      const u64 wr = wave_sum(u64(mine));
-      if (lane_id() == 0 && wr) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wr);
-    }
-    if (p.maxrun) {
-      for (int d = kWave / 2; d >= 1; d >>= 1) {
-        const u32 o = __shfl_xor(longest, d, kWave);
-        longest = o > longest ? o : longest;
-      }
-      if (lane_id() == 0 && longest)
-        atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)longest);
+      mine += slack * c[k];
+      rows_acc += c[k];
+      keys_acc += c[k] ? 1u : 0u;
+      longest_acc = c[k] > longest_acc ? c[k] : longest_acc;
     }
     u32 tot;
     const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
@@ -197,12 +190,24 @@ __global__ __launch_bounds__(kBlock) void k_idx_scan(IndexParams p) {
       if (s0 + k < p.cap) {
         p.table[s0 + k].start = u32(run);
         if (!kKeep) p.table[s0 + k].count = 0u;
-        if (p.pcap) p.pcap[s0 + k] = c[k];
+        if (p.pcap) p.pcap[s0 + k] = slack * c[k];
       }
-      run += c[k];
+      run += slack * c[k];
     }
-    if (tile == ntiles - 1 && threadIdx.x == 0 && p.top) *p.top = s_excl + tot;
+    if (tile == ntiles - 1 && threadIdx.x == 0) {
+      const u64 total = s_excl + tot;
+      if (p.top) *p.top = total;
+      if (total > p.perm_cap && p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+    }
     __syncthreads();
+  }
+  const u64 bk = block_sum<kBlock>(keys_acc, s_red);
+  const u64 br = block_sum<kBlock>(rows_acc, s_red);
+  const u64 bl = block_max<kBlock>(longest_acc, s_red);
+  if (threadIdx.x == 0) {
+    if (p.ndv && bk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)bk);
+    if (p.rows && br) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)br);
+    if (p.maxrun && bl) atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)bl);
   }
 }
 
@@ -217,11 +222,9 @@ __global__ __launch_bounds__(kBlock) void k_idx_fill(IndexParams p) {
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
   const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
-  if (p.full && (*p.full & 1)) return;   // keys are missing: the index is rebuilt larger
-  if (*p.rows > p.perm_cap) {   // the runs would not fit: flag it, write nothing
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
-    return;
-  }
+  // keys are missing (the index is rebuilt larger) or the regions do not
+  // fit (flagged by the scan): write nothing
+  if (p.full && (*p.full & 3)) return;
   for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     lds_map_clear(m);
     __syncthreads();
@@ -275,6 +278,8 @@ __global__ __launch_bounds__(kBlock) void k_idx_rehash(const Slot* __restrict__ 
 // whose dcnt was zero joins the work list (one atomic per wave).
 __global__ __launch_bounds__(kBlock) void k_upd_count(IndexParams p) {
   __shared__ IdxLds m;
+  __shared__ u32 s_c[kBlock / kWave + 1];
+  __shared__ u64 s_wbase;
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
@@ -288,25 +293,31 @@ __global__ __launch_bounds__(kBlock) void k_upd_count(IndexParams p) {
     u32 ent[kIdxItems], rank[kIdxItems];
     map_tile(p, m, begin, n, tile, ent, rank);
     __syncthreads();
-    // kLdsMap / kBlock steps for every thread: the wave's ballot below
-    // always has all its lanes
+    // the tile's newly touched slots (kept in m.pos) join the work list
+    // with one atomic per tile
+    u32 pushes = 0;
     for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
       const u32 c = m.cnt[e];
-      bool push = false;
-      u64 h = kNoSlot;
+      u32 slot = ~0u;
       if (c && !(__hip_atomic_load(p.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1)) {
-        h = index_insert(p.table, mask, m.key[e]);
+        const u64 h = index_insert(p.table, mask, m.key[e]);
         if (h == kNoSlot) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
-        else push = atomicAdd(&p.dcnt[h], c) == 0u;
+        else if (atomicAdd(&p.dcnt[h], c) == 0u) slot = u32(h);
       }
-      const u64 ball = __ballot(push);
-      if (ball) {
-        u64 base = 0;
-        if (lane_id() == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(p.wl_n), (unsigned long long)__popcll(ball));
-        base = __shfl(base, 0, kWave);
-        const u64 at = base + __popcll(ball & ((1ull << lane_id()) - 1));
-        if (push && at < p.cap) p.wl[at] = u32(h);
-      }
+      m.pos[e] = slot;
+      pushes += slot != ~0u ? 1u : 0u;
+    }
+    u32 tot;
+    const u32 ex = block_exclusive_sum<kBlock>(pushes, s_c, &tot);
+    if (threadIdx.x == 0)
+      s_wbase = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(p.wl_n), (unsigned long long)tot) : 0;
+    __syncthreads();
+    u64 at = s_wbase + ex;
+    for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
+      const u32 slot = m.pos[e];
+      if (slot == ~0u) continue;
+      if (at < p.cap) p.wl[at] = slot;
+      ++at;
     }
     __syncthreads();
   }
@@ -320,90 +331,121 @@ __global__ __launch_bounds__(kBlock) void k_upd_count(IndexParams p) {
 constexpr u32 kInlineCopy = 64;
 __device__ __forceinline__ void wave_copy_runs(u32* perm, bool want, u32 from, u64 to, u32 count) {
   u64 ball = __ballot(want);
+  const u32 lane = u32(lane_id());
   while (ball) {
-    const int l = __ffsll((unsigned long long)ball) - 1;
-    ball &= ball - 1;
-    const u32 f = __shfl(from, l, kWave);
-    const u64 t = __shfl(to, l, kWave);
-    const u32 c = __shfl(count, l, kWave);
-    if (u32(lane_id()) < c) perm[t + lane_id()] = perm[f + lane_id()];
+    // four runs per step: all their loads go out before any store
+    u32 f[4], c[4], v[4];
+    u64 t[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      c[q] = 0;
+      f[q] = 0;
+      t[q] = 0;
+      if (ball) {
+        const int l = __ffsll((unsigned long long)ball) - 1;
+        ball &= ball - 1;
+        f[q] = __shfl(from, l, kWave);
+        t[q] = __shfl(to, l, kWave);
+        c[q] = __shfl(count, l, kWave);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = lane < c[q] ? perm[f[q] + lane] : 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (lane < c[q]) perm[t[q] + lane] = v[q];
   }
 }
 
-// Update, step 2: per touched slot, room for its appended rows.  A run whose
-// old rows plus appended rows exceed its region moves to a region of twice
-// that size taken from the bump pointer (one atomic per wave); its old rows
-// are copied right away when there are at most kInlineCopy of them, else
-// listed in chunks of kMoveChunk for step 3.  The slot's appended count is
-// cleared (also when the update fails, so that the rebuild finds it zero),
-// and the index statistics grow by the round's rows and keys.
-constexpr u32 kMoveChunk = 1u << 16;
+constexpr u32 kMoveChunk = 1u << 16;   // rows per listed chunk of an old run
+
+// Room for the run of slot s (act): when its old rows plus appended rows
+// exceed its region, a region of twice that many positions from the bump
+// pointer (one atomic per block step), the old rows copied there by the wave
+// (at most kInlineCopy) or listed in chunks, and start / region size set.  A
+// block-uniform call: every thread of the block must make it.
+__device__ __forceinline__ void reserve_run(const IndexParams& p, bool act, u32 s, u32 c_old, u64 need, u64* s_scan,
+                                            u64* s_base) {
+  const u64 newcap = act && need > p.pcap[s] ? (need < 8 ? 16 : 2 * need) : 0;
+  u64 btot;
+  const u64 excl = block_exclusive_sum<kBlock>(newcap, s_scan, &btot);
+  if (threadIdx.x == 0) *s_base = btot ? atomicAdd(reinterpret_cast<unsigned long long*>(p.top), (unsigned long long)btot) : 0;
+  __syncthreads();
+  const u64 start_new = *s_base + excl;
+  __syncthreads();
+  const bool fits = newcap && start_new + newcap <= p.perm_cap;
+  const u32 from = fits ? p.table[s].start : 0u;
+  wave_copy_runs(p.perm, fits && c_old <= kInlineCopy, from, start_new, c_old);
+  if (!newcap) return;
+  if (!fits) {
+    atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);   // rebuilt with more positions
+    return;
+  }
+  if (c_old > kInlineCopy) {
+    const u32 chunks = (c_old + kMoveChunk - 1) / kMoveChunk;
+    const u64 at = atomicAdd(reinterpret_cast<unsigned long long*>(p.moves_n), (unsigned long long)chunks);
+    if (at + chunks > p.moves_cap) {
+      atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+    } else {
+      if (p.moved_rows) atomicAdd(reinterpret_cast<unsigned long long*>(p.moved_rows), (unsigned long long)c_old);
+      for (u32 q = 0; q < chunks; ++q) {
+        const u32 off = q * kMoveChunk;
+        p.moves[at + q] = RunMove{from + off, u32(start_new) + off, min_u32(kMoveChunk, c_old - off)};
+      }
+    }
+  }
+  p.table[s].start = u32(start_new);
+  p.pcap[s] = u32(newcap);
+}
+
+// The index statistics grow by the round's rows and new keys: one atomic per
+// counter and block (every thread of the block must call this).
+__device__ __forceinline__ void flush_update_stats(const IndexParams& p, u64 rows, u64 keys, u64 longest, u64* s_red) {
+  const u64 br = block_sum<kBlock>(rows, s_red);
+  const u64 bk = block_sum<kBlock>(keys, s_red);
+  const u64 bl = block_max<kBlock>(longest, s_red);
+  if (threadIdx.x == 0) {
+    if (br) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)br);
+    if (bk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)bk);
+    if (bl) atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)bl);
+  }
+}
+
+// Update, step 2: per touched slot (the work list), room for its appended
+// rows (reserve_run).  The slot's appended count is cleared (also when the
+// update fails, so that the rebuild finds it zero), and the index statistics
+// grow by the round's rows and keys.
 __global__ __launch_bounds__(kBlock) void k_upd_reserve(IndexParams p) {
+  __shared__ u64 s_scan[kBlock / kWave + 1];
+  __shared__ u64 s_base;
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
   const u64 n = min_u64(*p.wl_n, p.cap);   // the work list holds at most one entry per slot
   const bool failed = (*p.full & 1) != 0;   // keys missing: the index is rebuilt, only clear dcnt
-  // every thread of a block runs the same number of steps (the wave
-  // operations below need all lanes)
+  u64 st_rows = 0, st_keys = 0, st_long = 0;
+  // every thread of a block runs the same number of steps (the block and
+  // wave operations below need all of them)
   for (u64 b0 = u64(blockIdx.x) * kBlock; b0 < n; b0 += u64(gridDim.x) * kBlock) {
     const u64 i = b0 + threadIdx.x;
     const bool valid = i < n;
     u32 s = 0, d = 0, c_old = 0;
-    u64 need = 0, newcap = 0;
     if (valid) {
       s = p.wl[i];
       d = p.dcnt[s];
       p.dcnt[s] = 0u;
       c_old = p.table[s].count;
-      need = u64(c_old) + d;
-      if (!failed && need > p.pcap[s]) newcap = need < 8 ? 16 : 2 * need;
     }
-    // bump allocation of the new regions, one atomic per wave
-    const u64 incl = wave_inclusive_sum(newcap);
-    const u64 wtot = __shfl(incl, kWave - 1, kWave);
-    u64 wbase = 0;
-    if (lane_id() == 0 && wtot) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(p.top), (unsigned long long)wtot);
-    wbase = __shfl(wbase, 0, kWave);
-    const u64 start_new = wbase + incl - newcap;
-    const bool fits = newcap && start_new + newcap <= p.perm_cap;
-    const u32 from = fits ? p.table[s].start : 0u;
-    wave_copy_runs(p.perm, fits && c_old <= kInlineCopy, from, start_new, c_old);
-    if (newcap) {
-      if (!fits) {
-        atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);   // rebuilt with more positions
-      } else {
-        if (c_old > kInlineCopy) {
-          const u32 chunks = (c_old + kMoveChunk - 1) / kMoveChunk;
-          const u64 at = atomicAdd(reinterpret_cast<unsigned long long*>(p.moves_n), (unsigned long long)chunks);
-          if (at + chunks > p.moves_cap) {
-            atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
-          } else {
-            if (p.moved_rows) atomicAdd(reinterpret_cast<unsigned long long*>(p.moved_rows), (unsigned long long)c_old);
-            for (u32 q = 0; q < chunks; ++q) {
-              const u32 off = q * kMoveChunk;
-              p.moves[at + q] = RunMove{from + off, u32(start_new) + off, min_u32(kMoveChunk, c_old - off)};
-            }
-          }
-        }
-        p.table[s].start = u32(start_new);
-        p.pcap[s] = u32(newcap);
-      }
-    }
-    // statistics of the updated index
-    const u64 wd = wave_sum(u64(valid && !failed ? d : 0u));
-    const u64 wk = wave_sum(u64(valid && !failed && c_old == 0 ? 1u : 0u));
-    u64 longest = valid && !failed ? need : 0;
-    for (int o = kWave / 2; o >= 1; o >>= 1) {
-      const u64 x = __shfl_xor(longest, o, kWave);
-      longest = x > longest ? x : longest;
-    }
-    if (lane_id() == 0) {
-      if (wd) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wd);
-      if (wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
-      if (longest) atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)longest);
+    const bool act = valid && !failed;
+    const u64 need = u64(c_old) + d;
+    reserve_run(p, act, s, c_old, need, s_scan, &s_base);
+    if (act) {
+      st_rows += d;
+      st_keys += c_old == 0 ? 1u : 0u;
+      st_long = need > st_long ? need : st_long;
     }
   }
+  flush_update_stats(p, st_rows, st_keys, st_long, s_scan);
   ktime_end(p.ts);
 }
 
@@ -498,6 +540,8 @@ __global__ __launch_bounds__(kBlock) void k_upds_runs(IndexParams p, const u64* 
 // the slot's count becomes old + appended rows (dcnt keeps the appended
 // count for the placement, which then clears it).
 __global__ __launch_bounds__(kBlock) void k_upds_reserve(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  __shared__ u64 s_scan[kBlock / kWave + 1];
+  __shared__ u64 s_base;
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
@@ -505,66 +549,31 @@ __global__ __launch_bounds__(kBlock) void k_upds_reserve(IndexParams p, const u6
   source_range(p.src, begin, n);
   const u64 smask = (u64(1) << row_shift) - 1;
   const bool failed = (*p.full & 1) != 0;   // keys missing: the index is rebuilt
+  u64 st_rows = 0, st_keys = 0, st_long = 0;
   for (u64 b0 = u64(blockIdx.x) * kBlock; b0 < n; b0 += u64(gridDim.x) * kBlock) {
     const u64 j = b0 + threadIdx.x;
-    u64 s = 0;
+    u32 s = 0;
     bool act = false;
     if (j < n) {
-      s = keys[j] & smask;
-      act = s < p.cap && run_head(keys, j, smask) && !failed;
+      const u64 sl = keys[j] & smask;
+      act = sl < p.cap && run_head(keys, j, smask) && !failed;
+      s = act ? u32(sl) : 0u;
     }
     u32 d = 0, c_old = 0;
-    u64 need = 0, newcap = 0;
     if (act) {
       d = p.dcnt[s];
       c_old = p.table[s].count;
-      need = u64(c_old) + d;
-      if (need > p.pcap[s]) newcap = need < 8 ? 16 : 2 * need;
     }
-    const u64 incl = wave_inclusive_sum(newcap);
-    const u64 wtot = __shfl(incl, kWave - 1, kWave);
-    u64 wbase = 0;
-    if (lane_id() == 0 && wtot) wbase = atomicAdd(reinterpret_cast<unsigned long long*>(p.top), (unsigned long long)wtot);
-    wbase = __shfl(wbase, 0, kWave);
-    const u64 start_new = wbase + incl - newcap;
-    const bool fits = newcap && start_new + newcap <= p.perm_cap;
-    const u32 from = fits ? p.table[s].start : 0u;
-    wave_copy_runs(p.perm, fits && c_old <= kInlineCopy, from, start_new, c_old);
-    if (newcap) {
-      if (!fits) {
-        atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
-      } else {
-        if (c_old > kInlineCopy) {
-          const u32 chunks = (c_old + kMoveChunk - 1) / kMoveChunk;
-          const u64 at = atomicAdd(reinterpret_cast<unsigned long long*>(p.moves_n), (unsigned long long)chunks);
-          if (at + chunks > p.moves_cap) {
-            atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
-          } else {
-            if (p.moved_rows) atomicAdd(reinterpret_cast<unsigned long long*>(p.moved_rows), (unsigned long long)c_old);
-            for (u32 q = 0; q < chunks; ++q) {
-              const u32 off = q * kMoveChunk;
-              p.moves[at + q] = RunMove{from + off, u32(start_new) + off, min_u32(kMoveChunk, c_old - off)};
-            }
-          }
-        }
-        p.table[s].start = u32(start_new);
-        p.pcap[s] = u32(newcap);
-      }
-    }
-    if (act) p.table[s].count = u32(need);
-    const u64 wd = wave_sum(u64(act ? d : 0u));
-    const u64 wk = wave_sum(u64(act && c_old == 0 ? 1u : 0u));
-    u64 longest = act ? need : 0;
-    for (int o = kWave / 2; o >= 1; o >>= 1) {
-      const u64 x = __shfl_xor(longest, o, kWave);
-      longest = x > longest ? x : longest;
-    }
-    if (lane_id() == 0) {
-      if (wd) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wd);
-      if (wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.ndv), (unsigned long long)wk);
-      if (longest) atomicMax(reinterpret_cast<unsigned long long*>(p.maxrun), (unsigned long long)longest);
+    const u64 need = u64(c_old) + d;
+    reserve_run(p, act, s, c_old, need, s_scan, &s_base);
+    if (act) {
+      p.table[s].count = u32(need);
+      st_rows += d;
+      st_keys += c_old == 0 ? 1u : 0u;
+      st_long = need > st_long ? need : st_long;
     }
   }
+  flush_update_stats(p, st_rows, st_keys, st_long, s_scan);
   ktime_end(p.ts);
 }
 
@@ -682,22 +691,42 @@ __global__ __launch_bounds__(kBlock) void k_idx_runs(IndexParams p, const u64* _
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 smask = (u64(1) << row_shift) - 1;
+  // a loaded relation's index takes the packed layout (word i at position i);
+  // a derived one's runs get regions with room to grow, placed after the
+  // scan (k_idx_place), so here only each run's first word is noted
+  const bool packed = p.pcap == nullptr;
   bool over = false;
   for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
     const u64 k = keys[i];
     const u64 s = k & smask;
     if (s >= p.cap) continue;   // outside the filter (sorted last)
-    if (i < p.perm_cap) {
-      p.perm[i] = u32(begin + (k >> row_shift));
-    } else {
-      over = true;
+    if (packed) {
+      if (i < p.perm_cap) p.perm[i] = u32(begin + (k >> row_shift));
+      else over = true;
     }
     const bool head = i == 0 || (keys[i - 1] & smask) != s;
     const bool tail = i + 1 == n || (keys[i + 1] & smask) != s;
+    if (head && !packed) p.wl[s] = u32(i);
     if (head || tail) atomicAdd(&p.table[s].count, (tail ? u32(i + 1) : 0u) - (head ? u32(i) : 0u));
   }
   // the runs would not fit: flag it (the host regrows the positions)
   if (over && p.full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+}
+
+// Sorted build of a derived relation's index, after the scan: word i of
+// slot s goes to start(s) + (i - first word of s).
+__global__ __launch_bounds__(kBlock) void k_idx_place(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
+  if (p.abort && *p.abort) return;
+  if (p.full && (*p.full & 3)) return;   // keys missing or regions past the positions: rebuilt
+  u64 begin, n;
+  source_range(p.src, begin, n);
+  const u64 smask = (u64(1) << row_shift) - 1;
+  for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) {
+    const u64 k = keys[i];
+    const u64 s = k & smask;
+    if (s >= p.cap) continue;
+    p.perm[u64(p.table[s].start) + (i - p.wl[s])] = u32(begin + (k >> row_shift));
+  }
 }
 
 static int grid_rows(u64 n, int cap) {
@@ -772,6 +801,8 @@ int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_idx_runs, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, sorted, row_shift);
   hipLaunchKernelGGL(k_idx_scan<true>, dim3(grid_scan(p.cap)), dim3(kBlock), 0, s, p);
+  if (p.pcap)
+    hipLaunchKernelGGL(k_idx_place, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, sorted, row_shift);
   return int(hipGetLastError());
 }
 

@@ -183,6 +183,17 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       }
       if (threadIdx.x == 0) s_tstart[kRadix] = ttot;
     }
+    __syncthreads();
+    // stage the tile in LDS in digit order now (the local positions are
+    // known), so that the keys and ranks are dead during the look-back
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+      const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
+      if (idx < n) {
+        const u32 dig = u32((key[i] >> shift) & (kRadix - 1));
+        s_keys[s_tstart[dig] + s_wcnt[w][dig] + rank[i]] = key[i];
+      }
+    }
     for (int j = 0; j < kDpt; ++j) {
       const int d = threadIdx.x * kDpt + j;
       if (d >= kRadix) continue;
@@ -215,15 +226,6 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
         atomic_store_u64(status + u64(tile) * kRadix + d, lb_word(epoch, kFlagPrefix, excl + tcount[j]));
       }
       s_base[d] = dbase[j] + excl;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kItems; ++i) {
-      const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
-      if (idx < n) {
-        const u32 dig = u32((key[i] >> shift) & (kRadix - 1));
-        s_keys[s_tstart[dig] + s_wcnt[w][dig] + rank[i]] = key[i];
-      }
     }
     __syncthreads();
     const u32 tn = u32(min_u64(kTile, n - t0));

@@ -40,14 +40,30 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const u64* keys, const u64* 
   // kH keys per thread and step, loaded before any is counted
   constexpr int kH = 8;
   const u64 stride = u64(gridDim.x) * kBlock;
+  const u64 lt_mask = (1ull << lane_id()) - 1;
   for (u64 i0 = u64(blockIdx.x) * kBlock + threadIdx.x; i0 < n; i0 += stride * kH) {
     u64 k[kH];
 #pragma unroll
     for (int j = 0; j < kH; ++j) k[j] = i0 + j * stride < n ? keys[i0 + j * stride] : 0;
 #pragma unroll
     for (int j = 0; j < kH; ++j) {
-      if (i0 + j * stride >= n) continue;
-      for (u32 p = 0; p < passes; ++p) atomicAdd(&s_h[p * kRadix + ((k[j] >> (p * kBits)) & (kRadix - 1))], 1u);
+      // lanes past n are the wave's top lanes (indices rise with the lane),
+      // so lane 0 is valid whenever any lane is
+      const bool valid = i0 + j * stride < n;
+      for (u32 p = 0; p < passes; ++p) {
+        // packed keys often share their high digits across a whole wave: the
+        // lanes holding lane 0's digit add once, through their lowest lane,
+        // instead of queueing on one LDS word; the others add one by one
+        const u32 d = u32(k[j] >> (p * kBits)) & (kRadix - 1);
+        const u32 d0 = __builtin_amdgcn_readfirstlane(d);
+        const bool same = valid && d == d0;
+        const u64 m = __ballot(same);
+        if (same) {
+          if ((m & lt_mask) == 0) atomicAdd(&s_h[p * kRadix + d0], u32(__popcll(m)));
+        } else if (valid) {
+          atomicAdd(&s_h[p * kRadix + d], 1u);
+        }
+      }
     }
   }
   __syncthreads();

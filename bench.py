@@ -119,6 +119,16 @@ class Runner:
         self.relations = relations
         torch.cuda.synchronize()
 
+    @staticmethod
+    def arity_of(fv, program, edb):
+        ar = {}
+        for head, body, _ in fv.parse_program(program):
+            for name, ts in [head] + body:
+                ar.setdefault(name, len(ts))
+        for k, v in edb.items():
+            ar.setdefault(k, len(v))
+        return ar
+
     def make(self, **kw):
         e = self.fv.Engine(**kw)
         for name, a in self.arity.items():
@@ -148,15 +158,42 @@ class Runner:
         return sorted(ms)[len(ms) // 2], st
 
 
+def training_suite(W):
+    """Plain-engine runs whose join traces train the predictor: transitive
+    closure, same generation, points-to and acknowledged reachability (its
+    recursive rule in both body orders, so that both join orders appear) at
+    several sizes and seeds, and single joins of uniform and Zipf keys.  The
+    RDFS headline workload is held out."""
+    ack_swapped = W.ACK_PROGRAM.replace("fan(y, z), ack(z, x)", "ack(z, x), fan(y, z)")
+    suite = [(W.TC_PROGRAM, {"edge": W.config_tc().edb["edge"]}, ["path"])]
+    for n, m, seed in ((1000, 3000, 21), (4000, 6000, 22), (500, 2500, 23)):
+        suite.append((W.TC_PROGRAM, {"edge": W.er_graph(n, m, seed=seed)}, ["path"]))
+    suite.append((W.SG_PROGRAM, W.config_sg().edb, ["sg"]))
+    for trees, nodes, extra, seed in ((16, 512, 0.10, 31), (32, 256, 0.02, 32)):
+        suite.append((W.SG_PROGRAM, {"edge": W.forest(trees, nodes, extra, seed=seed)}, ["sg"]))
+    for scale, seed in ((1.0, 1003), (0.2, 1013), (0.05, 1023)):
+        pt = W.config_pointsto(seed=seed, scale=scale)
+        suite.append((pt.program, pt.edb, list(pt.idb)))
+    for args in ((32, 256, 128, 16, 1007), (128, 128, 32, 32, 41), (64, 512, 64, 8, 42)):
+        a = W.ack_reach(*args)
+        suite.append((a.program, a.edb, ["r"]))
+        suite.append((ack_swapped, a.edb, ["r"]))
+    for n_probe, n_keys, zipf_s in ((1 << 16, 1 << 12, 0.0), (1 << 18, 1 << 10, 1.0), (1 << 17, 1 << 16, 0.5)):
+        j = W.join_case(n_probe, n_keys, zipf_s)
+        suite.append((j.program, j.edb, ["out"]))
+    return suite
+
+
 def collect_traces(fv, W, torch, np):
     """Join traces (features, true sizes) the plain engine logs on the
-    transitive-closure, same-generation, points-to and batched
-    transitive-closure workloads: the predictor's training data."""
+    training suite and on the batched transitive-closure instances: the
+    predictor's training data."""
     rows = []
-    for wl, rels in ((W.config_tc(), ["path"]), (W.config_sg(), ["sg"]), (W.config_pointsto(), None)):
-        r = Runner(fv, torch, np, wl.program, wl.edb, rels or list(wl.idb))
+    for program, edb, rels in training_suite(W):
+        r = Runner(fv, torch, np, program, edb, rels)
         _, _, trace = r.run_once(flags=fv.FV_LOG_JOINS)
         rows.append(trace)
+        del r
     insts = W.batched_tc_instances()
     es = []
     for x in insts:
@@ -229,9 +266,9 @@ def main():
         T, train_loss = np.zeros((0, 10), np.float32), float("nan")
         log(f"predictor parameters from {args.load_predictor}")
     else:
-        log("collecting join traces of the plain engine (TC, SG, points-to, batched TC)")
+        log("collecting join traces of the plain engine (training suite, batched TC)")
         T = collect_traces(fv, W, torch, np)
-        params, train_loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
+        params, train_loss = fv.mlp_train(T[:, :8], T[:, 8], steps=4000, lr=3e-3, seed=1)
         log(f"trained the predictor on {len(T)} join records, loss {train_loss:.5f}")
     if args.save_predictor:
         np.save(args.save_predictor, params)
@@ -342,6 +379,8 @@ def main():
 
     if not args.no_extras:
         out["forms"] = extras(fv, W, torch, np, args)
+        out["forms"]["learned_join_order"] = join_order_form(fv, W, torch, np, params, reps)
+        out["forms"]["host_engine"] = host_form(fv, W, torch, np)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W)
@@ -457,6 +496,68 @@ def extras(fv, W, torch, np, args):
                                    "derived_tuples": int(t_st["derived_tuples"]),
                                    "tuples_per_s_tuned": round(t_st["derived_tuples"] / (t_ms * 1e-3), 1)}
     return forms
+
+
+def join_order_form(fv, W, torch, np, params, reps):
+    """The acknowledged-reachability program (1024 groups of 256 nodes): its
+    recursive rule can join fan (about 128 rows per key) or ack (about 16)
+    first.  The plain engine and the zero predictor keep the default order;
+    the trained network picks the order from its predicted intermediate
+    sizes.  Untraced, median of `reps` fixpoints each."""
+    log("learned join order: acknowledged reachability")
+    w = W.ack_reach(1024)
+    r = Runner(fv, torch, np, w.program, w.edb, ["r"])
+    out = {"workload": w.name, "edb_rows": {k: int(len(v[0])) for k, v in w.edb.items()}}
+    for name, kw in (("plain", {}),
+                     ("zero_predictor", dict(flags=fv.FV_LEARNED, predictor=np.zeros(fv.MLP_PARAMS, np.float32))),
+                     ("trained", dict(flags=fv.FV_LEARNED, predictor=params))):
+        r.run_once(**kw)
+        ms, st = r.time_runs(reps, **kw)
+        out[name] = {"ms": round(ms, 2), "join_output_tuples": int(st["join_output_tuples"]),
+                     "reordered_rounds": int(st["reordered_rounds"]), "derived_tuples": int(st["derived_tuples"])}
+    out["speedup_trained_vs_zero_predictor"] = round(out["zero_predictor"]["ms"] / out["trained"]["ms"], 3)
+    out["speedup_trained_vs_plain"] = round(out["plain"]["ms"] / out["trained"]["ms"], 3)
+    del r
+    return out
+
+
+def host_form(fv, W, torch, np):
+    """The same engine on host threads (FV_HOST) against the GPU engine, on
+    the same-generation forest and on the RDFS generator at 1/20 scale; the
+    process is held to 16 host cores (its share of the machine) while the
+    host engine runs, and the GPU runs are the plain engine with default
+    knobs.  Median of three fixpoints each."""
+    out = {}
+    old = os.sched_getaffinity(0)
+    cores = sorted(old)[:16]
+    for label, w, rels in (("sg_forest_64x1024", W.config_sg(), ["sg"]),
+                           ("rdfs_1M_triples", W.config_rdfs(scale=0.05), ["t"])):
+        log(f"host engine form: {label}")
+        g = Runner(fv, torch, np, w.program, w.edb, rels)
+        g.run_once()
+        g_ms, g_st = g.time_runs(3)
+        del g
+        h_ms = []
+        try:
+            os.sched_setaffinity(0, set(cores))
+            for _ in range(3):
+                e = fv.Engine(flags=fv.FV_HOST)
+                for name, a in Runner.arity_of(fv, w.program, w.edb).items():
+                    e.relation(name, a)
+                for name, cols in w.edb.items():
+                    e.load(name, [np.ascontiguousarray(np.asarray(c, np.uint32)) for c in cols])
+                e.program(w.program)
+                st = e.run()
+                h_ms.append(st["ms_total"])
+                assert st["derived_tuples"] == g_st["derived_tuples"], (label, st["derived_tuples"])
+                e.close()
+        finally:
+            os.sched_setaffinity(0, old)
+        h = sorted(h_ms)[1]
+        out[label] = {"gpu_ms": round(g_ms, 2), "host_ms": round(h, 2), "host_threads": len(cores),
+                      "gpu_over_host": round(h / g_ms, 2), "derived_tuples": int(g_st["derived_tuples"]),
+                      "host_cpu": cpu_model()}
+    return out
 
 
 def join_sweep(fv, W, torch, np):

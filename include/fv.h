@@ -146,6 +146,9 @@ typedef struct {
   uint32_t predicted_joins;    /* FV_LEARNED: joins run with a predicted output size */
   double qerror_median;        /* FV_LEARNED: median of max(m/p, p/m) over those joins (sizes + 1) */
   double qerror_max;
+  uint32_t reordered_rounds;   /* FV_LEARNED: (round, rule variant) pairs run in a join order other than
+                                  the default most-bound-first one, because the predictor expected
+                                  fewer intermediate rows from it (bodies of three or more atoms) */
 } fv_stats;
 
 /* One kernel class in the profile returned by fv_profile (FV_TRACE only).

@@ -383,7 +383,7 @@ u32 Engine::get_index(u32 rel, u32 nkey, const u32* keycol, u32 nfilt, const u32
   return u32(indices_.size() - 1);
 }
 
-Plan Engine::plan_rule(u32 ri, int dpos) {
+Plan Engine::plan_rule(u32 ri, int dpos, int second) {
   const RuleR& r = rules_[ri];
   const u32 nb = u32(r.body.size());
   std::vector<bool> used(nb, false), bound(kMaxVars, false);
@@ -406,11 +406,16 @@ Plan Engine::plan_rule(u32 ri, int dpos) {
   // variable left to bind), then the fewest variables it newly binds (an atom
   // bound in every position is a semi-join and can only shrink the result),
   // then the most shared variables, the most constants, EDB before IDB.
+  // (`second`, when given, names the atom the first join reads instead)
   while (order.size() < nb) {
     int best = -1;
     long best_score = -1;
     for (u32 i = 0; i < nb; ++i) {
       if (used[i]) continue;
+      if (second >= 0 && order.size() == 1) {
+        if (int(i) == second) best = int(i);
+        continue;
+      }
       int shared = 0, consts = 0, fresh = 0;
       std::vector<bool> seen(kMaxVars, false);
       for (auto& t : r.body[i].t) {
@@ -436,6 +441,7 @@ Plan Engine::plan_rule(u32 ri, int dpos) {
   p.delta_pos = dpos;
   p.src_rel = r.body[first].rel;
   p.src_delta = dpos >= 0;
+  p.second = nb > 1 ? order[1] : 0;
 
   // which variables are still needed after body position k of `order`
   auto needed_after = [&](u32 k, const std::vector<bool>& neq_done) {
@@ -579,10 +585,37 @@ Plan Engine::plan_rule(u32 ri, int dpos) {
 void Engine::plan_all() {
   init_plans_.clear();
   delta_plans_.clear();
+  int groups = 0;
   for (u32 ri = 0; ri < rules_.size(); ++ri) {
+    const RuleR& r = rules_[ri];
     init_plans_.push_back(plan_rule(ri, -1));
-    for (u32 i = 0; i < rules_[ri].body.size(); ++i)
-      if (rels_[rules_[ri].body[i].rel].idb) delta_plans_.push_back(plan_rule(ri, int(i)));
+    for (u32 i = 0; i < r.body.size(); ++i) {
+      if (!rels_[r.body[i].rel].idb) continue;
+      Plan p = plan_rule(ri, int(i));
+      // FV_LEARNED: a body of three or more atoms where several atoms share a
+      // variable with the delta atom can start with any of them; those join
+      // orders are planned too, and each round runs the one with the fewest
+      // predicted intermediate rows (the default order first, so that ties
+      // keep it)
+      std::vector<Plan> alts;
+      if (learned_ && r.body.size() >= 3) {
+        for (u32 j = 0; j < r.body.size() && alts.size() < kMaxJoinOrders - 1; ++j) {
+          if (j == i || j == p.second) continue;
+          bool shares = false;
+          for (auto& t : r.body[j].t)
+            for (auto& u : r.body[i].t) shares = shares || (!t.is_const && !u.is_const && t.value == u.value);
+          if (shares) alts.push_back(plan_rule(ri, int(i), int(j)));
+        }
+      }
+      if (!alts.empty()) p.alt = groups;
+      delta_plans_.push_back(p);
+      for (auto& q : alts) {
+        q.alt = groups;
+        q.active = false;
+        delta_plans_.push_back(q);
+      }
+      if (!alts.empty()) ++groups;
+    }
   }
   for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
   // Algorithm 2's difference reads an index of full on every column of a
@@ -1698,12 +1731,12 @@ void Engine::emit_round(bool initial, bool all_plans, bool sticky) {
   for (auto* plans : {&init_plans_, &delta_plans_})
     for (auto& p : *plans)
       for (auto& s : p.steps)
-        if (s.out_buf < 0 && s.fused) rels_[s.head_rel].hist_by_writers = false;
+        if (p.active && s.out_buf < 0 && s.fused) rels_[s.head_rel].hist_by_writers = false;
   if (initial) {
     for (auto& p : init_plans_) exec_plan(p);
   } else {
     for (auto& p : delta_plans_)
-      if (all_plans || rels_[p.src_rel].n_delta > 0) exec_plan(p);
+      if (p.active && (all_plans || rels_[p.src_rel].n_delta > 0)) exec_plan(p);
   }
   // test hook: this emission fails as if a join had overflowed (before any
   // sort, difference or commit), so the round runs again
@@ -1786,18 +1819,43 @@ constexpr u64 kOnePassMaxRun = 256;
 
 void Engine::choose_join_algorithms(bool initial) {
   fused_steps_.clear();
-  for (auto& p : initial ? init_plans_ : delta_plans_)
+  for (auto& p : initial ? init_plans_ : delta_plans_) {
+    fused_steps_.push_back(p.active);
     for (auto& s : p.steps) {
-      s.fused = use_fused_ && !s.select_only && s.index != kNoIndex &&
+      s.fused = p.active && use_fused_ && !s.select_only && s.index != kNoIndex &&
                 ctr_host_[indices_[s.index].c_maxrun] <= kOnePassMaxRun;
       fused_steps_.push_back(s.fused);
     }
+  }
+}
+
+// FV_LEARNED: of each group of plans that differ in join order, run the one
+// whose intermediate results (every join output but the last, whose size
+// the order does not change) the predictor expects to be smallest.  The
+// predictions are those made at the end of the previous round.
+void Engine::choose_join_orders() {
+  for (size_t i = 0; i < delta_plans_.size();) {
+    if (delta_plans_[i].alt < 0) { ++i; continue; }
+    size_t j = i, best = i;
+    double best_rows = 0;
+    for (; j < delta_plans_.size() && delta_plans_[j].alt == delta_plans_[i].alt; ++j) {
+      const Plan& p = delta_plans_[j];
+      double rows = 0;
+      for (size_t k = 0; k + 1 < p.steps.size(); ++k)
+        if (p.steps[k].c_pred >= 0) rows += double(ctr_host_[p.steps[k].c_pred]);
+      if (j == i || rows < best_rows) { best = j; best_rows = rows; }
+    }
+    for (size_t k = i; k < j; ++k) delta_plans_[k].active = k == best;
+    if (best != i) ++reordered_rounds_;
+    i = j;
+  }
 }
 
 void Engine::run_round(bool initial) {
   auto th = std::chrono::steady_clock::now();
   start_ctr_.assign(ctr_host_, ctr_host_ + n_ctr_);
   use_fused_ = learned_;
+  if (learned_ && !initial) choose_join_orders();
   if (learned_) size_from_predictions(initial);
   choose_join_algorithms(initial);
   for (;;) {
@@ -2241,7 +2299,7 @@ void Engine::size_from_predictions(bool initial) {
   std::vector<u64> need_new(rels_.size(), 0);
   for (auto& p : initial ? init_plans_ : delta_plans_) {
     const Relation& S = rels_[p.src_rel];
-    if (!initial && S.n_delta == 0) continue;
+    if (!p.active || (!initial && S.n_delta == 0)) continue;
     double probe = 0;   // rows entering the current step (estimated past the first)
     for (size_t k = 0; k < p.steps.size(); ++k) {
       const Step& st = p.steps[k];
@@ -2289,7 +2347,7 @@ void Engine::log_joins(bool initial) {
   for (auto& p : initial ? init_plans_ : delta_plans_) {
     const Relation& S = rels_[p.src_rel];
     const u64 n_src = initial ? S.n_full : S.n_delta;   // mirrors still hold the round's start
-    if (!initial && n_src == 0) continue;
+    if (!p.active || (!initial && n_src == 0)) continue;
     u32 k = 0;
     for (size_t i = 0; i < p.steps.size(); ++i) {
       const Step& st = p.steps[i];
@@ -2392,6 +2450,7 @@ void Engine::run(fv_stats* stats) {
     stats->graph_replays = graph_replays_;
     stats->overflows = overflows_;
     stats->predicted_joins = u32(qerrors_.size());
+    stats->reordered_rounds = reordered_rounds_;
     stats->qerror_median = 0;
     stats->qerror_max = 0;
     if (!qerrors_.empty()) {

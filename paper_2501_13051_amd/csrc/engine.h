@@ -31,6 +31,7 @@ struct Buf {
 constexpr u32 kMaxVars = 16;
 constexpr u32 kMaxBody = 8;
 constexpr u32 kMaxNeq = 8;
+constexpr u32 kMaxJoinOrders = 3;   // join orders planned per rule variant (FV_LEARNED)
 constexpr u32 kNoIndex = ~0u;
 
 struct Term { u32 value; bool is_const; };
@@ -131,6 +132,9 @@ struct Plan {
   int delta_pos;              // body position read from delta; -1 = all full
   u32 src_rel;
   bool src_delta;
+  u32 second = 0;             // body position the first join reads (build side)
+  int alt = -1;               // plans of one rule and delta position in other join orders share an id
+  bool active = true;         // this round runs it (one plan of each alternative group)
   std::vector<Step> steps;
 };
 
@@ -226,7 +230,8 @@ class Engine {
   void alloc_control();
   void domain_analysis();
   void plan_all();
-  Plan plan_rule(u32 rule, int delta_pos);
+  Plan plan_rule(u32 rule, int delta_pos, int second = -1);
+  void choose_join_orders();
   u32 get_index(u32 rel, u32 nkey, const u32* keycol, u32 nfilt, const u32* fcol, const u32* fval);
   void ingest();
   // true if any buffer was (dry: would be) reallocated; with look-ahead every
@@ -345,6 +350,7 @@ class Engine {
   std::vector<u64> start_ctr_;            // counters as they were when the round started
   std::vector<float> trace_rows_;
   std::vector<double> qerrors_;
+  u32 reordered_rounds_ = 0;
   u32 overflows_ = 0;
   int c_ndv0_ = 0, c_hll0_ = 0, c_pred0_ = 0;
   u64 join_out_ = 0;

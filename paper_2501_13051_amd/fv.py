@@ -73,7 +73,7 @@ class Stats(ctypes.Structure):
                 ("ms_total", ctypes.c_double), ("graph_captures", ctypes.c_uint32),
                 ("graph_replays", ctypes.c_uint32), ("overflows", ctypes.c_uint32),
                 ("predicted_joins", ctypes.c_uint32), ("qerror_median", ctypes.c_double),
-                ("qerror_max", ctypes.c_double)]
+                ("qerror_max", ctypes.c_double), ("reordered_rounds", ctypes.c_uint32)]
 
 
 class KProf(ctypes.Structure):

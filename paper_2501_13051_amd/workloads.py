@@ -412,6 +412,38 @@ def config_rdfs(seed: int = 1005, scale: float = 1.0) -> Workload:
 
 
 # ---------------------------------------------------------------- join sweep
+# Reachability confirmed by the target: x reaches z over an edge y -> z of
+# `fan` only if z acknowledges x.  The recursive rule closes a triangle
+# (r, fan, ack share x, y, z), so after the delta atom r(x, y) either fan
+# (keyed on y) or ack (keyed on x) can be joined first: the same result,
+# intermediates of different sizes.
+ACK_PROGRAM = """
+r(x, y) :- e(x, y).
+r(x, z) :- r(x, y), fan(y, z), ack(z, x).
+"""
+
+
+def ack_reach(n_groups: int, group: int = 256, fan: int = 128, acks: int = 16, seed: int = 1007) -> Workload:
+    """Nodes in n_groups groups of `group` consecutive ids.  Every node has
+    one e edge, `fan` fan edges and `acks` ack edges, each to a uniform node of
+    its own group (duplicate pairs dropped).  A delta row r(x, y) meets about
+    `fan` fan rows on y but about `acks` ack rows on x, so joining ack first
+    keeps the intermediate result fan/acks times smaller."""
+    rng = SplitMix64(seed)
+    n = n_groups * group
+
+    def edges(per_node):
+        src = np.repeat(np.arange(n, dtype=np.int64), per_node)
+        dst = (src // group) * group + rng.below(group, len(src))
+        key = np.unique((src << 32) | dst)
+        return [(key >> 32).astype(np.uint32), (key & 0xFFFFFFFF).astype(np.uint32)]
+
+    e, f, a = edges(1), edges(fan), edges(acks)
+    return Workload(name=f"ack_reach_g{n_groups}x{group}_f{fan}_a{acks}", program=ACK_PROGRAM,
+                    edb={"e": e, "fan": f, "ack": a}, idb=("r",),
+                    meta={"groups": n_groups, "group": group, "fan": fan, "acks": acks, "seed": seed})
+
+
 JOIN_PROGRAM = """
 out(x, z) :- a(x, y), b(y, z).
 """

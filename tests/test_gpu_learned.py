@@ -217,3 +217,66 @@ def test_trained_predictor_gains_over_plain_engine():
     assert count_passes["learned"] < count_passes["plain"], count_passes
     assert runs["learned"][1]["join_onepass"]["launches"] > 0
     assert runs["learned"][0]["redo_rounds"] <= runs["plain"][0]["redo_rounds"]
+
+
+def test_trained_predictor_picks_the_join_order_with_fewer_rows():
+    """r(x, z) :- r(x, y), fan(y, z), ack(z, x) can join fan (about 128 rows
+    per key) or ack (about 16) right after the delta atom.  The default order
+    takes fan (a tie on bound variables, broken by body order); the zero stub
+    predicts nothing for either order and keeps it.  A network trained on the
+    plain engine's traces expects fewer rows from ack first and runs that
+    order: the same fixpoint with fewer join output rows (intermediates
+    included)."""
+    rows = []
+    w = W.ack_reach(32)
+    for program, edb, rels in _cases()[:3] + [(w.program, w.edb, ["r"])]:
+        *_, trace = fv.evaluate(program, edb, flags=fv.FV_LOG_JOINS, relations=rels, with_trace=True)
+        rows.append(trace)
+    T = np.concatenate(rows)
+    params, _ = fv.mlp_train(T[:, :8], T[:, 8], steps=1500, lr=3e-3, seed=3)
+    ref = oracle.evaluate(w.program, w.edb)
+    runs = {}
+    for name, kw in (("plain", {}), ("zero", dict(flags=fv.FV_LEARNED, predictor=ZERO)),
+                     ("trained", dict(flags=fv.FV_LEARNED, predictor=params))):
+        got, stats, deltas, _ = fv.evaluate(w.program, w.edb, relations=["r"], **kw)
+        assert np.array_equal(got["r"], ref["r"]) and deltas == ref.delta_sizes, name
+        runs[name] = stats
+        print(name, stats["join_output_tuples"], "join rows, reordered", stats["reordered_rounds"], flush=True)
+    assert runs["zero"]["reordered_rounds"] == 0
+    assert runs["zero"]["join_output_tuples"] == runs["plain"]["join_output_tuples"]
+    assert runs["trained"]["reordered_rounds"] > 0
+    assert runs["trained"]["join_output_tuples"] < runs["zero"]["join_output_tuples"] // 2
+
+
+def _hand_net(feature):
+    """A network whose output is feature `feature` itself: it predicts
+    m = 2^(16 x feature / 16) - 1 (build rows for feature 1, distinct probe
+    keys for feature 3), clamped to the join's worst case."""
+    net = np.zeros(fv.MLP_PARAMS, np.float32)
+    net[feature] = 1.0                        # W1[0][feature]
+    net[64 * 8 + 64 + 0] = 1.0                # W2[0][0]
+    net[64 * 8 + 64 + 64 * 64 + 64 + 0] = 1.0   # W3[0]
+    return net
+
+
+def test_join_orders_are_parity_green_whichever_is_chosen():
+    """Every join order the learned engine may pick gives the oracle's
+    fixpoint, on the three-atom rules of the acknowledged-reachability and
+    points-to programs: a predictor that expects huge outputs (each clamped to
+    its join's worst case, probe rows x longest build run, so the order with
+    the smaller worst case wins), one that predicts the build side's rows, and
+    one that predicts the probe key's distinct values."""
+    w = W.ack_reach(8)
+    pt = W.config_pointsto(scale=0.05)
+    reordered = {}
+    for name, program, edb, rels in (("ack", w.program, w.edb, ["r"]), ("pointsto", pt.program, pt.edb, list(pt.idb))):
+        ref = oracle.evaluate(program, edb)
+        for pname, params in (("huge", HUGE), ("build_rows", _hand_net(1)), ("probe_ndv", _hand_net(3))):
+            print(f"join orders: {name} with the {pname} predictor", flush=True)
+            got, stats, deltas, _ = fv.evaluate(program, edb, flags=fv.FV_LEARNED, relations=rels, predictor=params)
+            for r in rels:
+                assert np.array_equal(got[r], ref[r]), (name, pname, r)
+            assert deltas == ref.delta_sizes, (name, pname)
+            reordered[name, pname] = stats["reordered_rounds"]
+    # ack (16 rows per key) is both the smaller build and the smaller worst case
+    assert reordered["ack", "huge"] > 0 and reordered["ack", "build_rows"] > 0, reordered

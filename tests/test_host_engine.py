@@ -49,6 +49,14 @@ def test_pointsto_and_rdfs_small():
     _check(W.RDFS_PROGRAM, {"t": d["t"]}, relations=["t"])
 
 
+def test_ack_reachability():
+    w = W.ack_reach(4)
+    for name, (a, b) in w.edb.items():
+        assert np.all(a // 256 == b // 256), name          # edges stay inside a group
+        assert len(np.unique((a.astype(np.uint64) << np.uint64(32)) | b)) == len(a), name
+    _check(w.program, w.edb, relations=["r"])
+
+
 def test_empty_duplicates_and_reserved():
     _check(W.TC_PROGRAM, {"edge": [np.zeros(0, np.uint32), np.zeros(0, np.uint32)]}, relations=["path", "edge"])
     got, _, _ = _check(W.TC_PROGRAM, {"edge": [np.array([1, 1, 2], np.uint32), np.array([2, 2, 3], np.uint32)]})

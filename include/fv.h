@@ -49,7 +49,7 @@ typedef enum {
   FV_EHIP = -6,        /* a HIP runtime call failed */
   FV_ERESERVED = -7,   /* the reserved value 0xFFFFFFFF was passed in */
   FV_ETRUNC = -8,      /* export capacity smaller than the relation */
-  FV_ENOTSUP = -9      /* a relation's packed tuple needs more than 64 bits */
+  FV_ENOTSUP = -9      /* a relation's packed tuple needs more than 64 bits even with values renumbered */
 } fv_status;
 
 /* fv_options.flags */
@@ -206,7 +206,14 @@ fv_status fv_add_rule(fv_ctx* ctx, const fv_rule* rule);
  * relation is joined against full relations (Algorithm 1), the new tuples are
  * radix-sorted, deduplicated against full and merged into full, until no
  * relation gains a tuple.  Runs once per context; stats may be NULL.
- * Errors: FV_ESTATE (already run), FV_ENOTSUP, FV_ENOMEM, FV_EHIP. */
+ * Tuples are packed column by column into 64-bit keys, each column as wide as
+ * its largest possible value.  When some relation would need more than 64
+ * bits (three columns of large ids), every value of the loaded facts and of
+ * the rules' constants is first replaced by its rank among the distinct ones
+ * (values are only compared for equality and rules create none, so the
+ * fixpoint is the same up to that renaming; fv_export maps ranks back).
+ * Errors: FV_ESTATE (already run), FV_ENOTSUP (still more than 64 bits: an
+ * arity-3 relation over more than 2^21 distinct values), FV_ENOMEM, FV_EHIP. */
 fv_status fv_run_fixpoint(fv_ctx* ctx, fv_stats* stats);
 
 /* Batched form: evaluate n contexts that hold the same program (same

@@ -112,7 +112,7 @@ Engine::~Engine() {
   release(moves_);
   for (auto& I : inters_) for (auto& b : I.col) release(b);
   flags_dev_ = Buf{};   // a view into ctr_dev_
-  release(ctr_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_);
+  release(ctr_dev_); release(ticket_dev_); release(hist_dev_); release(maxv_dev_); release(dict_);
   release(stamps_dev_);
   release(m_row_); release(m_start_); release(m_off_);
   release(st_a_); release(st_b_); release(st_sort_);
@@ -256,7 +256,10 @@ void Engine::load_columns(u32 rel, const u32* const* cols, u64 n, bool on_device
   sync();
   for (u32 c = 0; c < R.arity; ++c)
     if (host_max[c] == 0xFFFFFFFFu) throw Error(FV_ERESERVED, "value 0xFFFFFFFF is reserved");
-  for (u32 c = 0; c < R.arity; ++c) R.maxv[c] = std::max(R.maxv[c], host_max[c]);
+  for (u32 c = 0; c < R.arity; ++c) {
+    R.maxv[c] = std::max(R.maxv[c], host_max[c]);
+    R.lmax[c] = std::max(R.lmax[c], host_max[c]);
+  }
   R.staged += n;
   R.has_rows = true;
 }
@@ -311,8 +314,9 @@ u64 Engine::relation_size(u32 rel) const {
 // Datalog without function symbols creates no values: a head column can only
 // hold constants of the rule or values of a body column its variable occurs
 // in, so its maximum is bounded by the smallest maximum over those columns.
-// The bounds give each column a bit width for the packed tuple key.
-void Engine::domain_analysis() {
+// The bounds give each column a bit width for the packed tuple key; false if
+// some relation's key would need more than 64 bits.
+bool Engine::domain_analysis() {
   for (auto& r : rules_) rels_[r.head.rel].idb = true;
   for (bool changed = true; changed;) {
     changed = false;
@@ -333,6 +337,7 @@ void Engine::domain_analysis() {
       }
     }
   }
+  bool fits = true;
   for (auto& R : rels_) {
     // a column needs bits(max) bits; a packed key can only equal the
     // all-ones empty-slot sentinel if it fills all 64 bits with every field
@@ -350,11 +355,140 @@ void Engine::domain_analysis() {
         R.bits += R.width[c];
       }
     }
-    if (R.bits > 64)
-      throw Error(FV_ENOTSUP, "relation " + R.name + " needs " + std::to_string(R.bits) + " bits per packed tuple");
+    if (R.bits > 64) { fits = false; continue; }
     u32 s = 0;
     for (int c = int(R.arity) - 1; c >= 0; --c) { R.shift[c] = s; s += R.width[c]; }
     R.set32 = R.bits <= 32;
+  }
+  return fits;
+}
+
+// Relations whose packed tuples need more than 64 bits (three columns of
+// large ids): values are only compared for equality and no rule creates new
+// ones, so every value of the loaded facts and of the rules' constants is
+// replaced by its rank among the distinct ones (order kept: exports map the
+// ranks back after sorting).  Widths then follow the number of distinct
+// values rather than their magnitude.
+void Engine::fit_packing() {
+  auto widest = [&]() {
+    const Relation* w = &rels_[0];
+    for (auto& R : rels_) if (R.bits > w->bits) w = &R;
+    return w;
+  };
+  if (rels_.empty() || domain_analysis()) return;
+  if (!allow_compaction_) {
+    const Relation* w = widest();
+    throw Error(FV_ENOTSUP, "relation " + w->name + " needs " + std::to_string(w->bits) + " bits per packed tuple");
+  }
+  if (host_mode_) host_compact_values();
+  else compact_values();
+  compacted_ = true;
+  auto rank = [&](u32 v) {
+    return u32(std::lower_bound(dict_host_.begin(), dict_host_.end(), v) - dict_host_.begin());
+  };
+  for (auto& r : rules_) {
+    for (auto& t : r.head.t) if (t.is_const) t.value = rank(t.value);
+    for (auto& a : r.body) for (auto& t : a.t) if (t.is_const) t.value = rank(t.value);
+  }
+  for (auto& R : rels_)
+    for (u32 c = 0; c < R.arity; ++c) R.maxv[c] = R.has_rows ? rank(R.lmax[c]) : 0;
+  if (!domain_analysis()) {
+    const Relation* w = widest();
+    throw Error(FV_ENOTSUP, "relation " + w->name + " needs " + std::to_string(w->bits) +
+                                " bits per packed tuple even with its values renumbered densely (" +
+                                std::to_string(dict_host_.size()) + " distinct values)");
+  }
+}
+
+// Sorted distinct values of every loaded column and rule constant (radix sort
+// of the values, then the heads of equal runs), and every loaded column
+// rewritten as ranks.  Runs before the control buffers exist, so the sort
+// gets look-back words, ticket and histogram of its own.
+void Engine::compact_values() {
+  std::vector<u64> consts;
+  for (auto& r : rules_) {
+    for (auto& t : r.head.t) if (t.is_const) consts.push_back(t.value);
+    for (auto& a : r.body) for (auto& t : a.t) if (t.is_const) consts.push_back(t.value);
+  }
+  u64 total = consts.size();
+  for (auto& R : rels_) total += R.staged * R.arity;
+  if (total == 0) total = 1;
+  const u64 stiles = (total + kSortTile - 1) / kSortTile + 1;
+  Buf a, b, ctl, hist, status, tiles, d;
+  auto release_all = [&]() {
+    release(a); release(b); release(ctl); release(hist); release(status); release(tiles);
+  };
+  try {
+    a = alloc(total * 8);
+    b = alloc(total * 8);
+    ctl = alloc(64);
+    hist = alloc(kHistWords * 4);
+    status = alloc(stiles * kMaxRadix * 8);
+    tiles = alloc((dict_tiles(total) + 1) * 8);
+    d = alloc(total * 4);
+    launched(launch_fill_u32(ctl.as<u32>(), 16, 0u, stream_), "fill");
+    launched(launch_fill_u64(status.as<u64>(), stiles * kMaxRadix, 0, stream_), "fill");
+    launched(launch_fill_u64(a.as<u64>(), total, 0, stream_), "fill");
+    u64 off = 0;
+    for (auto& R : rels_)
+      for (u32 c = 0; c < R.arity && R.staged; ++c) {
+        const u32* in[1] = {R.stage[c].as<u32>()};
+        const u32 sh[1] = {0};
+        launched(launch_pack(in, 1, sh, R.staged, a.as<u64>() + off, stream_), "pack launch");
+        off += R.staged;
+      }
+    if (!consts.empty())
+      hip(hipMemcpyAsync(a.as<u64>() + off, consts.data(), consts.size() * 8, hipMemcpyHostToDevice, stream_),
+          "constant copy");
+    SortParams sp{};
+    sp.a = a.as<u64>();
+    sp.b = b.as<u64>();
+    sp.n_const = total;
+    sp.cap = total;
+    sp.bits = 32;
+    sp.digit_bits = 8;
+    sp.max_blocks = tune_.max_blocks;
+    sp.hist = hist.as<u32>();
+    sp.status = status.as<u64>();
+    sp.ticket = ctl.as<u32>();
+    sp.epoch_base = ctl.as<u32>() + 8;
+    launched(launch_rs_hist(sp, stream_), "hist launch");
+    u64* src = sp.a;
+    u64* dst = sp.b;
+    for (u32 pass = 0; pass < sort_passes(32, 8); ++pass) {
+      launched(launch_rs_pass(sp, pass, src, dst, pass + 1, stream_), "sort pass launch");
+      std::swap(src, dst);
+    }
+    const u64 nt = dict_tiles(total);
+    launched(launch_dict_unique(src, total, tiles.as<u64>(), d.as<u32>(), tiles.as<u64>() + nt, stream_),
+             "dictionary launch");
+    u64 nd = 0;
+    hip(hipMemcpyAsync(&nd, tiles.as<u64>() + nt, 8, hipMemcpyDeviceToHost, stream_), "count readback");
+    sync();
+    dict_host_.resize(nd);
+    hip(hipMemcpyAsync(dict_host_.data(), d.p, nd * 4, hipMemcpyDeviceToHost, stream_), "dictionary readback");
+    for (auto& R : rels_)
+      for (u32 c = 0; c < R.arity && R.staged; ++c)
+        launched(launch_dict_remap(R.stage[c].as<u32>(), R.staged, d.as<u32>(), nd, stream_), "remap launch");
+    sync();
+  } catch (...) {
+    release_all();
+    release(d);
+    throw;
+  }
+  release_all();
+  dict_ = d;
+}
+
+// Exported rows hold ranks when the values were compacted: map them back.
+void Engine::map_back(u32* const* cols, u32 arity, u64 n, bool on_device) {
+  if (!compacted_ || n == 0) return;
+  if (on_device) {
+    for (u32 c = 0; c < arity; ++c) launched(launch_dict_gather(cols[c], n, dict_.as<u32>(), stream_), "gather launch");
+    sync();
+  } else {
+    for (u32 c = 0; c < arity; ++c)
+      for (u64 i = 0; i < n; ++i) cols[c][i] = dict_host_[cols[c][i]];
   }
 }
 
@@ -2411,7 +2545,7 @@ void Engine::run(fv_stats* stats) {
   ran_ = true;
   if (host_mode_) { run_host(stats); return; }
   const auto t0 = std::chrono::steady_clock::now();
-  domain_analysis();
+  fit_packing();
   plan_all();
   alloc_control();
   setup_learning();
@@ -2538,6 +2672,7 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
       else { tmp[c] = alloc(n * 4); outc[c] = tmp[c].as<u32>(); }
     }
     launched(launch_unpack(s, n, R.arity, R.shift, R.width, outc, stream_), "unpack launch");
+    if (compacted_) map_back(outc, R.arity, n, true);
     if (!on_device)
       for (u32 c = 0; c < R.arity; ++c)
         hip(hipMemcpyAsync(cols[c], outc[c], n * 4, hipMemcpyDeviceToHost, stream_), "export copy");
@@ -2633,6 +2768,7 @@ void Engine::run_batch(Engine* const* es, u32 n, fv_stats* stats) {
   B->merged = std::make_shared<Engine>(&mopt);
   B->stride = stride;
   Engine& M = *B->merged;
+  M.allow_compaction_ = false;   // instances are sliced by id range afterwards
   for (auto& R : E0.rels_) M.relation_create(R.name.c_str(), R.arity);
   // one gather launch per relation concatenates every instance's staged facts
   std::vector<GatherDesc> desc(n);

@@ -50,6 +50,7 @@ struct Relation {
   Buf stage[3];
   u64 staged = 0, stage_cap = 0;
   u32 maxv[3] = {0, 0, 0};   // per-column value bound (domain analysis)
+  u32 lmax[3] = {0, 0, 0};   // per-column maximum of the loaded facts
   bool has_rows = false;
   // full relation: contiguous columns; delta = rows [d_begin, n_full)
   Buf col[3];
@@ -228,7 +229,11 @@ class Engine {
 
   // setup
   void alloc_control();
-  void domain_analysis();
+  bool domain_analysis();    // false: some relation's packed tuple needs more than 64 bits
+  void fit_packing();
+  void compact_values();
+  void host_compact_values();
+  void map_back(u32* const* cols, u32 arity, u64 n, bool on_device);
   void plan_all();
   Plan plan_rule(u32 rule, int delta_pos, int second = -1);
   void choose_join_orders();
@@ -349,6 +354,12 @@ class Engine {
   Buf pspec_init_dev_, pspec_delta_dev_;
   std::vector<u64> start_ctr_;            // counters as they were when the round started
   std::vector<float> trace_rows_;
+  // value compaction (packed tuples wider than 64 bits): the sorted distinct
+  // values of the loaded facts and rule constants; a value's rank replaces it
+  bool compacted_ = false;
+  bool allow_compaction_ = true;
+  Buf dict_;
+  std::vector<u32> dict_host_;
   std::vector<double> qerrors_;
   u32 reordered_rounds_ = 0;
   u32 overflows_ = 0;

@@ -375,6 +375,14 @@ struct GatherDesc {
 int launch_gather_relabel(const GatherDesc* d, u32 n_src, u32 arity, u32* const* out, void* stream);
 // p[i] += delta (mod 2^32) for i < n.
 int launch_add_u32(u32* p, u64 n, u32 delta, void* stream);
+
+// Value compaction (kern_dict.hip).  launch_dict_unique writes the distinct
+// keys of a sorted array (low 32 bits) to dict in order and their number to
+// *count; tile_cnt holds dict_tiles(n) words of scratch.
+u64 dict_tiles(u64 n);
+int launch_dict_unique(const u64* sorted, u64 n, u64* tile_cnt, u32* dict, u64* count, void* stream);
+int launch_dict_remap(u32* col, u64 n, const u32* dict, u64 nd, void* stream);
+int launch_dict_gather(u32* col, u64 n, const u32* dict, void* stream);
 // Instance boundaries of a sorted column (see k_bounds).
 int launch_bounds(const u32* col, u64 n, u32 stride, u32 n_inst, u64* out, void* stream);
 

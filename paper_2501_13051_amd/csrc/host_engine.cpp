@@ -219,6 +219,7 @@ void Engine::host_load(u32 rel, const u32* const* cols, u64 n, bool on_device) {
   for (u32 c = 0; c < R.arity; ++c) {
     H.stage[c].insert(H.stage[c].end(), in[c].begin(), in[c].end());
     R.maxv[c] = std::max(R.maxv[c], mx[c]);
+    R.lmax[c] = std::max(R.lmax[c], mx[c]);
   }
   R.staged += n;
   R.has_rows = true;
@@ -453,7 +454,7 @@ void Engine::run_host(fv_stats* stats) {
   if (!host_) host_ = std::make_shared<HostState>(host_threads_);
   HostState& S = *host_;
   S.rels.resize(rels_.size());
-  domain_analysis();
+  fit_packing();
   plan_all();
   S.idx.assign(indices_.size(), HostIndex{});
   for (auto& v : S.inter) v.assign(inters_.size(), {});
@@ -517,6 +518,32 @@ void Engine::run_host(fv_stats* stats) {
   }
 }
 
+// The host side of value compaction: sorted distinct values of the loaded
+// columns and rule constants, and the loaded columns rewritten as ranks.
+void Engine::host_compact_values() {
+  HostState& S = *host_;
+  std::vector<u64> v;
+  for (auto& r : rules_) {
+    for (auto& t : r.head.t) if (t.is_const) v.push_back(t.value);
+    for (auto& a : r.body) for (auto& t : a.t) if (t.is_const) v.push_back(t.value);
+  }
+  for (u32 ri = 0; ri < rels_.size(); ++ri)
+    for (u32 c = 0; c < rels_[ri].arity; ++c) v.insert(v.end(), S.rels[ri].stage[c].begin(), S.rels[ri].stage[c].end());
+  radix_sort(S.pool, v, nullptr, 32);
+  dict_host_.clear();
+  for (u64 i = 0; i < v.size(); ++i)
+    if (i == 0 || v[i] != v[i - 1]) dict_host_.push_back(u32(v[i]));
+  std::vector<u64>().swap(v);
+  for (u32 ri = 0; ri < rels_.size(); ++ri)
+    for (u32 c = 0; c < rels_[ri].arity; ++c) {
+      std::vector<u32>& col = S.rels[ri].stage[c];
+      S.pool.parallel_for(col.size(), 1 << 16, [&](u64 b, u64 e, u32) {
+        for (u64 i = b; i < e; ++i)
+          col[i] = u32(std::lower_bound(dict_host_.begin(), dict_host_.end(), col[i]) - dict_host_.begin());
+      });
+    }
+}
+
 void Engine::host_export(u32 rel, u32* const* cols, u64 n, bool on_device) {
   const Relation& R = rels_[rel];
   const HostRel& H = host_->rels[rel];
@@ -531,6 +558,8 @@ void Engine::host_export(u32 rel, u32* const* cols, u64 n, bool on_device) {
   for (u32 c = 0; c < R.arity; ++c) {
     const u64 m = R.width[c] >= 32 ? 0xFFFFFFFFull : ((1ull << R.width[c]) - 1);
     for (u64 i = 0; i < n; ++i) out[i] = u32((k[i] >> R.shift[c]) & m);
+    if (compacted_)
+      for (u64 i = 0; i < n; ++i) out[i] = dict_host_[out[i]];
     if (on_device) hip(hipMemcpy(cols[c], out.data(), n * 4, hipMemcpyHostToDevice), "export copy");
     else std::memcpy(cols[c], out.data(), n * 4);
   }

@@ -156,6 +156,74 @@ def test_large_ids_and_wide_keys():
     _check(W.TC_PROGRAM, {"edge": [src[keep], dst[keep]]})
 
 
+def spread_ids(col, keep_below=6):
+    """Ids >= keep_below mapped one-to-one over [keep_below, 2^32 - 3]
+    (v -> keep_below + v * 2654435761 mod (2^32 - 8), a unit modulo 2^32 - 8):
+    the same relations with ids of full 32-bit magnitude."""
+    v = np.asarray(col, np.uint64)
+    m = np.uint64(2**32 - 8)
+    with np.errstate(over="ignore"):
+        f = np.uint64(keep_below) + (v * np.uint64(2654435761)) % m
+    return np.where(v < keep_below, v, f).astype(np.uint32)
+
+
+WIDE_EXTRA_RULES = """
+t(o, 4294967294, s) :- t(s, {p}, o).
+t(s, 4000000000, o) :- t(s, 3999999999, o).
+"""
+
+
+def wide_rdfs_case():
+    d = W.rdfs_triples(n_triples=60_000, class_depth=5, n_entities=8_000, trans_tree=32, seed=9)
+    t = [spread_ids(c) for c in d["t"]]
+    prog = W.RDFS_PROGRAM + WIDE_EXTRA_RULES.format(p=int(t[1][t[1] >= 6][0]))
+    return prog, {"t": t}
+
+
+@pytest.mark.parametrize("flags", [fv.FV_PLAIN, fv.FV_LEARNED], ids=["plain", "learned"])
+def test_packed_tuples_wider_than_64_bits(flags):
+    """Triples whose three columns hold ids of full 32-bit magnitude (96 bits
+    packed), rules with large constants (one absent from the facts): values
+    are renumbered densely before the fixpoint and mapped back on export; the
+    oracle works on the raw values."""
+    prog, edb = wide_rdfs_case()
+    kw = {"flags": flags}
+    if flags & fv.FV_LEARNED:
+        kw["predictor"] = np.zeros(fv.MLP_PARAMS, np.float32)
+    ref = oracle.evaluate(prog, edb)
+    got, stats, deltas, _ = fv.evaluate(prog, edb, relations=["t"], **kw)
+    assert np.array_equal(got["t"], ref["t"])
+    assert deltas == ref.delta_sizes
+    assert int(got["t"][:, 1].max()) == 4294967294
+
+
+def test_two_wide_columns_at_the_top_of_the_range():
+    # both columns reach 0xFFFFFFFE: 33 + 33 bits with the empty-slot margin
+    rng = W.SplitMix64(6)
+    src = (0xFFFFFFFE - rng.below(3000, 4000)).astype(np.uint32)
+    dst = (0xFFFFFFFE - rng.below(3000, 4000)).astype(np.uint32)
+    src[0], dst[0] = 0xFFFFFFFE, 0xFFFFFFFD
+    src[1], dst[1] = 0xFFFFFFFD, 0xFFFFFFFE
+    keep = src != dst
+    _check(W.TC_PROGRAM, {"edge": [src[keep], dst[keep]]})
+
+
+def test_too_many_distinct_values_for_a_packed_triple():
+    """2.1M distinct values over three columns still need 3 x 22 bits after
+    renumbering: FV_ENOTSUP, and the context can be destroyed."""
+    n = 700_000
+    i = np.arange(n, dtype=np.uint32)
+    e = fv.Engine()
+    e.relation("a", 3)
+    e.relation("b", 3)
+    e.load("a", [3 * i, 3 * i + 1, 3 * i + 2])
+    e.program("b(x, y, z) :- a(x, y, z).")
+    with pytest.raises(fv.FvError) as ei:
+        e.run()
+    assert ei.value.status == "FV_ENOTSUP" and "renumbered" in str(ei.value)
+    e.close()
+
+
 def test_sg_forest_small_both_forms():
     edge = W.forest(8, 256, 0.05, seed=1002)
     _check(W.SG_PROGRAM, {"edge": edge})

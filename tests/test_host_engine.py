@@ -57,6 +57,27 @@ def test_ack_reachability():
     _check(w.program, w.edb, relations=["r"])
 
 
+def test_wide_ids_renumbered():
+    from test_gpu_parity import wide_rdfs_case
+    prog, edb = wide_rdfs_case()
+    got, _, _ = _check(prog, edb, relations=["t"])
+    assert int(got["t"][:, 1].max()) == 4294967294
+
+
+def test_too_many_distinct_values_for_a_packed_triple():
+    n = 700_000
+    i = np.arange(n, dtype=np.uint32)
+    e = fv.Engine(flags=fv.FV_HOST)
+    e.relation("a", 3)
+    e.relation("b", 3)
+    e.load("a", [3 * i, 3 * i + 1, 3 * i + 2])
+    e.program("b(x, y, z) :- a(x, y, z).")
+    with pytest.raises(fv.FvError) as ei:
+        e.run()
+    assert ei.value.status == "FV_ENOTSUP" and "renumbered" in str(ei.value)
+    e.close()
+
+
 def test_empty_duplicates_and_reserved():
     _check(W.TC_PROGRAM, {"edge": [np.zeros(0, np.uint32), np.zeros(0, np.uint32)]}, relations=["path", "edge"])
     got, _, _ = _check(W.TC_PROGRAM, {"edge": [np.array([1, 1, 2], np.uint32), np.array([2, 2, 3], np.uint32)]})

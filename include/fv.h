@@ -103,6 +103,10 @@ typedef struct {
                               join indices' layout, kept up to date every round), a new tuple's
                               value ranges in them, an empty range or an empty intersection of
                               the ranges proving it new; no tuple set is kept */
+  uint8_t block_log2[2][4]; /* threads per block as log2 (7, 8 or 9; 0: 8) of the join kernels
+                              (probe, write, one-pass join, selection: [0][b]) and of the
+                              difference pass ([1][b]), per launch size bucket b: at most 2^16,
+                              2^20, 2^24 rows, more */
 } fv_tuning;
 
 typedef struct {
@@ -240,7 +244,8 @@ typedef fv_ctx* (*fv_make_ctx_fn)(const fv_options* opt, void* user);
 /* Autotuner.  Coordinate search over fv_tuning: starting from the defaults,
  * each knob in turn (radix_bits {8,11}, fuse_dedup {0,1}, set_load
  * {0.25,0.5}, index_load {0.25,0.5}, max_blocks {1024,2048,4096}, index_rebuild
- * {0,1}, index_sort {0,1}, lookahead {0,1}, dedup_ranges {0,1}) is set to
+ * {0,1}, index_sort {0,1}, lookahead {0,1}, dedup_ranges {0,1}, then each
+ * kernel class's block size per size bucket, block_log2[c][b] {7,8,9}) is set to
  * every candidate with the others at their best so far; a candidate is scored
  * by the median fv_run_fixpoint time of `reps` fresh contexts from make()
  * (reps 0 means 3).  The winner goes to *best and, if cache_path and key are

@@ -1,6 +1,7 @@
 // Autotuner: picks the engine's tuning knobs (radix digit width, fused or
 // separate difference pass, tuple-set and index load factors, grid cap of the
-// look-back kernels) by timed trials on the caller's own workload, and keeps
+// look-back kernels, block size of the join and difference kernels per launch
+// size bucket) by timed trials on the caller's own workload, and keeps
 // the winners in a small JSON cache keyed by GPU architecture and a caller
 // key.  The knobs change speed and memory only; every trial computes the same
 // fixpoint.
@@ -114,12 +115,20 @@ std::string render_cache(const std::map<std::string, Entry>& entries) {
   return o.str();
 }
 
+// block_log2[c][b] is stored as "block_<class>_b<bucket>"
+const char* const kBlockClass[2] = {"join", "dedup"};
+
+std::string block_key(int c, int b) { return std::string("block_") + kBlockClass[c] + "_b" + std::to_string(b); }
+
 Entry to_entry(const fv_tuning& t, double ms) {
-  return Entry{{"radix_bits", double(t.radix_bits)}, {"fuse_dedup", double(t.fuse_dedup)},
-               {"set_load", double(t.set_load)},     {"index_load", double(t.index_load)},
-               {"max_blocks", double(t.max_blocks)}, {"index_rebuild", double(t.index_rebuild)},
-               {"index_sort", double(t.index_sort)},   {"lookahead", double(t.lookahead)},
-               {"dedup_ranges", double(t.dedup_ranges)}, {"ms", ms}};
+  Entry e{{"radix_bits", double(t.radix_bits)}, {"fuse_dedup", double(t.fuse_dedup)},
+          {"set_load", double(t.set_load)},     {"index_load", double(t.index_load)},
+          {"max_blocks", double(t.max_blocks)}, {"index_rebuild", double(t.index_rebuild)},
+          {"index_sort", double(t.index_sort)},   {"lookahead", double(t.lookahead)},
+          {"dedup_ranges", double(t.dedup_ranges)}, {"ms", ms}};
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 4; ++b) e[block_key(c, b)] = t.block_log2[c][b] ? t.block_log2[c][b] : 8;
+  return e;
 }
 
 fv_tuning from_entry(const Entry& e) {
@@ -134,6 +143,8 @@ fv_tuning from_entry(const Entry& e) {
   t.index_sort = uint32_t(get("index_sort", 0));
   t.lookahead = uint32_t(get("lookahead", 0));
   t.dedup_ranges = uint32_t(get("dedup_ranges", 0));
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 4; ++b) t.block_log2[c][b] = uint8_t(get(block_key(c, b).c_str(), 8));
   return t;
 }
 
@@ -190,15 +201,20 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
   cur.set_load = 0.25f;
   cur.index_load = 0.5f;
   cur.max_blocks = 2048;
+  for (auto& cls : cur.block_log2)
+    for (auto& l : cls) l = 8;
   double cur_ms = trial(make, user, base, cur, reps);
   if (cur_ms < 0) return FV_EINVAL;
   // coordinate search: each knob in turn, the others at their best so far
   const std::vector<double> radix = {8, 11}, fuse = {0, 1}, sload = {0.25, 0.5}, iload = {0.25, 0.5},
                             blocks = {1024, 2048, 4096}, rebuild = {0, 1},
-                            isort = {0, 1}, ahead = {0, 1}, ranges = {0, 1};
+                            isort = {0, 1}, ahead = {0, 1}, ranges = {0, 1}, block = {7, 8, 9};
   struct Knob { const std::vector<double>* vals; int which; };
-  const Knob knobs[] = {{&radix, 0}, {&fuse, 1}, {&sload, 2}, {&iload, 3}, {&blocks, 4}, {&rebuild, 5},
-                        {&isort, 6}, {&ahead, 7}, {&ranges, 8}};
+  // then the block size of each kernel class in each launch size bucket
+  // (a bucket no launch falls in times the same as the default and keeps it)
+  std::vector<Knob> knobs = {{&radix, 0}, {&fuse, 1}, {&sload, 2}, {&iload, 3}, {&blocks, 4}, {&rebuild, 5},
+                             {&isort, 6}, {&ahead, 7}, {&ranges, 8}};
+  for (int w = 100; w < 108; ++w) knobs.push_back({&block, w});
   for (const Knob& k : knobs) {
     for (double v : *k.vals) {
       fv_tuning t = cur;
@@ -211,7 +227,8 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
         case 5: t.index_rebuild = uint32_t(v); break;
         case 6: t.index_sort = uint32_t(v); break;
         case 7: t.lookahead = uint32_t(v); break;
-        default: t.dedup_ranges = uint32_t(v); break;
+        case 8: t.dedup_ranges = uint32_t(v); break;
+        default: t.block_log2[(k.which - 100) / 4][(k.which - 100) % 4] = uint8_t(v); break;
       }
       if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
       const double ms = trial(make, user, base, t, reps);

@@ -39,6 +39,13 @@ u32 bits_for(u64 x) {   // number of bits to represent x (x >= 1)
 
 }  // namespace
 
+// Threads per block of a kernel class's launch over up to `rows` rows: the
+// tuning's choice for that size bucket.
+u32 Engine::block_for(int cls, u64 rows) const {
+  const int b = rows <= (u64(1) << 16) ? 0 : rows <= (u64(1) << 20) ? 1 : rows <= (u64(1) << 24) ? 2 : 3;
+  return 1u << tune_.block_log2[cls][b];
+}
+
 // ------------------------------------------------------------------ lifetime
 Engine::Engine(const fv_options* opt) {
   if (opt) opt_ = *opt;
@@ -53,6 +60,9 @@ Engine::Engine(const fv_options* opt) {
   if (tune_.index_sort > 2) tune_.index_sort = 0;
   tune_.lookahead = tune_.lookahead ? 1 : 0;
   tune_.dedup_ranges = tune_.dedup_ranges ? 1 : 0;
+  for (auto& cls : tune_.block_log2)
+    for (auto& l : cls)
+      if (l != 7 && l != 9) l = 8;
   if (opt_.dev_alloc && !opt_.dev_free) throw Error(FV_EINVAL, "dev_alloc given without dev_free");
   stream_ = static_cast<hipStream_t>(opt_.stream);
   host_mode_ = (opt_.flags & FV_HOST) != 0;
@@ -1101,7 +1111,8 @@ bool Engine::ensure_capacity(bool dry) {
     m_off_ = alloc(nc * 8);
     m_cap_ = nc;
   }
-  const u64 tiles = (std::max(max_probe, max_rows) + 1023) / 1024 + 2;
+  // (tiles of the smallest block size: 128 threads x 4 rows)
+  const u64 tiles = (std::max(max_probe, max_rows) + 511) / 512 + 2;
   if (st_cap_ < tiles) {
     if (dry) return true;
     const u64 nc = std::max<u64>(tiles, st_cap_ * 2);
@@ -1422,7 +1433,7 @@ void Engine::exec_plan(Plan& p) {
       sp.overflow = flags;
       const int kc = kclass("select");
       sp.ts = ev_begin(kc, true);
-      launched(launch_select(sp, std::max<u64>(probe_bound, 1), stream_), "select launch");
+      launched(launch_select(sp, std::max<u64>(probe_bound, 1), stream_, block_for(0, probe_bound)), "select launch");
       ev_end(kc, 0, 0);
       continue;
     }
@@ -1457,7 +1468,8 @@ void Engine::exec_plan(Plan& p) {
       fp.overflow = flags;
       const int kf = kclass("join_onepass");
       fp.ts = ev_begin(kf, true);
-      launched(launch_join_fused(fp, std::max<u64>(probe_bound, 1), stream_), "one-pass join launch");
+      launched(launch_join_fused(fp, std::max<u64>(probe_bound, 1), stream_, block_for(0, probe_bound)),
+               "one-pass join launch");
       ev_end(kf, 0, 7, s.c_n, s.c_t, probe_bound);
       continue;
     }
@@ -1493,7 +1505,7 @@ void Engine::exec_plan(Plan& p) {
     pp.fatal = flags + kFlagFatal;
     const int kp = kclass("join_probe");
     pp.ts = ev_begin(kp, true);
-    launched(launch_probe(pp, std::max<u64>(probe_bound, 1), 0, stream_), "probe launch");
+    launched(launch_probe(pp, std::max<u64>(probe_bound, 1), 0, stream_, block_for(0, probe_bound)), "probe launch");
     ev_end(kp, 0, 1, s.c_n, s.c_m, probe_bound);
 
     WriteParams wp{};
@@ -1519,7 +1531,7 @@ void Engine::exec_plan(Plan& p) {
     const u64 out_bytes = o.packed ? 8 : 4ull * o.ncols;
     const int kw = kclass("join_write");
     wp.ts = ev_begin(kw, true);
-    launched(launch_write(wp, std::max<u64>(o.cap, 1), stream_), "write launch");
+    launched(launch_write(wp, std::max<u64>(o.cap, 1), stream_, block_for(0, probe_bound)), "write launch");
     ev_end(kw, 0, 2, s.c_m, s.c_t, (ix ? 4 : 0) + 4ull * nbuild + out_bytes);
   }
 }
@@ -1617,7 +1629,7 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.abort = flags;
   const int kd = kclass("dedup_append");
   dp.ts = ev_begin(kd, true);
-  launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_), "dedup launch");
+  launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_, block_for(1, R.new_cap)), "dedup launch");
   ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
 }
 

@@ -237,6 +237,7 @@ class Engine {
   void plan_all();
   Plan plan_rule(u32 rule, int delta_pos, int second = -1);
   void choose_join_orders();
+  u32 block_for(int cls, u64 rows) const;
   u32 get_index(u32 rel, u32 nkey, const u32* keycol, u32 nfilt, const u32* fcol, const u32* fval);
   void ingest();
   // true if any buffer was (dry: would be) reallocated; with look-ahead every

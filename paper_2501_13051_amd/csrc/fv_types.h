@@ -216,11 +216,13 @@ struct CommitParams {
 // ------------------------------------------------------------------ launchers
 // Each wrapper enqueues kernels on `stream` (a hipStream_t) and returns the
 // hipError_t of the launch as int.
-int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream);
-int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream);
-int launch_select(const SelectParams& p, u64 rows_hint, void* stream);
-int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream);
-int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream);
+// `block`: threads per block of the launch, 128, 256 or 512 (others: 256).
+// A look-back launch of n rows uses ceil(n / (block x 4)) status words.
+int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream, u32 block = 256);
+int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream, u32 block = 256);
+int launch_select(const SelectParams& p, u64 rows_hint, void* stream, u32 block = 256);
+int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream, u32 block = 256);
+int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream, u32 block = 256);
 int launch_commit(const CommitParams& p, void* stream);
 // Zero n_ctr counters, n_hist histogram words and (if flag) the overflow and
 // set-full flags (flag[0], flag[2]), and advance the epoch base by kEpochStride.

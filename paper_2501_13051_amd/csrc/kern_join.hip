@@ -20,12 +20,11 @@
 
 namespace fv {
 
+// Rows per thread of the join, selection and difference kernels; a tile is
+// kB (the block size, a template parameter: 128, 256 or 512) times that.
 constexpr int kProbeItems = 4;
-constexpr u32 kProbeTile = kBlock * kProbeItems;
 constexpr int kWriteItems = 4;
-constexpr u32 kWriteTile = kBlock * kWriteItems;
 constexpr int kDedupItems = 4;
-constexpr u32 kDedupTile = kBlock * kDedupItems;
 
 __device__ __forceinline__ u32 probe_val(const Src& s, const u32* const* pcol, u64 row) {
   return s.kind == kSrcConst ? s.v : pcol[s.v][row];
@@ -99,10 +98,12 @@ __device__ __forceinline__ void lookup_many(const Slot* __restrict__ tab, u64 ma
 }
 
 // ------------------------------------------------------------------ probe
-__global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
+template <int kB>
+__global__ __launch_bounds__(kB) void k_probe(ProbeParams p) {
+  constexpr u32 kProbeTile = kB * kProbeItems;
   __shared__ u32 s_ticket;
-  __shared__ u32 s_m[kBlock / kWave + 1];
-  __shared__ u64 s_t[kBlock / kWave + 1];
+  __shared__ u32 s_m[kB / kWave + 1];
+  __shared__ u64 s_t[kB / kWave + 1];
   __shared__ u64 s_excl[2];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
@@ -134,8 +135,8 @@ __global__ __launch_bounds__(kBlock) void k_probe(ProbeParams p) {
       if (cnt[k]) { ++matched; tsum += cnt[k]; }
     u32 mtot;
     u64 ttot;
-    const u32 mex = block_exclusive_sum<kBlock>(matched, s_m, &mtot);
-    const u64 tex = block_exclusive_sum<kBlock>(tsum, s_t, &ttot);
+    const u32 mex = block_exclusive_sum<kB>(matched, s_m, &mtot);
+    const u64 tex = block_exclusive_sum<kB>(tsum, s_t, &ttot);
     const int w = threadIdx.x / kWave;
     if (tile == 0) {
       if (threadIdx.x == 0) {
@@ -197,28 +198,30 @@ struct OutVals {
 // for all passes, cleared before the block's first tile and added to the
 // relation's histogram after its last.
 constexpr u32 kOutHistWords = 8 * 256;
+template <int kB>
 __device__ __forceinline__ void out_hist_clear(const OutSpec& o, u32* s_hist) {
   if (!o.hist) return;
-  for (u32 i = threadIdx.x; i < o.hist_passes * 256; i += kBlock) s_hist[i] = 0;
+  for (u32 i = threadIdx.x; i < o.hist_passes * 256; i += kB) s_hist[i] = 0;
   __syncthreads();
 }
+template <int kB>
 __device__ __forceinline__ void out_hist_flush(const OutSpec& o, u32* s_hist) {
   if (!o.hist) return;
   __syncthreads();
-  for (u32 i = threadIdx.x; i < o.hist_passes * 256; i += kBlock) {
+  for (u32 i = threadIdx.x; i < o.hist_passes * 256; i += kB) {
     const u32 c = s_hist[i];
     if (c) atomicAdd(&o.hist[i], c);
   }
 }
 
-template <int kItems>
+template <int kB, int kItems>
 __device__ __forceinline__ void append_tile(const OutSpec& o, const bool* keep, const OutVals* vals,
                                             u32* s_cnt, u64* s_base, u32* overflow, u64* stat, u32* s_hist) {
   u32 mine = 0;
 #pragma unroll
   for (int k = 0; k < kItems; ++k) mine += keep[k] ? 1u : 0u;
   u32 tot;
-  const u32 ex = block_exclusive_sum<kBlock>(mine, s_cnt, &tot);
+  const u32 ex = block_exclusive_sum<kB>(mine, s_cnt, &tot);
   if (threadIdx.x == 0) {
     *s_base = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(o.count), (unsigned long long)tot) : 0;
     if (stat && tot) atomicAdd(reinterpret_cast<unsigned long long*>(stat), (unsigned long long)tot);
@@ -252,16 +255,18 @@ __device__ __forceinline__ void append_tile(const OutSpec& o, const bool* keep, 
 }
 
 // ------------------------------------------------------------------ write
-__global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
+template <int kB>
+__global__ __launch_bounds__(kB) void k_write(WriteParams p) {
+  constexpr u32 kWriteTile = kB * kWriteItems;
   __shared__ u64 s_off[kWriteTile + 1];
   __shared__ u64 s_j0;
-  __shared__ u32 s_cnt[kBlock / kWave + 1];
+  __shared__ u32 s_cnt[kB / kWave + 1];
   __shared__ u64 s_base;
   __shared__ u32 s_hist[kOutHistWords];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
-  out_hist_clear(p.out, s_hist);
+  out_hist_clear<kB>(p.out, s_hist);
   const u64 M = min_u64(*p.in_m, p.m_cap);
   const u64 T = *p.in_t;
   const u64 ntiles = (T + kWriteTile - 1) / kWriteTile;
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
     }
     __syncthreads();
     const u64 j0 = s_j0;
-    for (u32 i = threadIdx.x; i <= kWriteTile; i += kBlock)
+    for (u32 i = threadIdx.x; i <= kWriteTile; i += kB)
       s_off[i] = (j0 + i < M) ? p.m_off[j0 + i] : T;
     __syncthreads();
 
@@ -331,9 +336,9 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
 #pragma unroll
       for (int k = 0; k < kWriteItems; ++k) vals[k].v[c] = src_val(p.out.src[c], p.pcol, prow[k], p.bcol, brow[k]);
     }
-    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat, s_hist);
+    append_tile<kB, kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat, s_hist);
   }
-  out_hist_flush(p.out, s_hist);
+  out_hist_flush<kB>(p.out, s_hist);
   ktime_end(p.ts);
 }
 
@@ -341,12 +346,11 @@ __global__ __launch_bounds__(kBlock) void k_write(WriteParams p) {
 // their keys up, scans the match counts in LDS, reserves the tile's outputs
 // with one atomic and writes them output-balanced (each thread finds the probe
 // row of an output position by binary search over the tile's prefix).  With
-// write filters the outputs are compacted per chunk of kBlock instead, one
+// write filters the outputs are compacted per chunk of kB instead, one
 // reservation per chunk.  Outputs past the buffer are counted, not written,
 // and raise the overflow flag (the round then runs again with count-then-
 // write joins).
 constexpr u32 kFusedItems = 4;
-constexpr u32 kFusedTile = kBlock * kFusedItems;
 
 // Output position <- the projected values of (probe row, build row).
 __device__ __forceinline__ void fused_put(const OutSpec& out, const u32* const* pcol, const u32* const* bcol, u64 pos,
@@ -380,7 +384,9 @@ __device__ __forceinline__ void put_vals(const OutSpec& out, u64 pos, const OutV
 }
 
 // Tile index of output o: the last j with off[j] <= o (its count is > 0).
+template <int kB>
 __device__ __forceinline__ u32 fused_owner(const u64* off, u64 o) {
+  constexpr u32 kFusedTile = kB * kFusedItems;
   u32 lo = 0, hi = kFusedTile;
   while (hi - lo > 1) {
     const u32 mid = (lo + hi) >> 1;
@@ -390,11 +396,13 @@ __device__ __forceinline__ u32 fused_owner(const u64* off, u64 o) {
   return lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
+template <int kB>
+__global__ __launch_bounds__(kB) void k_join_fused(FusedJoinParams p) {
+  constexpr u32 kFusedTile = kB * kFusedItems;
   __shared__ u64 s_off[kFusedTile + 1];
   __shared__ u32 s_start[kFusedTile];
-  __shared__ u64 s_scan[kBlock / kWave + 1];
-  __shared__ u32 s_keep[kBlock / kWave + 1];
+  __shared__ u64 s_scan[kB / kWave + 1];
+  __shared__ u32 s_keep[kB / kWave + 1];
   __shared__ u64 s_base;
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
@@ -417,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
 #pragma unroll
     for (u32 k = 0; k < kFusedItems; ++k) mine += cnt[k];
     u64 tot;
-    u64 ex = block_exclusive_sum<kBlock>(mine, s_scan, &tot);
+    u64 ex = block_exclusive_sum<kB>(mine, s_scan, &tot);
 #pragma unroll
     for (u32 k = 0; k < kFusedItems; ++k) {
       s_off[threadIdx.x * kFusedItems + k] = ex;
@@ -438,18 +446,18 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
       } else {
         // kFusedItems outputs per thread and step: their build row ids are
         // read together, then their columns
-        for (u64 o0 = 0; o0 < tot; o0 += u64(kBlock) * kFusedItems) {
+        for (u64 o0 = 0; o0 < tot; o0 += u64(kB) * kFusedItems) {
           u32 j[kFusedItems];
           u64 idx[kFusedItems], brow[kFusedItems];
 #pragma unroll
           for (u32 k = 0; k < kFusedItems; ++k) {
-            const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
-            j[k] = o < tot ? fused_owner(s_off, o) : 0u;
+            const u64 o = o0 + u64(k) * kB + threadIdx.x;
+            j[k] = o < tot ? fused_owner<kB>(s_off, o) : 0u;
             idx[k] = o < tot ? u64(s_start[j[k]]) + (o - s_off[j[k]]) : 0;
           }
 #pragma unroll
           for (u32 k = 0; k < kFusedItems; ++k) {
-            const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
+            const u64 o = o0 + u64(k) * kB + threadIdx.x;
             brow[k] = (o < tot && p.perm) ? u64(p.perm[idx[k]]) : idx[k];
           }
           OutVals v[kFusedItems];
@@ -458,24 +466,24 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
             if (c >= p.out.ncols) break;
 #pragma unroll
             for (u32 k = 0; k < kFusedItems; ++k) {
-              const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
+              const u64 o = o0 + u64(k) * kB + threadIdx.x;
               v[k].v[c] = o < tot ? src_val(p.out.src[c], p.pcol, begin + t0 + j[k], p.bcol, brow[k]) : 0u;
             }
           }
 #pragma unroll
           for (u32 k = 0; k < kFusedItems; ++k) {
-            const u64 o = o0 + u64(k) * kBlock + threadIdx.x;
+            const u64 o = o0 + u64(k) * kB + threadIdx.x;
             if (o < tot) put_vals(p.out, base + o, v[k]);
           }
         }
       }
     } else {
-      for (u64 c0 = 0; c0 < tot; c0 += kBlock) {
+      for (u64 c0 = 0; c0 < tot; c0 += kB) {
         const u64 o = c0 + threadIdx.x;
         bool keep = false;
         u64 prow = 0, brow = 0;
         if (o < tot) {
-          const u32 j = fused_owner(s_off, o);
+          const u32 j = fused_owner<kB>(s_off, o);
           const u64 idx = u64(s_start[j]) + (o - s_off[j]);
           prow = begin + t0 + j;
           brow = p.perm ? u64(p.perm[idx]) : idx;
@@ -488,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
           keep = ok;
         }
         u32 kc;
-        const u32 kpos = block_exclusive_sum<kBlock>(keep ? 1u : 0u, s_keep, &kc);
+        const u32 kpos = block_exclusive_sum<kB>(keep ? 1u : 0u, s_keep, &kc);
         if (kc == 0) continue;   // block-uniform
         if (threadIdx.x == 0) s_base = atomicAdd(reinterpret_cast<unsigned long long*>(p.out.count), (unsigned long long)kc);
         __syncthreads();
@@ -513,13 +521,15 @@ __global__ __launch_bounds__(kBlock) void k_join_fused(FusedJoinParams p) {
 }
 
 // ------------------------------------------------------------------ select / project
-__global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
-  __shared__ u32 s_cnt[kBlock / kWave + 1];
+template <int kB>
+__global__ __launch_bounds__(kB) void k_select(SelectParams p) {
+  constexpr u32 kWriteTile = kB * kWriteItems;
+  __shared__ u32 s_cnt[kB / kWave + 1];
   __shared__ u64 s_base;
   __shared__ u32 s_hist[kOutHistWords];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
-  out_hist_clear(p.out, s_hist);
+  out_hist_clear<kB>(p.out, s_hist);
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 ntiles = (n + kWriteTile - 1) / kWriteTile;
@@ -528,7 +538,7 @@ __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
     OutVals vals[kWriteItems];
 #pragma unroll
     for (int k = 0; k < kWriteItems; ++k) {
-      const u64 r = tile * kWriteTile + u64(k) * kBlock + threadIdx.x;
+      const u64 r = tile * kWriteTile + u64(k) * kB + threadIdx.x;
       keep[k] = false;
       if (r >= n) continue;
       const u64 row = begin + r;
@@ -545,9 +555,9 @@ __global__ __launch_bounds__(kBlock) void k_select(SelectParams p) {
           if (c < p.out.ncols) vals[k].v[c] = probe_val(p.out.src[c], p.pcol, row);
       }
     }
-    append_tile<kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat, s_hist);
+    append_tile<kB, kWriteItems>(p.out, keep, vals, s_cnt, &s_base, p.overflow, p.join_out_stat, s_hist);
   }
-  out_hist_flush(p.out, s_hist);
+  out_hist_flush<kB>(p.out, s_hist);
   ktime_end(p.ts);
 }
 
@@ -602,9 +612,11 @@ __device__ __forceinline__ void ranges_present(const RangeDedup& rd, const u32* 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
+template <int kB>
+__global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
+  constexpr u32 kDedupTile = kB * kDedupItems;
   __shared__ u32 s_ticket;
-  __shared__ u32 s_c[kBlock / kWave + 1];
+  __shared__ u32 s_c[kB / kWave + 1];
   __shared__ u64 s_excl;
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
@@ -659,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_dedup(DedupParams p) {
       }
     }
     u32 tot;
-    const u32 ex = block_exclusive_sum<kBlock>(mine, s_c, &tot);
+    const u32 ex = block_exclusive_sum<kB>(mine, s_c, &tot);
     if (tile == 0) {
       if (threadIdx.x == 0) {
         atomic_store_u64(p.status + tile, lb_word(epoch, kFlagPrefix, tot));
@@ -743,34 +755,53 @@ static int grid_for(u64 tiles, int cap_blocks) {
   return int(tiles < u64(cap_blocks) ? tiles : u64(cap_blocks));
 }
 
-int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream) {
-  const u64 tiles = (probe_cap + kProbeTile - 1) / kProbeTile;
-  int g = grid > 0 ? grid : grid_for(tiles, 2048);
-  hipLaunchKernelGGL(k_probe, dim3(g), dim3(kBlock), 0, (hipStream_t)stream, p);
+// Launch kernel K<kB> with kB the block size given (128, 256 or 512; anything
+// else runs 256-thread blocks).
+#define FV_LAUNCH_BLOCK(K, block, grid, stream, arg)                                                              \
+  do {                                                                                                        \
+    if ((block) == 128)                                                                                       \
+      hipLaunchKernelGGL(K<128>, dim3(grid), dim3(128), 0, (hipStream_t)(stream), arg);                       \
+    else if ((block) == 512)                                                                                  \
+      hipLaunchKernelGGL(K<512>, dim3(grid), dim3(512), 0, (hipStream_t)(stream), arg);                       \
+    else                                                                                                      \
+      hipLaunchKernelGGL(K<256>, dim3(grid), dim3(256), 0, (hipStream_t)(stream), arg);                       \
+  } while (0)
+
+static u64 block_of(u32 block) { return block == 128 || block == 512 ? block : 256; }
+
+int launch_probe(const ProbeParams& p, u64 probe_cap, int grid, void* stream, u32 block) {
+  const u64 tile = block_of(block) * kProbeItems;
+  const u64 tiles = (probe_cap + tile - 1) / tile;
+  const int g = grid > 0 ? grid : grid_for(tiles, 2048);
+  FV_LAUNCH_BLOCK(k_probe, block, g, stream, p);
   return int(hipGetLastError());
 }
 
-int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream) {
-  const u64 tiles = (out_tiles_hint + kWriteTile - 1) / kWriteTile;
-  hipLaunchKernelGGL(k_write, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream, u32 block) {
+  const u64 tile = block_of(block) * kWriteItems;
+  const u64 tiles = (out_tiles_hint + tile - 1) / tile;
+  FV_LAUNCH_BLOCK(k_write, block, grid_for(tiles, 4096), stream, p);
   return int(hipGetLastError());
 }
 
-int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream) {
-  const u64 tiles = (rows_hint + kFusedTile - 1) / kFusedTile;
-  hipLaunchKernelGGL(k_join_fused, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream, u32 block) {
+  const u64 tile = block_of(block) * kFusedItems;
+  const u64 tiles = (rows_hint + tile - 1) / tile;
+  FV_LAUNCH_BLOCK(k_join_fused, block, grid_for(tiles, 4096), stream, p);
   return int(hipGetLastError());
 }
 
-int launch_select(const SelectParams& p, u64 rows_hint, void* stream) {
-  const u64 tiles = (rows_hint + kWriteTile - 1) / kWriteTile;
-  hipLaunchKernelGGL(k_select, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, p);
+int launch_select(const SelectParams& p, u64 rows_hint, void* stream, u32 block) {
+  const u64 tile = block_of(block) * kWriteItems;
+  const u64 tiles = (rows_hint + tile - 1) / tile;
+  FV_LAUNCH_BLOCK(k_select, block, grid_for(tiles, 4096), stream, p);
   return int(hipGetLastError());
 }
 
-int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream) {
-  const u64 tiles = (rows_cap + kDedupTile - 1) / kDedupTile;
-  hipLaunchKernelGGL(k_dedup, dim3(grid_for(tiles, 2048)), dim3(kBlock), 0, (hipStream_t)stream, p);
+int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream, u32 block) {
+  const u64 tile = block_of(block) * kDedupItems;
+  const u64 tiles = (rows_cap + tile - 1) / tile;
+  FV_LAUNCH_BLOCK(k_dedup, block, grid_for(tiles, 2048), stream, p);
   return int(hipGetLastError());
 }
 

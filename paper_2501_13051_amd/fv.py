@@ -42,10 +42,24 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void
 class Tuning(ctypes.Structure):
     _fields_ = [("radix_bits", ctypes.c_uint32), ("fuse_dedup", ctypes.c_uint32), ("set_load", ctypes.c_float),
                 ("index_load", ctypes.c_float), ("max_blocks", ctypes.c_uint32), ("index_rebuild", ctypes.c_uint32),
-                ("index_sort", ctypes.c_uint32), ("lookahead", ctypes.c_uint32), ("dedup_ranges", ctypes.c_uint32)]
+                ("index_sort", ctypes.c_uint32), ("lookahead", ctypes.c_uint32), ("dedup_ranges", ctypes.c_uint32),
+                ("block_log2", (ctypes.c_uint8 * 4) * 2)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["block_log2"] = [list(row) for row in self.block_log2]
+        return d
+
+
+def _tuning_from_dict(d: dict) -> Tuning:
+    d = dict(d)
+    blocks = d.pop("block_log2", None)
+    t = Tuning(**d)
+    if blocks is not None:
+        for c in range(2):
+            for b in range(4):
+                t.block_log2[c][b] = int(blocks[c][b])
+    return t
 
 
 class Options(ctypes.Structure):
@@ -266,7 +280,7 @@ class Engine:
             opt.stream = ctypes.c_void_p(s.cuda_stream)
         opt.flags = flags
         if tuning is not None:
-            self._tuning = tuning if isinstance(tuning, Tuning) else Tuning(**tuning)
+            self._tuning = tuning if isinstance(tuning, Tuning) else _tuning_from_dict(tuning)
             opt.tuning = ctypes.pointer(self._tuning)
         if trace_only is not None:
             self._trace_only = trace_only.encode()

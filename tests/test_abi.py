@@ -101,7 +101,8 @@ def test_tuning_cache_roundtrip_on_host(tmp_path):
                  '"set_load": 0.5, "index_load": 0.25, "max_blocks": 4096, "ms": 3.5}}}')
     t = fv.tuning_load(str(p), "sg")
     assert t == {"radix_bits": 11, "fuse_dedup": 1, "set_load": 0.5, "index_load": 0.25, "max_blocks": 4096,
-                 "index_rebuild": 0, "index_sort": 0, "lookahead": 0, "dedup_ranges": 0}
+                 "index_rebuild": 0, "index_sort": 0, "lookahead": 0, "dedup_ranges": 0,
+                 "block_log2": [[8, 8, 8, 8], [8, 8, 8, 8]]}
     assert fv.tuning_load(str(p), "other") is None
     assert fv.tuning_load(str(tmp_path / "missing.json"), "sg") is None
 
@@ -118,3 +119,31 @@ def test_library_shares_torchs_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.split()[0] == "1", out.stdout
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program built with the host compiler prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    mirrors = {"fv_tuning": fv.Tuning, "fv_options": fv.Options, "fv_stats": fv.Stats, "fv_term": fv.Term,
+               "fv_atom": fv.Atom, "fv_rule": fv.Rule, "fv_kprof": fv.KProf}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fv.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, got):
+        cname, field, value = line.split()
+        py = mirrors[cname]
+        want = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert int(value) == want, (cname, field, int(value), want)

@@ -22,7 +22,8 @@ def _digest(rows):
     return hashlib.sha256(np.ascontiguousarray(rows, dtype="<u4").tobytes()).hexdigest()
 
 
-MODES = {"plain": None, "tuned": {"radix_bits": 11, "fuse_dedup": 1}, "ranges": {"dedup_ranges": 1}}
+MODES = {"plain": None, "tuned": {"radix_bits": 11, "fuse_dedup": 1}, "ranges": {"dedup_ranges": 1},
+         "blocks": {"block_log2": [[7, 7, 9, 9], [7, 7, 9, 9]]}}
 
 
 @pytest.mark.parametrize("name", sorted(MAKERS))

@@ -33,6 +33,10 @@ TUNINGS = {
     "no_lookahead": {"lookahead": 1},    # every round waits for the one before
     "ranges": {"dedup_ranges": 1},       # Algorithm 2's difference over per-column indices of full
     "ranges_count": {"dedup_ranges": 1, "index_sort": 1},
+    # join and difference kernels in 128- or 512-thread blocks, or mixed by launch size
+    "blocks128": {"block_log2": [[7, 7, 7, 7], [7, 7, 7, 7]]},
+    "blocks512": {"block_log2": [[9, 9, 9, 9], [9, 9, 9, 9]]},
+    "blocks_mixed": {"block_log2": [[7, 9, 8, 9], [9, 7, 9, 7]], "fuse_dedup": 1},
 }
 
 
@@ -117,6 +121,7 @@ def test_autotune_picks_a_stored_tuning_with_the_same_fixpoint(tmp_path):
     best = fv.autotune(make, key="sg_small", cache_path=cache, reps=1)
     assert best["radix_bits"] in (8, 11) and best["fuse_dedup"] in (0, 1)
     assert best["max_blocks"] in (1024, 2048, 4096)
+    assert all(b in (7, 8, 9) for row in best["block_log2"] for b in row)
     assert fv.tuning_load(cache, "sg_small") == best
     _check(W.SG_PROGRAM, edb, relations=["sg"], tuning=best)
 

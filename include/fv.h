@@ -250,7 +250,8 @@ typedef fv_ctx* (*fv_make_ctx_fn)(const fv_options* opt, void* user);
  * by the median fv_run_fixpoint time of `reps` fresh contexts from make()
  * (reps 0 means 3).  The winner goes to *best and, if cache_path and key are
  * set, into a JSON cache file under "<gfx arch>/<key>" (other entries are
- * kept).  Errors: FV_EINVAL (null arguments, a failed trial or cache write;
+ * kept).  A candidate whose trial fails is passed over.  Errors: FV_EINVAL
+ * (null arguments, a failed trial of the defaults, or a cache write;
  * fv_global_error() tells which). */
 fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, uint32_t reps,
                       const char* cache_path, const char* key, fv_tuning* best);

@@ -231,9 +231,10 @@ fv_status fv_autotune(fv_make_ctx_fn make, void* user, const fv_options* base, u
         default: t.block_log2[(k.which - 100) / 4][(k.which - 100) % 4] = uint8_t(v); break;
       }
       if (std::memcmp(&t, &cur, sizeof(t)) == 0) continue;
+      // a candidate whose trial fails (out of memory, say) is passed over;
+      // only the defaults' trial must succeed
       const double ms = trial(make, user, base, t, reps);
-      if (ms < 0) return FV_EINVAL;
-      if (ms < cur_ms) { cur = t; cur_ms = ms; }
+      if (ms >= 0 && ms < cur_ms) { cur = t; cur_ms = ms; }
     }
   }
   *best = cur;

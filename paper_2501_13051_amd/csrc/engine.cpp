@@ -751,7 +751,7 @@ void Engine::plan_all() {
           if (shares) alts.push_back(plan_rule(ri, int(i), int(j)));
         }
       }
-      if (!alts.empty()) p.alt = groups;
+      if (!alts.empty()) { p.alt = groups; p.alt_default = true; }
       delta_plans_.push_back(p);
       for (auto& q : alts) {
         q.alt = groups;
@@ -761,6 +761,7 @@ void Engine::plan_all() {
       if (!alts.empty()) ++groups;
     }
   }
+  alt_distrusted_.assign(size_t(groups), 0);
   for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
   // Algorithm 2's difference reads an index of full on every column of a
   // derived relation (shared with any join that keys on that column alone)
@@ -1977,22 +1978,45 @@ void Engine::choose_join_algorithms(bool initial) {
 
 // FV_LEARNED: of each group of plans that differ in join order, run the one
 // whose intermediate results (every join output but the last, whose size
-// the order does not change) the predictor expects to be smallest.  The
-// predictions are those made at the end of the previous round.
+// the order does not change) the predictor expects to be smallest, if that
+// is under half of what it expects from the default order and if even the
+// worst case of that order (probe rows times each build index's longest run)
+// stays within four times that expectation: a prediction that is far too low
+// on skewed keys then cannot pick an order that explodes.  The predictions
+// are those made at the end of the previous round.  A group whose chosen
+// order once overflowed its presized buffers keeps the default order.
 void Engine::choose_join_orders() {
   for (size_t i = 0; i < delta_plans_.size();) {
     if (delta_plans_[i].alt < 0) { ++i; continue; }
-    size_t j = i, best = i;
-    double best_rows = 0;
-    for (; j < delta_plans_.size() && delta_plans_[j].alt == delta_plans_[i].alt; ++j) {
+    const int g = delta_plans_[i].alt;
+    size_t j = i;
+    std::vector<double> rows, worst;
+    double default_rows = 0;
+    for (; j < delta_plans_.size() && delta_plans_[j].alt == g; ++j) {
       const Plan& p = delta_plans_[j];
-      double rows = 0;
-      for (size_t k = 0; k + 1 < p.steps.size(); ++k)
-        if (p.steps[k].c_pred >= 0) rows += double(ctr_host_[p.steps[k].c_pred]);
-      if (j == i || rows < best_rows) { best = j; best_rows = rows; }
+      const Relation& S = rels_[p.src_rel];
+      double r = 0, w = 0;
+      double bound = double(p.steps.empty() || p.steps[0].hll < 0 ? S.n_delta
+                                                                   : ctr_host_[sketches_[p.steps[0].hll].ctr_rows]);
+      for (size_t k = 0; k + 1 < p.steps.size(); ++k) {
+        const Step& st = p.steps[k];
+        if (st.c_pred >= 0) r += double(ctr_host_[st.c_pred]);
+        bound *= st.index != kNoIndex ? double(std::max<u64>(ctr_host_[indices_[st.index].c_maxrun], 1))
+                                      : double(ctr_host_[c_full0_ + int(st.brel)]);
+        w += bound;
+      }
+      rows.push_back(r);
+      worst.push_back(w);
+      if (p.alt_default) default_rows = r;
     }
-    for (size_t k = i; k < j; ++k) delta_plans_[k].active = k == best;
-    if (best != i) ++reordered_rounds_;
+    size_t best = j;   // j: keep the default
+    if (!alt_distrusted_[size_t(g)])
+      for (size_t k = i; k < j; ++k)
+        if (!delta_plans_[k].alt_default && 2.0 * rows[k - i] < default_rows &&
+            worst[k - i] <= 4.0 * default_rows && (best == j || rows[k - i] < rows[best - i]))
+          best = k;
+    for (size_t k = i; k < j; ++k) delta_plans_[k].active = best == j ? delta_plans_[k].alt_default : k == best;
+    if (best != j) ++reordered_rounds_;
     i = j;
   }
 }
@@ -2060,9 +2084,17 @@ void Engine::grow_after_failure(bool initial) {
   for (bool f : fused_steps_) any_fused = any_fused || f;
   if (any_fused && flags_host_[0]) {
     // a presized one-pass join ran out of room: run the round again with
-    // exact count-then-write joins
+    // exact count-then-write joins, and in the default join order where the
+    // predictions had picked another (its intermediates can be far larger
+    // than predicted; it is not tried again in this fixpoint)
     ++overflows_;
     use_fused_ = false;
+    if (!initial)
+      for (auto& p : delta_plans_)
+        if (p.alt >= 0) {
+          if (p.active && !p.alt_default) alt_distrusted_[size_t(p.alt)] = 1;
+          p.active = p.alt_default;
+        }
     choose_join_algorithms(initial);
     graph_dirty_ = true;
   }
@@ -2079,9 +2111,15 @@ void Engine::grow_after_failure(bool initial) {
     const u64 need = ctr_host_[c_new0_ + int(&R - &rels_[0])];
     if (need > R.new_cap) R.new_cap = pow2_at_least(std::max<u64>(need + need / 4, R.new_cap * 2));
   }
-  for (auto& I : inters_) {
-    const u64 need = ctr_host_[I.ctr];
-    if (need > I.cap) I.cap = pow2_at_least(std::max<u64>(need + need / 4, I.cap * 2));
+  // (only the intermediates of the plans the rerun runs)
+  for (auto& p : initial ? init_plans_ : delta_plans_) {
+    if (!p.active) continue;
+    for (auto& st : p.steps) {
+      if (st.out_buf < 0) continue;
+      Inter& I = inters_[size_t(st.out_buf)];
+      const u64 need = ctr_host_[I.ctr];
+      if (need > I.cap) I.cap = pow2_at_least(std::max<u64>(need + need / 4, I.cap * 2));
+    }
   }
 }
 

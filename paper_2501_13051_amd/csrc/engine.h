@@ -135,6 +135,7 @@ struct Plan {
   bool src_delta;
   u32 second = 0;             // body position the first join reads (build side)
   int alt = -1;               // plans of one rule and delta position in other join orders share an id
+  bool alt_default = false;   // the group's most-bound-first order
   bool active = true;         // this round runs it (one plan of each alternative group)
   std::vector<Step> steps;
 };
@@ -363,6 +364,7 @@ class Engine {
   std::vector<u32> dict_host_;
   std::vector<double> qerrors_;
   u32 reordered_rounds_ = 0;
+  std::vector<char> alt_distrusted_;   // per join-order group: its predicted order overflowed once
   u32 overflows_ = 0;
   int c_ndv0_ = 0, c_hll0_ = 0, c_pred0_ = 0;
   u64 join_out_ = 0;

@@ -404,6 +404,7 @@ __global__ __launch_bounds__(kB) void k_join_fused(FusedJoinParams p) {
   __shared__ u64 s_scan[kB / kWave + 1];
   __shared__ u32 s_keep[kB / kWave + 1];
   __shared__ u64 s_base;
+  __shared__ u32 s_stop;
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   u64 begin, n;
@@ -414,6 +415,12 @@ __global__ __launch_bounds__(kB) void k_join_fused(FusedJoinParams p) {
   const u64 ntiles = (n + kFusedTile - 1) / kFusedTile;
   if (blockIdx.x == 0 && threadIdx.x == 0 && p.out_n) *p.out_n = n;
   for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // once some output did not fit, the round runs again with exact joins:
+    // the remaining tiles stop (their counts only size the rerun's buffers,
+    // which grow geometrically if they still fall short)
+    if (threadIdx.x == 0) s_stop = __hip_atomic_load(p.overflow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s_stop) break;
     const u64 t0 = tile * kFusedTile;
     u32 st[kFusedItems], cnt[kFusedItems];
     u64 mine = 0;

@@ -154,7 +154,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
       key[i] = idx < n ? in[idx] : 0;
     }
-#pragma unroll
+    // (unrolled by 8, not fully: the ranking then fits in 128 registers, four
+    // waves per SIMD, and the key and rank arrays are indexed with uniform
+    // register offsets)
+#pragma unroll 8
     for (int i = 0; i < kItems; ++i) {
       const u64 idx = t0 + u64(w) * (kWave * kItems) + u64(i) * kWave + lane;
       const bool valid = idx < n;

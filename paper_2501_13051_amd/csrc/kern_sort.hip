@@ -220,8 +220,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       if (tile > 0) {
         // walk this digit's chain back to the nearest inclusive prefix, reading
         // a window of kWin predecessor tiles per round trip (a row of the
-        // status array is contiguous over digits, so the loads coalesce)
-        constexpr int kWin = 16;
+        // status array is contiguous over digits, so the loads coalesce).
+        // The prefix is usually among the last few tiles: a window of 4 keeps
+        // the status reads at a quarter of the tile's key bytes (these loads
+        // bypass the L2, so each one costs HBM or Infinity Cache traffic).
+        constexpr int kWin = 4;
         long long t = (long long)tile - 1;
         for (;;) {
           u64 wd[kWin];

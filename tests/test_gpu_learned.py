@@ -280,3 +280,19 @@ def test_join_orders_are_parity_green_whichever_is_chosen():
             reordered[name, pname] = stats["reordered_rounds"]
     # ack (16 rows per key) is both the smaller build and the smaller worst case
     assert reordered["ack", "huge"] > 0 and reordered["ack", "build_rows"] > 0, reordered
+
+
+def test_a_failed_round_in_a_predicted_order_returns_to_the_default(monkeypatch):
+    """A round run in a join order the predictions picked that fails (forced
+    here through the test hook on the first recursive round) runs again in
+    the default order, and its group keeps the default order for the rest of
+    the fixpoint: the same result, fewer reordered rounds."""
+    w = W.ack_reach(8)
+    ref = oracle.evaluate(w.program, w.edb)
+    net = _hand_net(1)
+    _, free, _, _ = fv.evaluate(w.program, w.edb, flags=fv.FV_LEARNED, relations=["r"], predictor=net)
+    monkeypatch.setenv("FV_TEST_FAIL_ROUNDS", "2")
+    got, stats, deltas, _ = fv.evaluate(w.program, w.edb, flags=fv.FV_LEARNED, relations=["r"], predictor=net)
+    assert np.array_equal(got["r"], ref["r"]) and deltas == ref.delta_sizes
+    assert stats["redo_rounds"] >= 1
+    assert free["reordered_rounds"] >= 2 and stats["reordered_rounds"] == 1, (free, stats)

@@ -380,6 +380,7 @@ def main():
     if not args.no_extras:
         out["forms"] = extras(fv, W, torch, np, args)
         out["forms"]["learned_join_order"] = join_order_form(fv, W, torch, np, params, reps)
+        out["forms"]["difference_ab"] = difference_form(fv, W, torch, np, rd, tuning, learned, args)
         out["forms"]["host_engine"] = host_form(fv, W, torch, np)
 
     if not args.no_cpu_baseline:
@@ -518,6 +519,33 @@ def join_order_form(fv, W, torch, np, params, reps):
     out["speedup_trained_vs_zero_predictor"] = round(out["zero_predictor"]["ms"] / out["trained"]["ms"], 3)
     out["speedup_trained_vs_plain"] = round(out["plain"]["ms"] / out["trained"]["ms"], 3)
     del r
+    return out
+
+
+def difference_form(fv, W, torch, np, rd, tuning, learned, args):
+    """The two differences against full side by side: the tuple set of full's
+    packed tuples (the default) and Algorithm 2's range test over per-column
+    indices of full (dedup_ranges), on the headline (same knobs otherwise)
+    and on the same-generation forest.  Median of three fixpoints (five on the
+    forest), one for Algorithm 2 on RDFS."""
+    log("difference A/B: tuple set vs Algorithm 2")
+    out = {}
+    base = dict(tuning) if tuning else {}
+    # (Algorithm 2 takes about 20 s per RDFS fixpoint: one untimed-warm-up-free run)
+    for mode, reps in ((0, 3), (1, 1)):
+        t = dict(base, dedup_ranges=mode)
+        if mode == 0:
+            rd.run_once(tuning=t, **learned)
+        ms, st = rd.time_runs(reps, tuning=t, **learned)
+        out[f"rdfs_20M_learned_{'ranges' if mode else 'tuple_set'}_ms"] = round(ms, 2)
+    wsg = W.config_sg()
+    sg = Runner(fv, torch, np, wsg.program, wsg.edb, ["sg"])
+    for mode in (0, 1):
+        t = {"dedup_ranges": mode}
+        sg.run_once(tuning=t)
+        ms, _ = sg.time_runs(5, tuning=t)
+        out[f"sg_forest_64x1024_{'ranges' if mode else 'tuple_set'}_ms"] = round(ms, 3)
+    del sg
     return out
 
 

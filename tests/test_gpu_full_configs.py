@@ -65,8 +65,10 @@ def _plain_traces():
 
 
 def test_rdfs_full_size_learned_mode_matches_oracle_digest():
-    """Config 5 in its stated mode: the learned predictor on, trained (on the
-    GPU) from the plain engine's traces of the other four configurations."""
+    """The 20M-triple RDFS workload in its learned mode: the predictor on,
+    trained (on the GPU) from the plain engine's traces of the transitive-
+    closure, same-generation, points-to and batched transitive-closure
+    workloads."""
     T = _plain_traces()
     params, loss = fv.mlp_train(T[:, :8], T[:, 8], steps=2000, lr=3e-3, seed=1)
     assert np.isfinite(loss)

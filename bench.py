@@ -523,28 +523,31 @@ def join_order_form(fv, W, torch, np, params, reps):
 
 
 def difference_form(fv, W, torch, np, rd, tuning, learned, args):
-    """The two differences against full side by side: the tuple set of full's
-    packed tuples (the default) and Algorithm 2's range test over per-column
-    indices of full (dedup_ranges), on the headline (same knobs otherwise)
-    and on the same-generation forest.  Median of three fixpoints (five on the
-    forest), one for Algorithm 2 on RDFS."""
-    log("difference A/B: tuple set vs Algorithm 2")
+    """The three differences against full side by side: the tuple set of
+    full's packed tuples (the default), Algorithm 2's range test over
+    per-column indices of full, and the search of each sorted tile's window
+    of full's sorted keys with a merge after every round (dedup_ranges 0, 1,
+    2), on the headline (same knobs otherwise) and on the same-generation
+    forest.  Median of three fixpoints (five on the forest), one for
+    Algorithm 2 on RDFS."""
+    log("difference A/B: tuple set, Algorithm 2, sorted merge")
+    names = {0: "tuple_set", 1: "ranges", 2: "sorted_merge"}
     out = {}
     base = dict(tuning) if tuning else {}
-    # (Algorithm 2 takes about 20 s per RDFS fixpoint: one untimed-warm-up-free run)
-    for mode, reps in ((0, 3), (1, 1)):
+    # (Algorithm 2 takes about 20 s per RDFS fixpoint: one run, no warm-up)
+    for mode, reps in ((0, 3), (2, 3), (1, 1)):
         t = dict(base, dedup_ranges=mode)
-        if mode == 0:
+        if mode != 1:
             rd.run_once(tuning=t, **learned)
         ms, st = rd.time_runs(reps, tuning=t, **learned)
-        out[f"rdfs_20M_learned_{'ranges' if mode else 'tuple_set'}_ms"] = round(ms, 2)
+        out[f"rdfs_20M_learned_{names[mode]}_ms"] = round(ms, 2)
     wsg = W.config_sg()
     sg = Runner(fv, torch, np, wsg.program, wsg.edb, ["sg"])
-    for mode in (0, 1):
+    for mode in (0, 2, 1):
         t = {"dedup_ranges": mode}
         sg.run_once(tuning=t)
         ms, _ = sg.time_runs(5, tuning=t)
-        out[f"sg_forest_64x1024_{'ranges' if mode else 'tuple_set'}_ms"] = round(ms, 3)
+        out[f"sg_forest_64x1024_{names[mode]}_ms"] = round(ms, 3)
     del sg
     return out
 

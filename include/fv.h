@@ -98,11 +98,14 @@ typedef struct {
   uint32_t lookahead;      /* 0 (default): enqueue each plain eager round before the previous
                               round's counters are read back, where the program allows it
                               (no join reads an index of a derived relation); 1: never */
-  uint32_t dedup_ranges;   /* 0 (default): the difference against full probes a hash set of full's
+  uint32_t dedup_ranges;   /* the difference against full: 0 (default) probes a hash set of full's
                               packed tuples; 1: Algorithm 2 -- per-column indices of full (the
                               join indices' layout, kept up to date every round), a new tuple's
                               value ranges in them, an empty range or an empty intersection of
-                              the ranges proving it new; no tuple set is kept */
+                              the ranges proving it new; 2: full's packed tuples kept in ascending
+                              order, each tile of sorted new tuples searched in the window of
+                              them it spans, the survivors merged in after every round (merge
+                              path).  Modes 1 and 2 keep no tuple set and take no look-ahead. */
   uint8_t block_log2[2][4]; /* threads per block as log2 (7, 8 or 9; 0: 8) of the join kernels
                               (probe, write, one-pass join, selection: [0][b]) and of the
                               difference pass ([1][b]), per launch size bucket b: at most 2^16,
@@ -244,7 +247,7 @@ typedef fv_ctx* (*fv_make_ctx_fn)(const fv_options* opt, void* user);
 /* Autotuner.  Coordinate search over fv_tuning: starting from the defaults,
  * each knob in turn (radix_bits {8,11}, fuse_dedup {0,1}, set_load
  * {0.25,0.5}, index_load {0.25,0.5}, max_blocks {1024,2048,4096}, index_rebuild
- * {0,1}, index_sort {0,1}, lookahead {0,1}, dedup_ranges {0,1}, then each
+ * {0,1}, index_sort {0,1}, lookahead {0,1}, dedup_ranges {0,2}, then each
  * kernel class's block size per size bucket, block_log2[c][b] {7,8,9}) is set to
  * every candidate with the others at their best so far; a candidate is scored
  * by the median fv_run_fixpoint time of `reps` fresh contexts from make()

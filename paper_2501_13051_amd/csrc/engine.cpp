@@ -59,7 +59,7 @@ Engine::Engine(const fv_options* opt) {
   tune_.index_rebuild = tune_.index_rebuild ? 1 : 0;
   if (tune_.index_sort > 2) tune_.index_sort = 0;
   tune_.lookahead = tune_.lookahead ? 1 : 0;
-  tune_.dedup_ranges = tune_.dedup_ranges ? 1 : 0;
+  if (tune_.dedup_ranges > 2) tune_.dedup_ranges = 0;
   for (auto& cls : tune_.block_log2)
     for (auto& l : cls)
       if (l != 7 && l != 9) l = 8;
@@ -114,7 +114,7 @@ Engine::~Engine() {
   drop_graph();
   for (auto& R : rels_) {
     for (int c = 0; c < 3; ++c) { release(R.stage[c]); release(R.col[c]); }
-    release(R.newk); release(R.newk2); release(R.set);
+    release(R.newk); release(R.newk2); release(R.set); release(R.sfull); release(R.sfull2);
   }
   for (auto& ix : indices_) {
     release(ix.table); release(ix.perm); release(ix.pcap); release(ix.dcnt); release(ix.wl);
@@ -765,7 +765,7 @@ void Engine::plan_all() {
   for (auto& r : rules_) rels_[r.head.rel].used_as_head = true;
   // Algorithm 2's difference reads an index of full on every column of a
   // derived relation (shared with any join that keys on that column alone)
-  if (tune_.dedup_ranges)
+  if (tune_.dedup_ranges == 1)
     for (u32 ri = 0; ri < rels_.size(); ++ri)
       if (rels_[ri].used_as_head)
         for (u32 c = 0; c < rels_[ri].arity; ++c) rels_[ri].dix[c] = get_index(ri, 1, &c, 0, nullptr, nullptr);
@@ -928,6 +928,26 @@ bool Engine::ensure_capacity(bool dry) {
       release(R.newk2);
       R.newk = alloc(R.new_cap * 8);
       R.newk2 = alloc(R.new_cap * 8);
+    }
+    // the difference by merge: full's sorted keys and the merge's output hold
+    // full after this round (its rows plus every new tuple it may append)
+    const u64 need_sorted = R.n_full + std::max<u64>(R.new_cap, R.staged);
+    if (merge_diff() && R.sfull_cap < need_sorted) {
+      if (dry) return true;
+      const u64 nc = std::max<u64>(need_sorted, 2 * R.sfull_cap);
+      Buf a = alloc(nc * 8), b;
+      try {
+        b = alloc(nc * 8);
+      } catch (...) {
+        release(a);
+        throw;
+      }
+      if (R.n_full) hip(hipMemcpyAsync(a.p, R.sfull.p, R.n_full * 8, hipMemcpyDeviceToDevice, stream_), "sorted copy");
+      release(R.sfull);
+      release(R.sfull2);
+      R.sfull = a;
+      R.sfull2 = b;
+      R.sfull_cap = nc;
     }
     max_rows = std::max(max_rows, R.new_cap);
   }
@@ -1317,6 +1337,12 @@ void Engine::collect_events(u64 upto, bool discard) {
         }
         break;
       }
+      case 20: {   // merge of full's sorted keys with the survivors: every key of full read and written
+        const u64 n = C(pe.ref0);
+        bytes = double(n) * 16;
+        items = n;
+        break;
+      }
       case 5: {   // difference + append: key read, set probe, column writes of survivors
         const u64 n = C(pe.ref0), d = C(pe.ref1);
         bytes = double(n) * 16 + double(d) * 4 * double(pe.aux);
@@ -1602,7 +1628,15 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.set = use_set && !R.set32 ? R.set.as<u64>() : nullptr;
   dp.set32 = use_set && R.set32 ? R.set.as<u32>() : nullptr;
   dp.ones = use_set && R.set32 ? ctr(R.c_ones) : nullptr;
-  if (tune_.dedup_ranges && in_round && R.used_as_head) {
+  if (merge_diff() && R.used_as_head) {
+    // the difference against full's sorted keys; the survivors' keys go to the
+    // sort's free buffer, and one merge writes full's keys in order with them
+    // (taken over when the round succeeds)
+    dp.sorted_full = R.sfull.as<u64>();
+    dp.surv = dst;
+    R.merged_this_round = true;
+  }
+  if (tune_.dedup_ranges == 1 && in_round && R.used_as_head) {
     // full is empty before the first round (ingest), so only rounds need the test
     dp.rd.ncol = R.arity;
     for (u32 c = 0; c < R.arity; ++c) {
@@ -1632,6 +1666,25 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.ts = ev_begin(kd, true);
   launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_, block_for(1, R.new_cap)), "dedup launch");
   ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
+  if (dp.sorted_full) {
+    const int km = kclass("merge_full");
+    ev_begin(km);
+    launched(launch_merge_sorted(dp.surv, ctr(c_delta0_ + ri), R.sfull.as<u64>(), ctr(c_full0_ + ri),
+                                 R.sfull2.as<u64>(), R.n_full + R.new_cap, flags, stream_),
+             "merge launch");
+    ev_end(km, 0, 20, c_full0_ + ri);
+  }
+}
+
+// A round that succeeded (or the ingest) merged the survivors into the second
+// sorted copy of full: it becomes the current one.
+void Engine::take_merged_full() {
+  for (auto& R : rels_) {
+    if (!R.merged_this_round) continue;
+    std::swap(R.sfull, R.sfull2);
+    R.merged_this_round = false;
+    graph_dirty_ = true;   // a captured round holds the old pointers
+  }
 }
 
 void Engine::commit_relation(Relation& R) {
@@ -1847,6 +1900,7 @@ void Engine::ingest() {
   for (auto& R : rels_)
     if (R.staged) commit_relation(R);
   read_counters();
+  take_merged_full();
   for (auto& R : rels_) {
     const int ri = int(&R - &rels_[0]);
     R.n_full = ctr_host_[c_full0_ + ri];
@@ -2126,6 +2180,7 @@ void Engine::grow_after_failure(bool initial) {
 // A round that raised no flag: size the next one from it and take over its
 // counters (full, delta, derived) on the host.
 void Engine::finish_round(bool initial, std::chrono::steady_clock::time_point th) {
+  take_merged_full();
   if (log_joins_) log_joins(initial);
   // (a program without recursive rules derives nothing after round 0)
   if (!learned_ && !delta_plans_.empty()) {
@@ -2183,7 +2238,8 @@ void Engine::finish_round(bool initial, std::chrono::steady_clock::time_point th
 // Applies to eager plain rounds whose joins read no index of a derived
 // relation (those indices are updated between rounds on the host's word).
 bool Engine::can_look_ahead() const {
-  if (tune_.lookahead || learned_ || log_joins_ || use_graph_ || delta_plans_.empty()) return false;
+  // (the difference by merge swaps full's sorted copy after each round the host has seen succeed)
+  if (tune_.lookahead || learned_ || log_joins_ || use_graph_ || delta_plans_.empty() || merge_diff()) return false;
   for (auto& ix : indices_)
     if (rels_[ix.rel].used_as_head) return false;
   return true;

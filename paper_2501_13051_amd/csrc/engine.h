@@ -62,6 +62,12 @@ struct Relation {
   u64 prev_new = 0;          //   and of the round before it
   // tuple set of full, for the difference operator
   Buf set;
+  // difference by merge (dedup_ranges = 2): full's packed tuples in ascending
+  // order, and the buffer the round's merge writes (swapped in when the round
+  // succeeds)
+  Buf sfull, sfull2;
+  u64 sfull_cap = 0;
+  bool merged_this_round = false;
   u64 set_cap = 0;
   u64 set_min = 0;           // lower bound on the next set size (after a set-full round)
   bool set_stale = false;    // holds keys of an aborted round: rebuild before the next one
@@ -238,6 +244,8 @@ class Engine {
   void plan_all();
   Plan plan_rule(u32 rule, int delta_pos, int second = -1);
   void choose_join_orders();
+  void take_merged_full();
+  bool merge_diff() const { return tune_.dedup_ranges == 2; }
   u32 block_for(int cls, u64 rows) const;
   u32 get_index(u32 rel, u32 nkey, const u32* keycol, u32 nfilt, const u32* fcol, const u32* fval);
   void ingest();

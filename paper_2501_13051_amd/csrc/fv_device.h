@@ -394,6 +394,37 @@ __device__ __forceinline__ u32 take_ticket(u32* ticket, u32 ntiles, u32* lds_slo
 }
 
 __device__ __forceinline__ u64 min_u64(u64 a, u64 b) { return a < b ? a : b; }
+
+// lower_bound_u64 by a whole wave (every lane calls it with the same
+// arguments and gets the same result): each round probes 64 evenly spaced
+// keys at once and keeps the gap between the last one below k and the next,
+// so a search over n keys takes about log64(n) round trips instead of log2(n).
+__device__ __forceinline__ u64 wave_lower_bound_u64(const u64* v, u64 lo, u64 hi, u64 k) {
+  const u32 lane = u32(__lane_id());
+  while (hi - lo > u64(kWave)) {
+    const u64 step = (hi - lo + kWave - 1) / kWave;
+    const u64 pos = lo + u64(lane) * step;
+    const bool below = pos < hi && v[pos] < k;
+    const u32 c = u32(__popcll(__ballot(below)));   // the lanes below k are a prefix
+    if (c == 0) return lo;
+    const u64 nlo = lo + u64(c - 1) * step + 1;
+    const u64 nxt = lo + u64(c) * step;
+    if (c < u32(kWave) && nxt < hi) hi = nxt;
+    lo = nlo;
+  }
+  const bool below = lo + lane < hi && v[lo + lane] < k;
+  return lo + u64(__popcll(__ballot(below)));
+}
+
+// First index in [lo, hi) of ascending v whose key is >= k (hi if none).
+__device__ __forceinline__ u64 lower_bound_u64(const u64* v, u64 lo, u64 hi, u64 k) {
+  while (lo < hi) {
+    const u64 mid = (lo + hi) >> 1;
+    if (v[mid] < k) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
 __device__ __forceinline__ u32 min_u32(u32 a, u32 b) { return a < b ? a : b; }
 
 __device__ __forceinline__ u32 launch_epoch(const u32* base, u32 off) { return (*base + off) & kEpochMask; }

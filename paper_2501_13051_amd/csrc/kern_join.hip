@@ -625,6 +625,9 @@ __global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kB / kWave + 1];
   __shared__ u64 s_excl;
+  __shared__ u64 s_win[2];
+  constexpr u32 kWinKeys = 2048;   // full's keys staged per tile (difference by merge)
+  __shared__ u64 s_wkeys[kWinKeys];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   u64 begin, n;
@@ -660,6 +663,39 @@ __global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
       for (int k = 0; k < kDedupItems; ++k) {
         if (ins[k] < 0) *p.set_full = 1;   // never the flag this kernel checks on entry
         surv[k] = first[k] && ins[k] > 0;
+        mine += surv[k] ? 1u : 0u;
+      }
+    } else if (p.sorted_full) {
+      // full's keys that can equal this tile's lie in [lo, hi): the first
+      // two waves search all of full for the two ends at once (64 probes per
+      // round trip); a window of up to kWinKeys keys is staged in LDS and
+      // searched there, a longer one in place
+      const int wv = threadIdx.x / kWave;
+      if (wv < 2) {
+        const u64 nb = fbase;
+        const u64 k0 = p.keys[begin + u64(tile) * kDedupTile];
+        const u64 k1 = p.keys[begin + min_u64(u64(tile + 1) * kDedupTile, n) - 1];
+        u64 r;
+        if (wv == 0) r = wave_lower_bound_u64(p.sorted_full, 0, nb, k0);
+        else r = k1 == ~0ull ? nb : wave_lower_bound_u64(p.sorted_full, 0, nb, k1 + 1);
+        if (lane_id() == 0) s_win[wv] = r;
+      }
+      __syncthreads();
+      const u64 lo = s_win[0], hi = s_win[1];
+      const bool staged = hi - lo <= kWinKeys;
+      if (staged)
+        for (u64 q = threadIdx.x; q < hi - lo; q += kB) s_wkeys[q] = p.sorted_full[lo + q];
+      __syncthreads();
+      const u64* win = staged ? s_wkeys : p.sorted_full + lo;
+      const u64 wn = hi - lo;
+#pragma unroll
+      for (int k = 0; k < kDedupItems; ++k) {
+        bool present = false;
+        if (first[k]) {
+          const u64 q = lower_bound_u64(win, 0, wn, key[k]);
+          present = q < wn && win[q] == key[k];
+        }
+        surv[k] = first[k] && !present;
         mine += surv[k] ? 1u : 0u;
       }
     } else if (p.rd.ncol) {
@@ -703,12 +739,69 @@ __global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
         const u64 m = (p.width[c] >= 32) ? 0xFFFFFFFFull : ((1ull << p.width[c]) - 1);
         p.cols[c][pos] = u32((key[k] >> p.shift[c]) & m);
       }
+      if (p.surv) p.surv[pos - fbase] = key[k];
       ++pos;
     }
     if (tile == ntiles - 1 && threadIdx.x == 0) *p.out_delta = s_excl + tot;
     __syncthreads();
   }
   ktime_end(p.ts);
+}
+
+// ------------------------------------------------------------------ merge of sorted keys
+// Merge path: output tile t of kMergeTile keys takes a[i0, i1) and b[j0, j1),
+// where i + j = t * kMergeTile splits the two inputs at the t-th step of
+// their merge (found by binary search on that diagonal); the tile's inputs
+// are staged in LDS and each thread finds its own split there, then writes
+// its kMergeItems outputs in order.
+constexpr u32 kMergeItems = 8;
+constexpr u32 kMergeTile = kBlock * kMergeItems;
+
+// The split of the merge of a[0, na) and b[0, nb) after d outputs: the number
+// of a's keys among the first d (keys are distinct across the two arrays).
+__device__ __forceinline__ u64 merge_split(const u64* a, u64 na, const u64* b, u64 nb, u64 d) {
+  u64 lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const u64 i = (lo + hi) >> 1;   // take i of a and d - i of b: too few of a if a[i] < b[d - i - 1]
+    if (a[i] < b[d - i - 1]) lo = i + 1;
+    else hi = i;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_sorted(const u64* a, const u64* a_n, const u64* b, const u64* b_n,
+                                                         u64* out, const u32* abort) {
+  __shared__ u64 s_in[kMergeTile];
+  __shared__ u64 s_split[2];
+  if (abort && *abort) return;
+  const u64 na = *a_n, nb = *b_n, total = na + nb;
+  for (u64 t = blockIdx.x; t * kMergeTile < total; t += gridDim.x) {
+    const u64 d0 = t * kMergeTile;
+    const u64 d1 = min_u64(d0 + kMergeTile, total);
+    if (threadIdx.x == 0) {
+      s_split[0] = merge_split(a, na, b, nb, d0);
+      s_split[1] = merge_split(a, na, b, nb, d1);
+    }
+    __syncthreads();
+    const u64 i0 = s_split[0], i1 = s_split[1];
+    const u64 j0 = d0 - i0, j1 = d1 - i1;
+    const u32 la = u32(i1 - i0), lb = u32(j1 - j0);
+    for (u32 q = threadIdx.x; q < la + lb; q += kBlock) s_in[q] = q < la ? a[i0 + q] : b[j0 + (q - la)];
+    __syncthreads();
+    const u64* sa = s_in;
+    const u64* sb = s_in + la;
+    const u32 e0 = threadIdx.x * kMergeItems;
+    if (e0 < la + lb) {
+      u32 i = u32(merge_split(sa, la, sb, lb, e0));
+      u32 j = e0 - i;
+      const u32 e1 = e0 + kMergeItems < la + lb ? e0 + kMergeItems : la + lb;
+      for (u32 e = e0; e < e1; ++e) {
+        const bool take_a = j >= lb || (i < la && sa[i] < sb[j]);
+        out[d0 + e] = take_a ? sa[i++] : sb[j++];
+      }
+    }
+    __syncthreads();   // s_in and s_split are reused by the next tile
+  }
 }
 
 __global__ void k_commit(CommitParams p) {
@@ -809,6 +902,14 @@ int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream, u32 block) {
   const u64 tile = block_of(block) * kDedupItems;
   const u64 tiles = (rows_cap + tile - 1) / tile;
   FV_LAUNCH_BLOCK(k_dedup, block, grid_for(tiles, 2048), stream, p);
+  return int(hipGetLastError());
+}
+
+int launch_merge_sorted(const u64* a, const u64* a_n, const u64* b, const u64* b_n, u64* out, u64 cap,
+                        const u32* abort, void* stream) {
+  const u64 tiles = (cap + kMergeTile - 1) / kMergeTile;
+  hipLaunchKernelGGL(k_merge_sorted, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, a, a_n, b,
+                     b_n, out, abort);
   return int(hipGetLastError());
 }
 

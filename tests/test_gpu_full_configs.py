@@ -23,7 +23,7 @@ def _digest(rows):
 
 
 MODES = {"plain": None, "tuned": {"radix_bits": 11, "fuse_dedup": 1}, "ranges": {"dedup_ranges": 1},
-         "blocks": {"block_log2": [[7, 7, 9, 9], [7, 7, 9, 9]]}}
+         "blocks": {"block_log2": [[7, 7, 9, 9], [7, 7, 9, 9]]}, "merge": {"dedup_ranges": 2}}
 
 
 @pytest.mark.parametrize("name", sorted(MAKERS))

@@ -33,6 +33,8 @@ TUNINGS = {
     "no_lookahead": {"lookahead": 1},    # every round waits for the one before
     "ranges": {"dedup_ranges": 1},       # Algorithm 2's difference over per-column indices of full
     "ranges_count": {"dedup_ranges": 1, "index_sort": 1},
+    "merge": {"dedup_ranges": 2},        # difference against full's sorted keys, merged in every round
+    "merge_tight": {"dedup_ranges": 2, "radix_bits": 11, "max_blocks": 256},
     # join and difference kernels in 128- or 512-thread blocks, or mixed by launch size
     "blocks128": {"block_log2": [[7, 7, 7, 7], [7, 7, 7, 7]]},
     "blocks512": {"block_log2": [[9, 9, 9, 9], [9, 9, 9, 9]]},
@@ -447,6 +449,20 @@ def test_tiny_initial_capacities_grow(case, flags, monkeypatch):
     monkeypatch.setenv("FV_TEST_SMALL_CAPS", "1")
     _, stats, _ = _check(prog, edb, relations=rels, flags=flags)
     assert stats["redo_rounds"] >= 1, stats
+
+
+@pytest.mark.parametrize("case", ["tc", "sg", "pointsto", "rdfs"])
+@pytest.mark.parametrize("flags", [fv.FV_PLAIN, fv.FV_GRAPH], ids=["eager", "graph"])
+def test_merge_difference_with_failed_rounds_and_growth(case, flags, monkeypatch):
+    """The difference by merge keeps a sorted copy of full that a round
+    replaces only when it succeeds: rounds made to fail and buffers that start
+    at 256 rows (the sorted copies grow with them) leave the fixpoint as the
+    oracle's, eager and with the recursive round captured."""
+    prog, edb, rels = _workload(case)
+    monkeypatch.setenv("FV_TEST_SMALL_CAPS", "1")
+    monkeypatch.setenv("FV_TEST_FAIL_ROUNDS", "2,3,6")
+    _, stats, _ = _check(prog, edb, relations=rels, flags=flags, tuning={"dedup_ranges": 2})
+    assert stats["redo_rounds"] >= 3, stats
 
 
 @pytest.mark.parametrize("seed", range(38, 46))

@@ -306,7 +306,8 @@ def _batch_engines(instances, tuning=None, flags=fv.FV_PLAIN):
     return engines
 
 
-@pytest.mark.parametrize("n_inst,tuning", [(1, "default"), (7, "default"), (64, "default"), (7, "index_sort")])
+@pytest.mark.parametrize("n_inst,tuning", [(1, "default"), (7, "default"), (64, "default"), (7, "index_sort"),
+                                           (7, "merge"), (64, "blocks_mixed")])
 def test_batched_tc_matches_per_instance_oracle(n_inst, tuning):
     insts = W.batched_tc_instances(n_instances=n_inst, seed=77 + n_inst)
     engines = _batch_engines(insts, TUNINGS[tuning])

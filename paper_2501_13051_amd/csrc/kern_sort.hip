@@ -89,17 +89,17 @@ struct FuseArgs {
   u64* ts;             // trace timing slot (nullable)
 };
 
-template <int kBits, bool kFuse, int kItems>
-__global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, u64* __restrict__ out,
+template <int kBits, bool kFuse, int kItems, int kB>
+__global__ __launch_bounds__(kB) void k_rs_pass(const u64* __restrict__ in, u64* __restrict__ out,
                                                    const u64* n_ctr, u64 n_const, u64 cap, u32 shift,
                                                    const u32* hist_p, u64* status, u32* ticket,
                                                    const u32* epoch_base, u32 epoch_off, const u32* abort,
                                                    FuseArgs fz) {
   constexpr int kRadix = 1 << kBits;
-  constexpr int kWaves = kBlock / kWave;
+  constexpr int kWaves = kB / kWave;
   // kItems keys per thread (see launch_rs_pass for the choice)
-  constexpr u32 kTile = kBlock * kItems;
-  constexpr int kDpt = kRadix > kBlock ? kRadix / kBlock : 1;   // digits owned per thread
+  constexpr u32 kTile = kB * kItems;
+  constexpr int kDpt = kRadix > kB ? kRadix / kB : 1;   // digits owned per thread
   __shared__ u64 s_keys[kTile];
   __shared__ u32 s_wcnt[kWaves][kRadix];
   __shared__ u32 s_tstart[kRadix + 1];
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
       run += d < kRadix ? hist_p[d] : 0u;
     }
     u32 tot;
-    u32 ex = block_exclusive_sum<kBlock>(run, s_scan32, &tot);
+    u32 ex = block_exclusive_sum<kB>(run, s_scan32, &tot);
     for (int j = 0; j < kDpt; ++j) {
       const int d = threadIdx.x * kDpt + j;
       if (d < kRadix) { s_base[d] = ex; ex += hist_p[d]; }
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
   for (;;) {
     const u32 tile = take_ticket(ticket, ntiles, &s_ticket);
     if (tile >= ntiles) break;
-    for (int i = threadIdx.x; i < kWaves * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+    for (int i = threadIdx.x; i < kWaves * kRadix; i += kB) (&s_wcnt[0][0])[i] = 0;
     __syncthreads();
     const u64 t0 = u64(tile) * kTile;
     u64 key[kItems];
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     }
     {
       u32 ttot;
-      u32 ex = block_exclusive_sum<kBlock>(my_total, s_scan32, &ttot);
+      u32 ex = block_exclusive_sum<kB>(my_total, s_scan32, &ttot);
       for (int j = 0; j < kDpt; ++j) {
         const int d = threadIdx.x * kDpt + j;
         if (d < kRadix) s_tstart[d] = ex;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
     if (!kFuse) {
 #pragma unroll
       for (int i = 0; i < kItems; ++i) {
-        const u32 q = u32(i) * kBlock + threadIdx.x;
+        const u32 q = u32(i) * kB + threadIdx.x;
         if (q < tn) {
           const u64 k = s_keys[q];
           const u32 dq = u32((k >> shift) & (kRadix - 1));
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_pass(const u64* __restrict__ in, 
         mine += surv[i] ? 1u : 0u;
       }
       u32 tot;
-      const u32 ex = block_exclusive_sum<kBlock>(mine, s_scan32, &tot);
+      const u32 ex = block_exclusive_sum<kB>(mine, s_scan32, &tot);
       if (threadIdx.x == 0)
         s_out = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(fz.out_delta), (unsigned long long)tot) : 0;
       __syncthreads();
@@ -381,17 +381,22 @@ int launch_rs_pass(const SortParams& p, u32 pass, const u64* src, u64* dst, u32 
   // 8 otherwise, where more, smaller tiles keep the chip busy (small sorts),
   // 11-bit digit counters need the LDS, or the fused pass probes the set.
   const bool wide = db == 8 && !fuse && (p.n_hint ? p.n_hint : p.cap) >= (u64(1) << 22);
-#define FV_PASS(B, F, I)                                                                                     \
-  hipLaunchKernelGGL((k_rs_pass<B, F, I>), dim3(pgrid), dim3(kBlock), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, sh, \
-                     h, p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
+#define FV_PASS(B, F, I, T, G)                                                                               \
+  hipLaunchKernelGGL((k_rs_pass<B, F, I, T>), dim3(G), dim3(T), 0, s, src, dst, p.n_ctr, p.n_const, p.cap, sh, h, \
+                     p.status, p.ticket, p.epoch_base, epoch_off, p.abort, fz)
   if (db == 11) {
-    if (fuse) FV_PASS(11, true, 8); else FV_PASS(11, false, 8);
+    if (fuse) FV_PASS(11, true, 8, kBlock, pgrid); else FV_PASS(11, false, 8, kBlock, pgrid);
   } else if (fuse) {
-    FV_PASS(8, true, 8);
+    FV_PASS(8, true, 8, kBlock, pgrid);
   } else if (wide) {
-    FV_PASS(8, false, 16);
+    // 512-thread blocks: 8,192-key tiles, half the tiles (and their
+    // look-back chains) of 256-thread blocks, at the same four waves per SIMD
+    const u64 wtiles = (p.cap + 8192 - 1) / 8192;
+    const u64 wmax = maxg / 2 ? maxg / 2 : 1;
+    const int wgrid = int(wtiles == 0 ? 1 : (wtiles > wmax ? wmax : wtiles));
+    FV_PASS(8, false, 16, 512, wgrid);
   } else {
-    FV_PASS(8, false, 8);
+    FV_PASS(8, false, 8, kBlock, pgrid);
   }
 #undef FV_PASS
   return int(hipGetLastError());

@@ -1734,7 +1734,11 @@ void Engine::build_index(Index& ix) {
   ev_begin(kc);
   if (ix.sort_shift) {
     // sorted build: (row, slot) words, a radix sort over the slot bits, runs
-    launched(launch_index_slotkeys(p, R.cap, ixk_a_.as<u64>(), ix.sort_shift, stream_), "index keys launch");
+    // (the keys kernel counts the sort's digits: no histogram pass)
+    u32* ihist = hist_dev_.as<u32>() + rels_.size() * kHistWords;
+    launched(launch_index_slotkeys(p, R.cap, ixk_a_.as<u64>(), ix.sort_shift, ihist, sort_passes(ix.sort_bits, 8),
+                                   stream_),
+             "index keys launch");
     SortParams sp{};
     sp.a = ixk_a_.as<u64>();
     sp.b = ixk_b_.as<u64>();
@@ -1748,7 +1752,7 @@ void Engine::build_index(Index& ix) {
     sp.ticket = ticket_dev_.as<u32>();
     sp.epoch_base = epoch_base();
     sp.abort = flags_dev_.as<u32>();
-    launched(launch_rs_hist(sp, stream_, true), "index hist launch");
+    if (sort_passes(ix.sort_bits, 8) > 8) launched(launch_rs_hist(sp, stream_, true), "index hist launch");
     u64* src = sp.a;
     u64* dst = sp.b;
     for (u32 pass = 0; pass < sort_passes(ix.sort_bits, 8); ++pass) {
@@ -1821,12 +1825,6 @@ void Engine::update_index(Index& ix) {
     return;
   }
   // many appended rows with short runs: sort the appended rows by slot first
-  {
-    const int kc = kclass("index_upd_keys");
-    ev_begin(kc);
-    launched(launch_index_update_keys(p, dcap, ixk_a_.as<u64>(), ix.upd_shift, stream_), "index keys launch");
-    ev_end(kc, 0, 15, int(ix.rel), -1, u64(ix.nkey + ix.nfilt));
-  }
   SortParams sp{};
   sp.a = ixk_a_.as<u64>();
   sp.b = ixk_b_.as<u64>();
@@ -1840,10 +1838,21 @@ void Engine::update_index(Index& ix) {
   sp.ticket = ticket_dev_.as<u32>();
   sp.epoch_base = epoch_base();
   sp.abort = flags_dev_.as<u32>();
-  const int kh = kclass("sort_hist");
-  ev_begin(kh);
-  launched(launch_rs_hist(sp, stream_, true), "index hist launch");
-  ev_end(kh, 0, 4, c_delta0_ + int(ix.rel), -1, dcap);
+  {
+    // the keys kernel counts the sort's digits as it writes the words
+    const int kc = kclass("index_upd_keys");
+    ev_begin(kc);
+    launched(launch_index_update_keys(p, dcap, ixk_a_.as<u64>(), ix.upd_shift, sp.hist, sort_passes(sp.bits, 8),
+                                      stream_),
+             "index keys launch");
+    ev_end(kc, 0, 15, int(ix.rel), -1, u64(ix.nkey + ix.nfilt));
+  }
+  if (sort_passes(sp.bits, 8) > 8) {
+    const int kh = kclass("sort_hist");
+    ev_begin(kh);
+    launched(launch_rs_hist(sp, stream_, true), "index hist launch");
+    ev_end(kh, 0, 4, c_delta0_ + int(ix.rel), -1, dcap);
+  }
   u64* src = sp.a;
   u64* dst = sp.b;
   const int kpass = kclass("sort_pass");

@@ -346,7 +346,11 @@ int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 wl_cap, u6
 // listed old runs, places the appended rows and clears the counts, walking
 // the table in slot order.  ts[0..3] time the runs, reserve, move and fill
 // launches (nullable).
-int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, void* stream);
+// With hist (passes <= 8), the words' 8-bit digits of the first `passes`
+// radix passes are counted into hist (cleared here), so that the caller's
+// sort needs no histogram pass; hist may be null.
+int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, u32* hist,
+                             u32 passes, void* stream);
 // Move an index into a larger table (tab, pcap of cap slots, cleared here):
 // keys, runs and regions carried over, perm untouched; bit 0 of *full (also
 // cleared here) reports a key that found no slot.
@@ -357,10 +361,12 @@ int launch_index_update_sorted(const IndexParams& p, u64 delta_rows_cap, const u
 // Sorted build, in three steps on one stream: launch_index_slotkeys clears
 // the table and writes keys[r] = r << row_shift | slot for rows r < n of the
 // source (slot = cap for rows outside the filter); the caller radix-sorts
-// keys over bits [0, row_shift) (row_shift a multiple of the digit width);
+// keys over bits [0, row_shift) (row_shift a multiple of the digit width;
+// hist as for launch_index_update_keys);
 // launch_index_runs turns the sorted words into perm, counts and starts.
 // keys holds rows_cap words.
-int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, void* stream);
+int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, u32* hist, u32 passes,
+                          void* stream);
 int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32 row_shift, void* stream);
 
 int launch_fill_u64(u64* p, u64 n, u64 value, void* stream);

@@ -642,8 +642,20 @@ __device__ __forceinline__ u64 index_insert_probe(Slot* tab, u64 mask, u64 key) 
   return kNoSlot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_idx_slotkeys(IndexParams p, u64* keys, u32 row_shift) {
+// With hist, the words' 8-bit digits of the first `passes` passes are also
+// counted (an LDS copy per block, lanes that share a digit adding once), so
+// that their radix sort needs no histogram pass.
+constexpr u32 kSlotHistPasses = 8;
+
+__global__ __launch_bounds__(kBlock) void k_idx_slotkeys(IndexParams p, u64* keys, u32 row_shift, u32* hist,
+                                                         u32 passes) {
+  __shared__ u32 s_h[kSlotHistPasses * 256];
   if (p.abort && *p.abort) return;
+  if (hist) {
+    for (u32 i = threadIdx.x; i < passes * 256; i += kBlock) s_h[i] = 0;
+    __syncthreads();
+  }
+  const u64 lt_mask = (1ull << lane_id()) - 1;
   u64 begin, n;
   source_range(p.src, begin, n);
   const u64 mask = p.cap - 1;
@@ -667,20 +679,48 @@ __global__ __launch_bounds__(kBlock) void k_idx_slotkeys(IndexParams p, u64* key
     u64 home[kS];
 #pragma unroll
     for (int j = 0; j < kS; ++j) home[j] = (in[j] && !full) ? p.table[mix64(key[j]) & mask].key : kEmptyKey;
+    u64 word[kS];
 #pragma unroll
     for (int j = 0; j < kS; ++j) {
       const u64 r = r0 + j * stride;
-      if (r >= n) break;
-      u64 slot = p.cap;   // rows outside the filter sort after every slot
-      if (in[j]) {
-        slot = full ? kNoSlot
-                    : home[j] == key[j] ? (mix64(key[j]) & mask) : index_insert_probe(p.table, mask, key[j]);
-        if (slot == kNoSlot) {
-          if (p.full && !full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
-          slot = 0;
+      word[j] = 0;
+      if (r < n) {
+        u64 slot = p.cap;   // rows outside the filter sort after every slot
+        if (in[j]) {
+          slot = full ? kNoSlot
+                      : home[j] == key[j] ? (mix64(key[j]) & mask) : index_insert_probe(p.table, mask, key[j]);
+          if (slot == kNoSlot) {
+            if (p.full && !full) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
+            slot = 0;
+          }
+        }
+        word[j] = (r << row_shift) | slot;
+        keys[r] = word[j];
+      }
+    }
+    if (hist) {
+#pragma unroll
+      for (int j = 0; j < kS; ++j) {
+        const bool valid = r0 + j * stride < n;
+        for (u32 q = 0; q < passes; ++q) {
+          const u32 dg = u32(word[j] >> (8 * q)) & 255u;
+          const u32 d0 = __builtin_amdgcn_readfirstlane(dg);
+          const bool same = valid && dg == d0;
+          const u64 m = __ballot(same);
+          if (same) {
+            if ((m & lt_mask) == 0) atomicAdd(&s_h[q * 256 + d0], u32(__popcll(m)));
+          } else if (valid) {
+            atomicAdd(&s_h[q * 256 + dg], 1u);
+          }
         }
       }
-      keys[r] = (r << row_shift) | slot;
+    }
+  }
+  if (hist) {
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < passes * 256; i += kBlock) {
+      const u32 c = s_h[i];
+      if (c) atomicAdd(&hist[i], c);
     }
   }
 }
@@ -754,11 +794,15 @@ int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream) {
   return int(hipGetLastError());
 }
 
-int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, void* stream) {
+int launch_index_slotkeys(const IndexParams& p, u64 rows_cap, u64* keys, u32 row_shift, u32* hist, u32 passes,
+                          void* stream) {
   hipStream_t s = (hipStream_t)stream;
+  if (passes > kSlotHistPasses) hist = nullptr;
+  if (hist) launch_fill_u32(hist, u64(passes) * 256, 0u, stream);
   hipLaunchKernelGGL(k_idx_clear, dim3(grid_rows(p.cap, 4096)), dim3(kBlock), 0, s, p.table, p.cap, p.abort, p.ndv,
                      p.maxrun, p.full, p.rows);
-  hipLaunchKernelGGL(k_idx_slotkeys, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, keys, row_shift);
+  hipLaunchKernelGGL(k_idx_slotkeys, dim3(grid_rows(rows_cap, 8192)), dim3(kBlock), 0, s, p, keys, row_shift, hist,
+                     passes);
   return int(hipGetLastError());
 }
 
@@ -773,9 +817,12 @@ int launch_index_rehash(const Slot* old_tab, const u32* old_pcap, u64 old_cap, S
   return int(hipGetLastError());
 }
 
-int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, void* stream) {
+int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys, u32 row_shift, u32* hist,
+                             u32 passes, void* stream) {
+  if (passes > kSlotHistPasses) hist = nullptr;
+  if (hist) launch_fill_u32(hist, u64(passes) * 256, 0u, stream);
   hipLaunchKernelGGL(k_idx_slotkeys, dim3(grid_rows(delta_rows_cap, 8192)), dim3(kBlock), 0, (hipStream_t)stream, p,
-                     keys, row_shift);
+                     keys, row_shift, hist, passes);
   return int(hipGetLastError());
 }
 

@@ -56,6 +56,10 @@ def parse_args():
     ap.add_argument("--load-predictor", default=None,
                     help="use these parameters (.npy written by --save-predictor) instead of training, so that a "
                          "profiled run holds only the headline workload's kernels")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the large-join sweep (for profiling it) and print its result")
+    ap.add_argument("--sweep-case", type=int, default=-1,
+                    help="with --sweep-only: run only this case of the sweep (0, 1 or 2)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain and zero-predictor runs beside the headline")
     return ap.parse_args()
@@ -260,6 +264,11 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
+    if args.sweep_only:
+        copy_probe(torch, args)
+        print(json.dumps({"large_join_sweep": join_sweep(fv, W, torch, np, args.sweep_case)}), flush=True)
+        return
+
     # the predictor: trained here, on this GPU, from the plain engine's traces
     if args.load_predictor:
         params = np.load(args.load_predictor).astype(np.float32)
@@ -288,14 +297,7 @@ def main():
                                  reps=3)
             tuning_source = "autotuner (this run)"
         log(f"tuning {tuning} ({tuning_source})")
-    if args.copy_probe_mb > 0:
-        n = args.copy_probe_mb << 18
-        x = torch.ones(n, dtype=torch.float32, device="cuda")
-        y = torch.empty_like(x)
-        y.copy_(x)
-        torch.cuda.synchronize()
-        log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
-        del x, y
+    copy_probe(torch, args)
 
     # dominant kernel class: most time over three traced passes (outside the timed region)
     per_class = {}
@@ -401,10 +403,10 @@ def cpu_model():
 
 def cpu_baseline(W):
     """The oracle (single-threaded sorted-vector semi-naive) on the same
-    workload at 1/20 scale, pinned to one host core, once."""
+    workload at 1/10 scale, pinned to one host core, once."""
     import oracle
-    log("timing the oracle on a 1/20-scale sample of the RDFS workload")
-    sample = W.config_rdfs(scale=0.05)
+    log("timing the oracle on a 1/10-scale sample of the RDFS workload")
+    sample = W.config_rdfs(scale=0.1)
     old = os.sched_getaffinity(0)
     core = min(old)
     try:
@@ -414,7 +416,7 @@ def cpu_baseline(W):
         os.sched_setaffinity(0, old)
     derived = sum(r.delta_sizes)
     return {"value": round(derived / r.seconds, 1), "unit": "tuples/s", "cores": 1, "kind": "oracle",
-            "sample": f"the RDFS generator at 1/20 scale ({sample.meta['triples']} triples, same rules and "
+            "sample": f"the RDFS generator at 1/10 scale ({sample.meta['triples']} triples, same rules and "
                       f"hierarchies): {derived} derived tuples in {r.seconds:.2f} s, one run pinned to host core "
                       f"{core} ({cpu_model()}; {len(old)} cores available to the process)"}
 
@@ -591,9 +593,25 @@ def host_form(fv, W, torch, np):
     return out
 
 
-def join_sweep(fv, W, torch, np):
+def copy_probe(torch, args):
+    """A device copy of known size, for calibrating the HBM traffic counters."""
+    if args.copy_probe_mb <= 0:
+        return
+    n = args.copy_probe_mb << 18
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy probe: {args.copy_probe_mb} MiB read + {args.copy_probe_mb} MiB written")
+    del x, y
+
+
+def join_sweep(fv, W, torch, np, only=-1):
     cases = []
-    for n_probe, n_keys, zipf_s in ((1 << 24, 1 << 20, 0.0), (1 << 26, 1 << 22, 0.0), (1 << 25, 1 << 21, 1.0)):
+    sizes = ((1 << 24, 1 << 20, 0.0), (1 << 26, 1 << 22, 0.0), (1 << 25, 1 << 21, 1.0))
+    for i, (n_probe, n_keys, zipf_s) in enumerate(sizes):
+        if only >= 0 and i != only:
+            continue
         w = W.join_case(n_probe, n_keys, zipf_s)
         r = Runner(fv, torch, np, w.program, w.edb, ["out"])
         r.run_once(flags=fv.FV_TRACE)

@@ -72,7 +72,7 @@ KERNEL_SOURCES = {"sort_pass": "kern_sort.hip", "sort_pass_dedup": "kern_sort.hi
                   "join_onepass": "kern_join.hip", "select": "kern_join.hip", "index_build": "kern_index.hip",
                   "index_upd_count": "kern_index.hip", "index_upd_reserve": "kern_index.hip",
                   "index_upd_move": "kern_index.hip", "index_upd_fill": "kern_index.hip",
-                  "index_upd_keys": "kern_index.hip", "index_upds_runs": "kern_index.hip",
+                  "index_upd_keys": "kern_index.hip",
                   "index_upds_reserve": "kern_index.hip", "index_upds_fill": "kern_index.hip"}
 
 

@@ -849,7 +849,7 @@ bool Engine::ensure_capacity(bool dry) {
   // look-back status arrays and row-id scratch are sized for the largest
   // launch any round can make before capacities change again: a delta is at
   // most the previous round's new tuples, so new_cap bounds it
-  u64 max_probe = 1, max_rows = 1, sort_rows = 0, moves_need = 0;
+  u64 max_probe = 1, max_rows = 1, sort_rows = 0, word_rows = 0, moves_need = 0;
   auto plan_probe = [&](const Plan& p, bool initial) {
     const Relation& S = rels_[p.src_rel];
     const u64 n0 = initial ? S.n_full : std::max<u64>(S.n_delta, S.new_cap);
@@ -1078,12 +1078,14 @@ bool Engine::ensure_capacity(bool dry) {
     // over them): mostly distinct keys then cost random table and counter
     // accesses per row, and a few hot keys serialise the counting update's
     // atomics, where the sorted words are walked in slot order.  The words fit
-    // in new_cap words of scratch.
+    // in new_cap words of scratch.  Before the first round (which reads every
+    // fact as its delta) the facts stand in for the last round's rows.
     u32 upd_shift = 0;
     const double share = ix.rows_seen && R.n_full ? double(ix.rows_seen) / double(R.n_full) : 1.0;
+    const u64 last_rows = deltas_.empty() ? R.n_full : R.n_delta;
     if (R.used_as_head &&
         (tune_.index_sort == 2 ||
-         (tune_.index_sort == 0 && R.n_delta >= (u64(1) << 20) && (ix.nfilt == 0 || share >= 0.25)))) {
+         (tune_.index_sort == 0 && last_rows >= (u64(1) << 20) && (ix.nfilt == 0 || share >= 0.25)))) {
       const u32 slot_bits = bits_for(ix.cap) - 1 + (ix.nfilt ? 1 : 0);
       const u32 shift = sort_passes(slot_bits, 8) * 8;
       if (shift + bits_for(std::max<u64>(R.new_cap, 1) - 1) <= 64) {
@@ -1091,6 +1093,8 @@ bool Engine::ensure_capacity(bool dry) {
         sort_rows = std::max(sort_rows, R.new_cap);
       }
     }
+    // (a counting update notes a word per appended row in the same scratch)
+    if (R.used_as_head) word_rows = std::max(word_rows, R.new_cap);
     if (!dry) {
       ix.sort_shift = sort_shift;
       ix.sort_bits = sort_bits;
@@ -1103,12 +1107,13 @@ bool Engine::ensure_capacity(bool dry) {
     moves_ = alloc(moves_need * sizeof(RunMove));
     moves_cap_ = moves_need;
   }
-  if (ixk_cap_ < sort_rows) {
+  word_rows = std::max(word_rows, sort_rows);
+  if (ixk_cap_ < word_rows) {
     if (dry) return true;
     release(ixk_a_); release(ixk_b_);
-    ixk_a_ = alloc(sort_rows * 8);
-    ixk_b_ = alloc(sort_rows * 8);
-    ixk_cap_ = sort_rows;
+    ixk_a_ = alloc(word_rows * 8);
+    ixk_b_ = alloc(word_rows * 8);
+    ixk_cap_ = word_rows;
   }
   max_rows = std::max(max_rows, sort_rows);
   for (auto& I : inters_) {
@@ -1302,12 +1307,9 @@ void Engine::collect_events(u64 upto, bool discard) {
         items = appended;
         break;
       }
-      case 16: case 17: case 18: case 19: {   // sorted update steps: words in slot order
+      case 17: case 18: case 19: {   // sorted update steps: words in slot order
         const u64 appended = C(c_delta0_ + pe.ref0);
-        if (pe.kind == 16) {          // runs: words read (with a neighbour), counters at run ends
-          bytes = double(appended) * 8;
-          items = appended;
-        } else if (pe.kind == 17) {   // reserve: words read; slot, counters, region per run head
+        if (pe.kind == 17) {          // reserve: words read; slot, count, region per run head
           bytes = double(appended) * 8;
           items = appended;
         } else if (pe.kind == 18) {   // move: listed old rows read and written
@@ -1322,8 +1324,8 @@ void Engine::collect_events(u64 upto, bool discard) {
       case 10: case 11: case 12: case 13: {   // index update steps (see update_index)
         const u64 appended = C(c_delta0_ + pe.ref0), touched = C(pe.ref1);
         const double cols = double(pe.aux >> 32);
-        if (pe.kind == 10) {          // count: key columns of every appended row; per touched key slot + counters
-          bytes = double(appended) * 4 * cols + double(touched) * 24;
+        if (pe.kind == 10) {          // count: key columns read and (slot, place) written per appended row;
+          bytes = double(appended) * (4 * cols + 8) + double(touched) * 24;   // slot + counter per touched key
           items = appended;
         } else if (pe.kind == 11) {   // reserve: work list, counters, slot, region size per touched key
           bytes = double(touched) * 36;
@@ -1331,8 +1333,8 @@ void Engine::collect_events(u64 upto, bool discard) {
         } else if (pe.kind == 12) {   // move: listed old rows read and written
           items = C(int(pe.aux & 0xFFFFFFFFu));
           bytes = double(items) * 8;
-        } else {                      // fill: key columns again, row id written; slot per touched key
-          bytes = double(appended) * (4 * cols + 4) + double(touched) * 16;
+        } else {                      // fill: (slot, place) read, row id written; slot + counter per touched key
+          bytes = double(appended) * (8 + 4) + double(touched) * 20;
           items = appended;
         }
         break;
@@ -1807,8 +1809,8 @@ void Engine::update_index(Index& ix) {
   const u64 dcap = std::max<u64>(R.new_cap, 1);
   // each step is its own kernel class, timed by its own stamps (a step that
   // gets no stamp slot goes untimed)
-  auto stamps = [&](const char* const* names, int kind0, u64* ts) {
-    for (int k = 0; k < 4; ++k) {
+  auto stamps = [&](const char* const* names, int count, int kind0, u64* ts) {
+    for (int k = 0; k < count; ++k) {
       const int cls = kclass(names[k]);
       ts[k] = reinterpret_cast<u64>(ev_begin(cls, true));
       if (ts[k]) ev_end(cls, 0, kind0 + k, int(ix.rel), ix.c_wl, (u64(ix.nkey + ix.nfilt) << 32) | u64(ix.c_mrows));
@@ -1819,8 +1821,9 @@ void Engine::update_index(Index& ix) {
   u64* ts[4];
   if (!ix.upd_shift) {
     const char* names[4] = {"index_upd_count", "index_upd_reserve", "index_upd_move", "index_upd_fill"};
-    stamps(names, 10, tsv);
+    stamps(names, 4, 10, tsv);
     for (int k = 0; k < 4; ++k) ts[k] = reinterpret_cast<u64*>(tsv[k]);
+    p.rword = ixk_a_.as<u64>();   // new_cap words (sized in ensure_capacity)
     launched(launch_index_update(p, dcap, ix.cap, ts, stream_), "index update launch");
     return;
   }
@@ -1862,9 +1865,9 @@ void Engine::update_index(Index& ix) {
     ev_end(kpass, 0, 3, c_delta0_ + int(ix.rel), -1, dcap);
     std::swap(src, dst);
   }
-  const char* names[4] = {"index_upds_runs", "index_upds_reserve", "index_upd_move", "index_upds_fill"};
-  stamps(names, 16, tsv);
-  for (int k = 0; k < 4; ++k) ts[k] = reinterpret_cast<u64*>(tsv[k]);
+  const char* names[3] = {"index_upds_reserve", "index_upd_move", "index_upds_fill"};
+  stamps(names, 3, 17, tsv);
+  for (int k = 0; k < 3; ++k) ts[k] = reinterpret_cast<u64*>(tsv[k]);
   launched(launch_index_update_sorted(p, dcap, src, ix.upd_shift, ts, stream_), "index update launch");
 }
 

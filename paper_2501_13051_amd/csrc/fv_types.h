@@ -325,27 +325,29 @@ struct IndexParams {
   u64* moves_n;          // chunks listed (zero before the update)
   u64 moves_cap;
   u64* moved_rows;       // rows in the listed chunks (nullable; traces)
+  u64* rword;            // counting update: per appended row, slot << 32 | place (scratch, delta_rows_cap words)
   const u32* abort2;     // a second flag that cancels an update (set-full round)
   u64* ts;               // trace timing slot of the launch (see ktime_start), nullable
 };
 int launch_index_build(const IndexParams& p, u64 rows_cap, void* stream);
-// Incremental update over the appended rows, four launches on one stream:
-// count the appended rows per key (inserting new keys) and list the touched
-// slots; give every touched run room for its appended rows (a run that
+// Incremental update over the appended rows, five launches on one stream:
+// count the appended rows per key (inserting new keys), list the touched
+// slots and note each row's slot and place among its key's appended rows in
+// rword; give every touched run room for its appended rows (a run that
 // outgrows its region gets one of twice its new size at the bump pointer,
 // short runs copied on the spot, long ones listed in chunks); copy the listed
-// chunks; place the appended rows after each key's old rows.  No slot or row
-// that the round did not touch is read or written.  ts[0..3] time the four
-// launches (nullable).
+// chunks; place the appended rows after each key's old rows; clear the
+// touched slots' appended counts.  No slot or row that the round did not
+// touch is read or written.  ts[0..3] time the first four launches
+// (nullable).
 int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 wl_cap, u64* const* ts, void* stream);
 // The same update for many appended rows with mostly distinct keys, after
 // sorting them by slot: launch_index_update_keys writes the appended rows'
 // words (row - begin) << row_shift | slot (inserting new keys); the caller
-// radix-sorts them over the slot bits; launch_index_update_sorted derives
-// per-slot counts from run boundaries, reserves room per run head, copies
-// listed old runs, places the appended rows and clears the counts, walking
-// the table in slot order.  ts[0..3] time the runs, reserve, move and fill
-// launches (nullable).
+// radix-sorts them over the slot bits; launch_index_update_sorted reserves
+// room per run head (a run's length from its boundaries), copies listed old
+// runs and places the appended rows, walking the table in slot order.
+// ts[0..2] time the reserve, move and fill launches (nullable).
 // With hist (passes <= 8), the words' 8-bit digits of the first `passes`
 // radix passes are counted into hist (cleared here), so that the caller's
 // sort needs no histogram pass; hist may be null.

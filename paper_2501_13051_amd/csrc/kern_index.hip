@@ -275,7 +275,11 @@ __global__ __launch_bounds__(kBlock) void k_idx_rehash(const Slot* __restrict__ 
 // ------------------------------------------------------------------ update
 // Update, step 1: the appended rows per key, grouped per tile in LDS, added
 // to dcnt (new keys are inserted into the table with an empty run); a slot
-// whose dcnt was zero joins the work list (one atomic per wave).
+// whose dcnt was zero joins the work list (one atomic per tile).  The value
+// dcnt had before a group's add is the group's first place among the key's
+// appended rows, so every appended row leaves rword[r] = slot << 32 | place
+// (all ones when the row is not indexed): the placement then needs neither
+// the grouping nor the table probe nor a second atomic per group.
 __global__ __launch_bounds__(kBlock) void k_upd_count(IndexParams p) {
   __shared__ IdxLds m;
   __shared__ u32 s_c[kBlock / kWave + 1];
@@ -298,14 +302,22 @@ __global__ __launch_bounds__(kBlock) void k_upd_count(IndexParams p) {
     u32 pushes = 0;
     for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
       const u32 c = m.cnt[e];
-      u32 slot = ~0u;
+      u32 slot = ~0u, first = 0u;
       if (c && !(__hip_atomic_load(p.full, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1)) {
         const u64 h = index_insert(p.table, mask, m.key[e]);
-        if (h == kNoSlot) atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
-        else if (atomicAdd(&p.dcnt[h], c) == 0u) slot = u32(h);
+        if (h == kNoSlot) {
+          atomicOr(reinterpret_cast<unsigned long long*>(p.full), 1ull);
+        } else {
+          first = atomicAdd(&p.dcnt[h], c);
+          slot = u32(h);
+        }
       }
+      // the group's count is no longer needed: cnt now holds its first place
+      // (top bit: the slot joins the work list)
+      const bool push = slot != ~0u && first == 0u;
       m.pos[e] = slot;
-      pushes += slot != ~0u ? 1u : 0u;
+      m.cnt[e] = push ? (first | 0x80000000u) : first;
+      pushes += push ? 1u : 0u;
     }
     u32 tot;
     const u32 ex = block_exclusive_sum<kBlock>(pushes, s_c, &tot);
@@ -315,87 +327,92 @@ __global__ __launch_bounds__(kBlock) void k_upd_count(IndexParams p) {
     u64 at = s_wbase + ex;
     for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
       const u32 slot = m.pos[e];
-      if (slot == ~0u) continue;
+      if (slot == ~0u || !(m.cnt[e] & 0x80000000u)) continue;
       if (at < p.cap) p.wl[at] = slot;
       ++at;
+    }
+    // (only indexed rows get a word: the placement tests the filter again)
+#pragma unroll
+    for (u32 k = 0; k < kIdxItems; ++k) {
+      if (ent[k] == ~0u) continue;
+      const u32 slot = m.pos[ent[k]];
+      p.rword[tile * kIdxTile + threadIdx.x + u64(k) * kBlock] =
+          slot == ~0u ? ~0ull : (u64(slot) << 32) | u64((m.cnt[ent[k]] & 0x7FFFFFFFu) + rank[k]);
     }
     __syncthreads();
   }
   ktime_end(p.ts);
 }
 
-// Copy the old runs of the lanes that want one (at most kInlineCopy rows
-// each) with the whole wave: one run at a time, its rows spread over the
-// lanes, so each copy is one coalesced load and store.  Every lane of the
-// wave must call this.
+// Copy a lane's old run (at most kInlineCopy rows) to its new region by the
+// lane itself, kLaneCopy rows at a time with all of their loads in flight
+// before the stores: every lane of the wave copies at once, so a wave whose
+// lanes all move short runs waits for a few round trips, not one per run.
 constexpr u32 kInlineCopy = 64;
-__device__ __forceinline__ void wave_copy_runs(u32* perm, bool want, u32 from, u64 to, u32 count) {
-  u64 ball = __ballot(want);
-  const u32 lane = u32(lane_id());
-  while (ball) {
-    // four runs per step: all their loads go out before any store
-    u32 f[4], c[4], v[4];
-    u64 t[4];
+constexpr u32 kLaneCopy = 8;
+__device__ __forceinline__ void lane_copy_run(u32* perm, bool want, u32 from, u64 to, u32 count) {
+  if (!want) return;
+  for (u32 b = 0; b < count; b += kLaneCopy) {
+    u32 v[kLaneCopy];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      c[q] = 0;
-      f[q] = 0;
-      t[q] = 0;
-      if (ball) {
-        const int l = __ffsll((unsigned long long)ball) - 1;
-        ball &= ball - 1;
-        f[q] = __shfl(from, l, kWave);
-        t[q] = __shfl(to, l, kWave);
-        c[q] = __shfl(count, l, kWave);
-      }
-    }
+    for (u32 i = 0; i < kLaneCopy; ++i) v[i] = b + i < count ? perm[u64(from) + b + i] : 0u;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = lane < c[q] ? perm[f[q] + lane] : 0u;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (lane < c[q]) perm[t[q] + lane] = v[q];
+    for (u32 i = 0; i < kLaneCopy; ++i)
+      if (b + i < count) perm[to + b + i] = v[i];
   }
 }
 
 constexpr u32 kMoveChunk = 1u << 16;   // rows per listed chunk of an old run
 
-// Room for the run of slot s (act): when its old rows plus appended rows
-// exceed its region, a region of twice that many positions from the bump
-// pointer (one atomic per block step), the old rows copied there by the wave
-// (at most kInlineCopy) or listed in chunks, and start / region size set.  A
-// block-uniform call: every thread of the block must make it.
-__device__ __forceinline__ void reserve_run(const IndexParams& p, bool act, u32 s, u32 c_old, u64 need, u64* s_scan,
-                                            u64* s_base) {
-  const u64 newcap = act && need > p.pcap[s] ? (need < 8 ? 16 : 2 * need) : 0;
+// Room for the runs of kResItems slots per thread (act[i], slot s[i] with
+// c_old[i] old rows at position from[i], need[i] rows after the update):
+// a run whose rows exceed its region gets a region of twice that many
+// positions from the bump pointer (one atomic per block step for all of the
+// block's runs), its old rows copied there on the spot (at most kInlineCopy)
+// or listed in chunks, and its start / region size set.  A block-uniform
+// call: every thread of the block must make it.
+constexpr int kResItems = 8;
+__device__ __forceinline__ void reserve_runs(const IndexParams& p, const bool* act, const u32* s, const u32* c_old,
+                                             const u32* from, const u64* need, u64* s_scan, u64* s_base) {
+  u64 newcap[kResItems], mine = 0;
+#pragma unroll
+  for (int i = 0; i < kResItems; ++i) {
+    newcap[i] = act[i] && need[i] > p.pcap[s[i]] ? (need[i] < 8 ? 16 : 2 * need[i]) : 0;
+    mine += newcap[i];
+  }
   u64 btot;
-  const u64 excl = block_exclusive_sum<kBlock>(newcap, s_scan, &btot);
+  const u64 excl = block_exclusive_sum<kBlock>(mine, s_scan, &btot);
   if (threadIdx.x == 0) *s_base = btot ? atomicAdd(reinterpret_cast<unsigned long long*>(p.top), (unsigned long long)btot) : 0;
   __syncthreads();
-  const u64 start_new = *s_base + excl;
+  u64 at = *s_base + excl;
   __syncthreads();
-  const bool fits = newcap && start_new + newcap <= p.perm_cap;
-  const u32 from = fits ? p.table[s].start : 0u;
-  wave_copy_runs(p.perm, fits && c_old <= kInlineCopy, from, start_new, c_old);
-  if (!newcap) return;
-  if (!fits) {
-    atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);   // rebuilt with more positions
-    return;
-  }
-  if (c_old > kInlineCopy) {
-    const u32 chunks = (c_old + kMoveChunk - 1) / kMoveChunk;
-    const u64 at = atomicAdd(reinterpret_cast<unsigned long long*>(p.moves_n), (unsigned long long)chunks);
-    if (at + chunks > p.moves_cap) {
-      atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
-    } else {
-      if (p.moved_rows) atomicAdd(reinterpret_cast<unsigned long long*>(p.moved_rows), (unsigned long long)c_old);
-      for (u32 q = 0; q < chunks; ++q) {
-        const u32 off = q * kMoveChunk;
-        p.moves[at + q] = RunMove{from + off, u32(start_new) + off, min_u32(kMoveChunk, c_old - off)};
+#pragma unroll
+  for (int i = 0; i < kResItems; ++i) {
+    const u64 start_new = at;
+    at += newcap[i];
+    const bool fits = newcap[i] && start_new + newcap[i] <= p.perm_cap;
+    lane_copy_run(p.perm, fits && c_old[i] <= kInlineCopy, from[i], start_new, c_old[i]);
+    if (!newcap[i]) continue;
+    if (!fits) {
+      atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);   // rebuilt with more positions
+      continue;
+    }
+    if (c_old[i] > kInlineCopy) {
+      const u32 chunks = (c_old[i] + kMoveChunk - 1) / kMoveChunk;
+      const u64 m = atomicAdd(reinterpret_cast<unsigned long long*>(p.moves_n), (unsigned long long)chunks);
+      if (m + chunks > p.moves_cap) {
+        atomicOr(reinterpret_cast<unsigned long long*>(p.full), 2ull);
+      } else {
+        if (p.moved_rows) atomicAdd(reinterpret_cast<unsigned long long*>(p.moved_rows), (unsigned long long)c_old[i]);
+        for (u32 q = 0; q < chunks; ++q) {
+          const u32 off = q * kMoveChunk;
+          p.moves[m + q] = RunMove{from[i] + off, u32(start_new) + off, min_u32(kMoveChunk, c_old[i] - off)};
+        }
       }
     }
+    p.table[s[i]].start = u32(start_new);
+    p.pcap[s[i]] = u32(newcap[i]);
   }
-  p.table[s].start = u32(start_new);
-  p.pcap[s] = u32(newcap);
 }
 
 // The index statistics grow by the round's rows and new keys: one atomic per
@@ -412,9 +429,10 @@ __device__ __forceinline__ void flush_update_stats(const IndexParams& p, u64 row
 }
 
 // Update, step 2: per touched slot (the work list), room for its appended
-// rows (reserve_run).  The slot's appended count is cleared (also when the
-// update fails, so that the rebuild finds it zero), and the index statistics
-// grow by the round's rows and keys.
+// rows (reserve_run); the slot's count becomes old + appended rows (dcnt
+// keeps the appended count for the placement; k_upd_clear then clears it,
+// also when the update fails, so that the rebuild finds it zero), and the
+// index statistics grow by the round's rows and keys.
 __global__ __launch_bounds__(kBlock) void k_upd_reserve(IndexParams p) {
   __shared__ u64 s_scan[kBlock / kWave + 1];
   __shared__ u64 s_base;
@@ -422,27 +440,37 @@ __global__ __launch_bounds__(kBlock) void k_upd_reserve(IndexParams p) {
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
   const u64 n = min_u64(*p.wl_n, p.cap);   // the work list holds at most one entry per slot
-  const bool failed = (*p.full & 1) != 0;   // keys missing: the index is rebuilt, only clear dcnt
+  const bool failed = (*p.full & 1) != 0;   // keys missing: the index is rebuilt (k_upd_clear clears dcnt)
   u64 st_rows = 0, st_keys = 0, st_long = 0;
   // every thread of a block runs the same number of steps (the block and
   // wave operations below need all of them)
-  for (u64 b0 = u64(blockIdx.x) * kBlock; b0 < n; b0 += u64(gridDim.x) * kBlock) {
-    const u64 i = b0 + threadIdx.x;
-    const bool valid = i < n;
-    u32 s = 0, d = 0, c_old = 0;
-    if (valid) {
-      s = p.wl[i];
-      d = p.dcnt[s];
-      p.dcnt[s] = 0u;
-      c_old = p.table[s].count;
+  constexpr u64 kStep = u64(kBlock) * kResItems;
+  for (u64 b0 = u64(blockIdx.x) * kStep; b0 < n; b0 += u64(gridDim.x) * kStep) {
+    bool act[kResItems];
+    u32 s[kResItems], d[kResItems], c_old[kResItems], from[kResItems];
+    u64 need[kResItems];
+#pragma unroll
+    for (int i = 0; i < kResItems; ++i) {
+      const u64 k = b0 + u64(i) * kBlock + threadIdx.x;
+      act[i] = k < n && !failed;
+      s[i] = act[i] ? p.wl[k] : 0u;
     }
-    const bool act = valid && !failed;
-    const u64 need = u64(c_old) + d;
-    reserve_run(p, act, s, c_old, need, s_scan, &s_base);
-    if (act) {
-      st_rows += d;
-      st_keys += c_old == 0 ? 1u : 0u;
-      st_long = need > st_long ? need : st_long;
+#pragma unroll
+    for (int i = 0; i < kResItems; ++i) {
+      d[i] = act[i] ? p.dcnt[s[i]] : 0u;
+      const Slot sl = act[i] ? p.table[s[i]] : Slot{0, 0u, 0u};
+      c_old[i] = sl.count;
+      from[i] = sl.start;
+      need[i] = u64(c_old[i]) + d[i];
+    }
+    reserve_runs(p, act, s, c_old, from, need, s_scan, &s_base);
+#pragma unroll
+    for (int i = 0; i < kResItems; ++i) {
+      if (!act[i]) continue;
+      p.table[s[i]].count = u32(need[i]);
+      st_rows += d[i];
+      st_keys += c_old[i] == 0 ? 1u : 0u;
+      st_long = need[i] > st_long ? need[i] : st_long;
     }
   }
   flush_update_stats(p, st_rows, st_keys, st_long, s_scan);
@@ -464,42 +492,33 @@ __global__ __launch_bounds__(kBlock) void k_upd_move(IndexParams p) {
   ktime_end(p.ts);
 }
 
-// Update, step 4: each appended row goes after its key's old rows, at its
-// rank among the key's appended rows (one atomic per key and tile on the
-// run's count, which ends as old + appended rows).
+// Update, step 4: each appended row goes after its key's old rows, at the
+// place k_upd_count gave it (count - dcnt is the old row count).
 __global__ __launch_bounds__(kBlock) void k_upd_fill(IndexParams p) {
-  __shared__ IdxLds m;
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   if (p.abort2 && *p.abort2) return;
   if (*p.full & 3) return;   // keys or positions missing: the index is rebuilt
   u64 begin, n;
   source_range(p.src, begin, n);
-  const u64 mask = p.cap - 1;
-  const u64 ntiles = (n + kIdxTile - 1) / kIdxTile;
-  for (u64 tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    lds_map_clear(m);
-    __syncthreads();
-    u32 ent[kIdxItems], rank[kIdxItems];
-    map_tile(p, m, begin, n, tile, ent, rank);
-    __syncthreads();
-    for (u32 e = threadIdx.x; e < kLdsMap; e += kBlock) {
-      const u32 c = m.cnt[e];
-      if (!c) continue;
-      const u64 h = index_slot_of(p.table, mask, m.key[e]);
-      m.pos[e] = h == kNoSlot ? ~0u : p.table[h].start + atomicAdd(&p.table[h].count, c);
-    }
-    __syncthreads();
-#pragma unroll
-    for (u32 k = 0; k < kIdxItems; ++k) {
-      if (ent[k] == ~0u) continue;
-      const u32 base = m.pos[ent[k]];
-      if (base == ~0u) continue;
-      p.perm[base + rank[k]] = u32(begin + tile * kIdxTile + threadIdx.x + u64(k) * kBlock);
-    }
-    __syncthreads();
+  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < n; r += u64(gridDim.x) * kBlock) {
+    if (p.nfilt && !row_indexed(p, begin + r)) continue;
+    const u64 w = p.rword[r];
+    if (w == ~0ull) continue;
+    const u32 s = u32(w >> 32);
+    const Slot sl = p.table[s];
+    p.perm[u64(sl.start) + (sl.count - p.dcnt[s]) + u32(w)] = u32(begin + r);
   }
   ktime_end(p.ts);
+}
+
+// Update, step 5: the appended counts of the touched slots cleared for the
+// next update.
+__global__ __launch_bounds__(kBlock) void k_upd_clear(IndexParams p) {
+  if (p.abort && *p.abort) return;
+  if (p.abort2 && *p.abort2) return;
+  const u64 n = min_u64(*p.wl_n, p.cap);
+  for (u64 i = u64(blockIdx.x) * kBlock + threadIdx.x; i < n; i += u64(gridDim.x) * kBlock) p.dcnt[p.wl[i]] = 0u;
 }
 
 // ------------------------------------------------------------------ sorted update
@@ -508,37 +527,35 @@ __global__ __launch_bounds__(kBlock) void k_upd_fill(IndexParams p) {
 // accesses to the table and the counters) first sorts the appended rows'
 // (row, slot) words by slot, as the sorted build does (k_idx_slotkeys over the
 // appended range, then the radix sort).  Every per-slot access below then
-// walks the table in slot order: run boundaries give each touched slot's
-// appended count and where its rows begin among the words (wl doubles as that
-// per-slot position), the run head reserves room as k_upd_reserve does, and
-// appended word j of slot s goes to start(s) + old count(s) + (j - head(s)).
+// walks the table in slot order: the first word of each slot's run (its head)
+// finds where the run ends, reserves room as k_upd_reserve does and notes in
+// wl[s] the head's position minus the old row count, so that appended word j
+// of slot s goes to start(s) + (j - wl[s]).  dcnt is not used.
 
 __device__ __forceinline__ bool run_head(const u64* keys, u64 j, u64 smask) {
   return j == 0 || (keys[j - 1] & smask) != (keys[j] & smask);
 }
 
-// Sorted update, step 1: appended count and head position per touched slot.
-__global__ __launch_bounds__(kBlock) void k_upds_runs(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
-  ktime_start(p.ts);
-  if (p.abort && *p.abort) return;
-  if (p.abort2 && *p.abort2) return;
-  u64 begin, n;
-  source_range(p.src, begin, n);
-  const u64 smask = (u64(1) << row_shift) - 1;
-  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
-    const u64 s = keys[j] & smask;
-    if (s >= p.cap) continue;   // outside the filter (sorted last)
-    const bool head = run_head(keys, j, smask);
-    const bool tail = j + 1 == n || (keys[j + 1] & smask) != s;
-    if (head) p.wl[s] = u32(j);
-    if (head || tail) atomicAdd(&p.dcnt[s], (tail ? u32(j + 1) : 0u) - (head ? u32(j) : 0u));
+// One past the last word of the run of slot s that holds word j (sorted
+// words): a galloping search, so that the usual run of one or two words
+// costs a read or two and a run of m words about 2 log2(m).
+__device__ __forceinline__ u64 run_end(const u64* keys, u64 j, u64 n, u64 smask, u64 s) {
+  u64 lo = j, step = 1;   // keys[lo] is in the run; so is every word before it from j on
+  while (lo + step < n && (keys[lo + step] & smask) == s) {
+    lo += step;
+    step <<= 1;
   }
-  ktime_end(p.ts);
+  u64 hi = min_u64(lo + step, n);   // not in the run (or n)
+  while (hi - lo > 1) {
+    const u64 mid = lo + ((hi - lo) >> 1);
+    if ((keys[mid] & smask) == s) lo = mid;
+    else hi = mid;
+  }
+  return hi;
 }
 
-// Sorted update, step 2: k_upd_reserve's work, done by each run's head word;
-// the slot's count becomes old + appended rows (dcnt keeps the appended
-// count for the placement, which then clears it).
+// Sorted update, step 1: per run head, room for the appended rows and the
+// slot's count set to old + appended rows.
 __global__ __launch_bounds__(kBlock) void k_upds_reserve(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
   __shared__ u64 s_scan[kBlock / kWave + 1];
   __shared__ u64 s_base;
@@ -550,35 +567,47 @@ __global__ __launch_bounds__(kBlock) void k_upds_reserve(IndexParams p, const u6
   const u64 smask = (u64(1) << row_shift) - 1;
   const bool failed = (*p.full & 1) != 0;   // keys missing: the index is rebuilt
   u64 st_rows = 0, st_keys = 0, st_long = 0;
-  for (u64 b0 = u64(blockIdx.x) * kBlock; b0 < n; b0 += u64(gridDim.x) * kBlock) {
-    const u64 j = b0 + threadIdx.x;
-    u32 s = 0;
-    bool act = false;
-    if (j < n) {
-      const u64 sl = keys[j] & smask;
-      act = sl < p.cap && run_head(keys, j, smask) && !failed;
-      s = act ? u32(sl) : 0u;
+  constexpr u64 kStep = u64(kBlock) * kResItems;
+  for (u64 b0 = u64(blockIdx.x) * kStep; b0 < n; b0 += u64(gridDim.x) * kStep) {
+    bool act[kResItems];
+    u32 s[kResItems], c_old[kResItems], from[kResItems];
+    u64 j[kResItems], need[kResItems];
+#pragma unroll
+    for (int i = 0; i < kResItems; ++i) {
+      j[i] = b0 + u64(i) * kBlock + threadIdx.x;
+      act[i] = false;
+      s[i] = 0;
+      if (j[i] < n && !failed) {
+        const u64 sl = keys[j[i]] & smask;
+        act[i] = sl < p.cap && run_head(keys, j[i], smask);
+        s[i] = act[i] ? u32(sl) : 0u;
+      }
     }
-    u32 d = 0, c_old = 0;
-    if (act) {
-      d = p.dcnt[s];
-      c_old = p.table[s].count;
+#pragma unroll
+    for (int i = 0; i < kResItems; ++i) {
+      const u64 d = act[i] ? run_end(keys, j[i], n, smask, s[i]) - j[i] : 0;
+      const Slot sl = act[i] ? p.table[s[i]] : Slot{0, 0u, 0u};
+      c_old[i] = sl.count;
+      from[i] = sl.start;
+      need[i] = u64(c_old[i]) + d;
     }
-    const u64 need = u64(c_old) + d;
-    reserve_run(p, act, s, c_old, need, s_scan, &s_base);
-    if (act) {
-      p.table[s].count = u32(need);
-      st_rows += d;
-      st_keys += c_old == 0 ? 1u : 0u;
-      st_long = need > st_long ? need : st_long;
+    reserve_runs(p, act, s, c_old, from, need, s_scan, &s_base);
+#pragma unroll
+    for (int i = 0; i < kResItems; ++i) {
+      if (!act[i]) continue;
+      p.table[s[i]].count = u32(need[i]);
+      p.wl[s[i]] = u32(j[i]) - c_old[i];
+      st_rows += need[i] - c_old[i];
+      st_keys += c_old[i] == 0 ? 1u : 0u;
+      st_long = need[i] > st_long ? need[i] : st_long;
     }
   }
   flush_update_stats(p, st_rows, st_keys, st_long, s_scan);
   ktime_end(p.ts);
 }
 
-// Sorted update, step 3: appended word j of slot s to its place after the
-// key's old rows.
+// Sorted update, step 3 (after k_upd_move): appended word j of slot s to
+// its place after the key's old rows.
 __global__ __launch_bounds__(kBlock) void k_upds_fill(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
@@ -591,25 +620,9 @@ __global__ __launch_bounds__(kBlock) void k_upds_fill(IndexParams p, const u64* 
     const u64 k = keys[j];
     const u64 s = k & smask;
     if (s >= p.cap) continue;
-    const Slot sl = p.table[s];
-    const u64 pos = u64(sl.start) + (sl.count - p.dcnt[s]) + (j - p.wl[s]);
-    p.perm[pos] = u32(begin + (k >> row_shift));
+    p.perm[u64(p.table[s].start) + u32(u32(j) - p.wl[s])] = u32(begin + (k >> row_shift));
   }
   ktime_end(p.ts);
-}
-
-// Sorted update, step 4: the appended counts cleared for the next update
-// (also after a failed update, so that the rebuild finds them zero).
-__global__ __launch_bounds__(kBlock) void k_upds_clear(IndexParams p, const u64* __restrict__ keys, u32 row_shift) {
-  if (p.abort && *p.abort) return;
-  if (p.abort2 && *p.abort2) return;
-  u64 begin, n;
-  source_range(p.src, begin, n);
-  const u64 smask = (u64(1) << row_shift) - 1;
-  for (u64 j = u64(blockIdx.x) * kBlock + threadIdx.x; j < n; j += u64(gridDim.x) * kBlock) {
-    const u64 s = keys[j] & smask;
-    if (s < p.cap && run_head(keys, j, smask)) p.dcnt[s] = 0u;
-  }
 }
 
 // ------------------------------------------------------------------ sorted build
@@ -829,18 +842,13 @@ int launch_index_update_keys(const IndexParams& p, u64 delta_rows_cap, u64* keys
 int launch_index_update_sorted(const IndexParams& p, u64 delta_rows_cap, const u64* sorted, u32 row_shift,
                                u64* const* ts, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  const int g = grid_rows(delta_rows_cap, 8192);
   IndexParams q = p;
   q.ts = ts ? ts[0] : nullptr;
-  hipLaunchKernelGGL(k_upds_runs, dim3(g), dim3(kBlock), 0, s, q, sorted, row_shift);
+  hipLaunchKernelGGL(k_upds_reserve, dim3(grid_rows((delta_rows_cap + kResItems - 1) / kResItems, 4096)), dim3(kBlock), 0, s, q, sorted, row_shift);
   q.ts = ts ? ts[1] : nullptr;
-  hipLaunchKernelGGL(k_upds_reserve, dim3(grid_rows(delta_rows_cap, 4096)), dim3(kBlock), 0, s, q, sorted, row_shift);
-  q.ts = ts ? ts[2] : nullptr;
   hipLaunchKernelGGL(k_upd_move, dim3(2048), dim3(kBlock), 0, s, q);
-  q.ts = ts ? ts[3] : nullptr;
-  hipLaunchKernelGGL(k_upds_fill, dim3(g), dim3(kBlock), 0, s, q, sorted, row_shift);
-  q.ts = nullptr;
-  hipLaunchKernelGGL(k_upds_clear, dim3(g), dim3(kBlock), 0, s, q, sorted, row_shift);
+  q.ts = ts ? ts[2] : nullptr;
+  hipLaunchKernelGGL(k_upds_fill, dim3(grid_rows(delta_rows_cap, 8192)), dim3(kBlock), 0, s, q, sorted, row_shift);
   return int(hipGetLastError());
 }
 
@@ -859,11 +867,13 @@ int launch_index_update(const IndexParams& p, u64 delta_rows_cap, u64 wl_cap, u6
   q.ts = ts ? ts[0] : nullptr;
   hipLaunchKernelGGL(k_upd_count, dim3(grid_tiles(delta_rows_cap)), dim3(kBlock), 0, s, q);
   q.ts = ts ? ts[1] : nullptr;
-  hipLaunchKernelGGL(k_upd_reserve, dim3(grid_rows(wl_cap, 4096)), dim3(kBlock), 0, s, q);
+  hipLaunchKernelGGL(k_upd_reserve, dim3(grid_rows((wl_cap + kResItems - 1) / kResItems, 4096)), dim3(kBlock), 0, s, q);
   q.ts = ts ? ts[2] : nullptr;
   hipLaunchKernelGGL(k_upd_move, dim3(2048), dim3(kBlock), 0, s, q);
   q.ts = ts ? ts[3] : nullptr;
-  hipLaunchKernelGGL(k_upd_fill, dim3(grid_tiles(delta_rows_cap)), dim3(kBlock), 0, s, q);
+  hipLaunchKernelGGL(k_upd_fill, dim3(grid_rows(delta_rows_cap, 8192)), dim3(kBlock), 0, s, q);
+  q.ts = nullptr;
+  hipLaunchKernelGGL(k_upd_clear, dim3(grid_rows(wl_cap, 4096)), dim3(kBlock), 0, s, q);
   return int(hipGetLastError());
 }
 

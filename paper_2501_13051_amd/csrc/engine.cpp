@@ -126,6 +126,7 @@ Engine::~Engine() {
   release(stamps_dev_);
   release(m_row_); release(m_start_); release(m_off_);
   release(st_a_); release(st_b_); release(st_sort_);
+  release(mdiff_);
   release(ixk_a_); release(ixk_b_);
   for (auto& sk : sketches_) release(sk.regs);
   release(predictor_dev_); release(pspec_init_dev_); release(pspec_delta_dev_);
@@ -932,6 +933,13 @@ bool Engine::ensure_capacity(bool dry) {
     // the difference by merge: full's sorted keys and the merge's output hold
     // full after this round (its rows plus every new tuple it may append)
     const u64 need_sorted = R.n_full + std::max<u64>(R.new_cap, R.staged);
+    if (merge_diff() && mdiff_cap_ < diff_sorted_scratch_words(need_sorted)) {
+      if (dry) return true;
+      const u64 words = diff_sorted_scratch_words(2 * need_sorted);
+      release(mdiff_);
+      mdiff_ = alloc(words * 8);
+      mdiff_cap_ = words;
+    }
     if (merge_diff() && R.sfull_cap < need_sorted) {
       if (dry) return true;
       const u64 nc = std::max<u64>(need_sorted, 2 * R.sfull_cap);
@@ -1339,10 +1347,11 @@ void Engine::collect_events(u64 upto, bool discard) {
         }
         break;
       }
-      case 20: {   // merge of full's sorted keys with the survivors: every key of full read and written
-        const u64 n = C(pe.ref0);
-        bytes = double(n) * 16;
-        items = n;
+      case 20: {   // difference by merge: full's and the new keys read, full's and the survivors' keys
+                   // written, survivors' columns appended
+        const u64 n = C(pe.ref0), d = C(pe.ref1), f = C(int(pe.aux >> 32));   // f: full after the round
+        bytes = double(n) * 8 + double(f - d) * 8 + double(f) * 8 + double(d) * 4 * double(pe.aux & 0xFFFFFFFFu);
+        items = n + (f - d);
         break;
       }
       case 5: {   // difference + append: key read, set probe, column writes of survivors
@@ -1631,11 +1640,11 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.set32 = use_set && R.set32 ? R.set.as<u32>() : nullptr;
   dp.ones = use_set && R.set32 ? ctr(R.c_ones) : nullptr;
   if (merge_diff() && R.used_as_head) {
-    // the difference against full's sorted keys; the survivors' keys go to the
-    // sort's free buffer, and one merge writes full's keys in order with them
-    // (taken over when the round succeeds)
+    // the difference against full's sorted keys, which it merges with the
+    // new keys into the second copy (taken over when the round succeeds)
     dp.sorted_full = R.sfull.as<u64>();
-    dp.surv = dst;
+    dp.merged = R.sfull2.as<u64>();
+    dp.mtile = mdiff_.as<u64>();
     R.merged_this_round = true;
   }
   if (tune_.dedup_ranges == 1 && in_round && R.used_as_head) {
@@ -1666,15 +1675,13 @@ void Engine::finish_relation(Relation& R, bool in_round) {
   dp.abort = flags;
   const int kd = kclass("dedup_append");
   dp.ts = ev_begin(kd, true);
-  launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_, block_for(1, R.new_cap)), "dedup launch");
-  ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
   if (dp.sorted_full) {
-    const int km = kclass("merge_full");
-    ev_begin(km);
-    launched(launch_merge_sorted(dp.surv, ctr(c_delta0_ + ri), R.sfull.as<u64>(), ctr(c_full0_ + ri),
-                                 R.sfull2.as<u64>(), R.n_full + R.new_cap, flags, stream_),
-             "merge launch");
-    ev_end(km, 0, 20, c_full0_ + ri);
+    launched(launch_diff_sorted(dp, R.n_full + std::max<u64>(R.new_cap, 1), stream_, block_for(1, R.new_cap)),
+             "difference launch");
+    ev_end(kd, 0, 20, c_new0_ + ri, c_delta0_ + ri, (u64(c_full0_ + ri) << 32) | R.arity);
+  } else {
+    launched(launch_dedup(dp, std::max<u64>(R.new_cap, 1), stream_, block_for(1, R.new_cap)), "dedup launch");
+    ev_end(kd, 0, 5, c_new0_ + ri, c_delta0_ + ri, R.arity);
   }
 }
 

@@ -318,6 +318,8 @@ class Engine {
   Buf ixk_a_, ixk_b_;     // sorted index builds: (row, slot) words and the sort's second buffer
   std::vector<u32> rehashed_;   // indices moved to larger tables, to be checked before a round reads them
   Buf moves_;             // index updates: old-run chunks to copy (shared, updates run one by one)
+  Buf mdiff_;             // the difference by merge: per-tile splits, counts and ranks (shared)
+  u64 mdiff_cap_ = 0;     // its words
   u64 moves_cap_ = 0;
   u64 ixk_cap_ = 0;
   u64 st_cap_ = 0, st_sort_tiles_ = 0;

@@ -201,11 +201,12 @@ struct DedupParams {
   const u32* abort;
   u64* ts;               // trace timing slot (see ktime_start), nullable
   RangeDedup rd;         // with rd.ncol > 0 (and no set): the difference by per-column ranges
-  // with sorted_full (and no set, no ranges): the difference against full's
-  // packed tuples in ascending order, *full_n of them; every survivor's key
-  // is also written to surv[its rank among the survivors]
+  // with sorted_full (launch_diff_sorted): the difference against full's
+  // packed tuples in ascending order, *full_n of them, merged with the new
+  // ones into `merged`; mtile is the launches' per-tile scratch
   const u64* sorted_full;
-  u64* surv;
+  u64* merged;
+  u64* mtile;
 };
 
 struct CommitParams {
@@ -228,11 +229,15 @@ int launch_write(const WriteParams& p, u64 out_tiles_hint, void* stream, u32 blo
 int launch_select(const SelectParams& p, u64 rows_hint, void* stream, u32 block = 256);
 int launch_join_fused(const FusedJoinParams& p, u64 rows_hint, void* stream, u32 block = 256);
 int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream, u32 block = 256);
-// out[0, na + nb) = the merge of two ascending arrays with no key in common,
-// a (*a_n keys) and b (*b_n keys); nothing when *abort is set.  cap bounds
-// na + nb (it sizes the grid).
-int launch_merge_sorted(const u64* a, const u64* a_n, const u64* b, const u64* b_n, u64* out, u64 cap,
-                        const u32* abort, void* stream);
+// The difference against full's sorted keys fused with their merge
+// (p.sorted_full, p.merged and p.mtile set; set, set32 and ranges unused):
+// three launches (count, scan, write) over the merge of full's keys and the
+// new keys; the new keys are appended to full's columns, *out_delta receives
+// their number and merged[0, *full_n + *out_delta) full's keys after the
+// round, in order.  total_cap bounds full's keys plus the new keys;
+// p.mtile holds diff_sorted_scratch_words(total_cap) words.
+int launch_diff_sorted(const DedupParams& p, u64 total_cap, void* stream, u32 block = 256);
+u64 diff_sorted_scratch_words(u64 total_cap);
 int launch_commit(const CommitParams& p, void* stream);
 // Zero n_ctr counters, n_hist histogram words and (if flag) the overflow and
 // set-full flags (flag[0], flag[2]), and advance the epoch base by kEpochStride.

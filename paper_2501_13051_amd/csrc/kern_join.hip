@@ -625,9 +625,6 @@ __global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
   __shared__ u32 s_ticket;
   __shared__ u32 s_c[kB / kWave + 1];
   __shared__ u64 s_excl;
-  __shared__ u64 s_win[2];
-  constexpr u32 kWinKeys = 2048;   // full's keys staged per tile (difference by merge)
-  __shared__ u64 s_wkeys[kWinKeys];
   ktime_start(p.ts);
   if (p.abort && *p.abort) return;
   u64 begin, n;
@@ -663,39 +660,6 @@ __global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
       for (int k = 0; k < kDedupItems; ++k) {
         if (ins[k] < 0) *p.set_full = 1;   // never the flag this kernel checks on entry
         surv[k] = first[k] && ins[k] > 0;
-        mine += surv[k] ? 1u : 0u;
-      }
-    } else if (p.sorted_full) {
-      // full's keys that can equal this tile's lie in [lo, hi): the first
-      // two waves search all of full for the two ends at once (64 probes per
-      // round trip); a window of up to kWinKeys keys is staged in LDS and
-      // searched there, a longer one in place
-      const int wv = threadIdx.x / kWave;
-      if (wv < 2) {
-        const u64 nb = fbase;
-        const u64 k0 = p.keys[begin + u64(tile) * kDedupTile];
-        const u64 k1 = p.keys[begin + min_u64(u64(tile + 1) * kDedupTile, n) - 1];
-        u64 r;
-        if (wv == 0) r = wave_lower_bound_u64(p.sorted_full, 0, nb, k0);
-        else r = k1 == ~0ull ? nb : wave_lower_bound_u64(p.sorted_full, 0, nb, k1 + 1);
-        if (lane_id() == 0) s_win[wv] = r;
-      }
-      __syncthreads();
-      const u64 lo = s_win[0], hi = s_win[1];
-      const bool staged = hi - lo <= kWinKeys;
-      if (staged)
-        for (u64 q = threadIdx.x; q < hi - lo; q += kB) s_wkeys[q] = p.sorted_full[lo + q];
-      __syncthreads();
-      const u64* win = staged ? s_wkeys : p.sorted_full + lo;
-      const u64 wn = hi - lo;
-#pragma unroll
-      for (int k = 0; k < kDedupItems; ++k) {
-        bool present = false;
-        if (first[k]) {
-          const u64 q = lower_bound_u64(win, 0, wn, key[k]);
-          present = q < wn && win[q] == key[k];
-        }
-        surv[k] = first[k] && !present;
         mine += surv[k] ? 1u : 0u;
       }
     } else if (p.rd.ncol) {
@@ -739,7 +703,6 @@ __global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
         const u64 m = (p.width[c] >= 32) ? 0xFFFFFFFFull : ((1ull << p.width[c]) - 1);
         p.cols[c][pos] = u32((key[k] >> p.shift[c]) & m);
       }
-      if (p.surv) p.surv[pos - fbase] = key[k];
       ++pos;
     }
     if (tile == ntiles - 1 && threadIdx.x == 0) *p.out_delta = s_excl + tot;
@@ -748,60 +711,266 @@ __global__ __launch_bounds__(kB) void k_dedup(DedupParams p) {
   ktime_end(p.ts);
 }
 
-// ------------------------------------------------------------------ merge of sorted keys
-// Merge path: output tile t of kMergeTile keys takes a[i0, i1) and b[j0, j1),
-// where i + j = t * kMergeTile splits the two inputs at the t-th step of
-// their merge (found by binary search on that diagonal); the tile's inputs
-// are staged in LDS and each thread finds its own split there, then writes
-// its kMergeItems outputs in order.
-constexpr u32 kMergeItems = 8;
-constexpr u32 kMergeTile = kBlock * kMergeItems;
+// ------------------------------------------------------------------ difference by merge
+// The difference of the round's sorted new keys b (repeats adjacent) against
+// full's sorted keys a, fused with the merge that keeps full's keys sorted
+// for the next round.  In the merge of a and b in which a tie is taken from a
+// first, a key of b is new iff it differs from the key before it: a key of
+// full equal to it, or an earlier copy of it, would come just before.  The
+// merged sequence is cut into tiles of kDiffTile outputs; tile t takes
+// a[i0, i1) and b[j0, j1).
+//   k_diff_split: one wave per tile boundary: i0 found on the boundary's
+//                 diagonal by a 64-way search;
+//   k_diff_count: per tile, the number of new keys;
+//   k_diff_scan:  one block: each tile's first new-key and dropped-key ranks;
+//   k_diff_write: per tile, the merge again: a's keys and the new keys go to
+//                 the merged array (dropped repeats close up), the new keys'
+//                 columns are appended to full.
+// Every kernel is a grid-stride loop over independent tiles: no tile waits
+// for another.
+constexpr u32 kDiffItems = 16;
 
-// The split of the merge of a[0, na) and b[0, nb) after d outputs: the number
-// of a's keys among the first d (keys are distinct across the two arrays).
-__device__ __forceinline__ u64 merge_split(const u64* a, u64 na, const u64* b, u64 nb, u64 d) {
-  u64 lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+// Number of a's keys among the first d outputs of the merge of a[0, na) and
+// b[0, nb) with ties taken from a, by a whole wave (every lane calls it with
+// the same arguments): a's key i is among them iff a[i] <= b[d - i - 1],
+// which holds for a prefix of the candidates, 64 of them probed per round trip.
+__device__ __forceinline__ u64 wave_merge_split(const u64* a, u64 na, const u64* b, u64 nb, u64 d) {
+  const u32 lane = u32(__lane_id());
+  u64 lo = d > nb ? d - nb : 0, hi = d < na ? d : na;   // the answer lies in [lo, hi]
+  while (hi - lo > u64(kWave)) {
+    const u64 step = (hi - lo + kWave - 1) / kWave;
+    const u64 i = lo + u64(lane) * step;
+    const bool before = i < hi && a[i] <= b[d - i - 1];
+    const u32 c = u32(__popcll(__ballot(before)));
+    if (c == 0) return lo;
+    const u64 nxt = lo + u64(c) * step;
+    if (c < u32(kWave) && nxt < hi) hi = nxt;
+    lo = lo + u64(c - 1) * step + 1;
+  }
+  const u64 i = lo + lane;
+  const bool before = i < hi && a[i] <= b[d - i - 1];
+  return lo + u64(__popcll(__ballot(before)));
+}
+
+// The same split by one thread (binary search), within a tile's staged keys
+// (a's part at s[0, la), b's at s[la, la + lb)).
+__device__ __forceinline__ u32 merge_split_le(const u64* s, u32 la, u32 lb, u32 d) {
+  u32 lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
   while (lo < hi) {
-    const u64 i = (lo + hi) >> 1;   // take i of a and d - i of b: too few of a if a[i] < b[d - i - 1]
-    if (a[i] < b[d - i - 1]) lo = i + 1;
+    const u32 i = (lo + hi) >> 1;
+    if (s[i] <= s[la + d - i - 1]) lo = i + 1;
     else hi = i;
   }
   return lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_merge_sorted(const u64* a, const u64* a_n, const u64* b, const u64* b_n,
-                                                         u64* out, const u32* abort) {
-  __shared__ u64 s_in[kMergeTile];
-  __shared__ u64 s_split[2];
-  if (abort && *abort) return;
-  const u64 na = *a_n, nb = *b_n, total = na + nb;
-  for (u64 t = blockIdx.x; t * kMergeTile < total; t += gridDim.x) {
-    const u64 d0 = t * kMergeTile;
-    const u64 d1 = min_u64(d0 + kMergeTile, total);
-    if (threadIdx.x == 0) {
-      s_split[0] = merge_split(a, na, b, nb, d0);
-      s_split[1] = merge_split(a, na, b, nb, d1);
+// One thread's stretch of a tile's merge: outputs [e0, e1) (e1 - e0 <= kN)
+// of the merge of the staged a[0, la) and b[0, lb) (at s[i] and s[la + j]),
+// the key before output e0 being `prev` (has_prev false: none).  f(k, v, from_b, is_new) is called for output e0 + k, in order.
+template <int kN, class F>
+__device__ __forceinline__ void diff_walk(const u64* s, u32 la, u32 lb, u32 e0, u32 e1, bool has_prev, u64 prev,
+                                          F&& f) {
+  u32 i = merge_split_le(s, la, lb, e0);
+  u32 j = e0 - i;
+  if (e0 > 0) {   // the output before e0 is the larger of the last keys taken from each side
+    has_prev = true;
+    prev = i > 0 ? s[i - 1] : 0;
+    if (j > 0 && (i == 0 || s[la + j - 1] > prev)) prev = s[la + j - 1];
+  }
+#pragma unroll
+  for (u32 k = 0; k < u32(kN); ++k) {
+    if (e0 + k >= e1) break;
+    const bool take_a = j >= lb || (i < la && s[i] <= s[la + j]);
+    const u64 v = take_a ? s[i++] : s[la + j++];
+    f(k, v, !take_a, !take_a && !(has_prev && prev == v));
+    prev = v;
+    has_prev = true;
+  }
+}
+
+// Stage a[i0, i1) and b[j0, j1) in s_in and find the key before the tile
+// (the larger of a[i0 - 1] and b[j0 - 1]).  Block-uniform.
+__device__ __forceinline__ void diff_stage(const u64* a, const u64* b, u64 i0, u32 la, u64 j0, u32 lb, u64* s_in,
+                                           u32 nthreads, bool& has_prev, u64& prev) {
+  for (u32 q = threadIdx.x; q < la + lb; q += nthreads) s_in[q] = q < la ? a[i0 + q] : b[j0 + (q - la)];
+  has_prev = i0 > 0 || j0 > 0;
+  prev = i0 > 0 ? a[i0 - 1] : 0;
+  if (j0 > 0 && (i0 == 0 || b[j0 - 1] > prev)) prev = b[j0 - 1];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_diff_split(DedupParams p, u32 tile_keys) {
+  if (p.abort && *p.abort) return;
+  u64 begin, nb;
+  source_range(p.src, begin, nb);
+  const u64 na = *p.full_n;
+  const u64 total = na + nb;
+  const u64 ntiles = (total + tile_keys - 1) / tile_keys;
+  constexpr u32 kWaves = kBlock / kWave;
+  for (u64 t = u64(blockIdx.x) * kWaves + threadIdx.x / kWave; t <= ntiles; t += u64(gridDim.x) * kWaves) {
+    const u64 r = wave_merge_split(p.sorted_full, na, p.keys + begin, nb, min_u64(t * tile_keys, total));
+    if (lane_id() == 0) p.mtile[t] = r;
+  }
+}
+
+template <int kB>
+__global__ __launch_bounds__(kB) void k_diff_count(DedupParams p) {
+  constexpr u32 kDiffTile = kB * kDiffItems;
+  __shared__ u64 s_in[kDiffTile];
+  __shared__ u32 s_red[kB / kWave + 1];
+  if (p.abort && *p.abort) return;
+  u64 begin, nb;
+  source_range(p.src, begin, nb);
+  const u64* a = p.sorted_full;
+  const u64* b = p.keys + begin;
+  const u64 na = *p.full_n;
+  const u64 total = na + nb;
+  const u64 ntiles = (total + kDiffTile - 1) / kDiffTile;
+  const u64* split = p.mtile;          // ntiles + 1 splits
+  u64* cnt = p.mtile + (ntiles + 1);   // ntiles new-key counts
+  for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u64 d0 = t * kDiffTile, d1 = min_u64(d0 + kDiffTile, total);
+    const u64 i0 = split[t], i1 = split[t + 1];
+    const u64 j0 = d0 - i0;
+    const u32 la = u32(i1 - i0), lb = u32((d1 - i1) - j0);
+    u32 mine = 0;
+    if (lb) {   // block-uniform: a tile of a's keys alone has no new keys
+      bool has_prev;
+      u64 prev;
+      diff_stage(a, b, i0, la, j0, lb, s_in, kB, has_prev, prev);
+      const u32 e0 = threadIdx.x * kDiffItems;
+      if (e0 < la + lb)
+        diff_walk<kDiffItems>(s_in, la, lb, e0, min_u32(e0 + kDiffItems, la + lb), has_prev, prev,
+                              [&](u32, u64, bool, bool is_new) { mine += is_new ? 1u : 0u; });
     }
-    __syncthreads();
-    const u64 i0 = s_split[0], i1 = s_split[1];
-    const u64 j0 = d0 - i0, j1 = d1 - i1;
-    const u32 la = u32(i1 - i0), lb = u32(j1 - j0);
-    for (u32 q = threadIdx.x; q < la + lb; q += kBlock) s_in[q] = q < la ? a[i0 + q] : b[j0 + (q - la)];
-    __syncthreads();
-    const u64* sa = s_in;
-    const u64* sb = s_in + la;
-    const u32 e0 = threadIdx.x * kMergeItems;
-    if (e0 < la + lb) {
-      u32 i = u32(merge_split(sa, la, sb, lb, e0));
-      u32 j = e0 - i;
-      const u32 e1 = e0 + kMergeItems < la + lb ? e0 + kMergeItems : la + lb;
-      for (u32 e = e0; e < e1; ++e) {
-        const bool take_a = j >= lb || (i < la && sa[i] < sb[j]);
-        out[d0 + e] = take_a ? sa[i++] : sb[j++];
+    const u32 tot = block_sum<kB>(mine, s_red);
+    if (threadIdx.x == 0) cnt[t] = tot;
+    __syncthreads();   // s_in is reused by the next tile
+  }
+}
+
+// One block of 1024 threads, kScanItems tiles per thread and step: each
+// tile's rank of its first new key (soff) and of its first dropped key of b
+// (doff), and the number of new keys.
+constexpr u32 kDiffScanBlock = 1024;
+constexpr u32 kScanItems = 8;
+__global__ __launch_bounds__(kDiffScanBlock) void k_diff_scan(DedupParams p, u32 tile_keys) {
+  __shared__ u64 s_scan[kDiffScanBlock / kWave + 1];
+  if (p.abort && *p.abort) return;
+  u64 begin, nb;
+  source_range(p.src, begin, nb);
+  const u64 na = *p.full_n;
+  const u64 total = na + nb;
+  const u64 ntiles = (total + tile_keys - 1) / tile_keys;
+  const u64* split = p.mtile;
+  const u64* cnt = p.mtile + (ntiles + 1);
+  u64* soff = p.mtile + (ntiles + 1) + ntiles;
+  u64* doff = soff + ntiles;
+  u64 run_s = 0, run_d = 0;
+  for (u64 t0 = 0; t0 < ntiles; t0 += u64(kDiffScanBlock) * kScanItems) {
+    const u64 tb = t0 + u64(threadIdx.x) * kScanItems;
+    u64 cs[kScanItems], cd[kScanItems], ms = 0, md = 0;
+#pragma unroll
+    for (u32 k = 0; k < kScanItems; ++k) {
+      const u64 t = tb + k;
+      cs[k] = cd[k] = 0;
+      if (t < ntiles) {
+        const u64 d0 = t * tile_keys, d1 = min_u64(d0 + tile_keys, total);
+        const u64 lb = (d1 - split[t + 1]) - (d0 - split[t]);
+        cs[k] = cnt[t];
+        cd[k] = lb - cnt[t];
+      }
+      ms += cs[k];
+      md += cd[k];
+    }
+    u64 ts, td;
+    u64 es = block_exclusive_sum<kDiffScanBlock>(ms, s_scan, &ts);
+    u64 ed = block_exclusive_sum<kDiffScanBlock>(md, s_scan, &td);
+#pragma unroll
+    for (u32 k = 0; k < kScanItems; ++k) {
+      const u64 t = tb + k;
+      if (t < ntiles) {
+        soff[t] = run_s + es;
+        doff[t] = run_d + ed;
+      }
+      es += cs[k];
+      ed += cd[k];
+    }
+    run_s += ts;
+    run_d += td;
+  }
+  if (threadIdx.x == 0) *p.out_delta = run_s;
+}
+
+template <int kB>
+__global__ __launch_bounds__(kB) void k_diff_write(DedupParams p) {
+  constexpr u32 kDiffTile = kB * kDiffItems;
+  __shared__ u64 s_in[kDiffTile];
+  __shared__ u64 s_scan[kB / kWave + 1];
+  ktime_start(p.ts);
+  if (p.abort && *p.abort) return;
+  u64 begin, nb;
+  source_range(p.src, begin, nb);
+  const u64* a = p.sorted_full;
+  const u64* b = p.keys + begin;
+  const u64 na = *p.full_n;
+  const u64 total = na + nb;
+  const u64 ntiles = (total + kDiffTile - 1) / kDiffTile;
+  const u64* split = p.mtile;
+  const u64* soff = p.mtile + (ntiles + 1) + ntiles;
+  const u64* doff = soff + ntiles;
+  for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u64 d0 = t * kDiffTile, d1 = min_u64(d0 + kDiffTile, total);
+    const u64 i0 = split[t], i1 = split[t + 1];
+    const u64 j0 = d0 - i0;
+    const u32 la = u32(i1 - i0), lb = u32((d1 - i1) - j0);
+    bool has_prev;
+    u64 prev;
+    diff_stage(a, b, i0, la, j0, lb, s_in, kB, has_prev, prev);
+    const u32 e0 = threadIdx.x * kDiffItems;
+    const u32 e1 = min_u32(e0 + kDiffItems, la + lb);
+    // one walk: the thread's outputs and their kinds (0 kept from full, 1
+    // new, 2 dropped) in registers; new keys counted in the high half,
+    // dropped ones in the low half, then ranked in the block
+    u64 v[kDiffItems];
+    u32 kind[kDiffItems];
+    u64 mine = 0;
+#pragma unroll
+    for (u32 k = 0; k < kDiffItems; ++k) {
+      v[k] = 0;
+      kind[k] = 2u;
+    }
+    if (e0 < e1)
+      diff_walk<kDiffItems>(s_in, la, lb, e0, e1, has_prev, prev,
+                            [&](u32 k, u64 x, bool from_b, bool is_new) {
+                              v[k] = x;
+                              kind[k] = is_new ? 1u : (from_b ? 2u : 0u);
+                              mine += is_new ? (u64(1) << 32) : (from_b ? 1u : 0u);
+                            });
+    u64 tot;
+    const u64 ex = block_exclusive_sum<kB>(mine, s_scan, &tot);
+    u64 snew = soff[t] + (ex >> 32);                // rank of the thread's first new key
+    u64 drop = doff[t] + (ex & 0xFFFFFFFFull);     // dropped keys before its first output
+    const u64 m0 = d0 + e0;                         // merge position of its first output
+#pragma unroll
+    for (u32 k = 0; k < kDiffItems; ++k) {
+      if (e0 + k >= e1) break;
+      if (kind[k] == 2u) {
+        ++drop;
+        continue;
+      }
+      p.merged[m0 + k - drop] = v[k];
+      if (kind[k] == 1u) {
+        const u64 pos = na + snew++;
+        for (u32 c = 0; c < p.arity; ++c) {
+          const u64 mk = (p.width[c] >= 32) ? 0xFFFFFFFFull : ((1ull << p.width[c]) - 1);
+          p.cols[c][pos] = u32((v[k] >> p.shift[c]) & mk);
+        }
       }
     }
-    __syncthreads();   // s_in and s_split are reused by the next tile
+    __syncthreads();   // s_in is reused by the next tile
   }
+  ktime_end(p.ts);
 }
 
 __global__ void k_commit(CommitParams p) {
@@ -905,12 +1074,21 @@ int launch_dedup(const DedupParams& p, u64 rows_cap, void* stream, u32 block) {
   return int(hipGetLastError());
 }
 
-int launch_merge_sorted(const u64* a, const u64* a_n, const u64* b, const u64* b_n, u64* out, u64 cap,
-                        const u32* abort, void* stream) {
-  const u64 tiles = (cap + kMergeTile - 1) / kMergeTile;
-  hipLaunchKernelGGL(k_merge_sorted, dim3(grid_for(tiles, 4096)), dim3(kBlock), 0, (hipStream_t)stream, a, a_n, b,
-                     b_n, out, abort);
+int launch_diff_sorted(const DedupParams& p, u64 total_cap, void* stream, u32 block) {
+  const u64 tile = block_of(block) * kDiffItems;
+  const u64 tiles = (total_cap + tile - 1) / tile;
+  const int g = grid_for(tiles, 4096);
+  hipLaunchKernelGGL(k_diff_split, dim3(grid_for((tiles + 1 + kBlock / kWave - 1) / (kBlock / kWave), 4096)),
+                     dim3(kBlock), 0, (hipStream_t)stream, p, u32(tile));
+  FV_LAUNCH_BLOCK(k_diff_count, block, g, stream, p);
+  hipLaunchKernelGGL(k_diff_scan, dim3(1), dim3(kDiffScanBlock), 0, (hipStream_t)stream, p, u32(tile));
+  FV_LAUNCH_BLOCK(k_diff_write, block, g, stream, p);
   return int(hipGetLastError());
+}
+
+u64 diff_sorted_scratch_words(u64 total_cap) {
+  const u64 tiles = (total_cap + 128 * kDiffItems - 1) / (128 * kDiffItems);   // the smallest tiles
+  return 4 * (tiles + 1);
 }
 
 int launch_commit(const CommitParams& p, void* stream) {

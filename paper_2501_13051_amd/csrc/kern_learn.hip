@@ -49,8 +49,12 @@ __global__ __launch_bounds__(kBlock) void k_hll(HllBatch b) {
   const u64 wk = wave_sum(kept);
   if (lane_id() == 0 && wk) atomicAdd(reinterpret_cast<unsigned long long*>(p.rows), (unsigned long long)wk);
   __syncthreads();
+  // registers only grow, so a register already at least this block's value
+  // (read plainly: a stale read is only lower) needs no atomic; after the
+  // first blocks most registers hold their final value and the flush is a
+  // coalesced read
   for (int i = threadIdx.x; i < kHllM; i += kBlock)
-    if (s_reg[i]) atomicMax(&p.regs[i], s_reg[i]);
+    if (s_reg[i] > p.regs[i]) atomicMax(&p.regs[i], s_reg[i]);
 }
 
 // One block per sketch: the estimate (as a double's bits in a u64 counter

@@ -91,7 +91,7 @@ int launch_hll_batch(const HllBatch& b, u64 rows_hint, void* stream) {
   if (b.n == 0) return 0;
   hipStream_t s = (hipStream_t)stream;
   const u64 blocks = (rows_hint + kBlock - 1) / kBlock;
-  const u32 g = u32(blocks == 0 ? 1 : (blocks > 256 ? 256 : blocks));
+  const u32 g = u32(blocks == 0 ? 1 : (blocks > 1024 ? 1024 : blocks));
   hipLaunchKernelGGL(k_hll, dim3(g, b.n), dim3(kBlock), 0, s, b);
   hipLaunchKernelGGL(k_hll_estimate, dim3(b.n), dim3(kBlock), 0, s, b);
   return int(hipGetLastError());

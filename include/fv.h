@@ -103,9 +103,10 @@ typedef struct {
                               join indices' layout, kept up to date every round), a new tuple's
                               value ranges in them, an empty range or an empty intersection of
                               the ranges proving it new; 2: full's packed tuples kept in ascending
-                              order, each tile of sorted new tuples searched in the window of
-                              them it spans, the survivors merged in after every round (merge
-                              path).  Modes 1 and 2 keep no tuple set and take no look-ahead. */
+                              order and merged with the sorted new tuples every round: in that
+                              merge (ties from full first) a new tuple is one that differs from
+                              the tuple before it.  Modes 1 and 2 keep no tuple set and take no
+                              look-ahead. */
   uint8_t block_log2[2][4]; /* threads per block as log2 (7, 8 or 9; 0: 8) of the join kernels
                               (probe, write, one-pass join, selection: [0][b]) and of the
                               difference pass ([1][b]), per launch size bucket b: at most 2^16,

@@ -17,6 +17,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <array>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -348,6 +349,7 @@ bool Engine::domain_analysis() {
       }
     }
   }
+  refine_bounds();
   bool fits = true;
   for (auto& R : rels_) {
     // a column needs bits(max) bits; a packed key can only equal the
@@ -372,6 +374,145 @@ bool Engine::domain_analysis() {
     R.set32 = R.bits <= 32;
   }
   return fits;
+}
+
+// Tighter bounds from the rules' constant conditions.  The bound above takes
+// a head variable's maximum over whole body columns; but a body atom with
+// constants reads only the rows that match them, and rules often fill a
+// column with values drawn from such rows (RDFS: the property column of a
+// derived triple filled from subPropertyOf rows, whose objects are
+// properties).  Every relation gets one interval per column for each set of
+// constant positions a body atom over it has, and one for all of its rows.
+// The facts give the first intervals (one pass over them); a rule adds to a
+// condition set of its head when its head row can meet the conditions (a
+// head constant equal to the value, or a variable whose interval holds it,
+// which is then fixed to it), each head column bounded by its constant or by
+// the intersection of the intervals of the body columns its variable reads,
+// under those atoms' conditions.  Intervals only widen, to endpoints taken
+// from the facts and the constants, so the iteration ends.  A column's bound
+// becomes the smaller of the one above and its all-rows interval's maximum.
+void Engine::refine_bounds() {
+  struct Ival {
+    u32 lo = 1, hi = 0;   // empty
+    bool empty() const { return lo > hi; }
+  };
+  const u32 nrel = u32(rels_.size());
+  std::vector<std::vector<CondSet>> sets(nrel, std::vector<CondSet>(1, CondSet{}));
+  std::vector<std::vector<u32>> atom_set(rules_.size());
+  bool any_const = false;
+  for (size_t ri = 0; ri < rules_.size(); ++ri)
+    for (auto& a : rules_[ri].body) {
+      CondSet q{};
+      for (u32 k = 0; k < a.t.size(); ++k)
+        if (a.t[k].is_const) {
+          q.col[q.n] = k;
+          q.val[q.n] = a.t[k].value;
+          ++q.n;
+        }
+      any_const = any_const || q.n > 0;
+      auto& v = sets[a.rel];
+      u32 at = 0;
+      while (at < v.size() && !(v[at].n == q.n && std::equal(q.col, q.col + q.n, v[at].col) &&
+                                std::equal(q.val, q.val + q.n, v[at].val)))
+        ++at;
+      if (at == v.size()) v.push_back(q);
+      atom_set[ri].push_back(at);
+    }
+  if (!any_const) return;
+  std::vector<std::vector<std::array<Ival, 3>>> iv(nrel);
+  for (u32 r = 0; r < nrel; ++r) {
+    const Relation& R = rels_[r];
+    iv[r].assign(sets[r].size(), std::array<Ival, 3>{});
+    if (!R.has_rows || R.staged == 0) continue;
+    std::vector<u32> out(kCondSets * 8);
+    for (u32 q0 = 0; q0 < sets[r].size(); q0 += kCondSets) {
+      const u32 nq = std::min<u32>(kCondSets, u32(sets[r].size()) - q0);
+      if (host_mode_) host_fact_bounds(r, &sets[r][q0], nq, out.data());
+      else fact_bounds(r, &sets[r][q0], nq, out.data());
+      for (u32 q = 0; q < nq; ++q) {
+        if (!out[q * 8 + 6]) continue;
+        for (u32 c = 0; c < R.arity; ++c) iv[r][q0 + q][c] = Ival{out[q * 8 + c], out[q * 8 + 3 + c]};
+      }
+    }
+  }
+  bool settled = false;
+  for (int it = 0; it < 100000 && !settled; ++it) {
+    settled = true;
+    for (size_t ri = 0; ri < rules_.size(); ++ri) {
+      const RuleR& rule = rules_[ri];
+      Ival var[kMaxVars];
+      for (auto& v : var) v = Ival{0, 0xFFFFFFFEu};
+      bool feasible = true;
+      for (size_t b = 0; b < rule.body.size() && feasible; ++b) {
+        const AtomR& a = rule.body[b];
+        const auto& I = iv[a.rel][atom_set[ri][b]];
+        if (I[0].empty()) { feasible = false; break; }   // no row can match the atom
+        for (u32 k = 0; k < a.t.size(); ++k) {
+          if (a.t[k].is_const) continue;
+          Ival& x = var[a.t[k].value];
+          x.lo = std::max(x.lo, I[k].lo);
+          x.hi = std::min(x.hi, I[k].hi);
+          if (x.empty()) feasible = false;
+        }
+      }
+      if (!feasible) continue;
+      const u32 h = rule.head.rel;
+      for (u32 si = 0; si < sets[h].size(); ++si) {
+        const CondSet& q = sets[h][si];
+        Ival loc[kMaxVars];
+        std::copy(var, var + kMaxVars, loc);
+        bool meets = true;
+        for (u32 i = 0; i < q.n && meets; ++i) {
+          const Term& t = rule.head.t[q.col[i]];
+          if (t.is_const) {
+            meets = t.value == q.val[i];
+          } else {
+            Ival& x = loc[t.value];
+            meets = q.val[i] >= x.lo && q.val[i] <= x.hi;
+            x = Ival{q.val[i], q.val[i]};
+          }
+        }
+        if (!meets) continue;
+        for (u32 c = 0; c < rels_[h].arity; ++c) {
+          const Term& t = rule.head.t[c];
+          const Ival v = t.is_const ? Ival{t.value, t.value} : loc[t.value];
+          Ival& d = iv[h][si][c];
+          if (d.empty()) {
+            d = v;
+            settled = false;
+          } else {
+            if (v.lo < d.lo) { d.lo = v.lo; settled = false; }
+            if (v.hi > d.hi) { d.hi = v.hi; settled = false; }
+          }
+        }
+      }
+    }
+  }
+  if (!settled) return;   // (not reached: the endpoints are finitely many)
+  for (u32 r = 0; r < nrel; ++r)
+    for (u32 c = 0; c < rels_[r].arity; ++c)
+      if (!iv[r][0][c].empty()) rels_[r].maxv[c] = std::min(rels_[r].maxv[c], iv[r][0][c].hi);
+}
+
+void Engine::fact_bounds(u32 rel, const CondSet* q, u32 nq, u32* out) {
+  const Relation& R = rels_[rel];
+  Buf d = alloc(kCondSets * 8 * 4);
+  try {
+    CondBoundsArgs a{};
+    for (u32 c = 0; c < R.arity; ++c) a.col[c] = R.stage[c].as<u32>();
+    a.arity = R.arity;
+    a.n_rows = R.staged;
+    a.nq = nq;
+    for (u32 i = 0; i < nq; ++i) a.q[i] = q[i];
+    a.out = d.as<u32>();
+    launched(launch_cond_bounds(a, stream_), "bounds launch");
+    hip(hipMemcpyAsync(out, d.p, size_t(nq) * 8 * 4, hipMemcpyDeviceToHost, stream_), "bounds readback");
+    sync();
+  } catch (...) {
+    release(d);
+    throw;
+  }
+  release(d);
 }
 
 // Relations whose packed tuples need more than 64 bits (three columns of

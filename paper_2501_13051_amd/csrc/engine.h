@@ -237,6 +237,10 @@ class Engine {
   // setup
   void alloc_control();
   bool domain_analysis();    // false: some relation's packed tuple needs more than 64 bits
+  void refine_bounds();      // tighter column bounds from the rules' constant conditions
+  // bounds of the loaded facts of `rel` under condition sets (launch_cond_bounds' layout)
+  void fact_bounds(u32 rel, const CondSet* q, u32 nq, u32* out);
+  void host_fact_bounds(u32 rel, const CondSet* q, u32 nq, u32* out);
   void fit_packing();
   void compact_values();
   void host_compact_values();

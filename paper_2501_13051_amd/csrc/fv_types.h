@@ -379,6 +379,27 @@ int launch_index_runs(const IndexParams& p, u64 rows_cap, const u64* sorted, u32
 int launch_fill_u64(u64* p, u64 n, u64 value, void* stream);
 int launch_fill_u32(u32* p, u64 n, u32 value, void* stream);
 int launch_colmax(const u32* col, u64 n, u32* out_max, void* stream);
+// Column bounds under conditions: for each condition set q < nq (rows whose
+// column col[i] equals val[i], i < n, n <= 3; n = 0: every row), the minimum
+// and maximum of each column over the qualifying rows of the first n_rows
+// rows: out[q * 8 + c] = minimum, out[q * 8 + 3 + c] = maximum (c < arity),
+// out[q * 8 + 6] = 1 if any row qualified.  out holds nq * 8 words and is
+// initialised here.
+constexpr u32 kCondSets = 8;
+struct CondSet {
+  u32 n;
+  u32 col[3];
+  u32 val[3];
+};
+struct CondBoundsArgs {
+  const u32* col[3];
+  u32 arity;
+  u64 n_rows;
+  u32 nq;
+  CondSet q[kCondSets];
+  u32* out;
+};
+int launch_cond_bounds(const CondBoundsArgs& a, void* stream);
 // Pack columns into keys (rows [0,n)), shift per column.
 int launch_pack(const u32* const* cols, u32 arity, const u32* shift, u64 n, u64* keys, void* stream);
 int launch_unpack(const u64* keys, u64 n, u32 arity, const u32* shift, const u32* width,

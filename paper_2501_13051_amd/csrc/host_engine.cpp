@@ -449,6 +449,25 @@ u64 Engine::host_finish_relation(u32 ri) {
   return d;
 }
 
+// The loaded facts' column bounds under condition sets (the layout of
+// launch_cond_bounds), on the host.
+void Engine::host_fact_bounds(u32 rel, const CondSet* q, u32 nq, u32* out) {
+  const Relation& R = rels_[rel];
+  const HostRel& H = host_->rels[rel];
+  for (u32 i = 0; i < nq * 8; ++i) out[i] = (i % 8) < 3 ? 0xFFFFFFFFu : 0u;
+  for (u64 r = 0; r < R.staged; ++r)
+    for (u32 k = 0; k < nq; ++k) {
+      bool ok = true;
+      for (u32 i = 0; i < q[k].n; ++i) ok = ok && H.stage[q[k].col[i]][r] == q[k].val[i];
+      if (!ok) continue;
+      out[k * 8 + 6] = 1;
+      for (u32 c = 0; c < R.arity; ++c) {
+        out[k * 8 + c] = std::min(out[k * 8 + c], H.stage[c][r]);
+        out[k * 8 + 3 + c] = std::max(out[k * 8 + 3 + c], H.stage[c][r]);
+      }
+    }
+}
+
 void Engine::run_host(fv_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!host_) host_ = std::make_shared<HostState>(host_threads_);

@@ -895,6 +895,87 @@ int launch_colmax(const u32* col, u64 n, u32* out, void* stream) {
   return int(hipGetLastError());
 }
 
+// Conditional column bounds (see launch_cond_bounds): every thread keeps
+// the minimum, maximum and "any" of each condition set in registers over its
+// rows, then waves and the block combine them and one atomic per value and
+// block goes to out.
+__global__ __launch_bounds__(kBlock) void k_cond_bounds(CondBoundsArgs a) {
+  __shared__ u32 s_red[kCondSets * 8];
+  u32 lo[kCondSets][3], hi[kCondSets][3], any[kCondSets];
+#pragma unroll
+  for (u32 q = 0; q < kCondSets; ++q) {
+    any[q] = 0;
+#pragma unroll
+    for (u32 c = 0; c < 3; ++c) {
+      lo[q][c] = 0xFFFFFFFFu;
+      hi[q][c] = 0;
+    }
+  }
+  for (u32 i = threadIdx.x; i < kCondSets * 8; i += kBlock) s_red[i] = (i % 8) < 3 ? 0xFFFFFFFFu : 0u;
+  __syncthreads();
+  for (u64 r = u64(blockIdx.x) * kBlock + threadIdx.x; r < a.n_rows; r += u64(gridDim.x) * kBlock) {
+    u32 v[3];
+#pragma unroll
+    for (u32 c = 0; c < 3; ++c) v[c] = c < a.arity ? a.col[c][r] : 0u;
+#pragma unroll
+    for (u32 q = 0; q < kCondSets; ++q) {
+      bool ok = q < a.nq;
+#pragma unroll
+      for (u32 i = 0; i < 3; ++i) {
+        const u32 k = a.q[q].col[i];
+        const u32 x = k == 0 ? v[0] : (k == 1 ? v[1] : v[2]);
+        ok = ok && (i >= a.q[q].n || x == a.q[q].val[i]);
+      }
+      any[q] |= ok ? 1u : 0u;
+#pragma unroll
+      for (u32 c = 0; c < 3; ++c) {
+        lo[q][c] = ok && v[c] < lo[q][c] ? v[c] : lo[q][c];
+        hi[q][c] = ok && v[c] > hi[q][c] ? v[c] : hi[q][c];
+      }
+    }
+  }
+#pragma unroll
+  for (u32 q = 0; q < kCondSets; ++q) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+      any[q] |= __shfl_xor(any[q], d, kWave);
+#pragma unroll
+      for (u32 c = 0; c < 3; ++c) {
+        const u32 ol = __shfl_xor(lo[q][c], d, kWave), oh = __shfl_xor(hi[q][c], d, kWave);
+        lo[q][c] = ol < lo[q][c] ? ol : lo[q][c];
+        hi[q][c] = oh > hi[q][c] ? oh : hi[q][c];
+      }
+    }
+    if (lane_id() == 0 && any[q] && q < a.nq) {
+      atomicOr(&s_red[q * 8 + 6], 1u);
+#pragma unroll
+      for (u32 c = 0; c < 3; ++c) {
+        atomicMin(&s_red[q * 8 + c], lo[q][c]);
+        atomicMax(&s_red[q * 8 + 3 + c], hi[q][c]);
+      }
+    }
+  }
+  __syncthreads();
+  for (u32 q = 0; q < a.nq; ++q) {
+    if (!s_red[q * 8 + 6]) continue;   // block-uniform
+    if (threadIdx.x == 0) atomicOr(&a.out[q * 8 + 6], 1u);
+    if (threadIdx.x < 3) atomicMin(&a.out[q * 8 + threadIdx.x], s_red[q * 8 + threadIdx.x]);
+    else if (threadIdx.x < 6) atomicMax(&a.out[q * 8 + threadIdx.x], s_red[q * 8 + threadIdx.x]);
+  }
+}
+
+__global__ void k_cond_bounds_init(u32* out, u32 nq) {
+  for (u32 i = threadIdx.x; i < nq * 8; i += blockDim.x) out[i] = (i % 8) < 3 ? 0xFFFFFFFFu : 0u;
+}
+
+int launch_cond_bounds(const CondBoundsArgs& a, void* stream) {
+  if (a.nq == 0 || a.nq > kCondSets) return int(hipErrorInvalidValue);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_cond_bounds_init, dim3(1), dim3(64), 0, s, a.out, a.nq);
+  if (a.n_rows) hipLaunchKernelGGL(k_cond_bounds, dim3(grid_rows(a.n_rows, 1024)), dim3(kBlock), 0, s, a);
+  return int(hipGetLastError());
+}
+
 struct PackArgs {
   const u32* cols[3];
   u32 arity;

@@ -49,3 +49,26 @@ def random_edb(rnd: random.Random, dom: int = 5):
     c = [rnd.randrange(dom) for _ in range(rnd.randint(0, 3))]
     return {"e": [np.array([a for a, _ in e], np.uint32), np.array([b for _, b in e], np.uint32)],
             "c": [np.array(c, np.uint32)]}
+
+
+# Column bounds under constant conditions: p's middle column holds only small
+# constants in the facts, but the second rule fills it with values of rows
+# whose middle column is 2, and the first rule makes such rows from q, whose
+# values are large; q(5, 3) also lets the second rule make rows whose middle
+# column is 3, which that rule reads again.  A bound for p's middle column
+# that missed either path would cut values off.
+CONDITIONED_PROGRAM = """
+p(x, 2, y) :- q(x, y).
+p(x, y, z) :- p(x, 2, y), p(y, 3, z).
+s(x, y) :- p(x, 3, y).
+"""
+
+
+def conditioned_edb():
+    import numpy as np
+    i = np.arange(100, dtype=np.uint32)
+    q = [np.concatenate([i, [5]]).astype(np.uint32), np.concatenate([1_000_000 + i, [3]]).astype(np.uint32)]
+    ps = np.concatenate([1_000_000 + i, [3, 3, 7]]).astype(np.uint32)
+    pm = np.full(len(ps), 3, np.uint32)
+    po = np.concatenate([i % 7 + 10, [40, 41, 42]]).astype(np.uint32)
+    return {"q": q, "p": [ps, pm, po]}

@@ -231,6 +231,15 @@ def test_too_many_distinct_values_for_a_packed_triple():
     e.close()
 
 
+def test_bounds_under_constant_conditions():
+    from progs import CONDITIONED_PROGRAM, conditioned_edb
+    got, _, _ = _check(CONDITIONED_PROGRAM, conditioned_edb())
+    assert int(got["p"][:, 1].max()) == 1_000_099
+    got, _, _ = _check(CONDITIONED_PROGRAM, conditioned_edb(), flags=fv.FV_LEARNED,
+                       predictor=np.zeros(fv.MLP_PARAMS, np.float32))
+    assert int(got["p"][:, 1].max()) == 1_000_099
+
+
 def test_sg_forest_small_both_forms():
     edge = W.forest(8, 256, 0.05, seed=1002)
     _check(W.SG_PROGRAM, {"edge": edge})

@@ -96,3 +96,10 @@ def test_host_rejects_gpu_only_modes():
             fv.Engine(flags=fv.FV_HOST | flags,
                       predictor=np.zeros(fv.MLP_PARAMS, np.float32))
         assert ei.value.status == "FV_EINVAL"
+
+
+def test_bounds_under_constant_conditions():
+    from progs import CONDITIONED_PROGRAM, conditioned_edb
+    got, _, _ = _check(CONDITIONED_PROGRAM, conditioned_edb())
+    assert int(got["p"][:, 1].max()) == 1_000_099
+    assert [5, 40] in got["s"].tolist() and [5, 41] in got["s"].tolist()

@@ -339,7 +339,7 @@ int launch_rs_hist(const SortParams& p, void* stream, bool clear_hist) {
   if (passes == 0) return 0;
   if (clear_hist) launch_fill_u32(p.hist, u64(passes) << db, 0u, stream);
   const u64 tiles = (p.cap + kSortTile - 1) / kSortTile;
-  const int hgrid = int(tiles == 0 ? 1 : (tiles > 1024 ? 1024 : tiles));
+  const int hgrid = int(tiles == 0 ? 1 : (tiles > 4096 ? 4096 : tiles));
   if (db == 11)
     hipLaunchKernelGGL(k_rs_hist<11>, dim3(hgrid), dim3(kBlock), 0, (hipStream_t)stream, p.a, p.n_ctr, p.n_const,
                        p.cap, passes, p.hist, p.abort);

@@ -371,7 +371,7 @@ constexpr u32 kMoveChunk = 1u << 16;   // rows per listed chunk of an old run
 // block's runs), its old rows copied there on the spot (at most kInlineCopy)
 // or listed in chunks, and its start / region size set.  A block-uniform
 // call: every thread of the block must make it.
-constexpr int kResItems = 8;
+constexpr int kResItems = 2;
 __device__ __forceinline__ void reserve_runs(const IndexParams& p, const bool* act, const u32* s, const u32* c_old,
                                              const u32* from, const u64* need, u64* s_scan, u64* s_base) {
   u64 newcap[kResItems], mine = 0;

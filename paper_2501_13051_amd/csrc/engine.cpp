@@ -1303,8 +1303,8 @@ bool Engine::ensure_capacity(bool dry) {
     if (dry) return true;
     const u64 nc = std::max<u64>(stiles, st_sort_tiles_ * 2);
     release(st_sort_);
-    st_sort_ = alloc(nc * kMaxRadix * 8);
-    launched(launch_fill_u64(st_sort_.as<u64>(), nc * kMaxRadix, 0, stream_), "status clear");
+    st_sort_ = alloc(nc * sort_status_words() * 8);
+    launched(launch_fill_u64(st_sort_.as<u64>(), nc * sort_status_words(), 0, stream_), "status clear");
     st_sort_tiles_ = nc;
   }
   return n_allocs_ != allocs_before;
@@ -2907,8 +2907,8 @@ void Engine::export_rel(u32 rel, u32* const* cols, u64 capacity, u64* n_out, boo
     const u64 stiles = (n + kSortTile - 1) / kSortTile + 1;
     if (st_sort_tiles_ < stiles) {
       release(st_sort_);
-      st_sort_ = alloc(stiles * kMaxRadix * 8);
-      launched(launch_fill_u64(st_sort_.as<u64>(), stiles * kMaxRadix, 0, stream_), "status clear");
+      st_sort_ = alloc(stiles * sort_status_words() * 8);
+      launched(launch_fill_u64(st_sort_.as<u64>(), stiles * sort_status_words(), 0, stream_), "status clear");
       st_sort_tiles_ = stiles;
     }
     SortParams sp{};

@@ -256,6 +256,10 @@ class Engine {
   // true if any buffer was (dry: would be) reallocated; with look-ahead every
   // derived relation is sized for two rounds of new tuples
   bool ensure_capacity(bool dry = false);
+  // look-back words per tile of the shared sort status array: one per digit
+  // value of the widest digits any sort of this context uses (index sorts
+  // always take 8-bit digits)
+  u64 sort_status_words() const { return tune_.radix_bits == 11 ? kMaxRadix : 256; }
   void build_indices(bool idb_only);
   void build_index(Index& ix);
 
